@@ -1,0 +1,204 @@
+"""Closed-form checks ("pins") that fix the oracle independently of itself.
+
+Each check takes the oracle function it exercises as an argument and returns
+an error figure, so the same check can be run on the oracle (must pass) and
+on deliberately broken copies of it (must fail, see test_oracle_mutations).
+Expected values come from closed forms, from brute-force sums written with
+explicit loops, or from invariants -- never from the oracle itself.
+"""
+
+from __future__ import annotations
+
+import cmath
+import math
+
+import numpy as np
+
+LAMBDA = 852e-9
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+# ---------------------------------------------------------------- angular spectrum
+
+def plane_wave_error(as_fn, z=0.13, ny=24, nx=32, dx=20e-6, dy=15e-6):
+    """A sum of plane waves whose frequencies lie on the DFT grid propagates
+    exactly: each term picks up exp(2i pi z sqrt(1/lambda^2 - |f|^2))."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    xs, ys = xx * dx, yy * dy
+    terms = [(1.0 + 0.5j, 3, -2), (-0.25 + 0.75j, -5, 7), (0.6, 11, 0), (0.3j, 0, -9)]
+    x = np.zeros((ny, nx), np.complex128)
+    expect = np.zeros((ny, nx), np.complex128)
+    for a, i, j in terms:
+        fx, fy = i / (nx * dx), j / (ny * dy)
+        wave = a * np.exp(2j * np.pi * (fx * xs + fy * ys))
+        x += wave
+        expect += wave * cmath.exp(2j * math.pi * z * math.sqrt(LAMBDA ** -2 - fx * fx - fy * fy))
+    return rel(as_fn(x, LAMBDA, dx, dy, z), expect)
+
+
+def gaussian_beam(n, pitch, w0, z, coords):
+    """Paraxial Gaussian beam exp(ikz)/q exp(-r^2/(w0^2 q)), q = 1 + iz/zR."""
+    zr = math.pi * w0 * w0 / LAMBDA
+    q = 1 + 1j * z / zr
+    r2 = coords[0] ** 2 + coords[1] ** 2
+    return cmath.exp(2j * math.pi * z / LAMBDA) / q * np.exp(-r2 / (w0 * w0 * q))
+
+
+def gaussian_as_error(as_fn, z, n=128, pitch=20e-6, w0_px=8):
+    c = (np.arange(n) - n // 2) * pitch
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    w0 = w0_px * pitch
+    x0 = np.exp(-(xx ** 2 + yy ** 2) / w0 ** 2)
+    expect = gaussian_beam(n, pitch, w0, z, (xx, yy))
+    return rel(as_fn(x0, LAMBDA, pitch, pitch, z), expect)
+
+
+def gaussian_fresnel_error(fr_fn, z, n=128, pitch=20e-6, w0_px=8):
+    """Fresnel of a Gaussian, rescaled by the omitted physical constant
+    sqrt(N^2) exp(ikz)/(i lambda z) dx dy, sampled on the output grid."""
+    c = (np.arange(n) - n // 2) * pitch
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    w0 = w0_px * pitch
+    x0 = np.exp(-(xx ** 2 + yy ** 2) / w0 ** 2)
+    out_pitch = LAMBDA * abs(z) / (n * pitch)
+    co = (np.arange(n) - n // 2) * out_pitch
+    oy, ox = np.meshgrid(co, co, indexing="ij")
+    expect = gaussian_beam(n, pitch, w0, z, (ox, oy))
+    u = fr_fn(x0, LAMBDA, pitch, pitch, z)
+    phys = u * n * cmath.exp(2j * math.pi * z / LAMBDA) / (1j * LAMBDA * z) * pitch * pitch
+    return rel(phys, expect)
+
+
+def point_source_fresnel_error(fr_fn, z, ny=16, nx=32, dx=20e-6, dy=30e-6, at=(5, 21)):
+    """A Kronecker delta at (eta0, xi0) gives the paraxial spherical wave
+    centred there, exp(i pi ((x - xi0)^2 + (y - eta0)^2) / (lambda z)), with
+    the unitary scale 1/sqrt(nx ny)."""
+    n0, m0 = at
+    x = np.zeros((ny, nx))
+    x[n0, m0] = 1.0
+    xi0, eta0 = (m0 - nx // 2) * dx, (n0 - ny // 2) * dy
+    px = (np.arange(nx) - nx // 2) * LAMBDA * abs(z) / (nx * dx)
+    py = (np.arange(ny) - ny // 2) * LAMBDA * abs(z) / (ny * dy)
+    yy, xx = np.meshgrid(py, px, indexing="ij")
+    expect = np.exp(1j * np.pi * ((xx - xi0) ** 2 + (yy - eta0) ** 2) / (LAMBDA * z)) / math.sqrt(nx * ny)
+    return rel(fr_fn(x, LAMBDA, dx, dy, z), expect)
+
+
+def brute_force_as(x, wavelength, dx, dy, z):
+    """Direct O(N^4) sums: forward DFT, transfer function, inverse DFT."""
+    ny, nx = x.shape
+    spec = np.zeros((ny, nx), np.complex128)
+    for q in range(ny):
+        for p in range(nx):
+            acc = 0j
+            for n in range(ny):
+                for m in range(nx):
+                    acc += x[n, m] * cmath.exp(-2j * math.pi * (p * m / nx + q * n / ny))
+            fx = (p if p < (nx + 1) // 2 else p - nx) / (nx * dx)
+            fy = (q if q < (ny + 1) // 2 else q - ny) / (ny * dy)
+            rad = wavelength ** -2 - fx * fx - fy * fy
+            spec[q, p] = acc * (cmath.exp(2j * math.pi * z * math.sqrt(rad)) if rad > 0 else 0)
+    out = np.zeros((ny, nx), np.complex128)
+    for n in range(ny):
+        for m in range(nx):
+            acc = 0j
+            for q in range(ny):
+                for p in range(nx):
+                    acc += spec[q, p] * cmath.exp(2j * math.pi * (p * m / nx + q * n / ny))
+            out[n, m] = acc / (nx * ny)
+    return out
+
+
+def brute_force_fresnel(x, wavelength, dx, dy, z):
+    """Direct sum of the Fresnel integral with the quadratic phase of
+    |x - xi|^2 kept whole (not split into chirps), on the output grid."""
+    ny, nx = x.shape
+    opx = wavelength * abs(z) / (nx * dx)
+    opy = wavelength * abs(z) / (ny * dy)
+    out = np.zeros((ny, nx), np.complex128)
+    for q in range(ny):
+        for p in range(nx):
+            xo, yo = (p - nx // 2) * opx, (q - ny // 2) * opy
+            acc = 0j
+            for n in range(ny):
+                for m in range(nx):
+                    xi, eta = (m - nx // 2) * dx, (n - ny // 2) * dy
+                    acc += x[n, m] * cmath.exp(1j * math.pi * ((xo - xi) ** 2 + (yo - eta) ** 2) / (wavelength * z))
+            out[q, p] = acc / math.sqrt(nx * ny)
+    return out
+
+
+def brute_force_stft(u, window, stride):
+    t_count = u.shape[0]
+    j_count = (t_count - window) // stride + 1
+    out = np.zeros((j_count, window) + u.shape[1:], np.complex128)
+    for j in range(j_count):
+        for k in range(window):
+            for t in range(window):
+                out[j, k] += u[j * stride + t] * cmath.exp(-2j * math.pi * k * t / window)
+    return out
+
+
+# ---------------------------------------------------------------- temporal
+
+def pure_tone_errors(stft_fn, moments_fn, window=32, k0=5, fs=33e3):
+    """U[t] = a(r) exp(2i pi k0 t / W): all energy lands in bin k0 with
+    |S_k0|^2 = W^2 |a|^2; M1 = f_k0 M0 and M2 = f_k0^2 M0 in a band that
+    contains k0."""
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal((6, 5)) + 1j * rng.standard_normal((6, 5))
+    t = np.arange(window)
+    u = a[None] * np.exp(2j * np.pi * k0 * t / window)[:, None, None]
+    s = stft_fn(u, window, window)
+    leak = np.sum(np.abs(np.delete(s[0], k0, axis=0)) ** 2) / np.sum(np.abs(s[0]) ** 2)
+    peak = rel(np.abs(s[0, k0]) ** 2, window ** 2 * np.abs(a) ** 2)
+    fk = k0 * fs / window
+    bins = np.array([k0 - 1, k0, k0 + 1])
+    freqs = bins * fs / window
+    m0, m1, m2 = moments_fn(s, bins, freqs)
+    e0 = rel(m0[0], window ** 2 * np.abs(a) ** 2)
+    e1 = rel(m1[0], fk * window ** 2 * np.abs(a) ** 2)
+    e2 = rel(m2[0], fk * fk * window ** 2 * np.abs(a) ** 2)
+    return max(leak, peak, e0, e1, e2)
+
+
+# ---------------------------------------------------------------- PCA
+
+def pca_construction_error(pca_window_fn, w=8, ny=12, nx=10, c1=1, c2=5):
+    """X = Q diag(sigma) P^H with orthonormal Q [P x W] and unitary P:
+    eigenvalues sigma^2 (descending), C = P diag(sigma^2) P^H and
+    M0[p] = sum_{c1..c2} sigma_c^2 |Q[p, c]|^2."""
+    rng = np.random.default_rng(11)
+    npx = ny * nx
+    qm, _ = np.linalg.qr(rng.standard_normal((npx, w)) + 1j * rng.standard_normal((npx, w)))
+    pm, _ = np.linalg.qr(rng.standard_normal((w, w)) + 1j * rng.standard_normal((w, w)))
+    sigma = np.array([9.0, 5.0, 4.0, 3.0, 2.5, 1.5, 1.0, 0.5])[:w]
+    x = qm @ np.diag(sigma) @ pm.conj().T
+    u = x.T.reshape(w, ny, nx)
+    r = pca_window_fn(u, c1, c2)
+    e_lam = rel(r["eigvals"], sigma ** 2)
+    e_cov = rel(r["cov"], pm @ np.diag(sigma ** 2) @ pm.conj().T)
+    m0 = np.sum((sigma[c1:c2 + 1] ** 2)[None, :] * np.abs(qm[:, c1:c2 + 1]) ** 2, axis=1).reshape(ny, nx)
+    e_m0 = rel(r["m0"], m0)
+    v = r["eigvecs"]
+    e_orth = float(np.linalg.norm(v.conj().T @ v - np.eye(w)))
+    return max(e_lam, e_cov, e_m0, e_orth)
+
+
+def pca_rank1_error(pca_window_fn, w=6, ny=5, nx=7):
+    """X = a b^T: lambda_0 = |a|^2 |b|^2 and the other eigenvalues vanish;
+    M0 over components 1..W-1 is zero."""
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(ny * nx) + 1j * rng.standard_normal(ny * nx)
+    b = rng.standard_normal(w) + 1j * rng.standard_normal(w)
+    x = np.outer(a, b)
+    r = pca_window_fn(x.T.reshape(w, ny, nx), 1, w - 1)
+    lam0 = np.linalg.norm(a) ** 2 * np.linalg.norm(b) ** 2
+    return max(abs(r["eigvals"][0] - lam0) / lam0,
+               float(np.max(np.abs(r["eigvals"][1:]))) / lam0,
+               float(np.max(r["m0"])) / lam0)
