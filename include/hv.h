@@ -1,0 +1,168 @@
+/* hv.h -- C-ABI of the MI355X (gfx950) hologram-rendering hot path.
+ *
+ * The operations follow "Holovibes: Real-time Ultrahigh-Speed Digital
+ * Hologram Rendering and Short-Time Analysis" (arXiv 2508.03911):
+ *   - camera integers converted to complex and spatially transformed frame
+ *     by frame, by angular-spectrum propagation or a Fresnel transform
+ *     (Abstract; Sec. II-B.3; Sec. III-B.1);
+ *   - a temporal transform over a user-sized window of consecutive frames:
+ *     a short-time Fourier transform, or PCA via covariance,
+ *     eigendecomposition and projection onto a sub-basis (Sec. III-B.1);
+ *   - a per-pixel statistical moment over a range of temporal indices
+ *     (Sec. III-B.1);
+ *   - settings: reconstruction distance, propagation method, temporal
+ *     transform, window size and stride (Sec. III-B; Sec. VI-B);
+ *   - the back-end exposed as a library (Sec. VII-A, VII-B);
+ *   - buffers allocated once, not per frame (Sec. VII-C).
+ *
+ * Conventions
+ *   Arrays are row-major [frames][ny][nx]; x is the fast axis.  Complex
+ *   values are interleaved (re, im) float32 ("c64").  z is the signed
+ *   propagation distance in metres: a hologram recorded at distance z is
+ *   reconstructed with -z.  Supported frame sizes: nx, ny powers of two in
+ *   [64, 1024] (non-square allowed).  Windows: 8, 16, 32 or 64 frames.
+ *
+ * Ownership and asynchrony
+ *   Every data pointer is caller-owned DEVICE memory on the context's
+ *   device; the library never frees it.  Plans (FP64-built tables,
+ *   coefficient fragments) and workspaces belong to the context and are
+ *   allocated on first use for a given shape/setting and stream, then
+ *   reused; hv_ctx_destroy frees them.  Calls enqueue work on `hip_stream`
+ *   (a hipStream_t; NULL = the default stream) and return without waiting.
+ *   A context may be used from one host thread at a time; calls on
+ *   different streams use different workspaces.
+ *
+ * Errors
+ *   Every call returns HV_OK (0) or a negative hv_status; hv_last_error()
+ *   returns a thread-local message for the last failure.  No C++ exception
+ *   crosses this boundary.  Invalid shapes return HV_ERR_SHAPE before any
+ *   work is enqueued.
+ */
+#ifndef HV_H
+#define HV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HV_OK = 0,
+  HV_ERR_ARG = -1,      /* null pointer, bad enum, bad band or range */
+  HV_ERR_SHAPE = -2,    /* unsupported frame size, window or frame count */
+  HV_ERR_NOMEM = -3,    /* device allocation failed */
+  HV_ERR_BUDGET = -4,   /* stream refused: HBM budget exceeded */
+  HV_ERR_DEVICE = -5,   /* HIP runtime error */
+  HV_ERR_OVERFLOW = -6, /* stream ring full: frames would be lost */
+  HV_ERR_STATE = -7     /* nothing to pop / object in the wrong state */
+} hv_status;
+
+typedef enum {
+  HV_U8 = 0,   /* camera frames, 8 bit */
+  HV_U16 = 1,  /* camera frames, up to 16 bit (12-bit data low-bit aligned) */
+  HV_C64 = 3   /* complex field, interleaved float32 */
+} hv_dtype;
+
+typedef enum { HV_AS = 0, HV_FRESNEL = 1 } hv_method;
+
+/* HV_PREC_FP32: FP32 FFT arithmetic, c64 intermediates, FP32 MFMA GEMMs.
+ * HV_PREC_MIXED: FP32 FFT arithmetic, fp16 intermediates in memory with
+ * power-of-two scaling, split fp16 (hi + lo) MFMA GEMMs with FP32
+ * accumulation; eigensolves stay FP64. */
+typedef enum { HV_PREC_FP32 = 0, HV_PREC_MIXED = 1 } hv_precision;
+
+typedef struct hv_ctx hv_ctx;
+
+/* Spatial step (Abstract; Sec. II-B.3; Sec. III-B.1). */
+typedef struct {
+  double wavelength_m;
+  double pitch_x_m;
+  double pitch_y_m;
+  double z_m;   /* signed propagation distance, metres; != 0 for Fresnel */
+  int method;   /* hv_method */
+} hv_optics;
+
+/* Temporal step (Sec. III-B.1; Sec. VI-B: window and stride).  The band
+ * [f_lo_hz, f_hi_hz] keeps DFT bins ceil(f_lo W/fs) .. floor(f_hi W/fs),
+ * limited to 0..W/2 (decided in float64); symmetric_band adds the mirrored
+ * bins W-k.  f_k = k fs / W and M_n = sum_k f_k^n |S_k|^2. */
+typedef struct {
+  int window;
+  int stride;
+  double fs_hz;
+  double f_lo_hz;
+  double f_hi_hz;
+  int symmetric_band;
+} hv_temporal;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory the serving loop may admit (0 = no limit). */
+hv_status hv_ctx_create(int device, size_t hbm_budget_bytes, hv_ctx** out);
+void hv_ctx_destroy(hv_ctx* ctx);
+/* Thread-local text of the last error (never NULL). */
+const char* hv_last_error(void);
+/* Bytes of device memory held by the context's plans and workspaces. */
+size_t hv_ctx_workspace_bytes(const hv_ctx* ctx);
+/* Frames per spatial chunk (workspace size knob; 0 = automatic). */
+hv_status hv_ctx_set_chunk_frames(hv_ctx* ctx, int frames);
+
+/* ---------------------------------------------------------------- spatial */
+
+/* Reconstruct n frames (Sec. III-B.1 spatial transformation).
+ *   in   [n][ny][nx] of in_t (HV_U8, HV_U16 or HV_C64)
+ *   out  [n][ny][nx] c64: angular spectrum U = IDFT2(DFT2(x) H_z) with
+ *        H_z = exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)) (0 if
+ *        evanescent), or the single-FFT Fresnel transform
+ *        U = Q_out DFT_c(x Q_in) / sqrt(nx ny) on the output grid of pitch
+ *        lambda|z|/(n pitch) (centred DFT of sign sgn(z)).
+ *   prec selects the intermediate storage (see hv_precision). */
+hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                       int prec, void* out, void* hip_stream);
+
+/* ---------------------------------------------------------------- temporal */
+
+/* Doppler moment images (Sec. III-B.1: STFT over the window, then moments
+ * over a range of temporal indices).
+ *   in        [n][ny][nx] camera frames (HV_U8/HV_U16), or a field (HV_C64)
+ *             when optics is NULL.
+ *   m0,m1,m2  [J][ny][nx] float32 with J = floor((n - W)/stride) + 1; any of
+ *             them may be NULL to skip it (at least one non-NULL).
+ * Window j covers frames [j*stride, j*stride + W); S_j[k] =
+ * sum_t U[j*stride+t] exp(-2 pi i k t / W) (rectangular, unnormalised).
+ * Returns HV_ERR_SHAPE when n < W. */
+hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                          const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
+                          void* hip_stream);
+
+/* The windowed spectrum itself on the band bins, in band order:
+ *   spec [J][nbins][ny][nx] c64, nbins as returned by hv_band_bins. */
+hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                       const hv_temporal* temporal, int prec, void* spec, void* hip_stream);
+
+/* The band's bins and frequencies as the library decides them (host call).
+ * bins/freqs may be NULL; *nbins receives the count. */
+hv_status hv_band_bins(const hv_temporal* temporal, int* nbins, int* bins, double* freqs);
+
+/* ---------------------------------------------------------------- PCA */
+
+/* PCA over each window (Sec. III-B.1: covariance, eigendecomposition,
+ * projection onto a sub-basis).  X_j is the window's field as a [P x W]
+ * matrix; C_j = X_j^H X_j (no centring, no 1/P); eigenpairs by FP64 Jacobi,
+ * eigenvalues descending; m0[p] = sum_{c=comp_lo..comp_hi} |(X_j V)[p,c]|^2.
+ *   in       frames (HV_U8/HV_U16 with optics) or field (HV_C64, optics NULL)
+ *   m0       [J][ny][nx] float32
+ *   eigvals  [J][W] float64, descending (nullable)
+ *   cov      [J][W][W] complex float64 interleaved (nullable)
+ * 0 <= comp_lo <= comp_hi < W. */
+hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics, int window,
+                 int stride, int comp_lo, int comp_hi, int prec, float* m0, double* eigvals, double* cov,
+                 void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HV_H */

@@ -1,0 +1,639 @@
+// C-ABI entry points, context, plan cache and workspaces.
+//
+// Plans hold tables computed once in float64 on the host and stored on the
+// device as float32: the angular-spectrum transfer function (its phase
+// 2 pi z sqrt(1/lambda^2 - f^2) reaches ~1e6 rad, far beyond what float32
+// can carry), the Fresnel chirps with the centring checkerboard folded in,
+// and the MFMA fragments of the DFT coefficient matrix.  Workspaces are
+// per stream and grow only when a larger shape arrives (allocation is kept
+// out of the steady state, Sec. VII-C).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "hv_ctx.h"
+#include "hv_internal.h"
+
+namespace hvi {
+
+static thread_local char g_err[512] = "";
+
+hv_status fail(hv_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+const char* last_error() { return g_err; }
+
+// ---------------------------------------------------------------- device buffers
+
+DevBuf::~DevBuf() { release(); }
+void DevBuf::release() {
+  if (ptr) hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+hv_status DevBuf::ensure(size_t want, size_t* accounted) {
+  if (want <= bytes) return HV_OK;
+  if (accounted) *accounted -= bytes;
+  if (ptr) hipDeviceSynchronize();  // queued work may still read the old buffer
+  release();
+  if (hipMalloc(&ptr, want) != hipSuccess) {
+    hipGetLastError();
+    ptr = nullptr;
+    return fail(HV_ERR_NOMEM, "hipMalloc of %zu bytes failed", want);
+  }
+  bytes = want;
+  if (accounted) *accounted += bytes;
+  return HV_OK;
+}
+hv_status DevBuf::upload(const void* host, size_t n, size_t* accounted) {
+  hv_status st = ensure(n, accounted);
+  if (st) return st;
+  if (hipMemcpy(ptr, host, n, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(HV_ERR_DEVICE, "table upload failed: %s", hipGetErrorString(hipGetLastError()));
+  return HV_OK;
+}
+
+// ---------------------------------------------------------------- band
+
+int band_bins(const hv_temporal& tp, std::vector<int>& bins, std::vector<double>& freqs) {
+  bins.clear();
+  freqs.clear();
+  const int w = tp.window;
+  long lo = (long)std::ceil(tp.f_lo_hz * w / tp.fs_hz);
+  long hi = (long)std::floor(tp.f_hi_hz * w / tp.fs_hz);
+  if (lo < 0) lo = 0;
+  if (hi > w / 2) hi = w / 2;
+  for (long k = lo; k <= hi; ++k) {
+    bins.push_back((int)k);
+    freqs.push_back((double)k * tp.fs_hz / w);
+  }
+  if (tp.symmetric_band) {
+    const size_t npos = bins.size();
+    for (size_t i = 0; i < npos; ++i) {
+      const int k = bins[i];
+      if (k > 0 && 2 * k != w) {
+        bins.push_back(w - k);
+        freqs.push_back((double)k * tp.fs_hz / w);
+      }
+    }
+  }
+  return (int)bins.size();
+}
+
+// ---------------------------------------------------------------- table builders (float64)
+
+static hv_status build_as_table(Ctx* c, AsPlan& p) {
+  const int ny = p.ny, nx = p.nx;
+  std::vector<float2> h((size_t)nx * ny);
+  const double inv_l2 = 1.0 / (p.wavelength * p.wavelength);
+  for (int cx = 0; cx < nx; ++cx) {
+    const double fx = (cx < (nx + 1) / 2 ? cx : cx - nx) / (nx * p.dx);
+    for (int cy = 0; cy < ny; ++cy) {
+      const double fy = (cy < (ny + 1) / 2 ? cy : cy - ny) / (ny * p.dy);
+      const double rad = inv_l2 - fx * fx - fy * fy;
+      double re = 0.0, im = 0.0;
+      if (rad > 0) {
+        const double ph = 2.0 * M_PI * p.z * std::sqrt(rad);
+        re = std::cos(ph) / ny;
+        im = std::sin(ph) / ny;
+      }
+      h[(size_t)cx * ny + cy] = make_float2((float)re, (float)im);
+    }
+  }
+  return p.ht.upload(h.data(), h.size() * sizeof(float2), &c->held);
+}
+
+static hv_status build_fresnel_tables(Ctx* c, FresnelPlan& p) {
+  const int ny = p.ny, nx = p.nx;
+  const double lz = p.wavelength * p.z;
+  const double opx = p.wavelength * std::fabs(p.z) / (nx * p.dx);
+  const double opy = p.wavelength * std::fabs(p.z) / (ny * p.dy);
+  std::vector<float2> t(2 * (size_t)(nx + ny));
+  auto chirp = [&](double r, int idx) {
+    const double ph = M_PI * r * r / lz;
+    const double sg = (idx & 1) ? -1.0 : 1.0;  // (-1)^index: centring of the DFT
+    return make_float2((float)(sg * std::cos(ph)), (float)(sg * std::sin(ph)));
+  };
+  for (int m = 0; m < nx; ++m) t[m] = chirp((m - nx / 2) * p.dx, m);
+  for (int n = 0; n < ny; ++n) t[nx + n] = chirp((n - ny / 2) * p.dy, n);
+  for (int m = 0; m < nx; ++m) t[nx + ny + m] = chirp((m - nx / 2) * opx, m);
+  for (int n = 0; n < ny; ++n) t[2 * nx + ny + n] = chirp((n - ny / 2) * opy, n);
+  return p.tables.upload(t.data(), t.size() * sizeof(float2), &c->held);
+}
+
+static hv_status build_dft_plan(Ctx* c, DftPlan& p) {
+  const int w = p.window;
+  const int nb = (int)p.bins.size();
+  p.mtiles = (nb + 15) / 16;
+  const int mt = p.mtiles;
+  auto coef = [&](int m, int k) -> double {
+    const int b = m >> 1, t = k >> 1;
+    if (b >= nb) return 0.0;
+    const long prod = ((long)p.bins[b] * t) % w;
+    const double th = 2.0 * M_PI * (double)prod / w;
+    const double cs = std::cos(th), sn = std::sin(th);
+    if ((m & 1) == 0) return (k & 1) == 0 ? cs : sn;
+    return (k & 1) == 0 ? -sn : cs;
+  };
+  std::vector<float> a32((size_t)mt * w * 64);
+  for (int m_t = 0; m_t < mt; ++m_t)
+    for (int kk = 0; kk < w; ++kk)
+      for (int lane = 0; lane < 64; ++lane)
+        a32[((size_t)m_t * w + kk) * 64 + lane] = (float)coef(32 * m_t + (lane & 31), 2 * kk + (lane >> 5));
+  std::vector<hv_h8> hi((size_t)mt * (w / 8) * 64), lo(hi.size());
+  for (int m_t = 0; m_t < mt; ++m_t)
+    for (int kk = 0; kk < w / 8; ++kk)
+      for (int lane = 0; lane < 64; ++lane) {
+        hv_h8 h, l;
+        for (int e = 0; e < 8; ++e) {
+          const float a = (float)coef(32 * m_t + (lane & 31), 16 * kk + 8 * (lane >> 5) + e);
+          h[e] = (_Float16)a;
+          l[e] = (_Float16)(a - (float)h[e]);
+        }
+        hi[((size_t)m_t * (w / 8) + kk) * 64 + lane] = h;
+        lo[((size_t)m_t * (w / 8) + kk) * 64 + lane] = l;
+      }
+  std::vector<float> wts((size_t)3 * mt * 16, 0.f);
+  for (int b = 0; b < nb; ++b) {
+    wts[b] = 1.0f;
+    wts[mt * 16 + b] = (float)p.freqs[b];
+    wts[2 * mt * 16 + b] = (float)(p.freqs[b] * p.freqs[b]);
+  }
+  hv_status st = p.a32.upload(a32.data(), a32.size() * sizeof(float), &c->held);
+  if (!st) st = p.a16hi.upload(hi.data(), hi.size() * sizeof(hv_h8), &c->held);
+  if (!st) st = p.a16lo.upload(lo.data(), lo.size() * sizeof(hv_h8), &c->held);
+  if (!st) st = p.wts.upload(wts.data(), wts.size() * sizeof(float), &c->held);
+  return st;
+}
+
+// ---------------------------------------------------------------- plan lookup
+
+AsPlan* Ctx::as_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
+  auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m);
+  auto it = as_plans.find(key);
+  if (it != as_plans.end()) return it->second.get();
+  auto p = std::make_unique<AsPlan>();
+  p->ny = ny;
+  p->nx = nx;
+  p->wavelength = o.wavelength_m;
+  p->dx = o.pitch_x_m;
+  p->dy = o.pitch_y_m;
+  p->z = o.z_m;
+  *st = build_as_table(this, *p);
+  if (*st) return nullptr;
+  AsPlan* raw = p.get();
+  as_plans[key] = std::move(p);
+  return raw;
+}
+
+FresnelPlan* Ctx::fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
+  auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m);
+  auto it = fr_plans.find(key);
+  if (it != fr_plans.end()) return it->second.get();
+  auto p = std::make_unique<FresnelPlan>();
+  p->ny = ny;
+  p->nx = nx;
+  p->wavelength = o.wavelength_m;
+  p->dx = o.pitch_x_m;
+  p->dy = o.pitch_y_m;
+  p->z = o.z_m;
+  *st = build_fresnel_tables(this, *p);
+  if (*st) return nullptr;
+  FresnelPlan* raw = p.get();
+  fr_plans[key] = std::move(p);
+  return raw;
+}
+
+DftPlan* Ctx::dft_plan(const hv_temporal& tp, hv_status* st) {
+  std::vector<int> bins;
+  std::vector<double> freqs;
+  band_bins(tp, bins, freqs);
+  if (bins.empty()) {
+    *st = fail(HV_ERR_ARG, "band [%g, %g] Hz holds no DFT bin at W=%d fs=%g", tp.f_lo_hz, tp.f_hi_hz, tp.window,
+               tp.fs_hz);
+    return nullptr;
+  }
+  auto key = std::make_tuple(tp.window, bins, freqs);
+  auto it = dft_plans.find(key);
+  if (it != dft_plans.end()) return it->second.get();
+  auto p = std::make_unique<DftPlan>();
+  p->window = tp.window;
+  p->bins = bins;
+  p->freqs = freqs;
+  *st = build_dft_plan(this, *p);
+  if (*st) return nullptr;
+  DftPlan* raw = p.get();
+  dft_plans[key] = std::move(p);
+  return raw;
+}
+
+DevBuf& Ctx::work(hipStream_t s, int slot) { return ws[std::make_pair((void*)s, slot)]; }
+
+int Ctx::chunk_frames_for(int ny, int nx) const {
+  if (chunk_frames > 0) return chunk_frames;
+  // about 256 MiB of c64 spectrum + field per chunk, at least 64 frames
+  const long per = (long)ny * nx * 8 * 2;
+  long f = (256L << 20) / per;
+  if (f < 64) f = 64;
+  if (f > 2048) f = 2048;
+  return (int)f;
+}
+
+}  // namespace hvi
+
+using namespace hvi;
+
+// ---------------------------------------------------------------- validation helpers
+
+static hv_status check_frame(int n, int ny, int nx) {
+  if (n < 0) return fail(HV_ERR_SHAPE, "negative frame count");
+  if (!pow2_in(nx, 64, 1024) || !pow2_in(ny, 64, 1024))
+    return fail(HV_ERR_SHAPE, "frame %dx%d: nx and ny must be powers of two in [64, 1024]", nx, ny);
+  return HV_OK;
+}
+
+static hv_status check_optics(const hv_optics* o) {
+  if (!o) return fail(HV_ERR_ARG, "optics is NULL");
+  if (!(o->wavelength_m > 0) || !(o->pitch_x_m > 0) || !(o->pitch_y_m > 0) || !std::isfinite(o->z_m))
+    return fail(HV_ERR_ARG, "wavelength and pitches must be positive, z finite");
+  if (o->method != HV_AS && o->method != HV_FRESNEL) return fail(HV_ERR_ARG, "unknown method %d", o->method);
+  if (o->method == HV_FRESNEL && o->z_m == 0.0) return fail(HV_ERR_ARG, "Fresnel transform needs z != 0");
+  return HV_OK;
+}
+
+static hv_status check_dtype(int t, bool allow_field) {
+  if (t == HV_U8 || t == HV_U16) return HV_OK;
+  if (t == HV_C64 && allow_field) return HV_OK;
+  return fail(HV_ERR_ARG, "input dtype %d not allowed here", t);
+}
+
+static size_t in_elem(int t) { return t == HV_U8 ? 1 : t == HV_U16 ? 2 : 8; }
+
+static hv_status enter(hv_ctx* ctx) {
+  if (!ctx) return fail(HV_ERR_ARG, "context is NULL");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice(%d) failed", ctx->device);
+  return HV_OK;
+}
+
+// Power-of-two scale that keeps a unitary transform of the input inside the
+// fp16 range: |U| <= ||x||_2 <= sqrt(P) * max input value.
+static float fp16_field_scale(int in_t, int ny, int nx) {
+  if (in_t == HV_C64) return 1.0f;  // a field input is taken as |u| < 32768
+  const double maxv = in_t == HV_U8 ? 255.0 : 65535.0;
+  const double bound = std::sqrt((double)ny * nx) * maxv;
+  int k = 0;
+  while (bound * std::ldexp(1.0, -k) > 32768.0) ++k;
+  return (float)std::ldexp(1.0, -k);
+}
+
+// ---------------------------------------------------------------- spatial driver
+
+namespace hvi {
+
+// Spatial transform of nf frames starting at `in` into either the AS column
+// output Z (as_z_only, real AS input: row inverse left to the caller) or the
+// field F.  Returns the buffers used through zbuf/fbuf.
+struct SpatialOut {
+  void* z = nullptr;   // [nf][ny][nx] after the AS column pass (AS only)
+  void* f = nullptr;   // [nf][ny][nx] field
+  bool half = false;
+  float z_to_field = 1.f;  // field = z_to_field * IDFT_x(z)
+  float f_scale = 1.f;     // stored field = f_scale * U
+};
+
+hv_status spatial(Ctx* c, const void* in, int in_t, int nf, int ny, int nx, const hv_optics& o, bool mixed,
+                  bool want_field, float f_scale, hipStream_t st, SpatialOut& out) {
+  const size_t cplx = mixed ? 4 : 8;
+  const size_t frame = (size_t)ny * nx;
+  const float s1 = mixed ? (in_t == HV_U16 ? 1.0f / (16.0f * nx) : 1.0f / nx) : 1.0f;
+  out.half = mixed;
+  out.f_scale = f_scale;
+  hv_status s;
+  if (o.method == HV_AS) {
+    AsPlan* p = c->as_plan(ny, nx, o, &s);
+    if (!p) return s;
+    DevBuf& zb = c->work(st, 1);
+    if ((s = zb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
+    if (in_t == HV_C64) {
+      DevBuf& tb = c->work(st, 0);
+      if ((s = tb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
+      if ((s = launch_rows_c2c(in, in_t, tb.ptr, mixed, nullptr, nullptr, -1, nf, ny, nx, s1, st))) return s;
+      if ((s = launch_col_full(tb.ptr, zb.ptr, mixed, p->ht_ptr(), nf, ny, nx, st))) return s;
+    } else {
+      DevBuf& tb = c->work(st, 0);
+      if ((s = tb.ensure((size_t)nf * (frame / 2) * cplx, &c->held))) return s;
+      if ((s = launch_row_r2c(in, (hv_dtype)in_t, tb.ptr, mixed, nf, ny, nx, s1, st))) return s;
+      if ((s = launch_col_as(tb.ptr, zb.ptr, mixed, p->ht_ptr(), nf, ny, nx, st))) return s;
+    }
+    out.z = zb.ptr;
+    out.z_to_field = 1.0f / (nx * s1);
+    if (want_field) {
+      DevBuf& fb = c->work(st, 2);
+      if ((s = fb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
+      if ((s = launch_row_inv(zb.ptr, mixed, fb.ptr, mixed, nf, ny, nx, out.z_to_field * f_scale, st))) return s;
+      out.f = fb.ptr;
+    }
+    return HV_OK;
+  }
+  FresnelPlan* p = c->fresnel_plan(ny, nx, o, &s);
+  if (!p) return s;
+  const int dir = o.z_m > 0 ? -1 : +1;
+  DevBuf& tb = c->work(st, 0);
+  if ((s = tb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
+  DevBuf& fb = c->work(st, 2);
+  if ((s = fb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
+  const float2* q = (const float2*)p->tables.ptr;
+  if ((s = launch_rows_c2c(in, in_t, tb.ptr, mixed, q, q + nx, dir, nf, ny, nx, s1, st))) return s;
+  const float unit = (float)(1.0 / std::sqrt((double)nx * ny));
+  if ((s = launch_fresnel_cols(tb.ptr, mixed, fb.ptr, mixed, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
+                               unit / s1 * f_scale, st)))
+    return s;
+  out.f = fb.ptr;
+  return HV_OK;
+}
+
+}  // namespace hvi
+
+// ---------------------------------------------------------------- C-ABI
+
+extern "C" {
+
+const char* hv_last_error(void) { return hvi::last_error(); }
+
+hv_status hv_ctx_create(int device, size_t hbm_budget_bytes, hv_ctx** out) {
+  if (!out) return fail(HV_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    hipGetLastError();
+    return fail(HV_ERR_DEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= count) return fail(HV_ERR_ARG, "device %d out of range (%d devices)", device, count);
+  if (hipSetDevice(device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice(%d) failed", device);
+  hv_ctx* c = new (std::nothrow) hv_ctx();
+  if (!c) return fail(HV_ERR_NOMEM, "host allocation failed");
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  if (const char* e = std::getenv("HV_CHUNK_FRAMES")) c->chunk_frames = std::atoi(e);
+  *out = c;
+  return HV_OK;
+}
+
+void hv_ctx_destroy(hv_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  delete ctx;
+}
+
+size_t hv_ctx_workspace_bytes(const hv_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+hv_status hv_ctx_set_chunk_frames(hv_ctx* ctx, int frames) {
+  if (!ctx) return fail(HV_ERR_ARG, "context is NULL");
+  if (frames < 0) return fail(HV_ERR_ARG, "negative chunk");
+  ctx->chunk_frames = frames;
+  return HV_OK;
+}
+
+hv_status hv_band_bins(const hv_temporal* tp, int* nbins, int* bins, double* freqs) {
+  if (!tp || !nbins) return fail(HV_ERR_ARG, "NULL argument");
+  if (tp->window <= 0 || !(tp->fs_hz > 0)) return fail(HV_ERR_ARG, "window and fs must be positive");
+  std::vector<int> b;
+  std::vector<double> f;
+  *nbins = band_bins(*tp, b, f);
+  for (size_t i = 0; i < b.size(); ++i) {
+    if (bins) bins[i] = b[i];
+    if (freqs) freqs[i] = f[i];
+  }
+  return HV_OK;
+}
+
+hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                       int prec, void* out, void* hip_stream) {
+  hv_status s;
+  if ((s = enter(ctx))) return s;
+  if ((s = check_frame(n, ny, nx)) || (s = check_optics(optics)) || (s = check_dtype(in_t, true))) return s;
+  if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
+  if (n == 0) return HV_OK;
+  if (!in || !out) return fail(HV_ERR_ARG, "NULL data pointer");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool mixed = prec == HV_PREC_MIXED;
+  const int chunk = ctx->chunk_frames_for(ny, nx);
+  const size_t frame = (size_t)ny * nx;
+  for (int f0 = 0; f0 < n; f0 += chunk) {
+    const int nf = n - f0 < chunk ? n - f0 : chunk;
+    const char* src = (const char*)in + (size_t)f0 * frame * in_elem(in_t);
+    float2* dst = (float2*)out + (size_t)f0 * frame;
+    SpatialOut so;
+    if (optics->method == HV_AS) {
+      if ((s = spatial(ctx, src, in_t, nf, ny, nx, *optics, mixed, false, 1.f, st, so))) return s;
+      if ((s = launch_row_inv(so.z, so.half, dst, false, nf, ny, nx, so.z_to_field, st))) return s;
+    } else {
+      // Fresnel writes the field straight from its column pass
+      const bool mix = mixed;
+      const int dir = optics->z_m > 0 ? -1 : +1;
+      FresnelPlan* p = ctx->fresnel_plan(ny, nx, *optics, &s);
+      if (!p) return s;
+      DevBuf& tb = ctx->work(st, 0);
+      if ((s = tb.ensure((size_t)nf * frame * (mix ? 4 : 8), &ctx->held))) return s;
+      const float s1 = mix ? (in_t == HV_U16 ? 1.0f / (16.0f * nx) : 1.0f / nx) : 1.0f;
+      const float2* q = (const float2*)p->tables.ptr;
+      if ((s = launch_rows_c2c(src, in_t, tb.ptr, mix, q, q + nx, dir, nf, ny, nx, s1, st))) return s;
+      const float unit = (float)(1.0 / std::sqrt((double)nx * ny));
+      if ((s = launch_fresnel_cols(tb.ptr, mix, dst, false, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
+                                   unit / s1, st)))
+        return s;
+    }
+  }
+  return HV_OK;
+}
+
+// Shared driver of hv_stft_moments and hv_stft_bins.
+static hv_status stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                             const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
+                             void* hip_stream) {
+  hv_status s;
+  if ((s = enter(ctx))) return s;
+  if ((s = check_frame(n, ny, nx))) return s;
+  if (!tp) return fail(HV_ERR_ARG, "temporal is NULL");
+  const int w = tp->window, stride = tp->stride;
+  if (w != 8 && w != 16 && w != 32 && w != 64) return fail(HV_ERR_SHAPE, "window %d: use 8, 16, 32 or 64", w);
+  if (stride <= 0) return fail(HV_ERR_ARG, "stride must be positive");
+  if (!(tp->fs_hz > 0)) return fail(HV_ERR_ARG, "fs must be positive");
+  if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
+  if (optics) {
+    if ((s = check_optics(optics)) || (s = check_dtype(in_t, true))) return s;
+  } else if (in_t != HV_C64) {
+    return fail(HV_ERR_ARG, "without optics the input must be a field (HV_C64)");
+  }
+  if (n < w) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, w);
+  if (!in || (!m0 && !m1 && !m2 && !spec)) return fail(HV_ERR_ARG, "NULL data pointer");
+  DftPlan* dp = ctx->dft_plan(*tp, &s);
+  if (!dp) return s;
+  const int nwin_total = (n - w) / stride + 1;
+  const bool mixed = prec == HV_PREC_MIXED;
+  const size_t frame = (size_t)ny * nx;
+  hipStream_t st = (hipStream_t)hip_stream;
+  CoefGemm g{w, dp->mtiles, (int)dp->bins.size(), (const float*)dp->a32.ptr, (const hv_h8*)dp->a16hi.ptr,
+             (const hv_h8*)dp->a16lo.ptr, (const float*)dp->wts.ptr, 3};
+  const int nb = (int)dp->bins.size();
+  if (!optics) {
+    const float bsc = mixed ? fp16_field_scale(HV_C64, ny, nx) : 1.f;
+    return launch_field_coef(in, false, (long)frame, stride, nwin_total, g, mixed, bsc, mixed ? 1.f / bsc : 1.f, m0,
+                             m1, m2, spec, st);
+  }
+  const int chunk = ctx->chunk_frames_for(ny, nx);
+  int gw = chunk >= w ? (chunk - w) / stride + 1 : 1;
+  if (gw < 1) gw = 1;
+  const float fsc = mixed ? fp16_field_scale(in_t, ny, nx) : 1.f;
+  for (int j0 = 0; j0 < nwin_total; j0 += gw) {
+    const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
+    const int f0 = j0 * stride;
+    const int nf = (g_n - 1) * stride + w;
+    const char* src = (const char*)in + (size_t)f0 * frame * in_elem(in_t);
+    float* o0 = m0 ? m0 + (size_t)j0 * frame : nullptr;
+    float* o1 = m1 ? m1 + (size_t)j0 * frame : nullptr;
+    float* o2 = m2 ? m2 + (size_t)j0 * frame : nullptr;
+    float2* os = spec ? spec + (size_t)j0 * nb * frame : nullptr;
+    const bool fused = optics->method == HV_AS && rowinv_coef_fits(nx, w);
+    SpatialOut so;
+    if ((s = spatial(ctx, src, in_t, nf, ny, nx, *optics, mixed, !fused, fsc, st, so))) return s;
+    if (fused) {
+      // B = z_to_field * IDFT_x(z) * bsc with bsc keeping fp16 in range
+      const float bsc = mixed ? so.z_to_field * fsc : 1.f;
+      const float amp = mixed ? 1.f / fsc : so.z_to_field;
+      if ((s = launch_rowinv_coef(so.z, so.half, ny, nx, stride, g_n, g, mixed, bsc, amp, o0, o1, o2, os, st)))
+        return s;
+    } else {
+      if ((s = launch_field_coef(so.f, so.half, (long)frame, stride, g_n, g, mixed, 1.f, 1.f / so.f_scale, o0, o1,
+                                 o2, os, st)))
+        return s;
+    }
+  }
+  return HV_OK;
+}
+
+hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                          const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
+                          void* hip_stream) {
+  if (!m0 && !m1 && !m2) return fail(HV_ERR_ARG, "no moment requested");
+  return stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, m0, m1, m2, nullptr, hip_stream);
+}
+
+hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                       const hv_temporal* temporal, int prec, void* spec, void* hip_stream) {
+  if (!spec) return fail(HV_ERR_ARG, "spec is NULL");
+  return stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, nullptr, nullptr, nullptr, (float2*)spec,
+                     hip_stream);
+}
+
+hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics, int window,
+                 int stride, int comp_lo, int comp_hi, int prec, float* m0, double* eigvals, double* cov,
+                 void* hip_stream) {
+  hv_status s;
+  if ((s = enter(ctx))) return s;
+  if ((s = check_frame(n, ny, nx))) return s;
+  if (window != 16 && window != 32 && window != 64) return fail(HV_ERR_SHAPE, "PCA window %d: use 16, 32 or 64", window);
+  if (stride <= 0) return fail(HV_ERR_ARG, "stride must be positive");
+  if (!(0 <= comp_lo && comp_lo <= comp_hi && comp_hi < window))
+    return fail(HV_ERR_ARG, "component range [%d, %d] outside [0, %d)", comp_lo, comp_hi, window);
+  if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
+  if (optics) {
+    if ((s = check_optics(optics)) || (s = check_dtype(in_t, true))) return s;
+  } else if (in_t != HV_C64) {
+    return fail(HV_ERR_ARG, "without optics the input must be a field (HV_C64)");
+  }
+  if (n < window) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, window);
+  if (!in || !m0) return fail(HV_ERR_ARG, "NULL data pointer");
+  const bool mixed = prec == HV_PREC_MIXED;
+  const int w = window;
+  const int nwin_total = (n - w) / stride + 1;
+  const size_t frame = (size_t)ny * nx;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int npair = comp_hi - comp_lo + 1;
+  const int mtiles = (npair + 15) / 16;
+  const int nblk = (int)std::max<long>(1, std::min<long>(256, (long)frame / 4096));
+  const int chunk = ctx->chunk_frames_for(ny, nx);
+  int gw = chunk >= w ? (chunk - w) / stride + 1 : 1;
+  if (gw < 1) gw = 1;
+  // per-window scratch
+  DevBuf& part = ctx->work(st, 10);
+  DevBuf& cv = ctx->work(st, 11);
+  DevBuf& ev = ctx->work(st, 12);
+  DevBuf& vec = ctx->work(st, 13);
+  DevBuf& a32 = ctx->work(st, 14);
+  DevBuf& a16h = ctx->work(st, 15);
+  DevBuf& a16l = ctx->work(st, 16);
+  DevBuf& wts = ctx->work(st, 17);
+  const size_t M = 2 * (size_t)w;
+  if ((s = part.ensure((size_t)gw * nblk * M * M * 4, &ctx->held))) return s;
+  if ((s = cv.ensure((size_t)gw * w * w * 16, &ctx->held))) return s;
+  if ((s = ev.ensure((size_t)gw * w * 8, &ctx->held))) return s;
+  if ((s = vec.ensure((size_t)gw * w * w * 16, &ctx->held))) return s;
+  if ((s = a32.ensure((size_t)gw * mtiles * w * 64 * 4, &ctx->held))) return s;
+  if ((s = a16h.ensure((size_t)gw * mtiles * (w / 8) * 64 * 16, &ctx->held))) return s;
+  if ((s = a16l.ensure((size_t)gw * mtiles * (w / 8) * 64 * 16, &ctx->held))) return s;
+  {
+    std::vector<float> hw((size_t)3 * mtiles * 16, 0.f);
+    for (int i = 0; i < npair; ++i) hw[i] = 1.f;
+    if ((s = wts.upload(hw.data(), hw.size() * 4, &ctx->held))) return s;
+  }
+  const float fsc = mixed ? fp16_field_scale(optics ? in_t : HV_C64, ny, nx) : 1.f;
+  for (int j0 = 0; j0 < nwin_total; j0 += gw) {
+    const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
+    const int f0 = j0 * stride;
+    const int nf = (g_n - 1) * stride + w;
+    const void* field;
+    bool half;
+    float fs;
+    if (optics) {
+      const char* src = (const char*)in + (size_t)f0 * frame * in_elem(in_t);
+      SpatialOut so;
+      if ((s = spatial(ctx, src, in_t, nf, ny, nx, *optics, mixed, true, fsc, st, so))) return s;
+      field = so.f;
+      half = so.half;
+      fs = so.f_scale;
+    } else {
+      field = (const float2*)in + (size_t)f0 * frame;
+      half = false;
+      fs = fsc;
+    }
+    if ((s = launch_gram_partials(field, half, (long)frame, stride, g_n, w, mixed, half ? 1.f : fs,
+                                  (float*)part.ptr, nblk, st)))
+      return s;
+    if ((s = launch_gram_reduce((const float*)part.ptr, g_n, nblk, w, 1.0 / ((double)fs * fs), (double*)cv.ptr, st)))
+      return s;
+    if ((s = launch_jacobi((const double*)cv.ptr, g_n, w, (double*)ev.ptr, (double*)vec.ptr, 40, st))) return s;
+    if ((s = launch_proj_coefs((const double*)vec.ptr, g_n, w, comp_lo, comp_hi, mtiles, (float*)a32.ptr,
+                               (hv_h8*)a16h.ptr, (hv_h8*)a16l.ptr, st)))
+      return s;
+    if ((s = launch_proj_energy(field, half, (long)frame, stride, g_n, w, mtiles, npair, (const float*)a32.ptr,
+                                (const hv_h8*)a16h.ptr, (const hv_h8*)a16l.ptr, (const float*)wts.ptr, mixed,
+                                half ? 1.f : fs, 1.f / fs, m0 + (size_t)j0 * frame, st)))
+      return s;
+    if (eigvals && hipMemcpyAsync(eigvals + (size_t)j0 * w, ev.ptr, (size_t)g_n * w * 8, hipMemcpyDeviceToDevice,
+                                  st) != hipSuccess)
+      return fail(HV_ERR_DEVICE, "eigenvalue copy failed");
+    if (cov && hipMemcpyAsync(cov + (size_t)j0 * w * w * 2, cv.ptr, (size_t)g_n * w * w * 16,
+                              hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return fail(HV_ERR_DEVICE, "covariance copy failed");
+  }
+  return HV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+// LDS-resident batched radix FFT for gfx950 (wave64).
+//
+// A workgroup transforms NB sequences of length N that sit in LDS.  Each
+// pass is a Stockham step of radix R: every butterfly reads R values at
+// stride N/R, applies the twiddles, does an R-point DFT in registers and
+// writes R values at stride Ns (the product of the earlier radices).  The
+// transform is done in place: all reads of a pass complete before a
+// workgroup barrier, then all writes, then another barrier.
+//
+// Layout of sequence b in LDS (float2 units): base b*STRIDE, element i at
+// i + (i >> 4).  The skew of one slot every 16 elements and an odd row
+// stride keep the strided butterfly writes and the transposed reads of the
+// callers off the same LDS banks.
+//
+// Direction: DIR = -1 computes sum_m a[m] exp(-2 pi i k m / N) (forward),
+// DIR = +1 the unnormalised inverse.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hvk {
+
+struct c2 {
+  __device__ static inline float2 add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+  __device__ static inline float2 sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+  __device__ static inline float2 mul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  }
+  __device__ static inline float2 conj(float2 a) { return make_float2(a.x, -a.y); }
+  __device__ static inline float2 scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+  // multiply by DIR*i : (x + iy) * (DIR i) = DIR * (-y + i x)
+  template <int DIR>
+  __device__ static inline float2 rot(float2 a) {
+    return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+  }
+};
+
+// Skewed LDS index within one sequence.
+__device__ __host__ constexpr inline int skew(int i) { return i + (i >> 4); }
+// Row stride (float2 units) for sequences of length N: skewed length + 1 (odd).
+__device__ __host__ constexpr inline int lds_stride(int n) { return n + (n >> 4) + 1; }
+
+// ---------------------------------------------------------------- small DFTs
+
+template <int DIR>
+__device__ inline void dft2(float2& a, float2& b) {
+  float2 t = a;
+  a = c2::add(t, b);
+  b = c2::sub(t, b);
+}
+
+template <int DIR>
+__device__ inline void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+  float2 s02 = c2::add(v0, v2), d02 = c2::sub(v0, v2);
+  float2 s13 = c2::add(v1, v3), d13 = c2::rot<DIR>(c2::sub(v1, v3));
+  v0 = c2::add(s02, s13);
+  v2 = c2::sub(s02, s13);
+  v1 = c2::add(d02, d13);
+  v3 = c2::sub(d02, d13);
+}
+
+// exp(DIR * 2 pi i m / 16) for m = 0..15 (cos and sin of multiples of pi/8).
+__device__ inline float2 w16(int m, int dir) {
+  constexpr float C1 = 0.92387953251128674f;   // cos(pi/8)
+  constexpr float S1 = 0.38268343236508978f;   // sin(pi/8)
+  constexpr float H = 0.70710678118654752f;    // cos(pi/4)
+  const float cs[16] = {1.f, C1, H, S1, 0.f, -S1, -H, -C1, -1.f, -C1, -H, -S1, 0.f, S1, H, C1};
+  const float sn[16] = {0.f, S1, H, C1, 1.f, C1, H, S1, 0.f, -S1, -H, -C1, -1.f, -C1, -H, -S1};
+  return make_float2(cs[m & 15], dir * sn[m & 15]);
+}
+
+// R-point DFT of v[0..R) in registers, natural order in and out.
+template <int R, int DIR>
+__device__ inline void dft_reg(float2* v) {
+  if constexpr (R == 2) {
+    dft2<DIR>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<DIR>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    // X[k] = E[k] + w8^k O[k], X[k+4] = E[k] - w8^k O[k]
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    o1 = c2::mul(o1, w16(2, DIR));
+    o2 = c2::rot<DIR>(o2);
+    o3 = c2::mul(o3, w16(6, DIR));
+    v[0] = c2::add(e0, o0); v[4] = c2::sub(e0, o0);
+    v[1] = c2::add(e1, o1); v[5] = c2::sub(e1, o1);
+    v[2] = c2::add(e2, o2); v[6] = c2::sub(e2, o2);
+    v[3] = c2::add(e3, o3); v[7] = c2::sub(e3, o3);
+  } else if constexpr (R == 16) {
+    // n = 4 n2 + n1 ; k = k1 + 4 k2
+    float2 y[4][4];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+      y[n1][0] = v[n1]; y[n1][1] = v[n1 + 4]; y[n1][2] = v[n1 + 8]; y[n1][3] = v[n1 + 12];
+      dft4<DIR>(y[n1][0], y[n1][1], y[n1][2], y[n1][3]);
+#pragma unroll
+      for (int k1 = 1; k1 < 4; ++k1)
+        if (n1 > 0) y[n1][k1] = c2::mul(y[n1][k1], w16(n1 * k1, DIR));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 a = y[0][k1], b = y[1][k1], c = y[2][k1], d = y[3][k1];
+      dft4<DIR>(a, b, c, d);
+      v[k1] = a; v[k1 + 4] = b; v[k1 + 8] = c; v[k1 + 12] = d;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- twiddles
+
+// tw[m] = exp(-2 pi i m / N), m in [0, N), filled cooperatively.
+template <int N>
+__device__ inline void fill_twiddles(float2* tw, int tid, int nthreads) {
+  for (int m = tid; m < N; m += nthreads) {
+    float s, c;
+    sincospif(-2.0f * (float)m / (float)N, &s, &c);
+    tw[m] = make_float2(c, s);
+  }
+}
+
+// ---------------------------------------------------------------- passes
+
+constexpr int radix_of_pass(int n, int pass) {
+  // radices: 16 while the remaining factor allows it, then the remainder
+  int rem = n;
+  int r = 1;
+  for (int p = 0; p <= pass; ++p) {
+    r = rem >= 16 ? 16 : rem;
+    rem /= r;
+  }
+  return r;
+}
+constexpr int num_passes(int n) {
+  int p = 0;
+  for (int rem = n; rem > 1; rem /= (rem >= 16 ? 16 : rem)) ++p;
+  return p;
+}
+
+// One Stockham pass of radix R over NB sequences of length N (in place).
+template <int N, int R, int NS, int NB, int NT, int DIR>
+__device__ inline void stockham_pass(float2* buf, const float2* tw, int tid) {
+  constexpr int BF = NB * (N / R);             // butterflies in the pass
+  constexpr int U = (BF + NT - 1) / NT;        // per thread
+  constexpr int S = lds_stride(N);
+  float2 v[U][R];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    int q = tid + u * NT;
+    if (BF % NT == 0 || q < BF) {
+      int b = q / (N / R), j = q % (N / R);
+      const float2* src = buf + b * S;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[u][r] = src[skew(j + r * (N / R))];
+      int k = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[(k * r * (N / (NS * R))) & (N - 1)];
+          if (DIR > 0) w.y = -w.y;
+          v[u][r] = c2::mul(v[u][r], w);
+        }
+      }
+      dft_reg<R, DIR>(v[u]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    int q = tid + u * NT;
+    if (BF % NT == 0 || q < BF) {
+      int b = q / (N / R), j = q % (N / R);
+      int k = j % NS;
+      float2* dst = buf + b * S;
+      int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[skew(base + r * NS)] = v[u][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int PASS, int NS, int NB, int NT, int DIR>
+__device__ inline void fft_passes(float2* buf, const float2* tw, int tid) {
+  if constexpr (PASS < num_passes(N)) {
+    constexpr int R = radix_of_pass(N, PASS);
+    stockham_pass<N, R, NS, NB, NT, DIR>(buf, tw, tid);
+    fft_passes<N, PASS + 1, NS * R, NB, NT, DIR>(buf, tw, tid);
+  }
+}
+
+// NB in-place FFTs of length N held in LDS at buf[b * lds_stride(N) + skew(i)].
+// Requires a barrier before (data written) -- provided by the caller -- and
+// leaves a barrier after.  tw must hold fill_twiddles<N>.
+template <int N, int NB, int NT, int DIR>
+__device__ inline void fft_lds(float2* buf, const float2* tw, int tid) {
+  fft_passes<N, 0, 1, NB, NT, DIR>(buf, tw, tid);
+}
+
+}  // namespace hvk

@@ -1,0 +1,86 @@
+// Context, plans and workspaces behind the hv_ctx handle (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "hv_internal.h"
+
+namespace hvi {
+
+// A device allocation that only grows.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  void release();
+  // Make room for `want` bytes (contents are not preserved); `accounted`
+  // tracks the bytes held by the owner.
+  hv_status ensure(size_t want, size_t* accounted);
+  hv_status upload(const void* host, size_t n, size_t* accounted);
+};
+
+struct AsPlan {
+  int ny = 0, nx = 0;
+  double wavelength = 0, dx = 0, dy = 0, z = 0;
+  DevBuf ht;  // [nx][ny] float2: H_z(fx = column, fy) / ny
+  const float2* ht_ptr() const { return (const float2*)ht.ptr; }
+};
+
+struct FresnelPlan {
+  int ny = 0, nx = 0;
+  double wavelength = 0, dx = 0, dy = 0, z = 0;
+  DevBuf tables;  // float2: qx_in[nx], qy_in[ny], qx_out[nx], qy_out[ny]
+};
+
+struct DftPlan {
+  int window = 0, mtiles = 0;
+  std::vector<int> bins;
+  std::vector<double> freqs;
+  DevBuf a32, a16hi, a16lo, wts;
+};
+
+int band_bins(const hv_temporal& tp, std::vector<int>& bins, std::vector<double>& freqs);
+const char* last_error();
+
+struct StreamState;  // serving loop (stream.cpp)
+
+struct Ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t held = 0;  // bytes of plans and workspaces
+  int chunk_frames = 0;
+  using OptKey = std::tuple<int, int, double, double, double, double>;
+  std::map<OptKey, std::unique_ptr<AsPlan>> as_plans;
+  std::map<OptKey, std::unique_ptr<FresnelPlan>> fr_plans;
+  std::map<std::tuple<int, std::vector<int>, std::vector<double>>, std::unique_ptr<DftPlan>> dft_plans;
+  std::map<std::pair<void*, int>, DevBuf> ws;
+
+  AsPlan* as_plan(int ny, int nx, const hv_optics& o, hv_status* st);
+  FresnelPlan* fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st);
+  DftPlan* dft_plan(const hv_temporal& tp, hv_status* st);
+  DevBuf& work(hipStream_t s, int slot);
+  int chunk_frames_for(int ny, int nx) const;
+};
+
+// Row C2C FFT of sign dir with an optional separable chirp (qx[m] qy[n]),
+// transposed write [n][nx][ny]; input u8, u16 or c64.
+hv_status launch_rows_c2c(const void* in, int in_t, void* out, bool half_out, const float2* qx, const float2* qy,
+                          int dir, int n, int ny, int nx, float scale, hipStream_t st);
+// Column pass for a full complex spectrum [n][nx][ny]: column FFT, multiply
+// by ht[column][fy], inverse column FFT, write [n][ny][nx].
+hv_status launch_col_full(const void* in, void* out, bool half_io, const float2* ht, int n, int ny, int nx,
+                          hipStream_t st);
+
+}  // namespace hvi
+
+struct hv_ctx : hvi::Ctx {};

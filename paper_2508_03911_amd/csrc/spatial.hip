@@ -1,0 +1,455 @@
+// Spatial demodulation kernels: angular spectrum and single-FFT Fresnel.
+//
+// Angular spectrum (Abstract; Sec. II-B.3): U = IDFT2(H_z DFT2(x)).  The 2D
+// transforms are split into a row pass and a column pass so that each pass
+// holds whole sequences in LDS:
+//   K1 row R2C  : unpack u8/u16 in the load, two real rows packed as one
+//                 complex FFT, half spectrum written transposed
+//                 [t][nx/2][ny] (column 0 packs the real DC and Nyquist
+//                 columns);
+//   K2 column   : column FFT, the -fx column from Hermitian symmetry,
+//                 multiply by H_z, inverse column FFT, write [t][ny][nx];
+//   K3 row inv  : inverse row FFT to the field (or fused with the temporal
+//                 GEMM elsewhere).
+// Fresnel (Abstract; Sec. VI-B.2): chirp * centred DFT * chirp, the
+// centring folded into the chirps as a (-1)^(m+n) checkerboard.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+#include "hv_ctx.h"
+#include "hv_internal.h"
+
+using namespace hvk;
+
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline void store_c(float2* p, float2 v) { *p = v; }
+__device__ inline void store_c(hv_h2* p, float2 v) {
+  hv_h2 h;
+  h.x = (_Float16)v.x;
+  h.y = (_Float16)v.y;
+  *p = h;
+}
+__device__ inline float2 load_c(const float2* p) { return *p; }
+__device__ inline float2 load_c(const hv_h2* p) {
+  hv_h2 h = *p;
+  return make_float2((float)h.x, (float)h.y);
+}
+
+// 8 consecutive camera values as floats (exact).
+__device__ inline void load8(const uint8_t* p, float* f) {
+  uint2 w = *reinterpret_cast<const uint2*>(p);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    f[e] = (float)((w.x >> (8 * e)) & 0xffu);
+    f[e + 4] = (float)((w.y >> (8 * e)) & 0xffu);
+  }
+}
+__device__ inline void load8(const uint16_t* p, float* f) {
+  uint4 w = *reinterpret_cast<const uint4*>(p);
+  uint32_t a[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    f[2 * e] = (float)(a[e] & 0xffffu);
+    f[2 * e + 1] = (float)(a[e] >> 16);
+  }
+}
+
+// 8 consecutive inputs of a row as complex values.
+__device__ inline void load8c(const uint8_t* p, float2* v) {
+  float f[8];
+  load8(p, f);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = make_float2(f[e], 0.f);
+}
+__device__ inline void load8c(const uint16_t* p, float2* v) {
+  float f[8];
+  load8(p, f);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = make_float2(f[e], 0.f);
+}
+__device__ inline void load8c(const float2* p, float2* v) {
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float4 a = q[e];
+    v[2 * e] = make_float2(a.x, a.y);
+    v[2 * e + 1] = make_float2(a.z, a.w);
+  }
+}
+
+// ------------------------------------------------------------------ K1
+template <int NX, int ROWS, typename TIN, typename TOUT>
+__global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT* __restrict__ out, int ny,
+                                                float scale) {
+  constexpr int NB = ROWS / 2;
+  constexpr int S = lds_stride(NX);
+  __shared__ float2 buf[NB * S];
+  __shared__ float2 tw[NX];
+  const int tid = threadIdx.x;
+  const int y0 = blockIdx.x * ROWS;
+  const long t = blockIdx.y;
+  fill_twiddles<NX>(tw, tid, NT);
+  const TIN* src = in + (t * ny + y0) * (long)NX;
+  for (int q = tid; q < NB * (NX / 8); q += NT) {
+    const int b = q / (NX / 8), c = q % (NX / 8);
+    float a8[8], b8[8];
+    load8(src + (2 * b) * NX + 8 * c, a8);
+    load8(src + (2 * b + 1) * NX + 8 * c, b8);
+    float2* dst = buf + b * S;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dst[skew(8 * c + e)] = make_float2(a8[e], b8[e]);
+  }
+  __syncthreads();
+  fft_lds<NX, NB, NT, -1>(buf, tw, tid);
+  TOUT* dst = out + t * (long)(NX / 2) * ny + y0;
+  for (int q = tid; q < (NX / 2) * ROWS; q += NT) {
+    const int fx = q / ROWS, r = q % ROWS, b = r >> 1;
+    const float2* row = buf + b * S;
+    float2 z1 = row[skew(fx)];
+    float2 v;
+    if (fx == 0) {
+      float2 zn = row[skew(NX / 2)];
+      v = (r & 1) ? make_float2(z1.y, zn.y) : make_float2(z1.x, zn.x);
+    } else {
+      float2 z2 = c2::conj(row[skew(NX - fx)]);
+      if (r & 1) {
+        float2 d = c2::sub(z1, z2);
+        v = make_float2(0.5f * d.y, -0.5f * d.x);
+      } else {
+        v = c2::scale(c2::add(z1, z2), 0.5f);
+      }
+    }
+    store_c(dst + (long)fx * ny + r, c2::scale(v, scale));
+  }
+}
+
+// ------------------------------------------------------------------ K2
+template <int NY, int BC, typename TIO>
+__global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* __restrict__ out,
+                                               const float2* __restrict__ ht, int nx) {
+  constexpr int S = lds_stride(NY);
+  constexpr int U = BC * NY / NT;
+  static_assert(BC * NY % NT == 0, "column tile must split evenly");
+  __shared__ float2 buf[2 * BC * S];
+  __shared__ float2 tw[NY];
+  const int tid = threadIdx.x;
+  const int f0 = blockIdx.x * BC;
+  const long t = blockIdx.y;
+  fill_twiddles<NY>(tw, tid, NT);
+  const TIO* src = in + (t * (nx / 2) + f0) * (long)NY;
+  for (int q = tid; q < BC * NY; q += NT) buf[(q / NY) * S + skew(q % NY)] = load_c(src + q);
+  __syncthreads();
+  fft_lds<NY, BC, NT, -1>(buf, tw, tid);
+  float2 va[U], vb[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * NT;
+    const int s = q / NY, fy = q % NY, fx = f0 + s;
+    const float2* col = buf + s * S;
+    float2 z1 = col[skew(fy)];
+    float2 z2 = c2::conj(col[skew((NY - fy) & (NY - 1))]);
+    float2 a, b;
+    int ca, cb;
+    if (fx == 0) {
+      a = c2::scale(c2::add(z1, z2), 0.5f);
+      float2 d = c2::sub(z1, z2);
+      b = make_float2(0.5f * d.y, -0.5f * d.x);
+      ca = 0;
+      cb = nx / 2;
+    } else {
+      a = z1;
+      b = z2;
+      ca = fx;
+      cb = nx - fx;
+    }
+    va[u] = c2::mul(a, ht[(long)ca * NY + fy]);
+    vb[u] = c2::mul(b, ht[(long)cb * NY + fy]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * NT;
+    const int s = q / NY, fy = q % NY;
+    buf[s * S + skew(fy)] = va[u];
+    buf[(BC + s) * S + skew(fy)] = vb[u];
+  }
+  __syncthreads();
+  fft_lds<NY, 2 * BC, NT, +1>(buf, tw, tid);
+  TIO* dst = out + t * (long)NY * nx;
+  for (int q = tid; q < 2 * BC * NY; q += NT) {
+    const int y = q / (2 * BC), i = q % (2 * BC);
+    int c, slot;
+    if (i < BC) {
+      c = f0 + i;
+      slot = i;
+    } else {
+      const int fx = f0 + i - BC;
+      c = fx == 0 ? nx / 2 : nx - fx;
+      slot = i;
+    }
+    store_c(dst + (long)y * nx + c, buf[slot * S + skew(y)]);
+  }
+}
+
+// ------------------------------------------------------------------ K3
+template <int NX, int ROWS, typename TIN, typename TOUT>
+__global__ __launch_bounds__(NT) void k_row_inv(const TIN* __restrict__ in, TOUT* __restrict__ out, int ny,
+                                                float scale) {
+  constexpr int S = lds_stride(NX);
+  __shared__ float2 buf[ROWS * S];
+  __shared__ float2 tw[NX];
+  const int tid = threadIdx.x;
+  const long base = ((long)blockIdx.y * ny + (long)blockIdx.x * ROWS) * NX;
+  fill_twiddles<NX>(tw, tid, NT);
+  for (int q = tid; q < ROWS * NX; q += NT) buf[(q / NX) * S + skew(q % NX)] = load_c(in + base + q);
+  __syncthreads();
+  fft_lds<NX, ROWS, NT, +1>(buf, tw, tid);
+  for (int q = tid; q < ROWS * NX; q += NT)
+    store_c(out + base + q, c2::scale(buf[(q / NX) * S + skew(q % NX)], scale));
+}
+
+// ------------------------------------------------------------------ K4 rows / complex rows
+// Row FFT of sign DIR of (input * qx[m] * qy[n]) (no chirp when qx is
+// null), transposed write [t][nx][ny].
+template <int NX, int ROWS, typename TIN, typename TOUT, int DIR>
+__global__ __launch_bounds__(NT) void k_rows_c2c(const TIN* __restrict__ in, TOUT* __restrict__ out,
+                                                 const float2* __restrict__ qx, const float2* __restrict__ qy,
+                                                 int ny, float scale) {
+  constexpr int S = lds_stride(NX);
+  __shared__ float2 buf[ROWS * S];
+  __shared__ float2 tw[NX];
+  const int tid = threadIdx.x;
+  const int y0 = blockIdx.x * ROWS;
+  const long t = blockIdx.y;
+  fill_twiddles<NX>(tw, tid, NT);
+  const TIN* src = in + (t * ny + y0) * (long)NX;
+  for (int q = tid; q < ROWS * (NX / 8); q += NT) {
+    const int r = q / (NX / 8), c = q % (NX / 8);
+    float2 v[8];
+    load8c(src + r * NX + 8 * c, v);
+    if (qx) {
+      const float2 cy = qy[y0 + r];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = c2::mul(v[e], c2::mul(qx[8 * c + e], cy));
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) buf[r * S + skew(8 * c + e)] = v[e];
+  }
+  __syncthreads();
+  fft_lds<NX, ROWS, NT, DIR>(buf, tw, tid);
+  TOUT* dst = out + t * (long)NX * ny + y0;
+  for (int q = tid; q < NX * ROWS; q += NT) {
+    const int p = q / ROWS, r = q % ROWS;
+    store_c(dst + (long)p * ny + r, c2::scale(buf[r * S + skew(p)], scale));
+  }
+}
+
+// ------------------------------------------------------------------ complex AS columns
+// Column FFT, multiply by ht[column][fy], inverse column FFT; in [t][nx][ny],
+// out [t][ny][nx].
+template <int NY, int BC, typename TIO>
+__global__ __launch_bounds__(NT) void k_col_full(const TIO* __restrict__ in, TIO* __restrict__ out,
+                                                 const float2* __restrict__ ht, int nx) {
+  constexpr int S = lds_stride(NY);
+  __shared__ float2 buf[BC * S];
+  __shared__ float2 tw[NY];
+  const int tid = threadIdx.x;
+  const int p0 = blockIdx.x * BC;
+  const long t = blockIdx.y;
+  fill_twiddles<NY>(tw, tid, NT);
+  const TIO* src = in + (t * nx + p0) * (long)NY;
+  for (int q = tid; q < BC * NY; q += NT) buf[(q / NY) * S + skew(q % NY)] = load_c(src + q);
+  __syncthreads();
+  fft_lds<NY, BC, NT, -1>(buf, tw, tid);
+  for (int q = tid; q < BC * NY; q += NT) {
+    const int i = q / NY, fy = q % NY;
+    float2* e = &buf[i * S + skew(fy)];
+    *e = c2::mul(*e, ht[(long)(p0 + i) * NY + fy]);
+  }
+  __syncthreads();
+  fft_lds<NY, BC, NT, +1>(buf, tw, tid);
+  TIO* dst = out + t * (long)NY * nx;
+  for (int q = tid; q < BC * NY; q += NT) {
+    const int y = q / BC, i = q % BC;
+    store_c(dst + (long)y * nx + p0 + i, buf[i * S + skew(y)]);
+  }
+}
+
+// ------------------------------------------------------------------ K4 columns
+template <int NY, int BC, typename TIN, typename TOUT, int DIR>
+__global__ __launch_bounds__(NT) void k_fresnel_cols(const TIN* __restrict__ in, TOUT* __restrict__ out,
+                                                     const float2* __restrict__ qx,
+                                                     const float2* __restrict__ qy, int nx, float scale) {
+  constexpr int S = lds_stride(NY);
+  __shared__ float2 buf[BC * S];
+  __shared__ float2 tw[NY];
+  const int tid = threadIdx.x;
+  const int p0 = blockIdx.x * BC;
+  const long t = blockIdx.y;
+  fill_twiddles<NY>(tw, tid, NT);
+  const TIN* src = in + (t * nx + p0) * (long)NY;
+  for (int q = tid; q < BC * NY; q += NT) buf[(q / NY) * S + skew(q % NY)] = load_c(src + q);
+  __syncthreads();
+  fft_lds<NY, BC, NT, DIR>(buf, tw, tid);
+  TOUT* dst = out + t * (long)NY * nx;
+  for (int q = tid; q < BC * NY; q += NT) {
+    const int y = q / BC, i = q % BC;
+    float2 v = c2::mul(buf[i * S + skew(y)], c2::mul(qx[p0 + i], qy[y]));
+    store_c(dst + (long)y * nx + p0 + i, c2::scale(v, scale));
+  }
+}
+
+// ------------------------------------------------------------------ dispatch helpers
+
+constexpr int cap64(int r) { return r > 64 ? 64 : r; }
+constexpr int cap32(int r) { return r > 32 ? 32 : r; }
+
+template <int NX, typename TIN, typename TOUT>
+void go_r2c(const void* in, void* out, int n, int ny, float scale, hipStream_t st) {
+  constexpr int ROWS = cap64(16384 / NX);
+  hipLaunchKernelGGL((k_row_r2c<NX, ROWS, TIN, TOUT>), dim3(ny / ROWS, n), dim3(NT), 0, st, (const TIN*)in,
+                     (TOUT*)out, ny, scale);
+}
+
+template <int NY, typename TIO>
+void go_col_as(const void* in, void* out, const float2* ht, int n, int nx, hipStream_t st) {
+  constexpr int BC = cap32(4096 / NY);  // nx/2 >= 32 >= BC, so BC divides nx/2
+  hipLaunchKernelGGL((k_col_as<NY, BC, TIO>), dim3((nx / 2) / BC, n), dim3(NT), 0, st, (const TIO*)in,
+                     (TIO*)out, ht, nx);
+}
+
+template <int NX, typename TIN, typename TOUT>
+void go_row_inv(const void* in, void* out, int n, int ny, float scale, hipStream_t st) {
+  constexpr int ROWS = cap64(8192 / NX);
+  hipLaunchKernelGGL((k_row_inv<NX, ROWS, TIN, TOUT>), dim3(ny / ROWS, n), dim3(NT), 0, st, (const TIN*)in,
+                     (TOUT*)out, ny, scale);
+}
+
+template <int NX, typename TIN, typename TOUT>
+void go_rows(const void* in, void* out, const float2* qx, const float2* qy, int dir, int n, int ny, float scale,
+             hipStream_t st) {
+  constexpr int ROWS = cap64(8192 / NX);
+  if (dir < 0)
+    hipLaunchKernelGGL((k_rows_c2c<NX, ROWS, TIN, TOUT, -1>), dim3(ny / ROWS, n), dim3(NT), 0, st,
+                       (const TIN*)in, (TOUT*)out, qx, qy, ny, scale);
+  else
+    hipLaunchKernelGGL((k_rows_c2c<NX, ROWS, TIN, TOUT, +1>), dim3(ny / ROWS, n), dim3(NT), 0, st,
+                       (const TIN*)in, (TOUT*)out, qx, qy, ny, scale);
+}
+
+template <int NY, typename TIO>
+void go_col_full(const void* in, void* out, const float2* ht, int n, int nx, hipStream_t st) {
+  constexpr int BC = cap32(8192 / NY);
+  hipLaunchKernelGGL((k_col_full<NY, BC, TIO>), dim3(nx / BC, n), dim3(NT), 0, st, (const TIO*)in, (TIO*)out, ht,
+                     nx);
+}
+
+template <int NY, typename TIN, typename TOUT>
+void go_fr_cols(const void* in, void* out, const float2* qx, const float2* qy, int dir, int n, int nx,
+                float scale, hipStream_t st) {
+  constexpr int BC = cap32(8192 / NY);
+  if (dir < 0)
+    hipLaunchKernelGGL((k_fresnel_cols<NY, BC, TIN, TOUT, -1>), dim3(nx / BC, n), dim3(NT), 0, st,
+                       (const TIN*)in, (TOUT*)out, qx, qy, nx, scale);
+  else
+    hipLaunchKernelGGL((k_fresnel_cols<NY, BC, TIN, TOUT, +1>), dim3(nx / BC, n), dim3(NT), 0, st,
+                       (const TIN*)in, (TOUT*)out, qx, qy, nx, scale);
+}
+
+hv_status launched(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hvi::fail(HV_ERR_DEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+  return HV_OK;
+}
+
+// Calls F<N>(args...) for N in {64, 128, 256, 512, 1024}.
+#define HV_SWITCH_N(n, CALL)          \
+  switch (n) {                        \
+    case 64: { constexpr int N_ = 64; CALL; } break;     \
+    case 128: { constexpr int N_ = 128; CALL; } break;   \
+    case 256: { constexpr int N_ = 256; CALL; } break;   \
+    case 512: { constexpr int N_ = 512; CALL; } break;   \
+    case 1024: { constexpr int N_ = 1024; CALL; } break; \
+    default: return hvi::fail(HV_ERR_SHAPE, "size %d not supported", n); \
+  }
+
+}  // namespace
+
+namespace hvi {
+
+hv_status launch_row_r2c(const void* in, hv_dtype in_t, void* out, bool half_out, int n, int ny, int nx,
+                         float scale, hipStream_t st) {
+  if (n <= 0) return HV_OK;
+  if (in_t == HV_U8) {
+    if (half_out) { HV_SWITCH_N(nx, (go_r2c<N_, uint8_t, hv_h2>(in, out, n, ny, scale, st))); }
+    else { HV_SWITCH_N(nx, (go_r2c<N_, uint8_t, float2>(in, out, n, ny, scale, st))); }
+  } else {
+    if (half_out) { HV_SWITCH_N(nx, (go_r2c<N_, uint16_t, hv_h2>(in, out, n, ny, scale, st))); }
+    else { HV_SWITCH_N(nx, (go_r2c<N_, uint16_t, float2>(in, out, n, ny, scale, st))); }
+  }
+  return launched("row_r2c");
+}
+
+hv_status launch_col_as(const void* in, void* out, bool half_io, const float2* ht, int n, int ny, int nx,
+                        hipStream_t st) {
+  if (n <= 0) return HV_OK;
+  if (half_io) { HV_SWITCH_N(ny, (go_col_as<N_, hv_h2>(in, out, ht, n, nx, st))); }
+  else { HV_SWITCH_N(ny, (go_col_as<N_, float2>(in, out, ht, n, nx, st))); }
+  return launched("col_as");
+}
+
+hv_status launch_row_inv(const void* in, bool half_in, void* out, bool half_out, int n, int ny, int nx,
+                         float scale, hipStream_t st) {
+  if (n <= 0) return HV_OK;
+  if (half_in) {
+    if (half_out) { HV_SWITCH_N(nx, (go_row_inv<N_, hv_h2, hv_h2>(in, out, n, ny, scale, st))); }
+    else { HV_SWITCH_N(nx, (go_row_inv<N_, hv_h2, float2>(in, out, n, ny, scale, st))); }
+  } else {
+    if (half_out) { HV_SWITCH_N(nx, (go_row_inv<N_, float2, hv_h2>(in, out, n, ny, scale, st))); }
+    else { HV_SWITCH_N(nx, (go_row_inv<N_, float2, float2>(in, out, n, ny, scale, st))); }
+  }
+  return launched("row_inv");
+}
+
+hv_status launch_rows_c2c(const void* in, int in_t, void* out, bool half_out, const float2* qx, const float2* qy,
+                          int dir, int n, int ny, int nx, float scale, hipStream_t st) {
+  if (n <= 0) return HV_OK;
+#define HV_ROWS_T(TIN)                                                                                     \
+  if (half_out) { HV_SWITCH_N(nx, (go_rows<N_, TIN, hv_h2>(in, out, qx, qy, dir, n, ny, scale, st))); }   \
+  else { HV_SWITCH_N(nx, (go_rows<N_, TIN, float2>(in, out, qx, qy, dir, n, ny, scale, st))); }
+  if (in_t == HV_U8) {
+    HV_ROWS_T(uint8_t)
+  } else if (in_t == HV_U16) {
+    HV_ROWS_T(uint16_t)
+  } else {
+    HV_ROWS_T(float2)
+  }
+#undef HV_ROWS_T
+  return launched("rows_c2c");
+}
+
+hv_status launch_col_full(const void* in, void* out, bool half_io, const float2* ht, int n, int ny, int nx,
+                          hipStream_t st) {
+  if (n <= 0) return HV_OK;
+  if (half_io) { HV_SWITCH_N(ny, (go_col_full<N_, hv_h2>(in, out, ht, n, nx, st))); }
+  else { HV_SWITCH_N(ny, (go_col_full<N_, float2>(in, out, ht, n, nx, st))); }
+  return launched("col_full");
+}
+
+hv_status launch_fresnel_cols(const void* in, bool half_in, void* out, bool half_out, const float2* qx,
+                              const float2* qy, int dir, int n, int ny, int nx, float scale, hipStream_t st) {
+  if (n <= 0) return HV_OK;
+  if (half_in) {
+    if (half_out) { HV_SWITCH_N(ny, (go_fr_cols<N_, hv_h2, hv_h2>(in, out, qx, qy, dir, n, nx, scale, st))); }
+    else { HV_SWITCH_N(ny, (go_fr_cols<N_, hv_h2, float2>(in, out, qx, qy, dir, n, nx, scale, st))); }
+  } else {
+    if (half_out) { HV_SWITCH_N(ny, (go_fr_cols<N_, float2, hv_h2>(in, out, qx, qy, dir, n, nx, scale, st))); }
+    else { HV_SWITCH_N(ny, (go_fr_cols<N_, float2, float2>(in, out, qx, qy, dir, n, nx, scale, st))); }
+  }
+  return launched("fresnel_cols");
+}
+
+}  // namespace hvi

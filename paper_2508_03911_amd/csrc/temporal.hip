@@ -1,0 +1,648 @@
+// Temporal transforms on MFMA: the short-time DFT as a dense GEMM with a
+// Doppler-moment epilogue, and the PCA projection energy, which has the same
+// shape (Sec. III-B.1: temporal transform over a window of consecutive
+// reconstructed frames, then a moment over a range of temporal indices).
+//
+// A window of W frames at P pixels is read as the real matrix
+// B [2W x P] with row 2t + c = component c (0 real, 1 imaginary) of frame t.
+// A coefficient matrix A [2M x 2W] whose rows come in (real, imaginary)
+// pairs turns B into M complex outputs per pixel:
+//   DFT:  pair b is bin k_b: Re = sum_t (ur cos + ui sin), Im = sum_t
+//         (ui cos - ur sin) with angle 2 pi k_b t / W;
+//   PCA:  pair c is component c: Y_c = sum_t X_t V[t, c].
+// The epilogue forms |.|^2 of every pair and sums them with up to three
+// weight vectors (f^0, f^1, f^2 for the moments; 1 for the PCA energy).
+//
+// MFMA layouts (gfx950, wave64).  v_mfma_f32_32x32x2f32: lane l holds
+// A[l%32][k0 + l/32] and B[k0 + l/32][l%32].  v_mfma_f32_32x32x16_f16: lane l
+// holds A[l%32][k0 + 8(l/32) + e] and B[k0 + 8(l/32) + e][l%32], e = 0..7
+// (any k assignment works as long as A and B agree).  Both write the 32x32
+// result with lane l, register r holding row 8(r/4) + 4(l/32) + r%4 of
+// column l%32, so a lane owns both rows of 8 (re, im) pairs of one pixel.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+#include "hv_internal.h"
+
+using namespace hvk;
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int MT_MAX = 4;  // up to 64 (re, im) pairs
+
+__device__ inline float2 load_c(const float2* p) { return *p; }
+__device__ inline float2 load_c(const hv_h2* p) {
+  hv_h2 h = *p;
+  return make_float2((float)h.x, (float)h.y);
+}
+
+// One 32x32 output tile: A fragments from global memory (L1/L2 resident),
+// B from the LDS tile buf[t * S + skew(x)].
+template <int W, bool MIXED, bool EXACT_B>
+__device__ inline f32x16 coef_tile(const float* __restrict__ a32, const hv_h8* __restrict__ ahi,
+                                   const hv_h8* __restrict__ alo, const float2* buf, int S, int x0, int lane,
+                                   float bsc) {
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  const int h = lane >> 5;
+  const int xs = skew(x0 + (lane & 31));
+  if constexpr (!MIXED) {
+    const float* col = reinterpret_cast<const float*>(buf + xs) + h;
+#pragma unroll 8
+    for (int kk = 0; kk < W; ++kk) {
+      float a = a32[kk * 64 + lane];
+      float b = col[2 * kk * S];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < W / 8; ++kk) {
+      hv_h8 bh, bl;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float2 v = buf[(8 * kk + 4 * h + i) * S + xs];
+        float x = v.x * bsc, y = v.y * bsc;
+        bh[2 * i] = (_Float16)x;
+        bh[2 * i + 1] = (_Float16)y;
+        if constexpr (!EXACT_B) {
+          bl[2 * i] = (_Float16)(x - (float)bh[2 * i]);
+          bl[2 * i + 1] = (_Float16)(y - (float)bh[2 * i + 1]);
+        }
+      }
+      hv_h8 a_hi = ahi[kk * 64 + lane];
+      hv_h8 a_lo = alo[kk * 64 + lane];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_lo, bh, acc, 0, 0, 0);
+      if constexpr (!EXACT_B) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi, bl, acc, 0, 0, 0);
+    }
+  }
+  return acc;
+}
+
+struct CoefArgs {
+  const float* a32;
+  const hv_h8* a16hi;
+  const hv_h8* a16lo;
+  long a_win_stride;  // elements of a32 (and of a16) per window; 0 = shared
+  const float* wts;   // [3][mtiles*16]
+  int mtiles, npair, nout;
+  float bsc;          // scale applied to B before the fp16 split
+  float amp;          // scale applied to every output amplitude
+  float* out[3];
+  float2* spec;       // [nwin][npair][npix] or null
+};
+
+// GEMM + epilogue for the wave's pixel tile [x0, x0+32) of the LDS tile.
+// Writes outputs at out[k][obase + x0 + lane] and spec[(jj*npair + pair)*npix + obase + x0 + lane].
+template <int W, bool MIXED, bool EXACT_B>
+__device__ inline void coef_pixels(const CoefArgs& g, const float* wts_lds, const float2* buf, int S, int x0,
+                                   int lane, long jj, long obase, long npix) {
+  const int h = lane >> 5;
+  float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+  const long aw = g.a_win_stride * jj;
+  for (int mt = 0; mt < g.mtiles; ++mt) {
+    f32x16 acc = coef_tile<W, MIXED, EXACT_B>(g.a32 + aw + (long)mt * W * 64,
+                                              g.a16hi + (aw >> 3) + (long)mt * (W / 8) * 64,
+                                              g.a16lo + (aw >> 3) + (long)mt * (W / 8) * 64, buf, S, x0, lane,
+                                              g.bsc);
+#pragma unroll
+    for (int gq = 0; gq < 4; ++gq) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int pair = 16 * mt + 4 * gq + 2 * h + p;
+        const float re = acc[4 * gq + 2 * p], im = acc[4 * gq + 2 * p + 1];
+        const float pw = re * re + im * im;
+        const int wi = 16 * mt + 4 * gq + 2 * h + p;
+        e0 += wts_lds[wi] * pw;
+        e1 += wts_lds[MT_MAX * 16 + wi] * pw;
+        e2 += wts_lds[2 * MT_MAX * 16 + wi] * pw;
+        if (g.spec && pair < g.npair)
+          g.spec[(jj * g.npair + pair) * npix + obase + x0 + (lane & 31)] =
+              make_float2(re * g.amp, im * g.amp);
+      }
+    }
+  }
+  e0 += __shfl_xor(e0, 32);
+  e1 += __shfl_xor(e1, 32);
+  e2 += __shfl_xor(e2, 32);
+  if (lane < 32) {
+    const float a2 = g.amp * g.amp;
+    const long o = jj * npix + obase + x0 + lane;
+    if (g.out[0]) g.out[0][o] = e0 * a2;
+    if (g.nout > 1 && g.out[1]) g.out[1][o] = e1 * a2;
+    if (g.nout > 2 && g.out[2]) g.out[2][o] = e2 * a2;
+  }
+}
+
+__device__ inline void load_wts(float* wts_lds, const CoefArgs& g, int tid) {
+  for (int i = tid; i < 3 * MT_MAX * 16; i += NT) {
+    const int k = i / (MT_MAX * 16), m = i % (MT_MAX * 16);
+    wts_lds[i] = (m < g.mtiles * 16 && k < g.nout) ? g.wts[k * g.mtiles * 16 + m] : 0.f;
+  }
+}
+
+// ------------------------------------------------------------------ fused row inverse + GEMM
+template <int NX, int W, bool MIXED, typename TIN>
+__global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, int ny, int stride, CoefArgs g) {
+  constexpr int S = lds_stride(NX);
+  __shared__ float2 buf[W * S];
+  __shared__ float2 tw[NX];
+  __shared__ float wts_lds[3 * MT_MAX * 16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int y = blockIdx.x;
+  const long jj = blockIdx.y;
+  fill_twiddles<NX>(tw, tid, NT);
+  load_wts(wts_lds, g, tid);
+  const TIN* src = z + ((jj * stride) * (long)ny + y) * NX;
+  for (int q = tid; q < W * NX; q += NT) {
+    const int t = q / NX, x = q % NX;
+    buf[t * S + skew(x)] = load_c(src + (long)t * ny * NX + x);
+  }
+  __syncthreads();
+  fft_lds<NX, W, NT, +1>(buf, tw, tid);
+  const long npix = (long)ny * NX;
+  for (int nt = wave; nt < NX / 32; nt += NT / 64)
+    coef_pixels<W, MIXED, false>(g, wts_lds, buf, S, nt * 32, lane, jj, (long)y * NX, npix);
+}
+
+// ------------------------------------------------------------------ GEMM from a field in memory
+constexpr int TPIX = 128;  // pixels per block tile (4 waves x 32)
+
+template <int W, bool MIXED, typename TIN>
+__global__ __launch_bounds__(NT) void k_field_coef(const TIN* __restrict__ u, long npix, int stride, CoefArgs g) {
+  constexpr int S = lds_stride(TPIX);
+  constexpr bool EXACT = MIXED && sizeof(TIN) == 4;  // fp16 storage is exact in fp16
+  __shared__ float2 buf[W * S];
+  __shared__ float wts_lds[3 * MT_MAX * 16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long p0 = (long)blockIdx.x * TPIX;
+  const long jj = blockIdx.y;
+  load_wts(wts_lds, g, tid);
+  const TIN* src = u + (jj * stride) * npix + p0;
+  for (int q = tid; q < W * TPIX; q += NT) {
+    const int t = q / TPIX, x = q % TPIX;
+    buf[t * S + skew(x)] = load_c(src + (long)t * npix + x);
+  }
+  __syncthreads();
+  coef_pixels<W, MIXED, EXACT>(g, wts_lds, buf, S, wave * 32, lane, jj, p0, npix);
+}
+
+// ------------------------------------------------------------------ Gram partials (PCA covariance)
+// Block (blk, jj) accumulates G = B^T B over its pixel range for window jj.
+// LDS holds the tile transposed, L[m][p] with m = 2t + c, so both MFMA
+// operands read contiguous pixel runs of one row.
+constexpr int GP = 64;  // pixels per LDS tile
+
+template <int W, bool MIXED, typename TIN>
+__global__ __launch_bounds__(NT) void k_gram(const TIN* __restrict__ u, long npix, int stride, long pix_per_blk,
+                                             float bsc, float* __restrict__ part, int nblk) {
+  constexpr int M = 2 * W;
+  constexpr int T = M / 32;             // tiles per dimension
+  constexpr int TPW = (T * T + 3) / 4;  // tiles per wave
+  constexpr int LS32 = GP + 1;          // f32 row stride (odd)
+  constexpr int LS16 = GP + 8;          // fp16 row stride (keeps 16-byte reads aligned)
+  __shared__ float l32[MIXED ? 1 : M * LS32];
+  __shared__ __attribute__((aligned(16))) _Float16 l16[MIXED ? M * LS16 : 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
+  const long jj = blockIdx.y;
+  const int blk = blockIdx.x;
+  const long pbeg = (long)blk * pix_per_blk;
+  const long pend = pbeg + pix_per_blk < npix ? pbeg + pix_per_blk : npix;
+  f32x16 acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+  const TIN* src = u + (jj * stride) * npix;
+  for (long p0 = pbeg; p0 < pend; p0 += GP) {
+    __syncthreads();
+    for (int q = tid; q < W * GP; q += NT) {
+      const int t = q / GP, x = q % GP;
+      float2 v = (p0 + x < pend) ? load_c(src + (long)t * npix + p0 + x) : make_float2(0.f, 0.f);
+      if constexpr (MIXED) {
+        l16[(2 * t) * LS16 + x] = (_Float16)(v.x * bsc);
+        l16[(2 * t + 1) * LS16 + x] = (_Float16)(v.y * bsc);
+      } else {
+        l32[(2 * t) * LS32 + x] = v.x;
+        l32[(2 * t + 1) * LS32 + x] = v.y;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int tile = wave + 4 * i;
+      if (tile < T * T) {
+        const int mt = tile / T, nt = tile % T;
+        const int ma = 32 * mt + (lane & 31), nb = 32 * nt + (lane & 31);
+        if constexpr (MIXED) {
+#pragma unroll
+          for (int kk = 0; kk < GP / 16; ++kk) {
+            hv_h8 a = *reinterpret_cast<const hv_h8*>(&l16[ma * LS16 + 16 * kk + 8 * h]);
+            hv_h8 b = *reinterpret_cast<const hv_h8*>(&l16[nb * LS16 + 16 * kk + 8 * h]);
+            acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[i], 0, 0, 0);
+          }
+        } else {
+#pragma unroll 8
+          for (int kk = 0; kk < GP / 2; ++kk) {
+            float a = l32[ma * LS32 + 2 * kk + h];
+            float b = l32[nb * LS32 + 2 * kk + h];
+            acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[i], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  float* dst = part + (jj * nblk + blk) * (long)M * M;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int tile = wave + 4 * i;
+    if (tile < T * T) {
+      const int mt = tile / T, nt = tile % T;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * mt + 8 * (r / 4) + 4 * h + (r % 4);
+        const int n = 32 * nt + (lane & 31);
+        dst[m * M + n] = acc[i][r];
+      }
+    }
+  }
+}
+
+// C[a][b] = sum_blk G[2a][2b] + G[2a+1][2b+1] + i (G[2a][2b+1] - G[2a+1][2b]),
+// summed in f64 in block order (deterministic).
+__global__ void k_gram_reduce(const float* __restrict__ part, int nblk, int W, double cscale,
+                              double* __restrict__ cov) {
+  const long jj = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= W * W) return;
+  const int a = idx / W, b = idx % W;
+  const int M = 2 * W;
+  double re = 0.0, im = 0.0;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const float* g = part + (jj * nblk + blk) * (long)M * M;
+    re += (double)g[(2 * a) * M + 2 * b] + (double)g[(2 * a + 1) * M + 2 * b + 1];
+    im += (double)g[(2 * a) * M + 2 * b + 1] - (double)g[(2 * a + 1) * M + 2 * b];
+  }
+  cov[(jj * W * W + idx) * 2] = re * cscale;
+  cov[(jj * W * W + idx) * 2 + 1] = im * cscale;
+}
+
+// ------------------------------------------------------------------ FP64 Jacobi
+// Cyclic Jacobi for a Hermitian W x W matrix, one block per window, with the
+// round-robin (circle) ordering: in each of the W-1 steps of a sweep, W/2
+// disjoint pairs rotate at once; column updates of all pairs, then row
+// updates, then the eigenvector columns.  Pair (p, q) with a = A_pp,
+// d = A_qq, b = A_pq = |b| e^{i phi}: J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
+// with t = sgn(th)/(|th| + sqrt(th^2 + 1)), th = (d - a)/(2|b|),
+// c = 1/sqrt(t^2 + 1), s = t c zeroes A_pq in J^H A J.
+struct dc {
+  double x, y;
+};
+__device__ inline dc dmul(dc a, dc b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline dc dadd(dc a, dc b) { return {a.x + b.x, a.y + b.y}; }
+__device__ inline dc dscale(dc a, double s) { return {a.x * s, a.y * s}; }
+__device__ inline dc dconj(dc a) { return {a.x, -a.y}; }
+
+template <int W>
+__global__ __launch_bounds__(NT) void k_jacobi(const double* __restrict__ cov, double* __restrict__ evals,
+                                               double* __restrict__ evecs, int max_sweeps) {
+  __shared__ dc A[W * W];
+  __shared__ dc V[W * W];
+  __shared__ int pp[W / 2], qq[W / 2];
+  __shared__ dc rc[W / 2], rs[W / 2], re[W / 2];  // c, s (real in .x), e^{-i phi}
+  __shared__ double red[NT];
+  __shared__ int perm[W];
+  const int tid = threadIdx.x;
+  const long jj = blockIdx.x;
+  const dc* src = reinterpret_cast<const dc*>(cov) + jj * W * W;
+  for (int i = tid; i < W * W; i += NT) {
+    A[i] = src[i];
+    V[i] = {(i / W == i % W) ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // convergence: off-diagonal energy relative to the total
+    double off = 0.0, tot = 0.0;
+    for (int i = tid; i < W * W; i += NT) {
+      const double m2 = A[i].x * A[i].x + A[i].y * A[i].y;
+      tot += m2;
+      if (i / W != i % W) off += m2;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    const double off_all = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    const double tot_all = red[0];
+    __syncthreads();
+    if (!(off_all > 1e-30 * tot_all)) break;
+    for (int step = 0; step < W - 1; ++step) {
+      if (tid < W / 2) {
+        const int k = tid;
+        auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + step) % (W - 1); };
+        int p = player(k), q = player(W - 1 - k);
+        if (p > q) {
+          int t = p;
+          p = q;
+          q = t;
+        }
+        pp[k] = p;
+        qq[k] = q;
+        const double a = A[p * W + p].x, d = A[q * W + q].x;
+        const dc b = A[p * W + q];
+        const double ab = sqrt(b.x * b.x + b.y * b.y);
+        if (ab < 1e-300) {
+          rc[k] = {1.0, 0.0};
+          rs[k] = {0.0, 0.0};
+          re[k] = {1.0, 0.0};
+        } else {
+          const double th = (d - a) / (2.0 * ab);
+          const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          const double c = 1.0 / sqrt(t * t + 1.0);
+          rc[k] = {c, 0.0};
+          rs[k] = {t * c, 0.0};
+          re[k] = {b.x / ab, -b.y / ab};  // e^{-i phi}
+        }
+      }
+      __syncthreads();
+      // columns: A[:,p] = c A[:,p] - s e A[:,q];  A[:,q] = s A[:,p] + c e A[:,q]; same for V
+      for (int i = tid; i < (W / 2) * W; i += NT) {
+        const int k = i / W, r = i % W;
+        const int p = pp[k], q = qq[k];
+        const double c = rc[k].x, s = rs[k].x;
+        const dc e = re[k];
+        dc ap = A[r * W + p], aq = A[r * W + q];
+        dc eq = dmul(e, aq);
+        A[r * W + p] = dadd(dscale(ap, c), dscale(eq, -s));
+        A[r * W + q] = dadd(dscale(ap, s), dscale(eq, c));
+        dc vp = V[r * W + p], vq = V[r * W + q];
+        dc ev = dmul(e, vq);
+        V[r * W + p] = dadd(dscale(vp, c), dscale(ev, -s));
+        V[r * W + q] = dadd(dscale(vp, s), dscale(ev, c));
+      }
+      __syncthreads();
+      // rows: A[p,:] = c A[p,:] - s conj(e) A[q,:];  A[q,:] = s A[p,:] + c conj(e) A[q,:]
+      for (int i = tid; i < (W / 2) * W; i += NT) {
+        const int k = i / W, col = i % W;
+        const int p = pp[k], q = qq[k];
+        const double c = rc[k].x, s = rs[k].x;
+        const dc ec = dconj(re[k]);
+        dc ap = A[p * W + col], aq = A[q * W + col];
+        dc eq = dmul(ec, aq);
+        A[p * W + col] = dadd(dscale(ap, c), dscale(eq, -s));
+        A[q * W + col] = dadd(dscale(ap, s), dscale(eq, c));
+      }
+      __syncthreads();
+    }
+  }
+  // descending order, ties keep the lower index
+  if (tid == 0) {
+    for (int i = 0; i < W; ++i) perm[i] = i;
+    for (int i = 0; i < W; ++i) {
+      int best = i;
+      for (int j = i + 1; j < W; ++j) {
+        const double vj = A[perm[j] * W + perm[j]].x, vb = A[perm[best] * W + perm[best]].x;
+        if (vj > vb || (vj == vb && perm[j] < perm[best])) best = j;
+      }
+      int t = perm[i];
+      perm[i] = perm[best];
+      perm[best] = t;
+    }
+  }
+  __syncthreads();
+  if (tid < W) evals[jj * W + tid] = A[perm[tid] * W + perm[tid]].x;
+  dc* dst = reinterpret_cast<dc*>(evecs) + jj * W * W;
+  for (int i = tid; i < W * W; i += NT) {
+    const int r = i / W, c = i % W;
+    dst[i] = V[r * W + perm[c]];
+  }
+}
+
+// ------------------------------------------------------------------ PCA projection coefficients
+// Pair i = component c1 + i: rows 2i (Re Y), 2i+1 (Im Y); columns 2t + comp:
+// A[2i][2t] = Vr, A[2i][2t+1] = -Vi, A[2i+1][2t] = Vi, A[2i+1][2t+1] = Vr.
+__device__ inline float proj_coef(const dc* v, int W, int c1, int npair, int m, int k) {
+  const int i = m >> 1, t = k >> 1;
+  if (i >= npair) return 0.f;
+  const dc e = v[t * W + c1 + i];
+  const int rm = m & 1, ck = k & 1;
+  double val = rm == 0 ? (ck == 0 ? e.x : -e.y) : (ck == 0 ? e.y : e.x);
+  return (float)val;
+}
+
+__global__ void k_proj_coefs(const double* __restrict__ evecs, int W, int c1, int npair, int mtiles,
+                             float* __restrict__ a32, hv_h8* __restrict__ a16hi, hv_h8* __restrict__ a16lo) {
+  const long jj = blockIdx.x;
+  const dc* v = reinterpret_cast<const dc*>(evecs) + jj * W * W;
+  const long per_win = (long)mtiles * W * 64;
+  for (int i = threadIdx.x; i < mtiles * W * 64; i += blockDim.x) {
+    const int lane = i % 64, kk = (i / 64) % W, mt = i / (64 * W);
+    a32[jj * per_win + i] = proj_coef(v, W, c1, npair, 32 * mt + (lane & 31), 2 * kk + (lane >> 5));
+  }
+  for (int i = threadIdx.x; i < mtiles * (W / 8) * 64; i += blockDim.x) {
+    const int lane = i % 64, kk = (i / 64) % (W / 8), mt = i / (64 * (W / 8));
+    hv_h8 hi, lo;
+    for (int e = 0; e < 8; ++e) {
+      float a = proj_coef(v, W, c1, npair, 32 * mt + (lane & 31), 16 * kk + 8 * (lane >> 5) + e);
+      hi[e] = (_Float16)a;
+      lo[e] = (_Float16)(a - (float)hi[e]);
+    }
+    a16hi[jj * (per_win / 8) + i] = hi;
+    a16lo[jj * (per_win / 8) + i] = lo;
+  }
+}
+
+hv_status launched(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hvi::fail(HV_ERR_DEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+  return HV_OK;
+}
+
+CoefArgs make_args(const hvi::CoefGemm& g, long a_win_stride, float bsc, float amp, float* o0, float* o1,
+                   float* o2, float2* spec) {
+  CoefArgs a;
+  a.a32 = g.a32;
+  a.a16hi = g.a16hi;
+  a.a16lo = g.a16lo;
+  a.a_win_stride = a_win_stride;
+  a.wts = g.wts;
+  a.mtiles = g.mtiles;
+  a.npair = g.npair;
+  a.nout = g.nout;
+  a.bsc = bsc;
+  a.amp = amp;
+  a.out[0] = o0;
+  a.out[1] = o1;
+  a.out[2] = o2;
+  a.spec = spec;
+  return a;
+}
+
+template <int NX, int W, bool MIXED>
+hv_status go_rowinv(const void* z, bool half_in, int ny, int stride, int nwin, const CoefArgs& a,
+                    hipStream_t st) {
+  if constexpr (W * NX <= 8192) {
+    if (half_in)
+      hipLaunchKernelGGL((k_rowinv_coef<NX, W, MIXED, hv_h2>), dim3(ny, nwin), dim3(NT), 0, st, (const hv_h2*)z,
+                         ny, stride, a);
+    else
+      hipLaunchKernelGGL((k_rowinv_coef<NX, W, MIXED, float2>), dim3(ny, nwin), dim3(NT), 0, st,
+                         (const float2*)z, ny, stride, a);
+    return launched("rowinv_coef");
+  } else {
+    return hvi::fail(HV_ERR_SHAPE, "fused row-inverse GEMM does not fit nx=%d W=%d", NX, W);
+  }
+}
+
+template <int W>
+hv_status go_rowinv_w(const void* z, bool half_in, int ny, int nx, int stride, int nwin, const CoefArgs& a,
+                      bool mixed, hipStream_t st) {
+  switch (nx) {
+    case 64: return mixed ? go_rowinv<64, W, true>(z, half_in, ny, stride, nwin, a, st)
+                          : go_rowinv<64, W, false>(z, half_in, ny, stride, nwin, a, st);
+    case 128: return mixed ? go_rowinv<128, W, true>(z, half_in, ny, stride, nwin, a, st)
+                           : go_rowinv<128, W, false>(z, half_in, ny, stride, nwin, a, st);
+    case 256: return mixed ? go_rowinv<256, W, true>(z, half_in, ny, stride, nwin, a, st)
+                           : go_rowinv<256, W, false>(z, half_in, ny, stride, nwin, a, st);
+    case 512: return mixed ? go_rowinv<512, W, true>(z, half_in, ny, stride, nwin, a, st)
+                           : go_rowinv<512, W, false>(z, half_in, ny, stride, nwin, a, st);
+    case 1024: return mixed ? go_rowinv<1024, W, true>(z, half_in, ny, stride, nwin, a, st)
+                            : go_rowinv<1024, W, false>(z, half_in, ny, stride, nwin, a, st);
+  }
+  return hvi::fail(HV_ERR_SHAPE, "nx=%d not supported", nx);
+}
+
+template <int W, bool MIXED>
+void go_field(const void* u, bool half_in, long npix, int stride, int nwin, const CoefArgs& a, hipStream_t st) {
+  dim3 grid((unsigned)(npix / TPIX), nwin);
+  if (half_in)
+    hipLaunchKernelGGL((k_field_coef<W, MIXED, hv_h2>), grid, dim3(NT), 0, st, (const hv_h2*)u, npix, stride, a);
+  else
+    hipLaunchKernelGGL((k_field_coef<W, MIXED, float2>), grid, dim3(NT), 0, st, (const float2*)u, npix, stride,
+                       a);
+}
+
+template <int W, bool MIXED>
+void go_gram(const void* u, bool half_in, long npix, int stride, int nwin, long ppb, float bsc, float* part,
+             int nblk, hipStream_t st) {
+  dim3 grid(nblk, nwin);
+  if (half_in)
+    hipLaunchKernelGGL((k_gram<W, MIXED, hv_h2>), grid, dim3(NT), 0, st, (const hv_h2*)u, npix, stride, ppb, bsc,
+                       part, nblk);
+  else
+    hipLaunchKernelGGL((k_gram<W, MIXED, float2>), grid, dim3(NT), 0, st, (const float2*)u, npix, stride, ppb,
+                       bsc, part, nblk);
+}
+
+}  // namespace
+
+namespace hvi {
+
+bool rowinv_coef_fits(int nx, int window) { return (long)nx * window <= 8192; }
+
+hv_status launch_rowinv_coef(const void* z, bool half_in, int ny, int nx, int stride, int nwin, const CoefGemm& g,
+                             bool mixed, float b_scale, float out_scale, float* out0, float* out1, float* out2,
+                             float2* spec, hipStream_t st) {
+  if (nwin <= 0) return HV_OK;
+  CoefArgs a = make_args(g, 0, b_scale, out_scale, out0, out1, out2, spec);
+  switch (g.window) {
+    case 8: return go_rowinv_w<8>(z, half_in, ny, nx, stride, nwin, a, mixed, st);
+    case 16: return go_rowinv_w<16>(z, half_in, ny, nx, stride, nwin, a, mixed, st);
+    case 32: return go_rowinv_w<32>(z, half_in, ny, nx, stride, nwin, a, mixed, st);
+    case 64: return go_rowinv_w<64>(z, half_in, ny, nx, stride, nwin, a, mixed, st);
+  }
+  return fail(HV_ERR_SHAPE, "window %d not supported", g.window);
+}
+
+static hv_status field_coef(const void* u, bool half_in, long npix, int stride, int nwin, const CoefArgs& a,
+                            int window, bool mixed, hipStream_t st) {
+  if (nwin <= 0) return HV_OK;
+  if (npix % TPIX) return fail(HV_ERR_SHAPE, "pixel count %ld not a multiple of %d", npix, TPIX);
+  switch (window) {
+    case 8: mixed ? go_field<8, true>(u, half_in, npix, stride, nwin, a, st)
+                  : go_field<8, false>(u, half_in, npix, stride, nwin, a, st); break;
+    case 16: mixed ? go_field<16, true>(u, half_in, npix, stride, nwin, a, st)
+                   : go_field<16, false>(u, half_in, npix, stride, nwin, a, st); break;
+    case 32: mixed ? go_field<32, true>(u, half_in, npix, stride, nwin, a, st)
+                   : go_field<32, false>(u, half_in, npix, stride, nwin, a, st); break;
+    case 64: mixed ? go_field<64, true>(u, half_in, npix, stride, nwin, a, st)
+                   : go_field<64, false>(u, half_in, npix, stride, nwin, a, st); break;
+    default: return fail(HV_ERR_SHAPE, "window %d not supported", window);
+  }
+  return launched("field_coef");
+}
+
+hv_status launch_field_coef(const void* u, bool half_in, long npix, int stride, int nwin, const CoefGemm& g,
+                            bool mixed, float b_scale, float out_scale, float* out0, float* out1, float* out2,
+                            float2* spec, hipStream_t st) {
+  CoefArgs a = make_args(g, 0, b_scale, out_scale, out0, out1, out2, spec);
+  return field_coef(u, half_in, npix, stride, nwin, a, g.window, mixed, st);
+}
+
+hv_status launch_gram_partials(const void* u, bool half_in, long npix, int stride, int nwin, int window,
+                               bool mixed, float b_scale, float* part, int nblk, hipStream_t st) {
+  if (nwin <= 0) return HV_OK;
+  const long ppb = (npix + nblk - 1) / nblk;
+  switch (window) {
+    case 16: mixed ? go_gram<16, true>(u, half_in, npix, stride, nwin, ppb, b_scale, part, nblk, st)
+                   : go_gram<16, false>(u, half_in, npix, stride, nwin, ppb, b_scale, part, nblk, st); break;
+    case 32: mixed ? go_gram<32, true>(u, half_in, npix, stride, nwin, ppb, b_scale, part, nblk, st)
+                   : go_gram<32, false>(u, half_in, npix, stride, nwin, ppb, b_scale, part, nblk, st); break;
+    case 64: mixed ? go_gram<64, true>(u, half_in, npix, stride, nwin, ppb, b_scale, part, nblk, st)
+                   : go_gram<64, false>(u, half_in, npix, stride, nwin, ppb, b_scale, part, nblk, st); break;
+    default: return fail(HV_ERR_SHAPE, "PCA window %d not supported (16, 32 or 64)", window);
+  }
+  return launched("gram");
+}
+
+hv_status launch_gram_reduce(const float* part, int nwin, int nblk, int window, double cscale, double* cov,
+                             hipStream_t st) {
+  if (nwin <= 0) return HV_OK;
+  dim3 grid((window * window + 255) / 256, nwin);
+  hipLaunchKernelGGL(k_gram_reduce, grid, dim3(256), 0, st, part, nblk, window, cscale, cov);
+  return launched("gram_reduce");
+}
+
+hv_status launch_jacobi(const double* cov, int nwin, int window, double* evals, double* evecs, int max_sweeps,
+                        hipStream_t st) {
+  if (nwin <= 0) return HV_OK;
+  switch (window) {
+    case 16: hipLaunchKernelGGL(k_jacobi<16>, dim3(nwin), dim3(NT), 0, st, cov, evals, evecs, max_sweeps); break;
+    case 32: hipLaunchKernelGGL(k_jacobi<32>, dim3(nwin), dim3(NT), 0, st, cov, evals, evecs, max_sweeps); break;
+    case 64: hipLaunchKernelGGL(k_jacobi<64>, dim3(nwin), dim3(NT), 0, st, cov, evals, evecs, max_sweeps); break;
+    default: return fail(HV_ERR_SHAPE, "PCA window %d not supported", window);
+  }
+  return launched("jacobi");
+}
+
+hv_status launch_proj_coefs(const double* evecs, int nwin, int window, int c1, int c2, int mtiles, float* a32,
+                            hv_h8* a16hi, hv_h8* a16lo, hipStream_t st) {
+  if (nwin <= 0) return HV_OK;
+  hipLaunchKernelGGL(k_proj_coefs, dim3(nwin), dim3(256), 0, st, evecs, window, c1, c2 - c1 + 1, mtiles, a32,
+                     a16hi, a16lo);
+  return launched("proj_coefs");
+}
+
+hv_status launch_proj_energy(const void* u, bool half_in, long npix, int stride, int nwin, int window, int mtiles,
+                             int npair, const float* a32, const hv_h8* a16hi, const hv_h8* a16lo,
+                             const float* wts, bool mixed, float b_scale, float out_scale, float* m0,
+                             hipStream_t st) {
+  CoefGemm g{window, mtiles, npair, a32, a16hi, a16lo, wts, 1};
+  CoefArgs a = make_args(g, (long)mtiles * window * 64, b_scale, out_scale, m0, nullptr, nullptr, nullptr);
+  return field_coef(u, half_in, npix, stride, nwin, a, window, mixed, st);
+}
+
+}  // namespace hvi

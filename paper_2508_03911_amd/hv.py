@@ -1,0 +1,231 @@
+"""ctypes binding of libhv.so (include/hv.h), same names as the C-ABI.
+
+Argument marshalling only: torch supplies device memory and the HIP stream,
+every step of the hot path runs in the library's kernels.  Importing this
+module loads the in-tree ``libhv.so`` and raises if it is missing -- there is
+no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhv.so")
+
+HV_OK, HV_ERR_ARG, HV_ERR_SHAPE, HV_ERR_NOMEM, HV_ERR_BUDGET, HV_ERR_DEVICE, HV_ERR_OVERFLOW, HV_ERR_STATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+HV_U8, HV_U16, HV_C64 = 0, 1, 3
+HV_AS, HV_FRESNEL = 0, 1
+HV_PREC_FP32, HV_PREC_MIXED = 0, 1
+
+_STATUS_NAMES = {0: "HV_OK", -1: "HV_ERR_ARG", -2: "HV_ERR_SHAPE", -3: "HV_ERR_NOMEM", -4: "HV_ERR_BUDGET",
+                 -5: "HV_ERR_DEVICE", -6: "HV_ERR_OVERFLOW", -7: "HV_ERR_STATE"}
+
+
+class HvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python -m paper_2508_03911_amd.build)")
+    return C.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+
+class hv_optics(C.Structure):
+    _fields_ = [("wavelength_m", C.c_double), ("pitch_x_m", C.c_double), ("pitch_y_m", C.c_double),
+                ("z_m", C.c_double), ("method", C.c_int)]
+
+
+class hv_temporal(C.Structure):
+    _fields_ = [("window", C.c_int), ("stride", C.c_int), ("fs_hz", C.c_double), ("f_lo_hz", C.c_double),
+                ("f_hi_hz", C.c_double), ("symmetric_band", C.c_int)]
+
+
+_P = C.c_void_p
+_I = C.c_int
+_sig = {
+    "hv_last_error": (C.c_char_p, []),
+    "hv_ctx_create": (_I, [_I, C.c_size_t, C.POINTER(_P)]),
+    "hv_ctx_destroy": (None, [_P]),
+    "hv_ctx_workspace_bytes": (C.c_size_t, [_P]),
+    "hv_ctx_set_chunk_frames": (_I, [_P, _I]),
+    "hv_band_bins": (_I, [C.POINTER(hv_temporal), C.POINTER(_I), C.POINTER(_I), C.POINTER(C.c_double)]),
+    "hv_propagate": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _P, _P]),
+    "hv_stft_moments": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P, _P,
+                             _P]),
+    "hv_stft_bins": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P]),
+    "hv_pca": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _I, _I, _P, _P, _P, _P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def last_error() -> str:
+    return lib.hv_last_error().decode()
+
+
+def _check(status: int):
+    if status != HV_OK:
+        raise HvError(status, last_error())
+
+
+@dataclass(frozen=True)
+class Optics:
+    wavelength: float
+    pitch_x: float
+    pitch_y: float
+    z: float
+    method: int = HV_AS
+
+    def c(self) -> hv_optics:
+        return hv_optics(self.wavelength, self.pitch_x, self.pitch_y, self.z, self.method)
+
+
+@dataclass(frozen=True)
+class Temporal:
+    window: int
+    stride: int
+    fs: float
+    f_lo: float
+    f_hi: float
+    symmetric: bool = False
+
+    def c(self) -> hv_temporal:
+        return hv_temporal(self.window, self.stride, self.fs, self.f_lo, self.f_hi, int(self.symmetric))
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.uint8:
+        return HV_U8
+    if t.dtype in (torch.int16, getattr(torch, "uint16", torch.int16)):
+        return HV_U16
+    if t.dtype == torch.complex64:
+        return HV_C64
+    raise TypeError(f"unsupported input dtype {t.dtype}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _frames(x: torch.Tensor):
+    if x.dim() != 3:
+        raise ValueError("expected a [frames, ny, nx] tensor")
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("input must be a contiguous device tensor")
+    return x.shape[0], x.shape[1], x.shape[2]
+
+
+def band_bins(temporal: Temporal):
+    tp = temporal.c()
+    n = C.c_int(0)
+    _check(lib.hv_band_bins(C.byref(tp), C.byref(n), None, None))
+    bins = (C.c_int * max(1, n.value))()
+    freqs = (C.c_double * max(1, n.value))()
+    _check(lib.hv_band_bins(C.byref(tp), C.byref(n), bins, freqs))
+    return list(bins)[:n.value], list(freqs)[:n.value]
+
+
+class Context:
+    """One hv_ctx on a HIP device (plans and workspaces live here)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        _check(lib.hv_ctx_create(device, hbm_budget, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib.hv_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self) -> int:
+        return lib.hv_ctx_workspace_bytes(self.handle)
+
+    def set_chunk_frames(self, frames: int):
+        _check(lib.hv_ctx_set_chunk_frames(self.handle, frames))
+
+    def _dev(self):
+        return torch.device("cuda", self.device)
+
+    # ---------------------------------------------------------------- spatial
+    def hv_propagate(self, x: torch.Tensor, optics: Optics, prec: int = HV_PREC_FP32, out=None) -> torch.Tensor:
+        n, ny, nx = _frames(x)
+        if out is None:
+            out = torch.empty((n, ny, nx), dtype=torch.complex64, device=x.device)
+        op = optics.c()
+        _check(lib.hv_propagate(self.handle, _ptr(x), _dtype_code(x), n, ny, nx, C.byref(op), prec, _ptr(out),
+                                _stream(x.device)))
+        return out
+
+    # ---------------------------------------------------------------- temporal
+    def n_windows(self, n: int, temporal: Temporal) -> int:
+        return 0 if n < temporal.window else (n - temporal.window) // temporal.stride + 1
+
+    def hv_stft_moments(self, x: torch.Tensor, optics: Optics | None, temporal: Temporal,
+                        prec: int = HV_PREC_FP32, want=(True, True, True), out=None):
+        n, ny, nx = _frames(x)
+        j = self.n_windows(n, temporal)
+        if out is None:
+            out = [torch.empty((j, ny, nx), dtype=torch.float32, device=x.device) if w else None for w in want]
+        op = optics.c() if optics is not None else None
+        tp = temporal.c()
+        _check(lib.hv_stft_moments(self.handle, _ptr(x), _dtype_code(x), n, ny, nx,
+                                   C.byref(op) if op is not None else None, C.byref(tp), prec,
+                                   _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream(x.device)))
+        return out
+
+    def hv_stft_bins(self, x: torch.Tensor, optics: Optics | None, temporal: Temporal,
+                     prec: int = HV_PREC_FP32, out=None) -> torch.Tensor:
+        n, ny, nx = _frames(x)
+        j = self.n_windows(n, temporal)
+        nb = len(band_bins(temporal)[0])
+        if out is None:
+            out = torch.empty((j, nb, ny, nx), dtype=torch.complex64, device=x.device)
+        op = optics.c() if optics is not None else None
+        tp = temporal.c()
+        _check(lib.hv_stft_bins(self.handle, _ptr(x), _dtype_code(x), n, ny, nx,
+                                C.byref(op) if op is not None else None, C.byref(tp), prec, _ptr(out),
+                                _stream(x.device)))
+        return out
+
+    # ---------------------------------------------------------------- PCA
+    def hv_pca(self, x: torch.Tensor, optics: Optics | None, window: int, stride: int, comp_lo: int = 1,
+               comp_hi: int | None = None, prec: int = HV_PREC_FP32, want_eig=True, want_cov=False):
+        n, ny, nx = _frames(x)
+        if comp_hi is None:
+            comp_hi = window - 1
+        j = 0 if n < window else (n - window) // stride + 1
+        m0 = torch.empty((j, ny, nx), dtype=torch.float32, device=x.device)
+        ev = torch.empty((j, window), dtype=torch.float64, device=x.device) if want_eig else None
+        cov = torch.empty((j, window, window), dtype=torch.complex128, device=x.device) if want_cov else None
+        op = optics.c() if optics is not None else None
+        _check(lib.hv_pca(self.handle, _ptr(x), _dtype_code(x), n, ny, nx, C.byref(op) if op is not None else None,
+                          window, stride, comp_lo, comp_hi, prec, _ptr(m0), _ptr(ev), _ptr(cov),
+                          _stream(x.device)))
+        return {"m0": m0, "eigvals": ev, "cov": cov}

@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports every entry point include/hv.h declares
+(CPU only: no compute call is made)."""
+
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_entry_points():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names.update(re.findall(r"\b(hv_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2508_03911_amd import LIB_PATH
+    assert os.path.exists(LIB_PATH), "libhv.so not built"
+    lib = ctypes.CDLL(LIB_PATH)
+    names = declared_entry_points()
+    assert "hv_stft_moments" in names and "hv_propagate" in names and "hv_pca" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_band_bins_host_call_matches_oracle():
+    # hv_band_bins runs on the host: no GPU needed
+    from oracle import temporal
+    from paper_2508_03911_amd import hv
+    for w, fs, lo, hi, sym in [(32, 71400.0, 3000.0, 35000.0, False), (32, 33000.0, 2000.0, 8000.0, False),
+                               (64, 5000.0, 156.25, 2421.875, False), (16, 1e4, 0.0, 5e3, True)]:
+        bins, freqs = hv.band_bins(hv.Temporal(w, w, fs, lo, hi, sym))
+        ob, of = temporal.band_bins(w, fs, lo, hi, sym)
+        assert bins == list(ob)
+        assert freqs == list(of)
+
+
+def test_context_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        return
+    from paper_2508_03911_amd import hv
+    try:
+        hv.Context(0)
+    except hv.HvError as e:
+        assert e.status in (hv.HV_ERR_DEVICE, hv.HV_ERR_ARG)
+    else:
+        raise AssertionError("context creation must fail without a device")
