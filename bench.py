@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Throughput of the 256x256 angular-spectrum + STFT32 + Doppler-moment path.
+
+Workload: a stream of 65,536 uint8 frames of 256x256 (4 GiB, resident in
+HBM before timing, like the paper's file mode), angular-spectrum
+reconstruction at a fixed z, STFT window 32 / stride 32, M0/M1/M2 over
+[3, 35] kHz at fs = 71.4 kHz.  One step = one pass of the whole path over the
+whole stream.  The FP32 form is the headline value; the mixed form is timed
+the same way and reported beside it.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this path runs on one
+GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "input frames/s @256² AS+STFT32+M0 (FP32 vs mixed, % HBM peak); p99 latency"
+HBM_PEAK_GBS = 8000.0
+NY = NX = 256
+W = 32
+# algorithmic bytes per pixel-frame of each kernel (read + write), W = 32, 3 moments
+BYTES_PER_PXF = {
+    0: {"row_r2c": 1 + 4, "col_as": 4 + 8, "rowinv_coef": 8 + 12 / W},
+    1: {"row_r2c": 1 + 2, "col_as": 2 + 4, "rowinv_coef": 4 + 12 / W},
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(ctx, hv, torch, x, opt, tp, prec, outs, steps):
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        ctx.hv_stft_moments(x, opt, tp, prec, out=outs)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def kernel_profile(ctx, hv, torch, x, opt, tp, prec, outs, steps, frames):
+    """Per-kernel average launch time from HIP events recorded around each
+    launch on the stream, and the achieved algorithmic bandwidth."""
+    ctx.set_timing(True)
+    for _ in range(steps):
+        ctx.hv_stft_moments(x, opt, tp, prec, out=outs)
+    torch.cuda.synchronize()
+    res = {}
+    for name, bpp in BYTES_PER_PXF[prec].items():
+        ms, n = ctx.kernel_time(name)
+        if n == 0:
+            continue
+        avg_ms = ms / n
+        pxf_per_launch = frames * steps * NY * NX / n
+        gbs = bpp * pxf_per_launch / (avg_ms * 1e-3) / 1e9
+        res[name] = {"launches": n, "avg_ms": avg_ms, "total_ms_per_step": ms / steps,
+                     "bytes_per_launch": bpp * pxf_per_launch, "achieved_GBs": gbs}
+    ctx.set_timing(False)
+    return res
+
+
+def cpu_baseline(block, spec, z):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import pipeline
+    sample = block
+    t0 = time.perf_counter()
+    pipeline.stft_moments(sample, pipeline.Optics(852e-9, spec.pitch, spec.pitch, -z), W, W, spec.fs, 3e3, 35e3)
+    dt = time.perf_counter() - t0
+    blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": sample.shape[0] / dt, "unit": "frames/s", "cores": int(blas), "kind": "oracle",
+            "sample": f"{sample.shape[0]} frames (64 windows) of the 256x256 stream, numpy float64; "
+                      f"FFTs single-threaded, BLAS {blas} threads", "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=65536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the windows are independent, "
+              "so N GPUs would each run this same per-GPU workload.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2508_03911_amd import hv
+    from synth import holograms
+
+    t0 = time.time()
+    block, spec = holograms.config_c2_block(2048)
+    log(f"generated base block {block.shape} in {time.time() - t0:.1f}s (z = {spec.z:.4f} m)")
+    reps = args.frames // block.shape[0]
+    frames = reps * block.shape[0]
+    xb = torch.from_numpy(block).cuda()
+    x = xb.repeat(reps, 1, 1).contiguous()  # the stream replays the base block cyclically
+    del xb
+    ctx = hv.Context(0)
+    opt = hv.Optics(852e-9, spec.pitch, spec.pitch, -spec.z, hv.HV_AS)
+    tp = hv.Temporal(W, W, spec.fs, 3e3, 35e3)
+    j = frames // W
+    outs = [torch.empty((j, NY, NX), dtype=torch.float32, device="cuda") for _ in range(3)]
+
+    res = {}
+    for prec in (hv.HV_PREC_FP32, hv.HV_PREC_MIXED):
+        for _ in range(args.warmup):
+            ctx.hv_stft_moments(x, opt, tp, prec, out=outs)
+        ms = time_steps(ctx, hv, torch, x, opt, tp, prec, outs, args.steps)
+        kern = kernel_profile(ctx, hv, torch, x, opt, tp, prec, outs, args.steps, frames)
+        res[prec] = {"ms_per_step": ms, "frames_per_s": frames / (ms * 1e-3), "kernels": kern}
+        log(f"prec {prec}: {ms:.3f} ms/step, {frames / (ms * 1e-3) / 1e6:.3f} M frames/s")
+
+    fp32, mixed = res[hv.HV_PREC_FP32], res[hv.HV_PREC_MIXED]
+    dom_name, dom = max(fp32["kernels"].items(), key=lambda kv: kv[1]["total_ms_per_step"])
+    pass_bytes = sum(BYTES_PER_PXF[0].values()) * NY * NX * frames
+    line = {
+        "metric": METRIC,
+        "value": fp32["frames_per_s"],
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fp32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"256x256 uint8 x {frames} frames resident in HBM; angular spectrum at z=-{spec.z:.4f} m; "
+                               "STFT window 32 stride 32; M0/M1/M2 over [3,35] kHz at fs 71.4 kHz",
+                   "frames": frames, "ny": NY, "nx": NX, "window": W, "stride": W, "precision": "fp32"},
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dom["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None},
+        "pass_level_hbm": {"GBs": pass_bytes / (fp32["ms_per_step"] * 1e-3) / 1e9,
+                           "frac": pass_bytes / (fp32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "bytes_per_pixel_frame": sum(BYTES_PER_PXF[0].values())},
+        "mixed": {"value": mixed["frames_per_s"], "ms_per_step": mixed["ms_per_step"],
+                  "speedup_vs_fp32": mixed["frames_per_s"] / fp32["frames_per_s"],
+                  "kernels": mixed["kernels"]},
+        "kernels_fp32": fp32["kernels"],
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a sample ...")
+        line["cpu_baseline"] = cpu_baseline(block, spec, spec.z)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

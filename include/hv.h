@@ -110,6 +110,16 @@ size_t hv_ctx_workspace_bytes(const hv_ctx* ctx);
 /* Frames per spatial chunk (workspace size knob; 0 = automatic). */
 hv_status hv_ctx_set_chunk_frames(hv_ctx* ctx, int frames);
 
+/* Per-kernel timing for profiling (Sec. VII-D): when on, every kernel launch
+ * is bracketed by HIP events on the caller's stream; no work is skipped.
+ * Turning it on or off clears the totals. */
+hv_status hv_ctx_set_timing(hv_ctx* ctx, int on);
+/* Waits for the recorded launches and returns the total milliseconds and the
+ * launch count of kernel `name` ("row_r2c", "col_as", "rowinv_coef",
+ * "row_inv", "field_coef", "rows_c2c", "col_full", "fresnel_rows",
+ * "fresnel_cols", "gram", "jacobi", "proj_energy"). */
+hv_status hv_ctx_kernel_time(hv_ctx* ctx, const char* name, double* total_ms, long* launches);
+
 /* ---------------------------------------------------------------- spatial */
 
 /* Reconstruct n frames (Sec. III-B.1 spatial transformation).

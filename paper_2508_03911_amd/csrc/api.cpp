@@ -68,6 +68,40 @@ hv_status DevBuf::upload(const void* host, size_t n, size_t* accounted) {
   return HV_OK;
 }
 
+// ---------------------------------------------------------------- timing
+
+hipEvent_t Timing::take() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+void Timing::collect() {
+  for (auto& r : pending) {
+    hipEventSynchronize(r.b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    auto& slot = acc[r.name];
+    slot.first += ms;
+    slot.second += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+}
+void Timing::reset() {
+  collect();
+  acc.clear();
+}
+Timing::~Timing() {
+  collect();
+  for (hipEvent_t e : pool) hipEventDestroy(e);
+}
+
 // ---------------------------------------------------------------- band
 
 int band_bins(const hv_temporal& tp, std::vector<int>& bins, std::vector<double>& freqs) {
@@ -332,20 +366,20 @@ hv_status spatial(Ctx* c, const void* in, int in_t, int nf, int ny, int nx, cons
     if (in_t == HV_C64) {
       DevBuf& tb = c->work(st, 0);
       if ((s = tb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
-      if ((s = launch_rows_c2c(in, in_t, tb.ptr, mixed, nullptr, nullptr, -1, nf, ny, nx, s1, st))) return s;
-      if ((s = launch_col_full(tb.ptr, zb.ptr, mixed, p->ht_ptr(), nf, ny, nx, st))) return s;
+      if ((s = timed(c, "rows_c2c", st, [&] { return launch_rows_c2c(in, in_t, tb.ptr, mixed, nullptr, nullptr, -1, nf, ny, nx, s1, st); }))) return s;
+      if ((s = timed(c, "col_full", st, [&] { return launch_col_full(tb.ptr, zb.ptr, mixed, p->ht_ptr(), nf, ny, nx, st); }))) return s;
     } else {
       DevBuf& tb = c->work(st, 0);
       if ((s = tb.ensure((size_t)nf * (frame / 2) * cplx, &c->held))) return s;
-      if ((s = launch_row_r2c(in, (hv_dtype)in_t, tb.ptr, mixed, nf, ny, nx, s1, st))) return s;
-      if ((s = launch_col_as(tb.ptr, zb.ptr, mixed, p->ht_ptr(), nf, ny, nx, st))) return s;
+      if ((s = timed(c, "row_r2c", st, [&] { return launch_row_r2c(in, (hv_dtype)in_t, tb.ptr, mixed, nf, ny, nx, s1, st); }))) return s;
+      if ((s = timed(c, "col_as", st, [&] { return launch_col_as(tb.ptr, zb.ptr, mixed, p->ht_ptr(), nf, ny, nx, st); }))) return s;
     }
     out.z = zb.ptr;
     out.z_to_field = 1.0f / (nx * s1);
     if (want_field) {
       DevBuf& fb = c->work(st, 2);
       if ((s = fb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
-      if ((s = launch_row_inv(zb.ptr, mixed, fb.ptr, mixed, nf, ny, nx, out.z_to_field * f_scale, st))) return s;
+      if ((s = timed(c, "row_inv", st, [&] { return launch_row_inv(zb.ptr, mixed, fb.ptr, mixed, nf, ny, nx, out.z_to_field * f_scale, st); }))) return s;
       out.f = fb.ptr;
     }
     return HV_OK;
@@ -358,10 +392,13 @@ hv_status spatial(Ctx* c, const void* in, int in_t, int nf, int ny, int nx, cons
   DevBuf& fb = c->work(st, 2);
   if ((s = fb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
   const float2* q = (const float2*)p->tables.ptr;
-  if ((s = launch_rows_c2c(in, in_t, tb.ptr, mixed, q, q + nx, dir, nf, ny, nx, s1, st))) return s;
+  if ((s = timed(c, "fresnel_rows", st, [&] { return launch_rows_c2c(in, in_t, tb.ptr, mixed, q, q + nx, dir, nf, ny, nx, s1, st); })))
+    return s;
   const float unit = (float)(1.0 / std::sqrt((double)nx * ny));
-  if ((s = launch_fresnel_cols(tb.ptr, mixed, fb.ptr, mixed, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
-                               unit / s1 * f_scale, st)))
+  if ((s = timed(c, "fresnel_cols", st, [&] {
+         return launch_fresnel_cols(tb.ptr, mixed, fb.ptr, mixed, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
+                                    unit / s1 * f_scale, st);
+       })))
     return s;
   out.f = fb.ptr;
   return HV_OK;
@@ -410,6 +447,22 @@ hv_status hv_ctx_set_chunk_frames(hv_ctx* ctx, int frames) {
   return HV_OK;
 }
 
+hv_status hv_ctx_set_timing(hv_ctx* ctx, int on) {
+  if (!ctx) return fail(HV_ERR_ARG, "context is NULL");
+  ctx->timing.reset();
+  ctx->timing.on = on != 0;
+  return HV_OK;
+}
+
+hv_status hv_ctx_kernel_time(hv_ctx* ctx, const char* name, double* total_ms, long* launches) {
+  if (!ctx || !name || !total_ms || !launches) return fail(HV_ERR_ARG, "NULL argument");
+  ctx->timing.collect();
+  auto it = ctx->timing.acc.find(name);
+  *total_ms = it == ctx->timing.acc.end() ? 0.0 : it->second.first;
+  *launches = it == ctx->timing.acc.end() ? 0 : it->second.second;
+  return HV_OK;
+}
+
 hv_status hv_band_bins(const hv_temporal* tp, int* nbins, int* bins, double* freqs) {
   if (!tp || !nbins) return fail(HV_ERR_ARG, "NULL argument");
   if (tp->window <= 0 || !(tp->fs_hz > 0)) return fail(HV_ERR_ARG, "window and fs must be positive");
@@ -442,7 +495,10 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
     SpatialOut so;
     if (optics->method == HV_AS) {
       if ((s = spatial(ctx, src, in_t, nf, ny, nx, *optics, mixed, false, 1.f, st, so))) return s;
-      if ((s = launch_row_inv(so.z, so.half, dst, false, nf, ny, nx, so.z_to_field, st))) return s;
+      if ((s = timed(ctx, "row_inv", st, [&] {
+             return launch_row_inv(so.z, so.half, dst, false, nf, ny, nx, so.z_to_field, st);
+           })))
+        return s;
     } else {
       // Fresnel writes the field straight from its column pass
       const bool mix = mixed;
@@ -482,7 +538,8 @@ static hv_status stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int n
     return fail(HV_ERR_ARG, "without optics the input must be a field (HV_C64)");
   }
   if (n < w) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, w);
-  if (!in || (!m0 && !m1 && !m2 && !spec)) return fail(HV_ERR_ARG, "NULL data pointer");
+  if (!in) return fail(HV_ERR_ARG, "input is NULL");
+  if (!m0 && !m1 && !m2 && !spec) return fail(HV_ERR_ARG, "no output requested");
   DftPlan* dp = ctx->dft_plan(*tp, &s);
   if (!dp) return s;
   const int nwin_total = (n - w) / stride + 1;
@@ -517,11 +574,15 @@ static hv_status stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int n
       // B = z_to_field * IDFT_x(z) * bsc with bsc keeping fp16 in range
       const float bsc = mixed ? so.z_to_field * fsc : 1.f;
       const float amp = mixed ? 1.f / fsc : so.z_to_field;
-      if ((s = launch_rowinv_coef(so.z, so.half, ny, nx, stride, g_n, g, mixed, bsc, amp, o0, o1, o2, os, st)))
+      if ((s = timed(ctx, "rowinv_coef", st, [&] {
+             return launch_rowinv_coef(so.z, so.half, ny, nx, stride, g_n, g, mixed, bsc, amp, o0, o1, o2, os, st);
+           })))
         return s;
     } else {
-      if ((s = launch_field_coef(so.f, so.half, (long)frame, stride, g_n, g, mixed, 1.f, 1.f / so.f_scale, o0, o1,
-                                 o2, os, st)))
+      if ((s = timed(ctx, "field_coef", st, [&] {
+             return launch_field_coef(so.f, so.half, (long)frame, stride, g_n, g, mixed, 1.f, 1.f / so.f_scale, o0,
+                                      o1, o2, os, st);
+           })))
         return s;
     }
   }
@@ -531,13 +592,11 @@ static hv_status stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int n
 hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                           const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
                           void* hip_stream) {
-  if (!m0 && !m1 && !m2) return fail(HV_ERR_ARG, "no moment requested");
   return stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, m0, m1, m2, nullptr, hip_stream);
 }
 
 hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                        const hv_temporal* temporal, int prec, void* spec, void* hip_stream) {
-  if (!spec) return fail(HV_ERR_ARG, "spec is NULL");
   return stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, nullptr, nullptr, nullptr, (float2*)spec,
                      hip_stream);
 }
@@ -613,18 +672,25 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
       half = false;
       fs = fsc;
     }
-    if ((s = launch_gram_partials(field, half, (long)frame, stride, g_n, w, mixed, half ? 1.f : fs,
-                                  (float*)part.ptr, nblk, st)))
+    if ((s = timed(ctx, "gram", st, [&] {
+           return launch_gram_partials(field, half, (long)frame, stride, g_n, w, mixed, half ? 1.f : fs,
+                                       (float*)part.ptr, nblk, st);
+         })))
       return s;
     if ((s = launch_gram_reduce((const float*)part.ptr, g_n, nblk, w, 1.0 / ((double)fs * fs), (double*)cv.ptr, st)))
       return s;
-    if ((s = launch_jacobi((const double*)cv.ptr, g_n, w, (double*)ev.ptr, (double*)vec.ptr, 40, st))) return s;
+    if ((s = timed(ctx, "jacobi", st, [&] {
+           return launch_jacobi((const double*)cv.ptr, g_n, w, (double*)ev.ptr, (double*)vec.ptr, 40, st);
+         })))
+      return s;
     if ((s = launch_proj_coefs((const double*)vec.ptr, g_n, w, comp_lo, comp_hi, mtiles, (float*)a32.ptr,
                                (hv_h8*)a16h.ptr, (hv_h8*)a16l.ptr, st)))
       return s;
-    if ((s = launch_proj_energy(field, half, (long)frame, stride, g_n, w, mtiles, npair, (const float*)a32.ptr,
-                                (const hv_h8*)a16h.ptr, (const hv_h8*)a16l.ptr, (const float*)wts.ptr, mixed,
-                                half ? 1.f : fs, 1.f / fs, m0 + (size_t)j0 * frame, st)))
+    if ((s = timed(ctx, "proj_energy", st, [&] {
+           return launch_proj_energy(field, half, (long)frame, stride, g_n, w, mtiles, npair, (const float*)a32.ptr,
+                                     (const hv_h8*)a16h.ptr, (const hv_h8*)a16l.ptr, (const float*)wts.ptr, mixed,
+                                     half ? 1.f : fs, 1.f / fs, m0 + (size_t)j0 * frame, st);
+         })))
       return s;
     if (eigvals && hipMemcpyAsync(eigvals + (size_t)j0 * w, ev.ptr, (size_t)g_n * w * 8, hipMemcpyDeviceToDevice,
                                   st) != hipSuccess)

@@ -4,6 +4,7 @@
 
 #include <atomic>
 #include <map>
+#include <string>
 #include <memory>
 #include <mutex>
 #include <tuple>
@@ -54,7 +55,25 @@ const char* last_error();
 
 struct StreamState;  // serving loop (stream.cpp)
 
+// Optional per-kernel timing with HIP events recorded around each launch on
+// the caller's stream (no work is skipped or reordered).
+struct Timing {
+  bool on = false;
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<double, long>> acc;  // total ms, launches
+  hipEvent_t take();
+  void collect();
+  void reset();
+  ~Timing();
+};
+
 struct Ctx {
+  Timing timing;
   int device = 0;
   size_t budget = 0;
   size_t held = 0;  // bytes of plans and workspaces
@@ -71,6 +90,18 @@ struct Ctx {
   DevBuf& work(hipStream_t s, int slot);
   int chunk_frames_for(int ny, int nx) const;
 };
+
+// Runs f() (a kernel launch), bracketed by timing events when enabled.
+template <class F>
+hv_status timed(Ctx* c, const char* name, hipStream_t st, F&& f) {
+  if (!c->timing.on) return f();
+  hipEvent_t a = c->timing.take(), b = c->timing.take();
+  hipEventRecord(a, st);
+  hv_status s = f();
+  hipEventRecord(b, st);
+  c->timing.pending.push_back({name, a, b});
+  return s;
+}
 
 // Row C2C FFT of sign dir with an optional separable chirp (qx[m] qy[n]),
 // transposed write [n][nx][ny]; input u8, u16 or c64.

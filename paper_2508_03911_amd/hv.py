@@ -61,6 +61,8 @@ _sig = {
     "hv_ctx_destroy": (None, [_P]),
     "hv_ctx_workspace_bytes": (C.c_size_t, [_P]),
     "hv_ctx_set_chunk_frames": (_I, [_P, _I]),
+    "hv_ctx_set_timing": (_I, [_P, _I]),
+    "hv_ctx_kernel_time": (_I, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_long)]),
     "hv_band_bins": (_I, [C.POINTER(hv_temporal), C.POINTER(_I), C.POINTER(_I), C.POINTER(C.c_double)]),
     "hv_propagate": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _P, _P]),
     "hv_stft_moments": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P, _P,
@@ -169,6 +171,17 @@ class Context:
 
     def set_chunk_frames(self, frames: int):
         _check(lib.hv_ctx_set_chunk_frames(self.handle, frames))
+
+    def set_timing(self, on: bool):
+        """Bracket every kernel launch with HIP events (clears the totals)."""
+        _check(lib.hv_ctx_set_timing(self.handle, int(on)))
+
+    def kernel_time(self, name: str):
+        """(total milliseconds, launches) of kernel `name` since timing was set."""
+        ms = C.c_double(0)
+        n = C.c_long(0)
+        _check(lib.hv_ctx_kernel_time(self.handle, name.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def _dev(self):
         return torch.device("cuda", self.device)

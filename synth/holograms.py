@@ -77,31 +77,43 @@ def drawn_z(seed: int, lo: float = 0.1, hi: float = 0.4) -> float:
     return float(lo + (hi - lo) * zrng.uniform())
 
 
-def hologram_stack(spec: HoloSpec, chunk: int = 64) -> np.ndarray:
-    """Frames [T, ny, nx] (uint8 or uint16) following the module recipe."""
+def hologram_stack(spec: HoloSpec, chunk: int | None = None) -> np.ndarray:
+    """Frames [T, ny, nx] (uint8 or uint16) following the module recipe.
+
+    Frames are produced ``chunk`` at a time (by default about 1 Mi pixels
+    per chunk, which keeps every temporary small)."""
+    if chunk is None:
+        chunk = max(1, (1 << 20) // (spec.ny * spec.nx))
     rng, _ = _child_streams(spec.seed)
     ny, nx = spec.ny, spec.nx
     s = (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))) / np.sqrt(2.0)
     fd = rng.uniform(0.0, spec.f_max, (ny, nx))
+    s64 = s.astype(np.complex64)
     kx = point_response_1d(nx, spec.pitch, spec.wavelength, spec.z)
     ky = point_response_1d(ny, spec.pitch, spec.wavelength, spec.z)
     norm = 1.0 / np.sqrt(max(1, np.count_nonzero(kx[nx // 2])) * max(1, np.count_nonzero(ky[ny // 2])))
     yy, xx = np.mgrid[0:ny, 0:nx]
-    carrier = np.exp(2j * np.pi * (xx + yy) / 4.0)
+    carrier = np.cos(np.pi * (xx + yy) / 2.0) + 1j * np.sin(np.pi * (xx + yy) / 2.0)
     out = np.empty((spec.frames, ny, nx), dtype=spec.dtype)
     r = None
     scale = None
     kxt = np.ascontiguousarray(kx.T)
     for t0 in range(0, spec.frames, chunk):
         t = np.arange(t0, min(spec.frames, t0 + chunk), dtype=np.float64)
-        a = (s[None] * np.exp(2j * np.pi * fd[None] * (t[:, None, None] / spec.fs))).astype(np.complex64)
+        phase = (2 * np.pi / spec.fs) * fd[None] * t[:, None, None]
+        rot = np.empty(phase.shape, np.complex64)  # exp(i phase), via real cos/sin
+        rot.real = np.cos(phase)
+        rot.imag = np.sin(phase)
+        a = s64[None] * rot
         o = (ky[None] @ a @ kxt[None]) * np.float32(norm)
         o = o.astype(np.complex128)
         if r is None:
-            rms = np.sqrt(np.mean(np.abs(o[0]) ** 2))
+            rms = np.sqrt(np.mean(o[0].real ** 2 + o[0].imag ** 2))
             r = spec.ref_ratio * rms * carrier
-            scale = spec.target_mean / np.mean(np.abs(r + o[0]) ** 2)
-        lam = np.abs(r[None] + o) ** 2 * scale
+            f0 = r + o[0]
+            scale = spec.target_mean / np.mean(f0.real ** 2 + f0.imag ** 2)
+        f = r[None] + o
+        lam = (f.real ** 2 + f.imag ** 2) * scale
         counts = rng.poisson(lam)
         np.clip(counts, 0, spec.max_dn, out=counts)
         out[t0:t0 + len(t)] = counts.astype(spec.dtype)
