@@ -23,7 +23,7 @@ using namespace hvk;
 
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 512;  // threads per block: 8 waves
 
 __device__ inline void store_c(float2* p, float2 v) { *p = v; }
 __device__ inline void store_c(hv_h2* p, float2 v) {

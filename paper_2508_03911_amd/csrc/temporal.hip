@@ -30,7 +30,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 512;  // threads per block: 8 waves
 constexpr int MT_MAX = 4;  // up to 64 (re, im) pairs
 
 __device__ inline float2 load_c(const float2* p) { return *p; }
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
 }
 
 // ------------------------------------------------------------------ GEMM from a field in memory
-constexpr int TPIX = 128;  // pixels per block tile (4 waves x 32)
+constexpr int TPIX = NT / 2;  // pixels per block tile (one 32-pixel tile per wave)
 
 template <int W, bool MIXED, typename TIN>
 __global__ __launch_bounds__(NT) void k_field_coef(const TIN* __restrict__ u, long npix, int stride, CoefArgs g) {
@@ -202,7 +202,8 @@ __global__ __launch_bounds__(NT) void k_gram(const TIN* __restrict__ u, long npi
                                              float bsc, float* __restrict__ part, int nblk) {
   constexpr int M = 2 * W;
   constexpr int T = M / 32;             // tiles per dimension
-  constexpr int TPW = (T * T + 3) / 4;  // tiles per wave
+  constexpr int NW = NT / 64;
+  constexpr int TPW = (T * T + NW - 1) / NW;  // tiles per wave
   constexpr int LS32 = GP + 1;          // f32 row stride (odd)
   constexpr int LS16 = GP + 8;          // fp16 row stride (keeps 16-byte reads aligned)
   __shared__ float l32[MIXED ? 1 : M * LS32];
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(NT) void k_gram(const TIN* __restrict__ u, long npi
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
-      const int tile = wave + 4 * i;
+      const int tile = wave + NW * i;
       if (tile < T * T) {
         const int mt = tile / T, nt = tile % T;
         const int ma = 32 * mt + (lane & 31), nb = 32 * nt + (lane & 31);
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(NT) void k_gram(const TIN* __restrict__ u, long npi
   float* dst = part + (jj * nblk + blk) * (long)M * M;
 #pragma unroll
   for (int i = 0; i < TPW; ++i) {
-    const int tile = wave + 4 * i;
+    const int tile = wave + NW * i;
     if (tile < T * T) {
       const int mt = tile / T, nt = tile % T;
 #pragma unroll
