@@ -172,6 +172,99 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
                  int stride, int comp_lo, int comp_hi, int prec, float* m0, double* eigvals, double* cov,
                  void* hip_stream);
 
+/* ---------------------------------------------------------------- serving loop */
+
+/* Camera streams processed as their frames arrive (Sec. II-B.1 and III-A:
+ * a GPU-resident input ring fed by frame packets and drained by windows,
+ * sized so that it never overflows; Sec. II-B.4: separate streams).  Each
+ * stream owns a device ring of ring_frames raw frames (plus W - stride
+ * mirrored slots), its own HIP stream, preallocated workspaces and a ring
+ * of output images.  Window j covers frames [j*stride, j*stride + W) and
+ * is launched as soon as its last frame is pushed; the images are M0/M1/M2
+ * exactly as hv_stft_moments computes them on the same frames. */
+typedef struct hv_stream hv_stream;
+
+typedef struct {
+  int64_t frames_in;          /* frames accepted by pushes */
+  int64_t frames_dropped;     /* frames refused with HV_ERR_OVERFLOW */
+  int64_t windows_done;       /* windows whose images are complete */
+  int64_t streams_admitted;
+  int64_t streams_refused;    /* HBM budget (or replay slot limit) */
+  int64_t images_overwritten; /* completed images replaced before a pop */
+  int64_t latency_samples;
+  int64_t lat_p50_ns, lat_p99_ns, lat_max_ns; /* image done - arrival of the window's last frame */
+  int64_t admitted_bytes;     /* device bytes charged to open streams */
+} hv_stats;
+
+/* Open a stream of ny x nx frames (HV_U8 or HV_U16).  ring_frames must be a
+ * multiple of the stride and >= 2 W (0 = 8 W), and should hold W frames plus
+ * the largest packet plus the frames pushed while a window computes;
+ * 1 <= stride <= W.  The ring,
+ * image slots, workspaces and tables are allocated here (none later) and
+ * charged to the context's HBM budget: HV_ERR_BUDGET refuses the stream. */
+hv_status hv_stream_open(hv_ctx* ctx, int ny, int nx, int raw_t, const hv_optics* optics,
+                         const hv_temporal* temporal, int prec, int ring_frames, hv_stream** out);
+/* Copy n_frames consecutive frames (device memory) into the ring and launch
+ * every window they complete.  arrival_ns[i] (CLOCK_MONOTONIC ns, nullable =
+ * now) is the arrival time of frame i, used for latency.  A packet that
+ * would overwrite frames still needed returns HV_ERR_OVERFLOW and is counted
+ * as dropped; nothing is overwritten silently. */
+hv_status hv_stream_push(hv_stream* s, const void* frames, int n_frames, const int64_t* arrival_ns);
+/* Oldest completed, unpopped window: copies its M0/M1/M2 (each ny*nx float32,
+ * device pointers, nullable) and returns its timestamps.  HV_ERR_STATE when
+ * none is ready.  Up to 4 completed images are kept; older ones are counted
+ * in images_overwritten. */
+hv_status hv_stream_pop(hv_stream* s, float* m0, float* m1, float* m2, int64_t* t_last_arrival_ns,
+                        int64_t* t_done_ns);
+/* Finish in-flight windows, free the stream and return its bytes to the budget. */
+hv_status hv_stream_close(hv_stream* s);
+/* Per-stream counters (nullable outputs). */
+hv_status hv_stream_frames(const hv_stream* s, int64_t* pushed, int64_t* dropped, int64_t* windows_done);
+/* Context-wide serving counters and latency percentiles (nearest rank). */
+hv_status hv_ctx_stats(hv_ctx* ctx, hv_stats* out);
+/* Clear the counters and latency samples. */
+hv_status hv_ctx_stats_reset(hv_ctx* ctx);
+
+/* Replay of device-resident synthetic camera blocks as a Poisson stream
+ * load (the paper's file mode, where a recording in GPU memory stands in
+ * for the camera, Table IV).  Streams arrive at arrival_hz, live
+ * Exp(mean_life_s), pick a class uniformly, draw z uniformly in
+ * [z_lo_m, z_hi_m] (reconstructed at -z by angular spectrum), and push
+ * packet_frames frames at the class frame rate from their block (cyclic).
+ * A class admits at most max_active streams; the HBM budget may refuse
+ * more.  Latency samples start after warmup_s. */
+#define HV_REPLAY_MAX_CLASSES 4
+typedef struct {
+  int ny, nx, raw_t;
+  double fps;               /* camera frame rate = temporal fs */
+  int window, stride;
+  double f_lo_hz, f_hi_hz;  /* band */
+  const void* block;        /* device frames [block_frames][ny][nx] */
+  int block_frames;
+  int max_active;
+  int ring_frames;          /* 0 = 8 W */
+} hv_replay_class;
+
+typedef struct {
+  int nclass;
+  hv_replay_class cls[HV_REPLAY_MAX_CLASSES];
+  double wavelength_m, pitch_m, z_lo_m, z_hi_m;
+  int prec;
+  double arrival_hz, mean_life_s, duration_s, warmup_s;
+  int packet_frames;
+  uint64_t seed;
+} hv_replay_config;
+
+typedef struct {
+  int64_t frames_offered, frames_in, frames_dropped, windows_done;
+  int64_t streams_admitted, streams_refused;
+  int64_t lat_p50_ns, lat_p99_ns, lat_max_ns, latency_samples;
+  double seconds, frames_per_s;
+  int64_t errors;
+} hv_replay_result;
+
+hv_status hv_replay_run(hv_ctx* ctx, const hv_replay_config* cfg, hv_replay_result* res);
+
 #ifdef __cplusplus
 }
 #endif

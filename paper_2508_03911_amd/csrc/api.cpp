@@ -434,6 +434,7 @@ hv_status hv_ctx_create(int device, size_t hbm_budget_bytes, hv_ctx** out) {
 void hv_ctx_destroy(hv_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
+  serve_shutdown(ctx);
   hipDeviceSynchronize();
   delete ctx;
 }
@@ -480,6 +481,7 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
                        int prec, void* out, void* hip_stream) {
   hv_status s;
   if ((s = enter(ctx))) return s;
+  std::lock_guard<std::recursive_mutex> lock(ctx->mu);
   if ((s = check_frame(n, ny, nx)) || (s = check_optics(optics)) || (s = check_dtype(in_t, true))) return s;
   if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
   if (n == 0) return HV_OK;
@@ -520,11 +522,12 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
 }
 
 // Shared driver of hv_stft_moments and hv_stft_bins.
-static hv_status stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
-                             const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
-                             void* hip_stream) {
+hv_status hvi_stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                          const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
+                          void* hip_stream) {
   hv_status s;
   if ((s = enter(ctx))) return s;
+  std::lock_guard<std::recursive_mutex> lock(ctx->mu);
   if ((s = check_frame(n, ny, nx))) return s;
   if (!tp) return fail(HV_ERR_ARG, "temporal is NULL");
   const int w = tp->window, stride = tp->stride;
@@ -592,12 +595,12 @@ static hv_status stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int n
 hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                           const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
                           void* hip_stream) {
-  return stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, m0, m1, m2, nullptr, hip_stream);
+  return hvi_stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, m0, m1, m2, nullptr, hip_stream);
 }
 
 hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                        const hv_temporal* temporal, int prec, void* spec, void* hip_stream) {
-  return stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, nullptr, nullptr, nullptr, (float2*)spec,
+  return hvi_stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, nullptr, nullptr, nullptr, (float2*)spec,
                      hip_stream);
 }
 
@@ -606,6 +609,7 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
                  void* hip_stream) {
   hv_status s;
   if ((s = enter(ctx))) return s;
+  std::lock_guard<std::recursive_mutex> lock(ctx->mu);
   if ((s = check_frame(n, ny, nx))) return s;
   if (window != 16 && window != 32 && window != 64) return fail(HV_ERR_SHAPE, "PCA window %d: use 16, 32 or 64", window);
   if (stride <= 0) return fail(HV_ERR_ARG, "stride must be positive");

@@ -53,7 +53,8 @@ struct DftPlan {
 int band_bins(const hv_temporal& tp, std::vector<int>& bins, std::vector<double>& freqs);
 const char* last_error();
 
-struct StreamState;  // serving loop (stream.cpp)
+struct ServeState;  // serving loop (stream.cpp)
+void serve_shutdown(struct Ctx* c);
 
 // Optional per-kernel timing with HIP events recorded around each launch on
 // the caller's stream (no work is skipped or reordered).
@@ -73,6 +74,8 @@ struct Timing {
 };
 
 struct Ctx {
+  std::recursive_mutex mu;  // plans, workspaces and launches (the serving loop uses several threads)
+  ServeState* serve = nullptr;
   Timing timing;
   int device = 0;
   size_t budget = 0;
@@ -115,3 +118,7 @@ hv_status launch_col_full(const void* in, void* out, bool half_io, const float2*
 }  // namespace hvi
 
 struct hv_ctx : hvi::Ctx {};
+
+extern "C" hv_status hvi_stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx,
+                                     const hv_optics* optics, const hv_temporal* tp, int prec, float* m0, float* m1,
+                                     float* m2, float2* spec, void* hip_stream);

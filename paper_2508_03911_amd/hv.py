@@ -53,6 +53,36 @@ class hv_temporal(C.Structure):
                 ("f_hi_hz", C.c_double), ("symmetric_band", C.c_int)]
 
 
+class hv_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "frames_in", "frames_dropped", "windows_done", "streams_admitted", "streams_refused",
+        "images_overwritten", "latency_samples", "lat_p50_ns", "lat_p99_ns", "lat_max_ns", "admitted_bytes")]
+
+
+HV_REPLAY_MAX_CLASSES = 4
+
+
+class hv_replay_class(C.Structure):
+    _fields_ = [("ny", C.c_int), ("nx", C.c_int), ("raw_t", C.c_int), ("fps", C.c_double), ("window", C.c_int),
+                ("stride", C.c_int), ("f_lo_hz", C.c_double), ("f_hi_hz", C.c_double), ("block", C.c_void_p),
+                ("block_frames", C.c_int), ("max_active", C.c_int), ("ring_frames", C.c_int)]
+
+
+class hv_replay_config(C.Structure):
+    _fields_ = [("nclass", C.c_int), ("cls", hv_replay_class * HV_REPLAY_MAX_CLASSES),
+                ("wavelength_m", C.c_double), ("pitch_m", C.c_double), ("z_lo_m", C.c_double),
+                ("z_hi_m", C.c_double), ("prec", C.c_int), ("arrival_hz", C.c_double),
+                ("mean_life_s", C.c_double), ("duration_s", C.c_double), ("warmup_s", C.c_double),
+                ("packet_frames", C.c_int), ("seed", C.c_uint64)]
+
+
+class hv_replay_result(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "frames_offered", "frames_in", "frames_dropped", "windows_done", "streams_admitted", "streams_refused",
+        "lat_p50_ns", "lat_p99_ns", "lat_max_ns", "latency_samples")] + [
+        ("seconds", C.c_double), ("frames_per_s", C.c_double), ("errors", C.c_int64)]
+
+
 _P = C.c_void_p
 _I = C.c_int
 _sig = {
@@ -68,6 +98,14 @@ _sig = {
     "hv_stft_moments": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P, _P,
                              _P]),
     "hv_stft_bins": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P]),
+    "hv_stream_open": (_I, [_P, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _I, C.POINTER(_P)]),
+    "hv_stream_push": (_I, [_P, _P, _I, C.POINTER(C.c_int64)]),
+    "hv_stream_pop": (_I, [_P, _P, _P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "hv_stream_close": (_I, [_P]),
+    "hv_stream_frames": (_I, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "hv_ctx_stats": (_I, [_P, C.POINTER(hv_stats)]),
+    "hv_ctx_stats_reset": (_I, [_P]),
+    "hv_replay_run": (_I, [_P, C.POINTER(hv_replay_config), C.POINTER(hv_replay_result)]),
     "hv_pca": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _I, _I, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -242,3 +280,82 @@ class Context:
                           window, stride, comp_lo, comp_hi, prec, _ptr(m0), _ptr(ev), _ptr(cov),
                           _stream(x.device)))
         return {"m0": m0, "eigvals": ev, "cov": cov}
+
+
+    # ---------------------------------------------------------------- serving loop
+    def stats(self) -> dict:
+        st = hv_stats()
+        _check(lib.hv_ctx_stats(self.handle, C.byref(st)))
+        return {n: getattr(st, n) for n, _ in hv_stats._fields_}
+
+    def stats_reset(self):
+        _check(lib.hv_ctx_stats_reset(self.handle))
+
+    def hv_stream_open(self, ny: int, nx: int, raw_dtype, optics: Optics, temporal: Temporal,
+                       prec: int = HV_PREC_FP32, ring_frames: int = 0) -> "Stream":
+        code = HV_U8 if raw_dtype == torch.uint8 else HV_U16
+        op, tp = optics.c(), temporal.c()
+        h = C.c_void_p()
+        _check(lib.hv_stream_open(self.handle, ny, nx, code, C.byref(op), C.byref(tp), prec, ring_frames,
+                                  C.byref(h)))
+        return Stream(self, h, ny, nx)
+
+    def hv_replay_run(self, classes, *, wavelength, pitch, z_lo, z_hi, prec, arrival_hz, mean_life_s,
+                      duration_s, warmup_s, packet_frames, seed) -> dict:
+        """classes: list of dicts with ny, nx, raw_t, fps, window, stride, f_lo, f_hi, block (device
+        tensor [frames, ny, nx]), max_active, ring_frames."""
+        cfg = hv_replay_config()
+        cfg.nclass = len(classes)
+        for i, k in enumerate(classes):
+            b = k["block"]
+            cfg.cls[i] = hv_replay_class(k["ny"], k["nx"], _dtype_code(b), k["fps"], k["window"], k["stride"],
+                                         k["f_lo"], k["f_hi"], C.c_void_p(b.data_ptr()), b.shape[0],
+                                         k["max_active"], k.get("ring_frames", 0))
+        cfg.wavelength_m, cfg.pitch_m, cfg.z_lo_m, cfg.z_hi_m = wavelength, pitch, z_lo, z_hi
+        cfg.prec, cfg.arrival_hz, cfg.mean_life_s = prec, arrival_hz, mean_life_s
+        cfg.duration_s, cfg.warmup_s, cfg.packet_frames, cfg.seed = duration_s, warmup_s, packet_frames, seed
+        res = hv_replay_result()
+        torch.cuda.synchronize()
+        st = lib.hv_replay_run(self.handle, C.byref(cfg), C.byref(res))
+        out = {n: getattr(res, n) for n, _ in hv_replay_result._fields_}
+        _check(st)
+        return out
+
+
+class Stream:
+    """An open serving-loop stream (hv_stream)."""
+
+    def __init__(self, ctx: Context, handle, ny: int, nx: int):
+        self.ctx, self.handle, self.ny, self.nx = ctx, handle, ny, nx
+
+    def push(self, frames: torch.Tensor, arrival_ns=None):
+        n = frames.shape[0]
+        arr = None
+        if arrival_ns is not None:
+            arr = (C.c_int64 * n)(*[int(a) for a in arrival_ns])
+        # the copy is ordered on the stream; the caller's producer work must be complete
+        torch.cuda.current_stream(frames.device).synchronize()
+        _check(lib.hv_stream_push(self.handle, _ptr(frames), n, arr))
+
+    def try_push(self, frames: torch.Tensor) -> int:
+        torch.cuda.current_stream(frames.device).synchronize()
+        return lib.hv_stream_push(self.handle, _ptr(frames), frames.shape[0], None)
+
+    def pop(self, m0=None, m1=None, m2=None):
+        """Returns (t_last_arrival_ns, t_done_ns) or None when nothing is ready."""
+        tl, td = C.c_int64(0), C.c_int64(0)
+        st = lib.hv_stream_pop(self.handle, _ptr(m0), _ptr(m1), _ptr(m2), C.byref(tl), C.byref(td))
+        if st == HV_ERR_STATE:
+            return None
+        _check(st)
+        return tl.value, td.value
+
+    def counters(self):
+        a, b, c = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        _check(lib.hv_stream_frames(self.handle, C.byref(a), C.byref(b), C.byref(c)))
+        return {"pushed": a.value, "dropped": b.value, "windows_done": c.value}
+
+    def close(self):
+        if self.handle:
+            _check(lib.hv_stream_close(self.handle))
+            self.handle = None
