@@ -87,6 +87,35 @@ def cpu_baseline(block, spec, z):
                       f"FFTs single-threaded, BLAS {blas} threads", "seconds": dt}
 
 
+def serving(hv, torch, seconds, prec):
+    """The mixed-size stream load: 4 slots each of 256x256 u8 at 71.4 kHz
+    (W 16), 512x512 u8 at 20 kHz (W 32) and 1024x512 u16 at 5 kHz (W 64),
+    Poisson arrivals at 6/s with Exp(2 s) lifetimes, z uniform in
+    [0.1, 0.4] m, HBM budget 32 GiB, device-resident camera blocks."""
+    from synth import holograms
+    classes = []
+    for cls in range(3):
+        t0 = time.time()
+        x, spec = holograms.stream_block(cls, cls)
+        ny, nx, bits, fs, w, _ = holograms.STREAM_CLASSES[cls]
+        classes.append(dict(ny=ny, nx=nx, raw_t=0, fps=fs, window=w, stride=w, f_lo=2 * fs / w,
+                            f_hi=(w // 2 - 1) * fs / w, block=torch.from_numpy(x).cuda(), max_active=4,
+                            ring_frames=0))
+        log(f"stream class {cls}: block {x.shape} {x.dtype} in {time.time() - t0:.1f}s")
+    ctx = hv.Context(0, hbm_budget=32 << 30)
+    r = ctx.hv_replay_run(classes, wavelength=852e-9, pitch=20e-6, z_lo=0.1, z_hi=0.4, prec=prec, arrival_hz=6.0,
+                          mean_life_s=2.0, duration_s=seconds, warmup_s=1.0, packet_frames=8, seed=5)
+    ctx.close()
+    return {"seconds": r["seconds"], "frames_per_s": r["frames_per_s"], "frames_offered": r["frames_offered"],
+            "frames_in": r["frames_in"], "frames_dropped": r["frames_dropped"], "windows_done": r["windows_done"],
+            "streams_admitted": r["streams_admitted"], "streams_refused": r["streams_refused"],
+            "lat_p50_ms": r["lat_p50_ns"] / 1e6, "lat_p99_ms": r["lat_p99_ns"] / 1e6,
+            "lat_max_ms": r["lat_max_ns"] / 1e6, "latency_samples": r["latency_samples"],
+            "precision": "fp32" if prec == 0 else "mixed",
+            "load": "12 slots (4 per class): 256x256 u8 71.4 kHz W16, 512x512 u8 20 kHz W32, "
+                    "1024x512 u16 5 kHz W64; Poisson 6/s, Exp(2 s) lifetimes; budget 32 GiB"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +123,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="stream-load replay length (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the windows are independent, "
@@ -158,6 +188,10 @@ def main():
                   "kernels": mixed["kernels"]},
         "kernels_fp32": fp32["kernels"],
     }
+    if args.serve_seconds > 0:
+        log(f"stream load replay for {args.serve_seconds:.0f}s ...")
+        line["serving"] = serving(hv, torch, args.serve_seconds, hv.HV_PREC_FP32)
+        log(f"serving: {line['serving']}")
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample ...")
         line["cpu_baseline"] = cpu_baseline(block, spec, spec.z)

@@ -131,7 +131,7 @@ int band_bins(const hv_temporal& tp, std::vector<int>& bins, std::vector<double>
 
 // ---------------------------------------------------------------- table builders (float64)
 
-static hv_status build_as_table(Ctx* c, AsPlan& p) {
+static hv_status build_as_table(size_t* held, AsPlan& p) {
   const int ny = p.ny, nx = p.nx;
   std::vector<float2> h((size_t)nx * ny);
   const double inv_l2 = 1.0 / (p.wavelength * p.wavelength);
@@ -149,10 +149,10 @@ static hv_status build_as_table(Ctx* c, AsPlan& p) {
       h[(size_t)cx * ny + cy] = make_float2((float)re, (float)im);
     }
   }
-  return p.ht.upload(h.data(), h.size() * sizeof(float2), &c->held);
+  return p.ht.upload(h.data(), h.size() * sizeof(float2), held);
 }
 
-static hv_status build_fresnel_tables(Ctx* c, FresnelPlan& p) {
+static hv_status build_fresnel_tables(size_t* held, FresnelPlan& p) {
   const int ny = p.ny, nx = p.nx;
   const double lz = p.wavelength * p.z;
   const double opx = p.wavelength * std::fabs(p.z) / (nx * p.dx);
@@ -167,10 +167,10 @@ static hv_status build_fresnel_tables(Ctx* c, FresnelPlan& p) {
   for (int n = 0; n < ny; ++n) t[nx + n] = chirp((n - ny / 2) * p.dy, n);
   for (int m = 0; m < nx; ++m) t[nx + ny + m] = chirp((m - nx / 2) * opx, m);
   for (int n = 0; n < ny; ++n) t[2 * nx + ny + n] = chirp((n - ny / 2) * opy, n);
-  return p.tables.upload(t.data(), t.size() * sizeof(float2), &c->held);
+  return p.tables.upload(t.data(), t.size() * sizeof(float2), held);
 }
 
-static hv_status build_dft_plan(Ctx* c, DftPlan& p) {
+static hv_status build_dft_plan(size_t* held, DftPlan& p) {
   const int w = p.window;
   const int nb = (int)p.bins.size();
   p.mtiles = (nb + 15) / 16;
@@ -208,49 +208,67 @@ static hv_status build_dft_plan(Ctx* c, DftPlan& p) {
     wts[mt * 16 + b] = (float)p.freqs[b];
     wts[2 * mt * 16 + b] = (float)(p.freqs[b] * p.freqs[b]);
   }
-  hv_status st = p.a32.upload(a32.data(), a32.size() * sizeof(float), &c->held);
-  if (!st) st = p.a16hi.upload(hi.data(), hi.size() * sizeof(hv_h8), &c->held);
-  if (!st) st = p.a16lo.upload(lo.data(), lo.size() * sizeof(hv_h8), &c->held);
-  if (!st) st = p.wts.upload(wts.data(), wts.size() * sizeof(float), &c->held);
+  hv_status st = p.a32.upload(a32.data(), a32.size() * sizeof(float), held);
+  if (!st) st = p.a16hi.upload(hi.data(), hi.size() * sizeof(hv_h8), held);
+  if (!st) st = p.a16lo.upload(lo.data(), lo.size() * sizeof(hv_h8), held);
+  if (!st) st = p.wts.upload(wts.data(), wts.size() * sizeof(float), held);
   return st;
 }
 
 // ---------------------------------------------------------------- plan lookup
 
+// Plans are looked up under the context lock but built outside it (the
+// float64 tables of a large frame take milliseconds), so a stream being
+// opened never stalls the launches of the streams already running.
+template <class Map, class Key, class Make>
+static auto* plan_lookup(Ctx* c, Map& m, const Key& key, Make make, hv_status* st) {
+  {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    auto it = m.find(key);
+    if (it != m.end()) return it->second.get();
+  }
+  size_t bytes = 0;
+  auto p = make(&bytes, st);
+  if (!p) return (decltype(p.get())) nullptr;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  auto it = m.find(key);
+  if (it != m.end()) return it->second.get();  // built meanwhile by another thread
+  c->held += bytes;
+  auto* raw = p.get();
+  m[key] = std::move(p);
+  return raw;
+}
+
 AsPlan* Ctx::as_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
   auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m);
-  auto it = as_plans.find(key);
-  if (it != as_plans.end()) return it->second.get();
-  auto p = std::make_unique<AsPlan>();
-  p->ny = ny;
-  p->nx = nx;
-  p->wavelength = o.wavelength_m;
-  p->dx = o.pitch_x_m;
-  p->dy = o.pitch_y_m;
-  p->z = o.z_m;
-  *st = build_as_table(this, *p);
-  if (*st) return nullptr;
-  AsPlan* raw = p.get();
-  as_plans[key] = std::move(p);
-  return raw;
+  return plan_lookup(this, as_plans, key, [&](size_t* bytes, hv_status* e) {
+    auto p = std::make_unique<AsPlan>();
+    p->ny = ny;
+    p->nx = nx;
+    p->wavelength = o.wavelength_m;
+    p->dx = o.pitch_x_m;
+    p->dy = o.pitch_y_m;
+    p->z = o.z_m;
+    *e = build_as_table(bytes, *p);
+    if (*e) p.reset();
+    return p;
+  }, st);
 }
 
 FresnelPlan* Ctx::fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
   auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m);
-  auto it = fr_plans.find(key);
-  if (it != fr_plans.end()) return it->second.get();
-  auto p = std::make_unique<FresnelPlan>();
-  p->ny = ny;
-  p->nx = nx;
-  p->wavelength = o.wavelength_m;
-  p->dx = o.pitch_x_m;
-  p->dy = o.pitch_y_m;
-  p->z = o.z_m;
-  *st = build_fresnel_tables(this, *p);
-  if (*st) return nullptr;
-  FresnelPlan* raw = p.get();
-  fr_plans[key] = std::move(p);
-  return raw;
+  return plan_lookup(this, fr_plans, key, [&](size_t* bytes, hv_status* e) {
+    auto p = std::make_unique<FresnelPlan>();
+    p->ny = ny;
+    p->nx = nx;
+    p->wavelength = o.wavelength_m;
+    p->dx = o.pitch_x_m;
+    p->dy = o.pitch_y_m;
+    p->z = o.z_m;
+    *e = build_fresnel_tables(bytes, *p);
+    if (*e) p.reset();
+    return p;
+  }, st);
 }
 
 DftPlan* Ctx::dft_plan(const hv_temporal& tp, hv_status* st) {
@@ -263,20 +281,21 @@ DftPlan* Ctx::dft_plan(const hv_temporal& tp, hv_status* st) {
     return nullptr;
   }
   auto key = std::make_tuple(tp.window, bins, freqs);
-  auto it = dft_plans.find(key);
-  if (it != dft_plans.end()) return it->second.get();
-  auto p = std::make_unique<DftPlan>();
-  p->window = tp.window;
-  p->bins = bins;
-  p->freqs = freqs;
-  *st = build_dft_plan(this, *p);
-  if (*st) return nullptr;
-  DftPlan* raw = p.get();
-  dft_plans[key] = std::move(p);
-  return raw;
+  return plan_lookup(this, dft_plans, key, [&](size_t* bytes, hv_status* e) {
+    auto p = std::make_unique<DftPlan>();
+    p->window = tp.window;
+    p->bins = bins;
+    p->freqs = freqs;
+    *e = build_dft_plan(bytes, *p);
+    if (*e) p.reset();
+    return p;
+  }, st);
 }
 
-DevBuf& Ctx::work(hipStream_t s, int slot) { return ws[std::make_pair((void*)s, slot)]; }
+DevBuf& Ctx::work(hipStream_t s, int slot) {
+  std::lock_guard<std::recursive_mutex> lk(mu);
+  return ws[std::make_pair((void*)s, slot)];
+}
 
 int Ctx::chunk_frames_for(int ny, int nx) const {
   if (chunk_frames > 0) return chunk_frames;

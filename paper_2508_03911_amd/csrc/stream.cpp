@@ -278,12 +278,20 @@ hv_status hv_stream_open(hv_ctx* ctx, int ny, int nx, int raw_t, const hv_optics
   for (int i = 0; i < 3; ++i)
     if (hipMalloc(&st->out_dev[i], out_b) != hipSuccess) return undo(fail(HV_ERR_NOMEM, "output allocation failed"));
   {
-    // preallocate workspaces and tables so the loop never allocates
-    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    // preallocate workspaces and tables so the loop never allocates; the
+    // allocations and the float64 table builds run outside the context lock
     hv_status e;
-    if ((e = ctx->work(st->st, 0).ensure(ws0, &ctx->held)) || (e = ctx->work(st->st, 1).ensure(ws1, &ctx->held)))
-      return undo(e);
-    if (ws2 && (e = ctx->work(st->st, 2).ensure(ws2, &ctx->held))) return undo(e);
+    const size_t want[3] = {ws0, ws1, ws2};
+    for (int slot = 0; slot < 3; ++slot) {
+      if (!want[slot]) continue;
+      void* p = nullptr;
+      if (hipMalloc(&p, want[slot]) != hipSuccess) return undo(fail(HV_ERR_NOMEM, "workspace allocation failed"));
+      std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+      DevBuf& b = ctx->ws[std::make_pair((void*)st->st, slot)];
+      b.ptr = p;
+      b.bytes = want[slot];
+      ctx->held += want[slot];
+    }
     if (optics->method == HV_AS) {
       if (!ctx->as_plan(ny, nx, *optics, &e)) return undo(e);
     } else if (!ctx->fresnel_plan(ny, nx, *optics, &e)) {
@@ -355,12 +363,18 @@ hv_status hv_stream_close(hv_stream* s) {
   }
   hipStreamSynchronize(s->st);
   drain(sv, s, true);
+  std::vector<void*> to_free;
+  std::vector<std::unique_ptr<AsPlan>> dead_as;
+  std::vector<std::unique_ptr<FresnelPlan>> dead_fr;
   {
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     for (int slot = 0; slot < 3; ++slot) {
       auto it = ctx->ws.find(std::make_pair((void*)s->st, slot));
       if (it != ctx->ws.end()) {
         ctx->held -= it->second.bytes;
+        to_free.push_back(it->second.ptr);
+        it->second.ptr = nullptr;  // freed below, outside the lock
+        it->second.bytes = 0;
         ctx->ws.erase(it);
       }
     }
@@ -377,19 +391,23 @@ hv_status hv_stream_close(hv_stream* s) {
     if (!shared) {
       auto key = std::make_tuple(s->ny, s->nx, s->optics.wavelength_m, s->optics.pitch_x_m, s->optics.pitch_y_m,
                                  s->optics.z_m);
-      auto& plans_as = ctx->as_plans;
-      auto ia = plans_as.find(key);
-      if (s->optics.method == HV_AS && ia != plans_as.end()) {
+      auto ia = ctx->as_plans.find(key);
+      if (s->optics.method == HV_AS && ia != ctx->as_plans.end()) {
         ctx->held -= ia->second->ht.bytes;
-        plans_as.erase(ia);
+        dead_as.push_back(std::move(ia->second));
+        ctx->as_plans.erase(ia);
       }
       auto ifr = ctx->fr_plans.find(key);
       if (s->optics.method == HV_FRESNEL && ifr != ctx->fr_plans.end()) {
         ctx->held -= ifr->second->tables.bytes;
+        dead_fr.push_back(std::move(ifr->second));
         ctx->fr_plans.erase(ifr);
       }
     }
   }
+  for (void* p : to_free) hipFree(p);
+  dead_as.clear();
+  dead_fr.clear();
   hipFree(s->ring_dev);
   for (float* p : s->out_dev) hipFree(p);
   hipStreamDestroy(s->st);
@@ -487,7 +505,13 @@ hv_status hv_replay_run(hv_ctx* ctx, const hv_replay_config* cfg, hv_replay_resu
     hv_optics op{cfg->wavelength_m, cfg->pitch_m, cfg->pitch_m, -z, HV_AS};
     hv_temporal tp{k.window, k.stride, k.fps, k.f_lo_hz, k.f_hi_hz, 0};
     hv_stream* s = nullptr;
-    hv_status st = hv_stream_open(ctx, k.ny, k.nx, k.raw_t, &op, &tp, cfg->prec, k.ring_frames, &s);
+    int ring = k.ring_frames;
+    if (ring <= 0) {  // at least 8 windows and 20 ms of frames, a multiple of the stride
+      const int by_time = (int)std::ceil(0.02 * k.fps);
+      ring = std::max(8 * k.window, by_time);
+      ring = (ring + k.stride - 1) / k.stride * k.stride;
+    }
+    hv_status st = hv_stream_open(ctx, k.ny, k.nx, k.raw_t, &op, &tp, cfg->prec, ring, &s);
     if (st == HV_ERR_BUDGET) continue;  // counted as refused by hv_stream_open
     if (st) {
       errors++;

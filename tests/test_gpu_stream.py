@@ -114,7 +114,7 @@ def test_replay_short_no_drops(ctx, hv):
     for (b, spec), w in zip(blocks, (16, 32)):
         classes.append(dict(ny=spec.ny, nx=spec.nx, raw_t=0, fps=spec.fs, window=w, stride=w,
                             f_lo=2 * spec.fs / w, f_hi=(w // 2 - 1) * spec.fs / w, block=b, max_active=2,
-                            ring_frames=8 * w))
+                            ring_frames=0))
     r = ctx.hv_replay_run(classes, wavelength=LAM, pitch=20e-6, z_lo=0.1, z_hi=0.4, prec=1, arrival_hz=6.0,
                           mean_life_s=0.5, duration_s=2.0, warmup_s=0.2, packet_frames=8, seed=3)
     say(f"  {r}")
