@@ -34,6 +34,27 @@ BYTES_PER_PXF = {
 }
 
 
+def source_sha() -> str:
+    import hashlib
+    d = os.path.join(ROOT, "paper_2508_03911_amd", "csrc")
+    src = sorted(os.path.join(d, f) for f in os.listdir(d) if f.endswith((".hip", ".h", ".cpp")))
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in src)).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, prec: str):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary,
+    or None when the library sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_as_stft32_256x256.json")
+    try:
+        d = json.load(open(path))
+    except OSError:
+        return None
+    if d.get("source_sha") != source_sha():
+        return None
+    k = d.get("kernels", {}).get(kernel, {}).get(prec)
+    return None if k is None else k.get("traffic_bytes_per_dispatch")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -190,7 +211,9 @@ def main():
                                "STFT window 32 stride 32; M0/M1/M2 over [3,35] kHz at fs 71.4 kHz",
                    "frames": frames, "ny": NY, "nx": NX, "window": W, "stride": W, "precision": "fp32"},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dom["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": dom["achieved_GBs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom_name, "fp32"),
+                     "algorithmic_bytes_per_launch": dom["bytes_per_launch"], "avg_launch_ms": dom["avg_ms"]},
         "pass_level_hbm": {"GBs": pass_bytes / (fp32["ms_per_step"] * 1e-3) / 1e9,
                            "frac": pass_bytes / (fp32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                            "bytes_per_pixel_frame": sum(BYTES_PER_PXF[0].values())},
