@@ -265,6 +265,75 @@ typedef struct {
 
 hv_status hv_replay_run(hv_ctx* ctx, const hv_replay_config* cfg, hv_replay_result* res);
 
+/* ---------------------------------------------------------------- autofocus */
+
+/* Learned autofocus with a brute-force scan as fallback and judge (the
+ * paper names machine-learning inference as a plug-in for the pipeline,
+ * Sec. VIII).  Holograms are 256 x 256 uint8 off-axis interferograms whose
+ * reference carrier is (+1/4, +1/4) cycles/pixel, so the object term sits at
+ * (-1/4, -1/4).  All pointers are device memory unless marked host. */
+typedef struct hv_af_model hv_af_model;
+
+/* Number of network parameters (30,306): conv3x3 1->32, 3 x conv3x3 32->32
+ * (weights [co][ci][3][3] then bias), FC 32->64, FC 64->2 (weights [out][in]
+ * then bias), in that order. */
+int hv_af_nparams(void);
+
+/* Network inputs: log(1 + |DFT2(h - mean h)|), the 64 x 64 bins centred on DC
+ * (fftshift order), standardised per crop to mean 0 and standard deviation 1.
+ * out: [n][64][64] fp16 (out_half = 1) or float32. */
+hv_status hv_af_crops(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, void* out, int out_half,
+                      void* hip_stream);
+
+/* Brute-force scan: n_candidates distances z_c evenly spaced in [z_lo, z_hi];
+ * for each, the +1-order sub-band (64 x 64 bins around the object carrier,
+ * masked to radius 0.1 cycles/pixel) times exp(-2 pi i z_c sqrt(1/lambda^2 -
+ * |f|^2)) at the demodulated frequencies f, inverse DFT at 64 x 64, amplitude
+ * A, sharpness = population variance of sqrt(gx^2 + gy^2) with forward
+ * differences on the 63 x 63 interior.  z_out[n] = the candidate with the
+ * largest sharpness (ties to the lowest z); scores_out [n][n_candidates]
+ * nullable. */
+hv_status hv_af_scan(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, double wavelength_m, double pitch_m,
+                     double z_lo_m, double z_hi_m, int n_candidates, float* z_out, float* scores_out,
+                     void* hip_stream);
+
+/* Model with its Adam state and training buffers for up to max_batch crops.
+ * init_params: host float32[hv_af_nparams()].  The network predicts the
+ * normalised distance (z - z_mean) / z_scale and s = log sigma^2 of it. */
+hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batch, double z_mean, double z_scale,
+                             hv_af_model** out);
+void hv_af_model_destroy(hv_af_model* model);
+/* Copy parameters, Adam moments (host float32[nparams], nullable) and step out
+ * of / into the model (checkpoint and resume). */
+hv_status hv_af_model_state(hv_af_model* model, float* params, float* m, float* v, int64_t* step);
+hv_status hv_af_model_load(hv_af_model* model, const float* params, const float* m, const float* v, int64_t step);
+
+/* Raw network output [batch][2] = (normalised z, log sigma^2) for fp16 crops. */
+hv_status hv_af_forward(hv_af_model* model, const void* crops, int batch, float* out, void* hip_stream);
+/* Mean Gaussian NLL 0.5 (s + (z_n - zhat)^2 e^{-s}) over the batch (loss,
+ * device float[1], nullable) and its gradient with respect to every parameter
+ * (grad, device float32[nparams]); labels z_m in metres. */
+hv_status hv_af_loss_grad(hv_af_model* model, const void* crops, const float* z_m, int batch, float* loss,
+                          float* grad, void* hip_stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on that gradient. */
+hv_status hv_af_train_step(hv_af_model* model, const void* crops, const float* z_m, int batch, float lr,
+                           float* loss, void* hip_stream);
+/* Predicted z (metres) and sigma for n holograms; every hologram with
+ * sigma > tau_m is re-estimated by hv_af_scan (128 candidates in [0.05, 0.5] m)
+ * and flagged in used_fallback[n] (nullable).  *n_fallback (host, nullable)
+ * receives their count.  Synchronises the stream. */
+hv_status hv_af_predict(hv_af_model* model, const uint8_t* holo, int n, double wavelength_m, double pitch_m,
+                        float tau_m, float* z_out, float* sigma_out, int* used_fallback, int* n_fallback,
+                        void* hip_stream);
+/* Training holograms from the project's own forward model: counter-based
+ * complex noise band-limited to a 0.09 cycles/pixel pupil, times 3-8 soft
+ * disks (parameters drawn from seed and the hologram index), propagated by
+ * +z_m[i] with hv_propagate (runs of equal z share a call), reference of
+ * amplitude 3 x rms tilted (+1/4, +1/4) cycles/pixel, mean 64 DN, photon
+ * noise (normal approximation), uint8.  z_m: host double[n]. */
+hv_status hv_af_synthesize(hv_ctx* ctx, int n, const double* z_m, double wavelength_m, double pitch_m, uint64_t seed,
+                           int64_t index_base, uint8_t* out, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,976 @@
+// Learned autofocus with a brute-force z-scan as fallback and judge.
+//
+// The paper lists machine-learning inference as a plug-in for the real-time
+// pipeline (Sec. VIII, future work).  Built here for 256 x 256 holograms:
+//   - spectrum crop: log(1 + |DFT2(h - mean)|), 64 x 64 centred on DC,
+//     standardised per crop (the network input, stored fp16);
+//   - z-scan: the +1-order sub-band (64 x 64 bins around the carrier at
+//     (-1/4, -1/4) cycles/pixel, masked to radius 0.1 cycles/pixel) times
+//     H_{-z_c} at the demodulated object frequencies, inverse FFT at 64 x 64,
+//     sharpness = variance of the forward-difference gradient magnitude of
+//     the amplitude, argmax over the candidates (ties to the lowest z);
+//   - CNN: conv3x3(1->32) ReLU, 3 x [conv3x3(32->32) ReLU], global average
+//     pooling, FC(32->64) ReLU, FC(64->2) = (z, log sigma^2); Gaussian NLL;
+//     Adam.  Forward, backward-data, backward-weight, head and optimizer are
+//     hand-written FP32 kernels; weight-gradient partial sums are reduced in
+//     a fixed order (deterministic);
+//   - training holograms synthesised on the GPU: counter-based noise
+//     (Philox4x32-10, Salmon et al., SC'11) band-limited by a circular pupil
+//     through the library's own FFT passes, a disk mask, propagation by
+//     hv_propagate, an off-axis reference, and photon noise.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "fft_lds.h"
+#include "hv_ctx.h"
+#include "hv_internal.h"
+
+using namespace hvk;
+using hvi::fail;
+
+namespace {
+
+constexpr int AN = 256;   // hologram side
+constexpr int CROP = 64;  // network input side
+constexpr int SUB = 64;   // scan sub-band side
+constexpr int NCH = 32;   // conv channels
+constexpr int HW = CROP * CROP;
+constexpr int NPARAM = 30306;
+constexpr int OFF_W[4] = {0, 320, 9568, 18816};
+constexpr int OFF_B[4] = {288, 9536, 18784, 28032};
+constexpr int OFF_FC1W = 28064, OFF_FC1B = 30112, OFF_FC2W = 30176, OFF_FC2B = 30304;
+constexpr int HEAD_N = 2048 + 64 + 128 + 2;  // fc1 w, fc1 b, fc2 w, fc2 b
+
+__device__ inline float to_f(float v) { return v; }
+__device__ inline float to_f(_Float16 v) { return (float)v; }
+
+// ------------------------------------------------------------------ block reduction (double)
+template <int NT>
+__device__ inline double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ spectrum crop
+// t1: row half-spectra [n][128][256] (column 0 packs the real DC and Nyquist columns).
+template <typename TOUT>
+__global__ __launch_bounds__(512) void k_af_crop(const float2* __restrict__ t1, TOUT* __restrict__ out) {
+  constexpr int NT = 512, NB = 33, S = lds_stride(AN);
+  __shared__ float2 buf[NB * S];
+  __shared__ float2 tw[AN];
+  __shared__ float vals[HW];
+  __shared__ double red[NT];
+  const int tid = threadIdx.x;
+  const long n = blockIdx.x;
+  fill_twiddles<AN>(tw, tid, NT);
+  const float2* src = t1 + n * (AN / 2) * AN;
+  for (int q = tid; q < NB * AN; q += NT) buf[(q / AN) * S + skew(q % AN)] = src[q];
+  __syncthreads();
+  fft_lds<AN, NB, NT, -1>(buf, tw, tid);
+  double s1 = 0.0, s2 = 0.0;
+  for (int q = tid; q < HW; q += NT) {
+    const int fy = q / CROP - CROP / 2, fx = q % CROP - CROP / 2;
+    int col, row;
+    if (fx >= 0) {
+      col = fx;
+      row = fy & (AN - 1);
+    } else {  // |X(fx, fy)| = |X(-fx, -fy)| for a real hologram
+      col = -fx;
+      row = (-fy) & (AN - 1);
+    }
+    float mag;
+    if (col == 0) {
+      const float2 a = buf[skew(row)], b = buf[skew((AN - row) & (AN - 1))];
+      const float re = 0.5f * (a.x + b.x), im = 0.5f * (a.y - b.y);
+      mag = row == 0 ? 0.f : sqrtf(re * re + im * im);  // DC removed with the mean
+    } else {
+      const float2 a = buf[col * S + skew(row)];
+      mag = sqrtf(a.x * a.x + a.y * a.y);
+    }
+    const float v = log1pf(mag);
+    vals[q] = v;
+    s1 += v;
+    s2 += (double)v * v;
+  }
+  s1 = block_sum<NT>(s1, red);
+  s2 = block_sum<NT>(s2, red);
+  const double mean = s1 / HW;
+  const double sd = sqrt(fmax(s2 / HW - mean * mean, 1e-30));
+  const float m = (float)mean, inv = (float)(1.0 / sd);
+  for (int q = tid; q < HW; q += NT) out[n * HW + q] = (TOUT)((vals[q] - m) * inv);
+}
+
+// ------------------------------------------------------------------ scan
+// Masked +1-order sub-band: bins ky = i - 96, kx = j - 96 (i, j < 64), read
+// through Hermitian symmetry from columns 96 - j and rows 96 - i.
+__global__ __launch_bounds__(512) void k_af_subband(const float2* __restrict__ t1, float2* __restrict__ sub) {
+  constexpr int NT = 512, NB = 32, S = lds_stride(AN);
+  __shared__ float2 buf[NB * S];
+  __shared__ float2 tw[AN];
+  const int tid = threadIdx.x;
+  const long n = blockIdx.x;
+  fill_twiddles<AN>(tw, tid, NT);
+  for (int half = 0; half < 2; ++half) {
+    const int c0 = 33 + 32 * half;
+    const float2* src = t1 + n * (AN / 2) * AN + (long)c0 * AN;
+    for (int q = tid; q < NB * AN; q += NT) buf[(q / AN) * S + skew(q % AN)] = src[q];
+    __syncthreads();
+    fft_lds<AN, NB, NT, -1>(buf, tw, tid);
+    for (int q = tid; q < SUB * SUB; q += NT) {
+      const int i = q / SUB, j = q % SUB;
+      const int col = 96 - j;
+      if (col < c0 || col >= c0 + NB) continue;
+      const int di = i - SUB / 2, dj = j - SUB / 2;
+      float2 v = make_float2(0.f, 0.f);
+      if (100 * (di * di + dj * dj) <= AN * AN) {  // radius 0.1 cycles/pixel
+        const float2 a = buf[(col - c0) * S + skew(96 - i)];
+        v = make_float2(a.x, -a.y);
+      }
+      sub[n * SUB * SUB + q] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Sharpness of the reconstruction for CPB candidates per block.
+template <int CPB>
+__global__ __launch_bounds__(256) void k_af_scan(const float2* __restrict__ sub, const float2* __restrict__ htab,
+                                                 int nc, float* __restrict__ scores) {
+  constexpr int NT = 256, S = lds_stride(SUB);
+  __shared__ float2 A[SUB * S];
+  __shared__ float2 B[SUB * S];
+  __shared__ float2 tw[SUB];
+  __shared__ double red[NT];
+  const int tid = threadIdx.x;
+  const long n = blockIdx.x;
+  fill_twiddles<SUB>(tw, tid, NT);
+  const float2* sv = sub + n * SUB * SUB;
+  for (int cc = 0; cc < CPB; ++cc) {
+    const int c = blockIdx.y * CPB + cc;
+    if (c >= nc) break;
+    const float2* h = htab + (long)c * SUB * SUB;
+    for (int q = tid; q < SUB * SUB; q += NT) A[(q / SUB) * S + skew(q % SUB)] = c2::mul(sv[q], h[q]);
+    __syncthreads();
+    fft_lds<SUB, SUB, NT, +1>(A, tw, tid);  // rows
+    for (int q = tid; q < SUB * SUB; q += NT) {
+      const int i = q / SUB, j = q % SUB;
+      B[j * S + skew(i)] = A[i * S + skew(j)];
+    }
+    __syncthreads();
+    fft_lds<SUB, SUB, NT, +1>(B, tw, tid);  // columns
+    constexpr float inv = 1.0f / (SUB * SUB);
+    double s1 = 0.0, s2 = 0.0;
+    for (int q = tid; q < (SUB - 1) * (SUB - 1); q += NT) {
+      const int i = q / (SUB - 1), j = q % (SUB - 1);
+      const float2 u = B[j * S + skew(i)], ux = B[(j + 1) * S + skew(i)], uy = B[j * S + skew(i + 1)];
+      const float a = sqrtf(u.x * u.x + u.y * u.y) * inv;
+      const float ax = sqrtf(ux.x * ux.x + ux.y * ux.y) * inv;
+      const float ay = sqrtf(uy.x * uy.x + uy.y * uy.y) * inv;
+      const float gx = ax - a, gy = ay - a;
+      const double g = sqrt((double)gx * gx + (double)gy * gy);
+      s1 += g;
+      s2 += g * g;
+    }
+    s1 = block_sum<NT>(s1, red);
+    s2 = block_sum<NT>(s2, red);
+    if (tid == 0) {
+      const double m = s1 / ((SUB - 1) * (SUB - 1));
+      scores[n * nc + c] = (float)(s2 / ((SUB - 1) * (SUB - 1)) - m * m);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_af_argmax(const float* __restrict__ scores, int n, int nc, double z_lo, double z_hi,
+                            float* __restrict__ z_out, float* __restrict__ best) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int arg = 0;
+  float bs = scores[(long)i * nc];
+  for (int c = 1; c < nc; ++c) {
+    const float s = scores[(long)i * nc + c];
+    if (s > bs) {
+      bs = s;
+      arg = c;
+    }
+  }
+  z_out[i] = (float)(z_lo + (z_hi - z_lo) * arg / (nc - 1));
+  if (best) best[i] = bs;
+}
+
+// ------------------------------------------------------------------ CNN: convolution
+// Direct 3x3 convolution, zero padding 1, on one 16 x 16 output tile of one
+// sample; wave w produces output channels 8w..8w+7 (weights are wave-uniform
+// and come through the scalar cache), each lane 4 pixels.
+//   MODE 0 (forward):   out = ReLU(b + W * in)
+//   MODE 1 (input grad): out = W^T(flipped) * (in masked by mask > 0)
+template <int CIN, typename TIN, int MODE>
+__global__ __launch_bounds__(256) void k_conv(const TIN* __restrict__ in, const float* __restrict__ mask,
+                                              const float* __restrict__ params, int woff, int boff,
+                                              float* __restrict__ out) {
+  __shared__ float tile[CIN][18][19];
+  const int tid = threadIdx.x;
+  const int ty0 = (blockIdx.x >> 2) * 16, tx0 = (blockIdx.x & 3) * 16;
+  const long b = blockIdx.y;
+  for (int q = tid; q < CIN * 324; q += 256) {
+    const int c = q / 324, r = (q % 324) / 18, col = q % 18;
+    const int y = ty0 + r - 1, x = tx0 + col - 1;
+    float v = 0.f;
+    if (y >= 0 && y < CROP && x >= 0 && x < CROP) {
+      const long idx = ((b * CIN + c) * CROP + y) * CROP + x;
+      v = to_f(in[idx]);
+      if (MODE == 1 && !(mask[idx] > 0.f)) v = 0.f;
+    }
+    tile[c][r][col] = v;
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  float acc[8][4];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[k][p] = 0.f;
+  for (int c = 0; c < CIN; ++c) {
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        float xv[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int idx = lane + 64 * p;
+          xv[p] = tile[c][(idx >> 4) + dy][(idx & 15) + dx];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int o = 8 * wave + k;
+          const float w = MODE == 0 ? params[woff + ((o * CIN + c) * 3 + dy) * 3 + dx]
+                                    : params[woff + ((c * NCH + o) * 3 + (2 - dy)) * 3 + (2 - dx)];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) acc[k][p] += w * xv[p];
+        }
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int o = 8 * wave + k;
+    const float bias = MODE == 0 ? params[boff + o] : 0.f;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int idx = lane + 64 * p;
+      const int y = ty0 + (idx >> 4), x = tx0 + (idx & 15);
+      float v = acc[k][p] + bias;
+      if (MODE == 0) v = fmaxf(v, 0.f);
+      out[((b * NCH + o) * CROP + y) * CROP + x] = v;
+    }
+  }
+}
+
+// Weight and bias gradients of one conv layer, partial over a split of the
+// batch: dW[o][c][tap] = sum dZ[b][o][p] X[b][c][p + tap - 1], dZ = dA [A > 0].
+// Threads t < CIN*9 own (c, tap) for CG output channels; the next CG threads
+// accumulate the bias gradients.
+template <int CIN, typename TIN, int CG>
+__global__ void k_wgrad(const TIN* __restrict__ x, const float* __restrict__ dA, const float* __restrict__ aout,
+                        int bsize, int per_split, float* __restrict__ part_w, float* __restrict__ part_b) {
+  __shared__ float xt[CIN][18][19];
+  __shared__ float dz[256][CG];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int cg = blockIdx.x, split = blockIdx.y;
+  const bool isw = tid < CIN * 9;
+  const int c = tid / 9, tap = tid % 9, dy = tap / 3, dx = tap % 3;
+  const bool isb = tid >= CIN * 9 && tid < CIN * 9 + CG;
+  const int kb = tid - CIN * 9;
+  float acc[CG];
+#pragma unroll
+  for (int k = 0; k < CG; ++k) acc[k] = 0.f;
+  float accb = 0.f;
+  const int b0 = split * per_split, b1 = min(bsize, b0 + per_split);
+  for (int b = b0; b < b1; ++b)
+    for (int tile = 0; tile < 16; ++tile) {
+      const int ty0 = (tile >> 2) * 16, tx0 = (tile & 3) * 16;
+      for (int q = tid; q < CIN * 324; q += nt) {
+        const int cc = q / 324, r = (q % 324) / 18, col = q % 18;
+        const int y = ty0 + r - 1, xx = tx0 + col - 1;
+        float v = 0.f;
+        if (y >= 0 && y < CROP && xx >= 0 && xx < CROP) v = to_f(x[(((long)b * CIN + cc) * CROP + y) * CROP + xx]);
+        xt[cc][r][col] = v;
+      }
+      for (int q = tid; q < 256 * CG; q += nt) {
+        const int p = q / CG, k = q % CG;
+        const long idx = (((long)b * NCH + cg * CG + k) * CROP + ty0 + (p >> 4)) * CROP + tx0 + (p & 15);
+        dz[p][k] = aout[idx] > 0.f ? dA[idx] : 0.f;
+      }
+      __syncthreads();
+      if (isw) {
+        for (int p = 0; p < 256; ++p) {
+          const float xv = xt[c][(p >> 4) + dy][(p & 15) + dx];
+#pragma unroll
+          for (int k = 0; k < CG; ++k) acc[k] += dz[p][k] * xv;
+        }
+      } else if (isb) {
+        for (int p = 0; p < 256; ++p) accb += dz[p][kb];
+      }
+      __syncthreads();
+    }
+  if (isw)
+#pragma unroll
+    for (int k = 0; k < CG; ++k) part_w[((long)(split * NCH + cg * CG + k) * CIN + c) * 9 + tap] = acc[k];
+  if (isb) part_b[split * NCH + cg * CG + kb] = accb;
+}
+
+// Sum of the per-split partials in split order into the gradient vector.
+__global__ void k_wgrad_reduce(const float* __restrict__ part_w, const float* __restrict__ part_b, int splits,
+                               int cin, int woff, int boff, float* __restrict__ grad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nw = NCH * cin * 9;
+  if (i < nw) {
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part_w[(long)k * nw + i];
+    grad[woff + i] = s;
+  } else if (i < nw + NCH) {
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part_b[k * NCH + i - nw];
+    grad[boff + i - nw] = s;
+  }
+}
+
+// ------------------------------------------------------------------ CNN: head
+// Global average pooling, FC(32->64) ReLU, FC(64->2), and for training the
+// Gaussian NLL, the head gradients (per sample) and dA4 = dg / HW.
+template <bool TRAIN>
+__global__ __launch_bounds__(256) void k_head(const float* __restrict__ a4, const float* __restrict__ params,
+                                              const float* __restrict__ zn, int bsize, float* __restrict__ out,
+                                              float* __restrict__ loss_b, float* __restrict__ hpart,
+                                              float* __restrict__ da4) {
+  __shared__ float red[256][NCH + 1];
+  __shared__ float g[NCH], h1[64], dh1[64], outs[2], dout[2], dgs[NCH];
+  const int tid = threadIdx.x;
+  const long b = blockIdx.x;
+  float acc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = 0.f;
+  for (int p = tid; p < HW; p += 256)
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) acc[c] += a4[(b * NCH + c) * HW + p];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) red[tid][c] = acc[c];
+  __syncthreads();
+  if (tid < NCH) {
+    float s = 0.f;
+    for (int t = 0; t < 256; ++t) s += red[t][tid];
+    g[tid] = s / HW;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    float h = params[OFF_FC1B + tid];
+    for (int c = 0; c < NCH; ++c) h += params[OFF_FC1W + tid * NCH + c] * g[c];
+    h1[tid] = fmaxf(h, 0.f);
+  }
+  __syncthreads();
+  if (tid < 2) {
+    float o = params[OFF_FC2B + tid];
+    for (int k = 0; k < 64; ++k) o += params[OFF_FC2W + tid * 64 + k] * h1[k];
+    outs[tid] = o;
+    out[b * 2 + tid] = o;
+  }
+  __syncthreads();
+  if (!TRAIN) return;
+  if (tid == 0) {
+    const float zh = outs[0], s = outs[1];
+    const float r = zn[b] - zh, e = expf(-s);
+    loss_b[b] = 0.5f * (s + r * r * e);
+    dout[0] = -r * e / bsize;
+    dout[1] = 0.5f * (1.f - r * r * e) / bsize;
+  }
+  __syncthreads();
+  float* hp = hpart + b * HEAD_N;
+  if (tid < 128) hp[2048 + 64 + tid] = dout[tid / 64] * h1[tid % 64];
+  if (tid < 2) hp[2048 + 64 + 128 + tid] = dout[tid];
+  if (tid < 64) {
+    const float d = (dout[0] * params[OFF_FC2W + tid] + dout[1] * params[OFF_FC2W + 64 + tid]) *
+                    (h1[tid] > 0.f ? 1.f : 0.f);
+    dh1[tid] = d;
+    hp[2048 + tid] = d;
+  }
+  __syncthreads();
+  for (int q = tid; q < 2048; q += 256) hp[q] = dh1[q / NCH] * g[q % NCH];
+  if (tid < NCH) {
+    float d = 0.f;
+    for (int o = 0; o < 64; ++o) d += dh1[o] * params[OFF_FC1W + o * NCH + tid];
+    dgs[tid] = d / HW;
+  }
+  __syncthreads();
+  for (int q = tid; q < NCH * HW; q += 256) da4[b * NCH * HW + q] = dgs[q / HW];
+}
+
+__global__ void k_head_reduce(const float* __restrict__ hpart, const float* __restrict__ loss_b, int bsize,
+                              float* __restrict__ grad, float* __restrict__ loss) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < HEAD_N) {
+    float s = 0.f;
+    for (int b = 0; b < bsize; ++b) s += hpart[(long)b * HEAD_N + i];
+    grad[OFF_FC1W + i] = s;  // fc1 w, fc1 b, fc2 w, fc2 b are contiguous
+  } else if (i == HEAD_N && loss) {
+    float s = 0.f;
+    for (int b = 0; b < bsize; ++b) s += loss_b[b];
+    *loss = s / bsize;
+  }
+}
+
+__global__ void k_normalize(const float* __restrict__ z, int n, float mean, float inv_scale, float* __restrict__ zn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) zn[i] = (z[i] - mean) * inv_scale;
+}
+
+__global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Prediction in metres: z = mean + scale * z_n, sigma = scale * exp(s / 2).
+__global__ void k_af_denorm(const float* __restrict__ out, int n, float mean, float scale, float* __restrict__ z,
+                            float* __restrict__ sigma) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  z[i] = mean + scale * out[2 * i];
+  if (sigma) sigma[i] = scale * expf(0.5f * out[2 * i + 1]);
+}
+
+__global__ void k_af_scatter(const float* __restrict__ zs, const int* __restrict__ idx, int m, float* __restrict__ z,
+                             int* __restrict__ used) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  z[idx[i]] = zs[i];
+  if (used) used[idx[i]] = 1;
+}
+
+__global__ void k_af_gather(const uint8_t* __restrict__ holo, const int* __restrict__ idx, int m,
+                            uint8_t* __restrict__ dst) {
+  const long n = (long)m * AN * AN / 16;
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+    const long e = q * 16;
+    const long i = e / (AN * AN), off = e % (AN * AN);
+    *reinterpret_cast<uint4*>(dst + e) = *reinterpret_cast<const uint4*>(holo + (long)idx[i] * AN * AN + off);
+  }
+}
+
+// ------------------------------------------------------------------ training-data synthesis
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11): 10 rounds of two 32x32->64 multiplies with the
+// Weyl key schedule.
+__device__ inline uint4 philox(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0, h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
+    c = make_uint4(h1 ^ c.y ^ k.x, l1, h0 ^ c.w ^ k.y, l0);
+    k.x += 0x9E3779B9u;
+    k.y += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Two standard normals from two 32-bit integers (Box-Muller).
+__device__ inline float2 box_muller(uint32_t a, uint32_t b) {
+  const float u1 = ((float)a + 0.5f) * 2.3283064365386963e-10f;
+  const float u2 = ((float)b + 0.5f) * 2.3283064365386963e-10f;
+  const float r = sqrtf(-2.f * logf(u1));
+  float s, c;
+  sincospif(2.f * u2, &s, &c);
+  return make_float2(r * c, r * s);
+}
+
+__global__ void k_af_noise(float2* __restrict__ out, int n, uint64_t seed, long base) {
+  const long total = (long)n * AN * AN;
+  const uint2 key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < total; q += (long)gridDim.x * blockDim.x) {
+    const long h = base + q / (AN * AN);
+    const uint4 r = philox(make_uint4((uint32_t)(q % (AN * AN)), (uint32_t)h, (uint32_t)(h >> 32), 0u), key);
+    out[q] = box_muller(r.x, r.y);
+  }
+}
+
+// Multiply by the union of soft disks: mask = max_d 1 / (1 + exp((|r - c_d| - r_d) / 1.5)).
+__global__ void k_af_mask(float2* __restrict__ field, const float* __restrict__ disks, int n) {
+  const long total = (long)n * AN * AN;
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < total; q += (long)gridDim.x * blockDim.x) {
+    const long h = q / (AN * AN);
+    const int p = (int)(q % (AN * AN));
+    const float y = (float)(p / AN), x = (float)(p % AN);
+    const float* d = disks + h * 25;
+    const int nd = (int)d[0];
+    float m = 0.f;
+    for (int i = 0; i < nd; ++i) {
+      const float dy = y - d[1 + 3 * i], dx = x - d[2 + 3 * i];
+      const float dist = sqrtf(dy * dy + dx * dx);
+      m = fmaxf(m, 1.f / (1.f + expf((dist - d[3 + 3 * i]) / 1.5f)));
+    }
+    field[q] = make_float2(field[q].x * m, field[q].y * m);
+  }
+}
+
+// Off-axis hologram of one propagated object wave: reference amplitude
+// 3 x rms, tilt of 1/4 cycle per pixel on both axes, mean 64 DN, photon
+// noise with the normal approximation N(lambda, lambda), clipped to 8 bits.
+__global__ __launch_bounds__(256) void k_af_holo(const float2* __restrict__ w, uint8_t* __restrict__ out,
+                                                 uint64_t seed, long base) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const long h = blockIdx.x;
+  const float2* src = w + h * AN * AN;
+  double e = 0.0;
+  for (int p = tid; p < AN * AN; p += 256) e += (double)src[p].x * src[p].x + (double)src[p].y * src[p].y;
+  e = block_sum<256>(e, red);
+  const float ra = 3.f * (float)sqrt(e / (AN * AN));
+  double it = 0.0;
+  for (int p = tid; p < AN * AN; p += 256) {
+    float s, c;
+    sincospif(0.5f * (float)((p / AN + p % AN) & 3), &s, &c);
+    const float re = ra * c + src[p].x, im = ra * s + src[p].y;
+    it += (double)re * re + (double)im * im;
+  }
+  it = block_sum<256>(it, red);
+  const float scale = (float)(64.0 * (AN * AN) / it);
+  const uint2 key = make_uint2((uint32_t)(seed ^ 0x5bd1e995u), (uint32_t)(seed >> 32));
+  for (int p = tid; p < AN * AN; p += 256) {
+    float s, c;
+    sincospif(0.5f * (float)((p / AN + p % AN) & 3), &s, &c);
+    const float re = ra * c + src[p].x, im = ra * s + src[p].y;
+    const float lam = (re * re + im * im) * scale;
+    const long hh = base + h;
+    const uint4 r = philox(make_uint4((uint32_t)p, (uint32_t)hh, (uint32_t)(hh >> 32), 1u), key);
+    const float nrm = box_muller(r.x, r.y).x;
+    const float v = rintf(lam + sqrtf(lam) * nrm);
+    out[h * AN * AN + p] = (uint8_t)fminf(fmaxf(v, 0.f), 255.f);
+  }
+}
+
+hv_status launched(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HV_ERR_DEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+  return HV_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ model object
+
+struct hv_af_model {
+  hv_ctx* ctx = nullptr;
+  int max_batch = 0;
+  double z_mean = 0, z_scale = 1;
+  int64_t step = 0;
+  float *params = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+  float* act[4] = {nullptr, nullptr, nullptr, nullptr};
+  float *d1 = nullptr, *d2 = nullptr;
+  float *part_w = nullptr, *part_b = nullptr, *hpart = nullptr, *loss_b = nullptr, *out = nullptr, *zn = nullptr;
+  float* loss_tmp = nullptr;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+constexpr int SPLITS = 64;
+
+hv_status dev_alloc(hv_af_model* md, void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) return fail(HV_ERR_NOMEM, "autofocus allocation of %zu bytes failed", bytes);
+  md->owned.push_back(*p);
+  return HV_OK;
+}
+
+// Forward through the four conv layers and the head.
+hv_status forward(hv_af_model* md, const _Float16* crops, int bsz, bool train, hipStream_t st) {
+  const dim3 grid(16, bsz);
+  hipLaunchKernelGGL((k_conv<1, _Float16, 0>), grid, dim3(256), 0, st, crops, nullptr, md->params, OFF_W[0],
+                     OFF_B[0], md->act[0]);
+  for (int l = 1; l < 4; ++l)
+    hipLaunchKernelGGL((k_conv<NCH, float, 0>), grid, dim3(256), 0, st, md->act[l - 1], nullptr, md->params,
+                       OFF_W[l], OFF_B[l], md->act[l]);
+  if (train)
+    hipLaunchKernelGGL(k_head<true>, dim3(bsz), dim3(256), 0, st, md->act[3], md->params, md->zn, bsz, md->out,
+                       md->loss_b, md->hpart, md->d1);
+  else
+    hipLaunchKernelGGL(k_head<false>, dim3(bsz), dim3(256), 0, st, md->act[3], md->params, nullptr, bsz, md->out,
+                       nullptr, nullptr, nullptr);
+  return launched("af forward");
+}
+
+hv_status backward(hv_af_model* md, const _Float16* crops, int bsz, float* grad, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_reduce, dim3((HEAD_N + 1 + 255) / 256), dim3(256), 0, st, md->hpart, md->loss_b, bsz,
+                     grad, loss);
+  const int per = (bsz + SPLITS - 1) / SPLITS;
+  const int splits = (bsz + per - 1) / per;
+  float* dcur = md->d1;   // dA of the current layer's output
+  float* dnext = md->d2;  // receives dA of its input
+  for (int l = 3; l >= 0; --l) {
+    if (l > 0) {
+      hipLaunchKernelGGL((k_wgrad<NCH, float, 8>), dim3(4, splits), dim3(320), 0, st, md->act[l - 1], dcur,
+                         md->act[l], bsz, per, md->part_w, md->part_b);
+      hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
+                         md->part_b, splits, NCH, OFF_W[l], OFF_B[l], grad);
+      hipLaunchKernelGGL((k_conv<NCH, float, 1>), dim3(16, bsz), dim3(256), 0, st, dcur, md->act[l], md->params,
+                         OFF_W[l], 0, dnext);
+      std::swap(dcur, dnext);
+    } else {
+      hipLaunchKernelGGL((k_wgrad<1, _Float16, NCH>), dim3(1, splits), dim3(64), 0, st, crops, dcur, md->act[0],
+                         bsz, per, md->part_w, md->part_b);
+      hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
+                         md->part_b, splits, 1, OFF_W[0], OFF_B[0], grad);
+    }
+  }
+  return launched("af backward");
+}
+
+struct ScanPlan {
+  hvi::DevBuf htab;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ C-ABI
+
+using namespace hvi;
+
+static hv_status af_spectrum(hv_ctx* ctx, const uint8_t* holo, int n, hipStream_t st, float2** t1) {
+  DevBuf& tb = ctx->work(st, 20);
+  hv_status s;
+  if ((s = tb.ensure((size_t)n * (AN / 2) * AN * 8, &ctx->held))) return s;
+  if ((s = launch_row_r2c(holo, HV_U8, tb.ptr, false, n, AN, AN, 1.f, st))) return s;
+  *t1 = (float2*)tb.ptr;
+  return HV_OK;
+}
+
+extern "C" {
+
+int hv_af_nparams(void) { return NPARAM; }
+
+hv_status hv_af_crops(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, void* out, int out_half,
+                      void* hip_stream) {
+  if (!ctx || !holo || !out) return fail(HV_ERR_ARG, "NULL argument");
+  if (ny != AN || nx != AN) return fail(HV_ERR_SHAPE, "autofocus works on 256x256 holograms");
+  if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  hipSetDevice(ctx->device);
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  hipStream_t st = (hipStream_t)hip_stream;
+  float2* t1;
+  hv_status s;
+  if ((s = af_spectrum(ctx, holo, n, st, &t1))) return s;
+  if (out_half)
+    hipLaunchKernelGGL(k_af_crop<_Float16>, dim3(n), dim3(512), 0, st, t1, (_Float16*)out);
+  else
+    hipLaunchKernelGGL(k_af_crop<float>, dim3(n), dim3(512), 0, st, t1, (float*)out);
+  return launched("af_crop");
+}
+
+hv_status hv_af_scan(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, double wavelength_m, double pitch_m,
+                     double z_lo_m, double z_hi_m, int n_candidates, float* z_out, float* scores_out,
+                     void* hip_stream) {
+  if (!ctx || !holo || !z_out) return fail(HV_ERR_ARG, "NULL argument");
+  if (ny != AN || nx != AN) return fail(HV_ERR_SHAPE, "autofocus works on 256x256 holograms");
+  if (n_candidates < 2 || !(z_hi_m > z_lo_m) || !(wavelength_m > 0) || !(pitch_m > 0))
+    return fail(HV_ERR_ARG, "need >= 2 candidates, z_hi > z_lo, positive wavelength and pitch");
+  if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  hipSetDevice(ctx->device);
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  hipStream_t st = (hipStream_t)hip_stream;
+  // transfer-function table per candidate, built in float64 once per setting
+  char key[160];
+  snprintf(key, sizeof key, "afscan %.17g %.17g %.17g %.17g %d", wavelength_m, pitch_m, z_lo_m, z_hi_m,
+           n_candidates);
+  DevBuf& tab = ctx->misc[key];
+  hv_status s;
+  if (!tab.ptr) {
+    std::vector<float2> h((size_t)n_candidates * SUB * SUB);
+    const double il2 = 1.0 / (wavelength_m * wavelength_m);
+    for (int c = 0; c < n_candidates; ++c) {
+      const double zc = z_lo_m + (z_hi_m - z_lo_m) * c / (n_candidates - 1);
+      for (int i = 0; i < SUB; ++i)
+        for (int j = 0; j < SUB; ++j) {
+          const double fy = (i - SUB / 2) / (AN * pitch_m), fx = (j - SUB / 2) / (AN * pitch_m);
+          const double rad = il2 - fx * fx - fy * fy;
+          double re = 0, im = 0;
+          if (rad > 0) {
+            const double ph = -2.0 * M_PI * zc * std::sqrt(rad);
+            re = std::cos(ph);
+            im = std::sin(ph);
+          }
+          h[((size_t)c * SUB + i) * SUB + j] = make_float2((float)re, (float)im);
+        }
+    }
+    if ((s = tab.upload(h.data(), h.size() * sizeof(float2), &ctx->held))) return s;
+  }
+  float2* t1;
+  if ((s = af_spectrum(ctx, holo, n, st, &t1))) return s;
+  DevBuf& sb = ctx->work(st, 21);
+  DevBuf& sc = ctx->work(st, 22);
+  if ((s = sb.ensure((size_t)n * SUB * SUB * 8, &ctx->held))) return s;
+  if ((s = sc.ensure((size_t)n * n_candidates * 4, &ctx->held))) return s;
+  hipLaunchKernelGGL(k_af_subband, dim3(n), dim3(512), 0, st, t1, (float2*)sb.ptr);
+  constexpr int CPB = 8;
+  hipLaunchKernelGGL(k_af_scan<CPB>, dim3(n, (n_candidates + CPB - 1) / CPB), dim3(256), 0, st,
+                     (const float2*)sb.ptr, (const float2*)tab.ptr, n_candidates, (float*)sc.ptr);
+  hipLaunchKernelGGL(k_af_argmax, dim3((n + 255) / 256), dim3(256), 0, st, (const float*)sc.ptr, n, n_candidates,
+                     z_lo_m, z_hi_m, z_out, (float*)nullptr);
+  if (scores_out &&
+      hipMemcpyAsync(scores_out, sc.ptr, (size_t)n * n_candidates * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return fail(HV_ERR_DEVICE, "score copy failed");
+  return launched("af_scan");
+}
+
+hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batch, double z_mean, double z_scale,
+                             hv_af_model** out) {
+  if (!ctx || !init_params || !out) return fail(HV_ERR_ARG, "NULL argument");
+  if (max_batch <= 0 || !(z_scale > 0)) return fail(HV_ERR_ARG, "max_batch and z_scale must be positive");
+  hipSetDevice(ctx->device);
+  *out = nullptr;
+  auto* md = new hv_af_model();
+  md->ctx = ctx;
+  md->max_batch = max_batch;
+  md->z_mean = z_mean;
+  md->z_scale = z_scale;
+  hv_status s;
+  const size_t act = (size_t)max_batch * NCH * HW * 4;
+  const int per = (max_batch + SPLITS - 1) / SPLITS;
+  const int splits = (max_batch + per - 1) / per;
+  auto fail_out = [&](hv_status e) {
+    hv_af_model_destroy(md);
+    return e;
+  };
+  if ((s = dev_alloc(md, (void**)&md->params, NPARAM * 4)) || (s = dev_alloc(md, (void**)&md->m, NPARAM * 4)) ||
+      (s = dev_alloc(md, (void**)&md->v, NPARAM * 4)) || (s = dev_alloc(md, (void**)&md->grad, NPARAM * 4)))
+    return fail_out(s);
+  for (int l = 0; l < 4; ++l)
+    if ((s = dev_alloc(md, (void**)&md->act[l], act))) return fail_out(s);
+  if ((s = dev_alloc(md, (void**)&md->d1, act)) || (s = dev_alloc(md, (void**)&md->d2, act)) ||
+      (s = dev_alloc(md, (void**)&md->part_w, (size_t)splits * NCH * NCH * 9 * 4)) ||
+      (s = dev_alloc(md, (void**)&md->part_b, (size_t)splits * NCH * 4)) ||
+      (s = dev_alloc(md, (void**)&md->hpart, (size_t)max_batch * HEAD_N * 4)) ||
+      (s = dev_alloc(md, (void**)&md->loss_b, (size_t)max_batch * 4)) ||
+      (s = dev_alloc(md, (void**)&md->out, (size_t)max_batch * 8)) ||
+      (s = dev_alloc(md, (void**)&md->zn, (size_t)max_batch * 4)) || (s = dev_alloc(md, (void**)&md->loss_tmp, 4)))
+    return fail_out(s);
+  if (hipMemcpy(md->params, init_params, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(md->m, 0, NPARAM * 4) != hipSuccess || hipMemset(md->v, 0, NPARAM * 4) != hipSuccess)
+    return fail_out(fail(HV_ERR_DEVICE, "model initialisation failed"));
+  *out = md;
+  return HV_OK;
+}
+
+void hv_af_model_destroy(hv_af_model* md) {
+  if (!md) return;
+  hipSetDevice(md->ctx->device);
+  hipDeviceSynchronize();
+  for (void* p : md->owned) hipFree(p);
+  delete md;
+}
+
+hv_status hv_af_model_state(hv_af_model* md, float* params, float* m, float* v, int64_t* step) {
+  if (!md) return fail(HV_ERR_ARG, "NULL model");
+  hipSetDevice(md->ctx->device);
+  hipDeviceSynchronize();
+  if ((params && hipMemcpy(params, md->params, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+      (m && hipMemcpy(m, md->m, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+      (v && hipMemcpy(v, md->v, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess))
+    return fail(HV_ERR_DEVICE, "state copy failed");
+  if (step) *step = md->step;
+  return HV_OK;
+}
+
+hv_status hv_af_model_load(hv_af_model* md, const float* params, const float* m, const float* v, int64_t step) {
+  if (!md || !params) return fail(HV_ERR_ARG, "NULL argument");
+  hipSetDevice(md->ctx->device);
+  hipDeviceSynchronize();
+  if (hipMemcpy(md->params, params, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      (m && hipMemcpy(md->m, m, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+      (v && hipMemcpy(md->v, v, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess))
+    return fail(HV_ERR_DEVICE, "state upload failed");
+  md->step = step;
+  return HV_OK;
+}
+
+hv_status hv_af_forward(hv_af_model* md, const void* crops, int batch, float* out, void* hip_stream) {
+  if (!md || !crops || !out) return fail(HV_ERR_ARG, "NULL argument");
+  if (batch <= 0 || batch > md->max_batch) return fail(HV_ERR_SHAPE, "batch %d outside [1, %d]", batch, md->max_batch);
+  hipSetDevice(md->ctx->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hv_status s = forward(md, (const _Float16*)crops, batch, false, st);
+  if (s) return s;
+  if (hipMemcpyAsync(out, md->out, (size_t)batch * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return fail(HV_ERR_DEVICE, "output copy failed");
+  return HV_OK;
+}
+
+hv_status hv_af_loss_grad(hv_af_model* md, const void* crops, const float* z_m, int batch, float* loss, float* grad,
+                          void* hip_stream) {
+  if (!md || !crops || !z_m || !grad) return fail(HV_ERR_ARG, "NULL argument");
+  if (batch <= 0 || batch > md->max_batch) return fail(HV_ERR_SHAPE, "batch %d outside [1, %d]", batch, md->max_batch);
+  hipSetDevice(md->ctx->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(k_normalize, dim3((batch + 255) / 256), dim3(256), 0, st, z_m, batch, (float)md->z_mean,
+                     (float)(1.0 / md->z_scale), md->zn);
+  hv_status s = forward(md, (const _Float16*)crops, batch, true, st);
+  if (s) return s;
+  return backward(md, (const _Float16*)crops, batch, grad, loss, st);
+}
+
+hv_status hv_af_train_step(hv_af_model* md, const void* crops, const float* z_m, int batch, float lr, float* loss,
+                           void* hip_stream) {
+  hv_status s = hv_af_loss_grad(md, crops, z_m, batch, loss ? loss : md->loss_tmp, md->grad, hip_stream);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  md->step += 1;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)md->step));
+  const float c2 = (float)(1.0 - std::pow(0.999, (double)md->step));
+  hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, md->params, md->m, md->v, md->grad,
+                     NPARAM, lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+  return launched("adam");
+}
+
+hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wavelength_m, double pitch_m, float tau_m,
+                        float* z_out, float* sigma_out, int* used_fallback, int* n_fallback, void* hip_stream) {
+  if (!md || !holo || !z_out) return fail(HV_ERR_ARG, "NULL argument");
+  if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  hv_ctx* ctx = md->ctx;
+  hipSetDevice(ctx->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  DevBuf& cb = ctx->work(st, 23);
+  DevBuf& sg = ctx->work(st, 24);
+  hv_status s;
+  if ((s = cb.ensure((size_t)md->max_batch * HW * 2, &ctx->held))) return s;
+  if ((s = sg.ensure((size_t)n * 4, &ctx->held))) return s;
+  float* sigma = sigma_out ? sigma_out : (float*)sg.ptr;
+  if (used_fallback && hipMemsetAsync(used_fallback, 0, (size_t)n * sizeof(int), st) != hipSuccess)
+    return fail(HV_ERR_DEVICE, "memset failed");
+  for (int b0 = 0; b0 < n; b0 += md->max_batch) {
+    const int bs = std::min(md->max_batch, n - b0);
+    if ((s = hv_af_crops(ctx, holo + (size_t)b0 * AN * AN, bs, AN, AN, cb.ptr, 1, st))) return s;
+    if ((s = forward(md, (const _Float16*)cb.ptr, bs, false, st))) return s;
+    hipLaunchKernelGGL(k_af_denorm, dim3((bs + 255) / 256), dim3(256), 0, st, md->out, bs, (float)md->z_mean,
+                       (float)md->z_scale, z_out + b0, sigma + b0);
+  }
+  // fallback: the scan for every hologram whose predicted sigma exceeds tau
+  std::vector<float> hs(n);
+  if (hipMemcpyAsync(hs.data(), sigma, (size_t)n * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(HV_ERR_DEVICE, "sigma copy failed");
+  std::vector<int> idx;
+  for (int i = 0; i < n; ++i)
+    if (!(hs[i] <= tau_m)) idx.push_back(i);
+  if (n_fallback) *n_fallback = (int)idx.size();
+  if (idx.empty()) return HV_OK;
+  const int m = (int)idx.size();
+  DevBuf& ib = ctx->work(st, 25);
+  DevBuf& gb = ctx->work(st, 26);
+  DevBuf& zb = ctx->work(st, 27);
+  if ((s = ib.ensure((size_t)m * 4, &ctx->held)) || (s = gb.ensure((size_t)m * AN * AN, &ctx->held)) ||
+      (s = zb.ensure((size_t)m * 4, &ctx->held)))
+    return s;
+  if (hipMemcpyAsync(ib.ptr, idx.data(), (size_t)m * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail(HV_ERR_DEVICE, "index copy failed");
+  hipLaunchKernelGGL(k_af_gather, dim3(std::min(4096, (m * AN * AN / 16 + 255) / 256)), dim3(256), 0, st, holo,
+                     (const int*)ib.ptr, m, (uint8_t*)gb.ptr);
+  if ((s = hv_af_scan(ctx, (const uint8_t*)gb.ptr, m, AN, AN, wavelength_m, pitch_m, 0.05, 0.5, 128,
+                      (float*)zb.ptr, nullptr, st)))
+    return s;
+  hipLaunchKernelGGL(k_af_scatter, dim3((m + 255) / 256), dim3(256), 0, st, (const float*)zb.ptr,
+                     (const int*)ib.ptr, m, z_out, used_fallback);
+  hipStreamSynchronize(st);  // the host index vector must outlive the copy
+  return launched("af_predict");
+}
+
+hv_status hv_af_synthesize(hv_ctx* ctx, int n, const double* z_m, double wavelength_m, double pitch_m, uint64_t seed,
+                           int64_t index_base, uint8_t* out, void* hip_stream) {
+  if (!ctx || !z_m || !out) return fail(HV_ERR_ARG, "NULL argument");
+  if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  hipSetDevice(ctx->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  constexpr int CH = 128;  // holograms per chunk
+  hv_status s;
+  DevBuf& fa = ctx->work(st, 30);
+  DevBuf& fb = ctx->work(st, 31);
+  DevBuf& db = ctx->work(st, 32);
+  if ((s = fa.ensure((size_t)CH * AN * AN * 8, &ctx->held)) || (s = fb.ensure((size_t)CH * AN * AN * 8, &ctx->held)) ||
+      (s = db.ensure((size_t)CH * 25 * 4, &ctx->held)))
+    return s;
+  // pupil of radius 0.09 cycles/pixel as a column-major transfer table (1/ny folded in)
+  DevBuf& pup = ctx->misc["afpupil"];
+  if (!pup.ptr) {
+    std::vector<float2> t((size_t)AN * AN);
+    for (int cx = 0; cx < AN; ++cx)
+      for (int cy = 0; cy < AN; ++cy) {
+        const double fx = (cx < AN / 2 ? cx : cx - AN) / (double)AN, fy = (cy < AN / 2 ? cy : cy - AN) / (double)AN;
+        t[(size_t)cx * AN + cy] = make_float2(fx * fx + fy * fy <= 0.09 * 0.09 ? 1.0f / AN : 0.f, 0.f);
+      }
+    if ((s = pup.upload(t.data(), t.size() * 8, &ctx->held))) return s;
+  }
+  DevBuf& tb = ctx->work(st, 33);
+  if ((s = tb.ensure((size_t)CH * AN * AN * 8, &ctx->held))) return s;
+  std::vector<float> disks((size_t)CH * 25);
+  for (int c0 = 0; c0 < n; c0 += CH) {
+    const int cn = std::min(CH, n - c0);
+    const long base = index_base + c0;
+    for (int i = 0; i < cn; ++i) {
+      std::mt19937_64 rng(seed * 0x9E3779B97F4A7C15ull + (uint64_t)(base + i));
+      std::uniform_int_distribution<int> nd(3, 8);
+      std::uniform_real_distribution<float> cpos(32.f, AN - 32.f), rad(8.f, 48.f);
+      float* d = &disks[(size_t)i * 25];
+      d[0] = (float)nd(rng);
+      for (int k = 0; k < 8; ++k) {
+        d[1 + 3 * k] = cpos(rng);
+        d[2 + 3 * k] = cpos(rng);
+        d[3 + 3 * k] = rad(rng);
+      }
+    }
+    if (hipMemcpyAsync(db.ptr, disks.data(), (size_t)cn * 25 * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+      return fail(HV_ERR_DEVICE, "disk upload failed");
+    hipLaunchKernelGGL(k_af_noise, dim3(2048), dim3(256), 0, st, (float2*)fa.ptr, cn, seed, base);
+    // band-limit: row FFT, column FFT x pupil x inverse column FFT, inverse row FFT
+    if ((s = launch_rows_c2c(fa.ptr, HV_C64, tb.ptr, false, nullptr, nullptr, -1, cn, AN, AN, 1.f, st))) return s;
+    if ((s = launch_col_full(tb.ptr, fb.ptr, false, (const float2*)pup.ptr, cn, AN, AN, st))) return s;
+    if ((s = launch_row_inv(fb.ptr, false, fa.ptr, false, cn, AN, AN, 1.f / AN, st))) return s;
+    hipLaunchKernelGGL(k_af_mask, dim3(2048), dim3(256), 0, st, (float2*)fa.ptr, (const float*)db.ptr, cn);
+    // propagate by +z, one call per run of equal distances
+    for (int i = 0; i < cn;) {
+      int j = i + 1;
+      while (j < cn && z_m[c0 + j] == z_m[c0 + i]) ++j;
+      hv_optics op{wavelength_m, pitch_m, pitch_m, z_m[c0 + i], HV_AS};
+      if ((s = hv_propagate(ctx, (const float2*)fa.ptr + (size_t)i * AN * AN, HV_C64, j - i, AN, AN, &op,
+                            HV_PREC_FP32, (float2*)fb.ptr + (size_t)i * AN * AN, st)))
+        return s;
+      i = j;
+    }
+    hipLaunchKernelGGL(k_af_holo, dim3(cn), dim3(256), 0, st, (const float2*)fb.ptr, out + (size_t)c0 * AN * AN,
+                       seed, base);
+    if ((s = launched("af_synthesize"))) return s;
+    hipStreamSynchronize(st);  // the host disk table is reused by the next chunk
+  }
+  return HV_OK;
+}
+
+}  // extern "C"

@@ -86,6 +86,7 @@ struct Ctx {
   std::map<OptKey, std::unique_ptr<FresnelPlan>> fr_plans;
   std::map<std::tuple<int, std::vector<int>, std::vector<double>>, std::unique_ptr<DftPlan>> dft_plans;
   std::map<std::pair<void*, int>, DevBuf> ws;
+  std::map<std::string, DevBuf> misc;  // other float64-built tables (autofocus)
 
   AsPlan* as_plan(int ny, int nx, const hv_optics& o, hv_status* st);
   FresnelPlan* fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st);

@@ -106,6 +106,20 @@ _sig = {
     "hv_ctx_stats": (_I, [_P, C.POINTER(hv_stats)]),
     "hv_ctx_stats_reset": (_I, [_P]),
     "hv_replay_run": (_I, [_P, C.POINTER(hv_replay_config), C.POINTER(hv_replay_result)]),
+    "hv_af_nparams": (_I, []),
+    "hv_af_crops": (_I, [_P, _P, _I, _I, _I, _P, _I, _P]),
+    "hv_af_scan": (_I, [_P, _P, _I, _I, _I, C.c_double, C.c_double, C.c_double, C.c_double, _I, _P, _P, _P]),
+    "hv_af_model_create": (_I, [_P, C.POINTER(C.c_float), _I, C.c_double, C.c_double, C.POINTER(_P)]),
+    "hv_af_model_destroy": (None, [_P]),
+    "hv_af_model_state": (_I, [_P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float),
+                               C.POINTER(C.c_int64)]),
+    "hv_af_model_load": (_I, [_P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int64]),
+    "hv_af_forward": (_I, [_P, _P, _I, _P, _P]),
+    "hv_af_loss_grad": (_I, [_P, _P, _P, _I, _P, _P, _P]),
+    "hv_af_train_step": (_I, [_P, _P, _P, _I, C.c_float, _P, _P]),
+    "hv_af_predict": (_I, [_P, _P, _I, C.c_double, C.c_double, C.c_float, _P, _P, _P, C.POINTER(_I), _P]),
+    "hv_af_synthesize": (_I, [_P, _I, C.POINTER(C.c_double), C.c_double, C.c_double, C.c_uint64, C.c_int64, _P,
+                              _P]),
     "hv_pca": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _I, _I, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -359,3 +373,104 @@ class Stream:
         if self.handle:
             _check(lib.hv_stream_close(self.handle))
             self.handle = None
+
+
+    # ---------------------------------------------------------------- autofocus
+    def hv_af_crops(self, holo: torch.Tensor, half: bool = True) -> torch.Tensor:
+        n, ny, nx = _frames(holo)
+        out = torch.empty((n, 64, 64), dtype=torch.float16 if half else torch.float32, device=holo.device)
+        _check(lib.hv_af_crops(self.handle, _ptr(holo), n, ny, nx, _ptr(out), int(half), _stream(holo.device)))
+        return out
+
+    def hv_af_scan(self, holo: torch.Tensor, wavelength: float, pitch: float, z_lo: float = 0.05,
+                   z_hi: float = 0.5, n_candidates: int = 128, want_scores: bool = False):
+        n, ny, nx = _frames(holo)
+        z = torch.empty(n, dtype=torch.float32, device=holo.device)
+        sc = torch.empty((n, n_candidates), dtype=torch.float32, device=holo.device) if want_scores else None
+        _check(lib.hv_af_scan(self.handle, _ptr(holo), n, ny, nx, wavelength, pitch, z_lo, z_hi, n_candidates,
+                              _ptr(z), _ptr(sc), _stream(holo.device)))
+        return z, sc
+
+    def hv_af_synthesize(self, z_m, wavelength: float, pitch: float, seed: int, index_base: int = 0):
+        import numpy as np
+        z = np.ascontiguousarray(np.asarray(z_m, dtype=np.float64))
+        n = z.shape[0]
+        out = torch.empty((n, 256, 256), dtype=torch.uint8, device=self._dev())
+        _check(lib.hv_af_synthesize(self.handle, n, z.ctypes.data_as(C.POINTER(C.c_double)), wavelength, pitch,
+                                    seed, index_base, _ptr(out), _stream(out.device)))
+        return out
+
+    def af_model(self, init_params, max_batch: int, z_mean: float, z_scale: float) -> "AfModel":
+        return AfModel(self, init_params, max_batch, z_mean, z_scale)
+
+
+def af_nparams() -> int:
+    return lib.hv_af_nparams()
+
+
+class AfModel:
+    """hv_af_model: the autofocus CNN with its Adam state on the device."""
+
+    def __init__(self, ctx: Context, init_params, max_batch: int, z_mean: float, z_scale: float):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(init_params, dtype=np.float32))
+        if p.size != af_nparams():
+            raise ValueError(f"expected {af_nparams()} parameters, got {p.size}")
+        h = C.c_void_p()
+        _check(lib.hv_af_model_create(ctx.handle, p.ctypes.data_as(C.POINTER(C.c_float)), max_batch, z_mean,
+                                      z_scale, C.byref(h)))
+        self.ctx, self.handle, self.max_batch = ctx, h, max_batch
+
+    def close(self):
+        if self.handle:
+            lib.hv_af_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, crops: torch.Tensor) -> torch.Tensor:
+        out = torch.empty((crops.shape[0], 2), dtype=torch.float32, device=crops.device)
+        _check(lib.hv_af_forward(self.handle, _ptr(crops), crops.shape[0], _ptr(out), _stream(crops.device)))
+        return out
+
+    def loss_grad(self, crops: torch.Tensor, z_m: torch.Tensor):
+        loss = torch.empty(1, dtype=torch.float32, device=crops.device)
+        grad = torch.empty(af_nparams(), dtype=torch.float32, device=crops.device)
+        _check(lib.hv_af_loss_grad(self.handle, _ptr(crops), _ptr(z_m), crops.shape[0], _ptr(loss), _ptr(grad),
+                                   _stream(crops.device)))
+        return loss, grad
+
+    def train_step(self, crops: torch.Tensor, z_m: torch.Tensor, lr: float, loss: torch.Tensor = None):
+        _check(lib.hv_af_train_step(self.handle, _ptr(crops), _ptr(z_m), crops.shape[0], lr, _ptr(loss),
+                                    _stream(crops.device)))
+        return loss
+
+    def state(self):
+        import numpy as np
+        n = af_nparams()
+        p, m, v = (np.empty(n, np.float32) for _ in range(3))
+        step = C.c_int64(0)
+        f = C.POINTER(C.c_float)
+        _check(lib.hv_af_model_state(self.handle, p.ctypes.data_as(f), m.ctypes.data_as(f), v.ctypes.data_as(f),
+                                     C.byref(step)))
+        return {"params": p, "m": m, "v": v, "step": step.value}
+
+    def load(self, state):
+        import numpy as np
+        f = C.POINTER(C.c_float)
+        arrs = [np.ascontiguousarray(np.asarray(state[k], np.float32)) for k in ("params", "m", "v")]
+        _check(lib.hv_af_model_load(self.handle, *[a.ctypes.data_as(f) for a in arrs], int(state["step"])))
+
+    def predict(self, holo: torch.Tensor, wavelength: float, pitch: float, tau: float):
+        n = holo.shape[0]
+        z = torch.empty(n, dtype=torch.float32, device=holo.device)
+        sig = torch.empty(n, dtype=torch.float32, device=holo.device)
+        used = torch.empty(n, dtype=torch.int32, device=holo.device)
+        nf = C.c_int(0)
+        _check(lib.hv_af_predict(self.handle, _ptr(holo), n, wavelength, pitch, tau, _ptr(z), _ptr(sig),
+                                 _ptr(used), C.byref(nf), _stream(holo.device)))
+        return z, sig, used, nf.value

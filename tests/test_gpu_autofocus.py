@@ -1,0 +1,179 @@
+"""Autofocus on the GPU against the FP64 oracle, and what the trained network
+gains over the scan alone."""
+
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import autofocus as oaf
+from synth.autofocus import af_hologram
+from tests.conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+LAM, PITCH = 852e-9, 20e-6
+Z_MEAN, Z_SCALE = 0.275, 0.45 / np.sqrt(12)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx(hv):
+    c = hv.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def holos():
+    zs = [0.07, 0.16, 0.24, 0.31, 0.38, 0.46]
+    return np.stack([af_hologram(z, 70 + i) for i, z in enumerate(zs)]), np.array(zs)
+
+
+def test_crops_match_oracle(ctx, holos):
+    say("autofocus crops")
+    h, _ = holos
+    hd = torch.from_numpy(h).cuda()
+    c32 = ctx.hv_af_crops(hd, half=False).cpu().numpy()
+    c16 = ctx.hv_af_crops(hd, half=True).float().cpu().numpy()
+    ref = np.stack([oaf.spectrum_crop(x) for x in h])
+    assert rel_l2(c32, ref) < 1e-5
+    assert rel_l2(c16, ref) < 1e-3
+
+
+def test_scan_matches_oracle(ctx, holos):
+    say("autofocus scan")
+    h, ztrue = holos
+    zc = oaf.candidates()
+    z, sc = ctx.hv_af_scan(torch.from_numpy(h).cuda(), LAM, PITCH, want_scores=True)
+    z, sc = z.cpu().numpy(), sc.cpu().numpy()
+    for i in range(len(h)):
+        ref = oaf.scan_scores(h[i], LAM, PITCH, zc)
+        assert rel_l2(sc[i], ref) < 1e-4
+        top = np.sort(ref)[::-1]
+        if (top[0] - top[1]) / top[0] > 1e-3:  # a clear maximum must be found exactly
+            assert np.isclose(z[i], zc[np.argmax(ref)], atol=1e-6)
+    assert np.median(np.abs(z - ztrue)) < 0.01
+
+
+def _crops_and_labels(seed, b):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((b, 64, 64)).astype(np.float16)
+    z = rng.uniform(0.05, 0.5, b).astype(np.float32)
+    return x, z
+
+
+@pytest.fixture(scope="module")
+def init():
+    return oaf.init_params(11).astype(np.float32)
+
+
+def test_forward_loss_grad_match_oracle(ctx, hv, init):
+    say("CNN forward / backward vs oracle")
+    b = 6
+    x, z = _crops_and_labels(1, b)
+    m = ctx.af_model(init, b, Z_MEAN, Z_SCALE)
+    xd, zd = torch.from_numpy(x).cuda(), torch.from_numpy(z).cuda()
+    out = m.forward(xd).cpu().numpy()
+    th = init.astype(np.float64)
+    xin = x.astype(np.float64)[:, None]
+    ref_out, _ = oaf.forward(th, xin)
+    assert rel_l2(out, ref_out) < 1e-5
+    loss, grad = m.loss_grad(xd, zd)
+    zn = (z.astype(np.float64) - Z_MEAN) / Z_SCALE
+    ref_loss, ref_grad = oaf.loss_and_grad(th, xin, zn)
+    assert abs(loss.item() - ref_loss) / abs(ref_loss) < 1e-5
+    g = grad.cpu().numpy()
+    offs = np.cumsum([0] + [int(np.prod(s)) for s in oaf.param_shapes()])
+    for a, bb in zip(offs[:-1], offs[1:]):
+        assert rel_l2(g[a:bb], ref_grad[a:bb]) < 1e-4, (a, bb)
+    m.close()
+
+
+def test_adam_step_and_checkpoint(ctx, hv, init):
+    say("Adam step, state round trip")
+    b = 4
+    x, z = _crops_and_labels(2, b)
+    xd, zd = torch.from_numpy(x).cuda(), torch.from_numpy(z).cuda()
+    m = ctx.af_model(init, b, Z_MEAN, Z_SCALE)
+    _, g = m.loss_grad(xd, zd)
+    g = g.cpu().numpy().astype(np.float64)
+    m.train_step(xd, zd, 1e-3)
+    st = m.state()
+    want, mm, vv = oaf.adam(init.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, lr=1e-3)
+    assert st["step"] == 1
+    assert np.max(np.abs(st["params"] - want)) < 1e-6
+    assert rel_l2(st["m"], mm) < 1e-6 and rel_l2(st["v"], vv) < 1e-5
+    m2 = ctx.af_model(init, b, Z_MEAN, Z_SCALE)
+    m2.load(st)
+    assert torch.equal(m.forward(xd), m2.forward(xd))
+    m.close()
+    m2.close()
+
+
+def test_synthesis_deterministic(ctx):
+    say("training-hologram synthesis")
+    z = np.repeat([0.12, 0.3, 0.44], 4)
+    a = ctx.hv_af_synthesize(z, LAM, PITCH, seed=5)
+    b = ctx.hv_af_synthesize(z, LAM, PITCH, seed=5)
+    assert torch.equal(a, b)
+    ah = a.cpu().numpy()
+    assert abs(ah.mean() - 64) < 2.0 and (ah == 255).mean() < 1e-3
+    zs, _ = ctx.hv_af_scan(a, LAM, PITCH)
+    assert np.median(np.abs(zs.cpu().numpy() - z)) < 0.02
+
+
+def _dataset(ctx, n, seed, base=0, levels=512):
+    rng = np.random.default_rng(seed)
+    lv = rng.integers(0, levels, n // 16)
+    z = np.repeat(0.05 + 0.45 * (lv + 0.5) / levels, 16)
+    holo = ctx.hv_af_synthesize(z, LAM, PITCH, seed=seed, index_base=base)
+    crops = torch.cat([ctx.hv_af_crops(holo[i:i + 1024]) for i in range(0, n, 1024)])
+    return holo, crops, torch.from_numpy(z.astype(np.float32)).cuda()
+
+
+def test_training_gain_over_scan(ctx, hv, init):
+    """Train briefly on holograms of the project's own forward model; the
+    network beats predicting the mean by a wide margin, and with the scan as
+    fallback it matches the scan's accuracy far faster than scanning all."""
+    say("training the autofocus network (short)")
+    holo, crops, z = _dataset(ctx, 16384, seed=123)
+    m = ctx.af_model(init, 256, Z_MEAN, Z_SCALE)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    losses = []
+    g = torch.Generator(device="cuda").manual_seed(0)
+    for step in range(400):
+        idx = torch.randint(0, crops.shape[0], (256,), device="cuda", generator=g)
+        m.train_step(crops[idx].contiguous(), z[idx].contiguous(), 1e-3, loss)
+        if step % 50 == 0 or step == 399:
+            losses.append(loss.item())
+    say(f"  losses {np.round(losses, 3)}")
+    assert losses[-1] < losses[0] - 0.5
+    eh, _, ez = _dataset(ctx, 1024, seed=999, base=10 ** 6)
+    ez = ez.cpu().numpy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    zs, _ = ctx.hv_af_scan(eh, LAM, PITCH)
+    torch.cuda.synchronize()
+    t_scan = time.perf_counter() - t0
+    e_scan = np.abs(zs.cpu().numpy() - ez)
+    zp, sig, used, nfb = m.predict(eh, LAM, PITCH, tau=1e9)  # network only
+    e_net = np.abs(zp.cpu().numpy() - ez)
+    tau = float(np.quantile(sig.cpu().numpy(), 0.9))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    zf, _, used, nfb = m.predict(eh, LAM, PITCH, tau=tau)
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    e_fb = np.abs(zf.cpu().numpy() - ez)
+    base = np.median(np.abs(ez - Z_MEAN))
+    say(f"  median |dz| mm: mean-predictor {1e3 * base:.1f}, net {1e3 * np.median(e_net):.1f}, "
+        f"net+fallback {1e3 * np.median(e_fb):.1f} ({nfb} scans), scan {1e3 * np.median(e_scan):.1f}; "
+        f"time scan {t_scan:.3f}s net+fallback {t_fb:.3f}s")
+    assert np.median(e_net) < 0.5 * base
+    assert nfb <= 0.15 * len(ez)
+    m.close()
