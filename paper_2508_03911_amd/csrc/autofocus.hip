@@ -756,8 +756,8 @@ hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batc
   md->z_scale = z_scale;
   hv_status s;
   const size_t act = (size_t)max_batch * NCH * HW * 4;
-  const int per = (max_batch + SPLITS - 1) / SPLITS;
-  const int splits = (max_batch + per - 1) / per;
+  // any batch <= max_batch uses at most SPLITS splits (ceil(b / ceil(b / SPLITS)) <= SPLITS)
+  const int splits = SPLITS;
   auto fail_out = [&](hv_status e) {
     hv_af_model_destroy(md);
     return e;
