@@ -440,14 +440,16 @@ __global__ void k_normalize(const float* __restrict__ z, int n, float mean, floa
   if (i < n) zn[i] = (z[i] - mean) * inv_scale;
 }
 
+// Adam; om1 = 1 - beta1 and om2 = 1 - beta2 come in already rounded from
+// float64 (1 - 0.999f in float32 would be off by 1.3e-5 relative).
 __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                       const float* __restrict__ g, int n, float lr, float b1, float b2, float eps, float c1,
-                       float c2) {
+                       const float* __restrict__ g, int n, float lr, float b1, float b2, float om1, float om2,
+                       float eps, float c1, float c2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  const float mi = b1 * m[i] + om1 * gi;
+  const float vi = b2 * v[i] + om2 * gi * gi;
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -848,7 +850,7 @@ hv_status hv_af_train_step(hv_af_model* md, const void* crops, const float* z_m,
   const float c1 = (float)(1.0 - std::pow(0.9, (double)md->step));
   const float c2 = (float)(1.0 - std::pow(0.999, (double)md->step));
   hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, md->params, md->m, md->v, md->grad,
-                     NPARAM, lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+                     NPARAM, lr, 0.9f, 0.999f, (float)(1.0 - 0.9), (float)(1.0 - 0.999), 1e-8f, c1, c2);
   return launched("adam");
 }
 

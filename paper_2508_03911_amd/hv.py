@@ -336,6 +336,35 @@ class Context:
         return out
 
 
+    # ---------------------------------------------------------------- autofocus
+    def hv_af_crops(self, holo: torch.Tensor, half: bool = True) -> torch.Tensor:
+        n, ny, nx = _frames(holo)
+        out = torch.empty((n, 64, 64), dtype=torch.float16 if half else torch.float32, device=holo.device)
+        _check(lib.hv_af_crops(self.handle, _ptr(holo), n, ny, nx, _ptr(out), int(half), _stream(holo.device)))
+        return out
+
+    def hv_af_scan(self, holo: torch.Tensor, wavelength: float, pitch: float, z_lo: float = 0.05,
+                   z_hi: float = 0.5, n_candidates: int = 128, want_scores: bool = False):
+        n, ny, nx = _frames(holo)
+        z = torch.empty(n, dtype=torch.float32, device=holo.device)
+        sc = torch.empty((n, n_candidates), dtype=torch.float32, device=holo.device) if want_scores else None
+        _check(lib.hv_af_scan(self.handle, _ptr(holo), n, ny, nx, wavelength, pitch, z_lo, z_hi, n_candidates,
+                              _ptr(z), _ptr(sc), _stream(holo.device)))
+        return z, sc
+
+    def hv_af_synthesize(self, z_m, wavelength: float, pitch: float, seed: int, index_base: int = 0):
+        import numpy as np
+        z = np.ascontiguousarray(np.asarray(z_m, dtype=np.float64))
+        n = z.shape[0]
+        out = torch.empty((n, 256, 256), dtype=torch.uint8, device=self._dev())
+        _check(lib.hv_af_synthesize(self.handle, n, z.ctypes.data_as(C.POINTER(C.c_double)), wavelength, pitch,
+                                    seed, index_base, _ptr(out), _stream(out.device)))
+        return out
+
+    def af_model(self, init_params, max_batch: int, z_mean: float, z_scale: float) -> "AfModel":
+        return AfModel(self, init_params, max_batch, z_mean, z_scale)
+
+
 class Stream:
     """An open serving-loop stream (hv_stream)."""
 
@@ -373,35 +402,6 @@ class Stream:
         if self.handle:
             _check(lib.hv_stream_close(self.handle))
             self.handle = None
-
-
-    # ---------------------------------------------------------------- autofocus
-    def hv_af_crops(self, holo: torch.Tensor, half: bool = True) -> torch.Tensor:
-        n, ny, nx = _frames(holo)
-        out = torch.empty((n, 64, 64), dtype=torch.float16 if half else torch.float32, device=holo.device)
-        _check(lib.hv_af_crops(self.handle, _ptr(holo), n, ny, nx, _ptr(out), int(half), _stream(holo.device)))
-        return out
-
-    def hv_af_scan(self, holo: torch.Tensor, wavelength: float, pitch: float, z_lo: float = 0.05,
-                   z_hi: float = 0.5, n_candidates: int = 128, want_scores: bool = False):
-        n, ny, nx = _frames(holo)
-        z = torch.empty(n, dtype=torch.float32, device=holo.device)
-        sc = torch.empty((n, n_candidates), dtype=torch.float32, device=holo.device) if want_scores else None
-        _check(lib.hv_af_scan(self.handle, _ptr(holo), n, ny, nx, wavelength, pitch, z_lo, z_hi, n_candidates,
-                              _ptr(z), _ptr(sc), _stream(holo.device)))
-        return z, sc
-
-    def hv_af_synthesize(self, z_m, wavelength: float, pitch: float, seed: int, index_base: int = 0):
-        import numpy as np
-        z = np.ascontiguousarray(np.asarray(z_m, dtype=np.float64))
-        n = z.shape[0]
-        out = torch.empty((n, 256, 256), dtype=torch.uint8, device=self._dev())
-        _check(lib.hv_af_synthesize(self.handle, n, z.ctypes.data_as(C.POINTER(C.c_double)), wavelength, pitch,
-                                    seed, index_base, _ptr(out), _stream(out.device)))
-        return out
-
-    def af_model(self, init_params, max_batch: int, z_mean: float, z_scale: float) -> "AfModel":
-        return AfModel(self, init_params, max_batch, z_mean, z_scale)
 
 
 def af_nparams() -> int:
