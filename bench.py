@@ -137,6 +137,88 @@ def serving(hv, torch, seconds, prec):
                     "1024x512 u16 5 kHz W64; Poisson 6/s, Exp(2 s) lifetimes; budget 32 GiB"}
 
 
+def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
+    """Learned autofocus: train the CNN on n_train holograms synthesised on
+    the GPU by the project's forward model (z uniform in [0.05, 0.5] m,
+    quantised to 512 levels), evaluate on n_eval held-out holograms against
+    the 128-candidate scan, with the scan as fallback for the 10 % least
+    confident predictions."""
+    import numpy as np
+
+    from oracle import autofocus as oaf  # initial weights only (He-normal from a seed)
+    lam, pitch = 852e-9, 20e-6
+    z_mean, z_scale = 0.275, 0.45 / np.sqrt(12)
+    ctx = hv.Context(0)
+
+    def dataset(n, seed, base):
+        rng = np.random.default_rng(seed)
+        lv = rng.integers(0, 512, n // 16)
+        z = np.repeat(0.05 + 0.45 * (lv + 0.5) / 512, 16)
+        crops, holos = [], []
+        for i in range(0, n, 4096):
+            h = ctx.hv_af_synthesize(z[i:i + 4096], lam, pitch, seed=seed, index_base=base + i)
+            crops.append(ctx.hv_af_crops(h))
+            holos.append(h)
+        return torch.cat(crops), holos, torch.from_numpy(z.astype(np.float32)).cuda()
+
+    t0 = time.time()
+    crops, holos, z = dataset(n_train, 1000, 0)
+    del holos
+    torch.cuda.synchronize()
+    t_gen = time.time() - t0
+    log(f"autofocus: {n_train} training holograms synthesised and cropped in {t_gen:.1f}s")
+    init = oaf.init_params(7).astype(np.float32)
+    model = ctx.af_model(init, batch, z_mean, z_scale)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    g = torch.Generator(device="cuda").manual_seed(0)
+    steps = epochs * (n_train // batch)
+    curve = []
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for step in range(steps):
+        idx = torch.randint(0, n_train, (batch,), device="cuda", generator=g)
+        rate = lr if step < steps * 0.7 else lr * 0.1
+        model.train_step(crops[idx].contiguous(), z[idx].contiguous(), rate, loss)
+        if step % max(1, steps // 10) == 0 or step == steps - 1:
+            curve.append(round(loss.item(), 4))
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    log(f"autofocus: {steps} steps in {t_train:.1f}s, loss {curve}")
+    del crops
+    _, eh, ez = dataset(n_eval, 9000000, 9000000)
+    eh = torch.cat(eh)
+    ez = ez.cpu().numpy()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    (zs, _), t_scan = timed(lambda: ctx.hv_af_scan(eh, lam, pitch))
+    (zn, sig, _, _), t_net = timed(lambda: model.predict(eh, lam, pitch, tau=1e9))
+    tau = float(np.quantile(sig.cpu().numpy(), 0.9))
+    (zf, _, used, nfb), t_fb = timed(lambda: model.predict(eh, lam, pitch, tau=tau))
+
+    def err(zhat):
+        e = np.abs(zhat.cpu().numpy() - ez) * 1e3
+        return {"median_mm": float(np.median(e)), "p90_mm": float(np.quantile(e, 0.9)),
+                "rms_mm": float(np.sqrt(np.mean(e ** 2)))}
+
+    out = {"train_holograms": n_train, "eval_holograms": n_eval, "epochs": epochs, "steps": steps,
+           "synth_seconds": t_gen, "train_seconds": t_train, "train_samples_per_s": steps * batch / t_train,
+           "loss_curve": curve,
+           "mean_predictor": {"median_mm": float(np.median(np.abs(ez - z_mean)) * 1e3)},
+           "cnn": {**err(zn), "holograms_per_s": n_eval / t_net},
+           "cnn_fallback": {**err(zf), "holograms_per_s": n_eval / t_fb, "fallback_fraction": nfb / n_eval,
+                            "tau_m": tau},
+           "scan": {**err(zs), "holograms_per_s": n_eval / t_scan, "candidates": 128}}
+    model.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +227,9 @@ def main():
     ap.add_argument("--frames", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="stream-load replay length (0 = skip)")
+    ap.add_argument("--af-train", type=int, default=200000, help="autofocus training holograms (0 = skip)")
+    ap.add_argument("--af-eval", type=int, default=10000)
+    ap.add_argument("--af-epochs", type=int, default=3)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale factor for HBM counters)")
     args = ap.parse_args()
@@ -226,6 +311,10 @@ def main():
         log(f"stream load replay for {args.serve_seconds:.0f}s ...")
         line["serving"] = serving(hv, torch, args.serve_seconds, hv.HV_PREC_FP32)
         log(f"serving: {line['serving']}")
+    if args.af_train > 0:
+        log("autofocus training and evaluation ...")
+        line["autofocus"] = autofocus(hv, torch, args.af_train, args.af_eval, args.af_epochs)
+        log(f"autofocus: {line['autofocus']}")
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample ...")
         line["cpu_baseline"] = cpu_baseline(block, spec, spec.z)
