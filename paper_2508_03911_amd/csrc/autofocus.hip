@@ -73,7 +73,7 @@ template <typename TOUT>
 __global__ __launch_bounds__(512) void k_af_crop(const float2* __restrict__ t1, TOUT* __restrict__ out) {
   constexpr int NT = 512, NB = 33, S = lds_stride(AN);
   __shared__ float2 buf[NB * S];
-  __shared__ float2 tw[AN];
+  __shared__ float2 tw[tw_size(AN) > 0 ? tw_size(AN) : 1];
   __shared__ float vals[HW];
   __shared__ double red[NT];
   const int tid = threadIdx.x;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(512) void k_af_crop(const float2* __restrict__ t1, 
 __global__ __launch_bounds__(512) void k_af_subband(const float2* __restrict__ t1, float2* __restrict__ sub) {
   constexpr int NT = 512, NB = 32, S = lds_stride(AN);
   __shared__ float2 buf[NB * S];
-  __shared__ float2 tw[AN];
+  __shared__ float2 tw[tw_size(AN) > 0 ? tw_size(AN) : 1];
   const int tid = threadIdx.x;
   const long n = blockIdx.x;
   fill_twiddles<AN>(tw, tid, NT);
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_af_scan(const float2* __restrict__ sub,
   constexpr int NT = 256, S = lds_stride(SUB);
   __shared__ float2 A[SUB * S];
   __shared__ float2 B[SUB * S];
-  __shared__ float2 tw[SUB];
+  __shared__ float2 tw[tw_size(SUB) > 0 ? tw_size(SUB) : 1];
   __shared__ double red[NT];
   const int tid = threadIdx.x;
   const long n = blockIdx.x;

@@ -108,18 +108,6 @@ __device__ inline void dft_reg(float2* v) {
   }
 }
 
-// ---------------------------------------------------------------- twiddles
-
-// tw[m] = exp(-2 pi i m / N), m in [0, N), filled cooperatively.
-template <int N>
-__device__ inline void fill_twiddles(float2* tw, int tid, int nthreads) {
-  for (int m = tid; m < N; m += nthreads) {
-    float s, c;
-    sincospif(-2.0f * (float)m / (float)N, &s, &c);
-    tw[m] = make_float2(c, s);
-  }
-}
-
 // ---------------------------------------------------------------- passes
 
 constexpr int radix_of_pass(int n, int pass) {
@@ -138,8 +126,41 @@ constexpr int num_passes(int n) {
   return p;
 }
 
+// ---------------------------------------------------------------- twiddles
+// One table per pass with Ns > 1, laid out [r][k] (k fastest): entry
+// exp(-2 pi i k r / (Ns R)), k < Ns, r < R.  Lanes of a butterfly group read
+// consecutive k for a fixed r, so the reads never collide on an LDS bank.
+constexpr int ns_of_pass(int n, int pass) {
+  int ns = 1;
+  for (int p = 0; p < pass; ++p) ns *= radix_of_pass(n, p);
+  return ns;
+}
+constexpr int tw_offset(int n, int pass) {
+  int off = 0;
+  for (int p = 0; p < pass; ++p) {
+    const int ns = ns_of_pass(n, p);
+    if (ns > 1) off += ns * radix_of_pass(n, p);
+  }
+  return off;
+}
+constexpr int tw_size(int n) { return tw_offset(n, num_passes(n)); }
+
+template <int N>
+__device__ inline void fill_twiddles(float2* tw, int tid, int nthreads) {
+  constexpr int P = num_passes(N);
+  for (int p = 1; p < P; ++p) {
+    const int ns = ns_of_pass(N, p), r_ = radix_of_pass(N, p), off = tw_offset(N, p);
+    for (int e = tid; e < ns * r_; e += nthreads) {
+      const int r = e / ns, k = e % ns;
+      float s, c;
+      sincospif(-2.0f * (float)((k * r) % (ns * r_)) / (float)(ns * r_), &s, &c);
+      tw[off + e] = make_float2(c, s);
+    }
+  }
+}
+
 // One Stockham pass of radix R over NB sequences of length N (in place).
-template <int N, int R, int NS, int NB, int NT, int DIR>
+template <int N, int R, int NS, int NB, int NT, int DIR, int TWOFF>
 __device__ inline void stockham_pass(float2* buf, const float2* tw, int tid) {
   constexpr int BF = NB * (N / R);             // butterflies in the pass
   constexpr int U = (BF + NT - 1) / NT;        // per thread
@@ -157,7 +178,7 @@ __device__ inline void stockham_pass(float2* buf, const float2* tw, int tid) {
       if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[(k * r * (N / (NS * R))) & (N - 1)];
+          float2 w = tw[TWOFF + r * NS + k];
           if (DIR > 0) w.y = -w.y;
           v[u][r] = c2::mul(v[u][r], w);
         }
@@ -185,14 +206,14 @@ template <int N, int PASS, int NS, int NB, int NT, int DIR>
 __device__ inline void fft_passes(float2* buf, const float2* tw, int tid) {
   if constexpr (PASS < num_passes(N)) {
     constexpr int R = radix_of_pass(N, PASS);
-    stockham_pass<N, R, NS, NB, NT, DIR>(buf, tw, tid);
+    stockham_pass<N, R, NS, NB, NT, DIR, tw_offset(N, PASS)>(buf, tw, tid);
     fft_passes<N, PASS + 1, NS * R, NB, NT, DIR>(buf, tw, tid);
   }
 }
 
 // NB in-place FFTs of length N held in LDS at buf[b * lds_stride(N) + skew(i)].
 // Requires a barrier before (data written) -- provided by the caller -- and
-// leaves a barrier after.  tw must hold fill_twiddles<N>.
+// leaves a barrier after.  tw (tw_size(N) entries) must hold fill_twiddles<N>.
 template <int N, int NB, int NT, int DIR>
 __device__ inline void fft_lds(float2* buf, const float2* tw, int tid) {
   fft_passes<N, 0, 1, NB, NT, DIR>(buf, tw, tid);

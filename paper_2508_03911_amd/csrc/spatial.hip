@@ -38,6 +38,20 @@ __device__ inline float2 load_c(const hv_h2* p) {
   return make_float2((float)h.x, (float)h.y);
 }
 
+// Grid of a persistent kernel: every CU filled to the kernel's occupancy.
+template <class K>
+int persistent_grid(K kernel, int nunits) {
+  static int blocks = 0;  // one per kernel instantiation
+  if (!blocks) {
+    int dev = 0, cus = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, NT, 0);
+    blocks = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
+  }
+  return nunits < blocks ? nunits : blocks;
+}
+
 // 8 consecutive camera values as floats (exact).
 __device__ inline void load8(const uint8_t* p, float* f) {
   uint2 w = *reinterpret_cast<const uint2*>(p);
@@ -81,48 +95,88 @@ __device__ inline void load8c(const float2* p, float2* v) {
 }
 
 // ------------------------------------------------------------------ K1
+// Persistent: block b handles units b, b + gridDim.x, ... (unit = frame x
+// row tile) and prefetches the next unit's camera bytes into registers while
+// it transforms the current one.
+template <typename TIN> struct Raw8;
+template <> struct Raw8<uint8_t> {
+  uint2 w;
+  __device__ void load(const uint8_t* p) { w = *reinterpret_cast<const uint2*>(p); }
+  __device__ float get(int e) const { return (float)(((e < 4 ? w.x : w.y) >> (8 * (e & 3))) & 0xffu); }
+};
+template <> struct Raw8<uint16_t> {
+  uint4 w;
+  __device__ void load(const uint16_t* p) { w = *reinterpret_cast<const uint4*>(p); }
+  __device__ float get(int e) const {
+    const uint32_t v = e < 2 ? w.x : e < 4 ? w.y : e < 6 ? w.z : w.w;
+    return (float)((v >> (16 * (e & 1))) & 0xffffu);
+  }
+};
+
 template <int NX, int ROWS, typename TIN, typename TOUT>
 __global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT* __restrict__ out, int ny,
-                                                float scale) {
+                                                int nunits, float scale) {
   constexpr int NB = ROWS / 2;
   constexpr int S = lds_stride(NX);
+  constexpr int CH = NB * (NX / 8);  // 8-element chunks of row pairs
+  constexpr int PER = (CH + NT - 1) / NT;
   __shared__ float2 buf[NB * S];
-  __shared__ float2 tw[NX];
+  __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
   const int tid = threadIdx.x;
-  const int y0 = blockIdx.x * ROWS;
-  const long t = blockIdx.y;
+  const int tiles = ny / ROWS;
   fill_twiddles<NX>(tw, tid, NT);
-  const TIN* src = in + (t * ny + y0) * (long)NX;
-  for (int q = tid; q < NB * (NX / 8); q += NT) {
-    const int b = q / (NX / 8), c = q % (NX / 8);
-    float a8[8], b8[8];
-    load8(src + (2 * b) * NX + 8 * c, a8);
-    load8(src + (2 * b + 1) * NX + 8 * c, b8);
-    float2* dst = buf + b * S;
+  Raw8<TIN> ra[PER], rb[PER];
+  auto fetch = [&](int u) {
+    const TIN* src = in + ((long)(u / tiles) * ny + (long)(u % tiles) * ROWS) * NX;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) dst[skew(8 * c + e)] = make_float2(a8[e], b8[e]);
-  }
-  __syncthreads();
-  fft_lds<NX, NB, NT, -1>(buf, tw, tid);
-  TOUT* dst = out + t * (long)(NX / 2) * ny + y0;
-  for (int q = tid; q < (NX / 2) * ROWS; q += NT) {
-    const int fx = q / ROWS, r = q % ROWS, b = r >> 1;
-    const float2* row = buf + b * S;
-    float2 z1 = row[skew(fx)];
-    float2 v;
-    if (fx == 0) {
-      float2 zn = row[skew(NX / 2)];
-      v = (r & 1) ? make_float2(z1.y, zn.y) : make_float2(z1.x, zn.x);
-    } else {
-      float2 z2 = c2::conj(row[skew(NX - fx)]);
-      if (r & 1) {
-        float2 d = c2::sub(z1, z2);
-        v = make_float2(0.5f * d.y, -0.5f * d.x);
-      } else {
-        v = c2::scale(c2::add(z1, z2), 0.5f);
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + i * NT;
+      if (CH % NT == 0 || q < CH) {
+        const int b = q / (NX / 8), c = q % (NX / 8);
+        ra[i].load(src + (2 * b) * NX + 8 * c);
+        rb[i].load(src + (2 * b + 1) * NX + 8 * c);
       }
     }
-    store_c(dst + (long)fx * ny + r, c2::scale(v, scale));
+  };
+  int u = blockIdx.x;
+  if (u < nunits) fetch(u);
+  for (; u < nunits; u += gridDim.x) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + i * NT;
+      if (CH % NT == 0 || q < CH) {
+        const int b = q / (NX / 8), c = q % (NX / 8);
+        float2* dst = buf + b * S;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dst[skew(8 * c + e)] = make_float2(ra[i].get(e), rb[i].get(e));
+      }
+    }
+    __syncthreads();
+    if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+    fft_lds<NX, NB, NT, -1>(buf, tw, tid);
+    const long t = u / tiles;
+    const int y0 = (u % tiles) * ROWS;
+    TOUT* dst = out + t * (long)(NX / 2) * ny + y0;
+    for (int q = tid; q < (NX / 2) * ROWS; q += NT) {
+      const int fx = q / ROWS, r = q % ROWS, b = r >> 1;
+      const float2* row = buf + b * S;
+      float2 z1 = row[skew(fx)];
+      float2 v;
+      if (fx == 0) {
+        float2 zn = row[skew(NX / 2)];
+        v = (r & 1) ? make_float2(z1.y, zn.y) : make_float2(z1.x, zn.x);
+      } else {
+        float2 z2 = c2::conj(row[skew(NX - fx)]);
+        if (r & 1) {
+          float2 d = c2::sub(z1, z2);
+          v = make_float2(0.5f * d.y, -0.5f * d.x);
+        } else {
+          v = c2::scale(c2::add(z1, z2), 0.5f);
+        }
+      }
+      store_c(dst + (long)fx * ny + r, c2::scale(v, scale));
+    }
+    __syncthreads();
   }
 }
 
@@ -134,16 +188,31 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
   constexpr int U = BC * NY / NT;
   static_assert(BC * NY % NT == 0, "column tile must split evenly");
   __shared__ float2 buf[2 * BC * S];
-  __shared__ float2 tw[NY];
+  __shared__ float2 tw[tw_size(NY) > 0 ? tw_size(NY) : 1];
   const int tid = threadIdx.x;
   const int f0 = blockIdx.x * BC;
   const long t = blockIdx.y;
   fill_twiddles<NY>(tw, tid, NT);
   const TIO* src = in + (t * (nx / 2) + f0) * (long)NY;
   for (int q = tid; q < BC * NY; q += NT) buf[(q / NY) * S + skew(q % NY)] = load_c(src + q);
+  // Transfer-function values for this thread's outputs, fetched now so that
+  // their latency hides behind the column FFT.  Column fx of the half
+  // spectrum yields output columns fx and nx - fx; fx = 0 packs the DC and
+  // Nyquist columns.
+  float2 ha[U], hb[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * NT;
+    const int fx = f0 + q / NY, fy = q % NY;
+    ha[u] = ht[(long)fx * NY + fy];
+    hb[u] = ht[(long)(fx == 0 ? nx / 2 : nx - fx) * NY + fy];
+  }
   __syncthreads();
   fft_lds<NY, BC, NT, -1>(buf, tw, tid);
-  float2 va[U], vb[U];
+  // Sequences BC..2BC-1 are free until the inverse transform: the -fx
+  // products go there at once, the +fx products after every read of the
+  // forward spectrum is done.
+  float2 va[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int q = tid + u * NT;
@@ -152,45 +221,36 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
     float2 z1 = col[skew(fy)];
     float2 z2 = c2::conj(col[skew((NY - fy) & (NY - 1))]);
     float2 a, b;
-    int ca, cb;
     if (fx == 0) {
       a = c2::scale(c2::add(z1, z2), 0.5f);
       float2 d = c2::sub(z1, z2);
       b = make_float2(0.5f * d.y, -0.5f * d.x);
-      ca = 0;
-      cb = nx / 2;
     } else {
       a = z1;
       b = z2;
-      ca = fx;
-      cb = nx - fx;
     }
-    va[u] = c2::mul(a, ht[(long)ca * NY + fy]);
-    vb[u] = c2::mul(b, ht[(long)cb * NY + fy]);
+    va[u] = c2::mul(a, ha[u]);
+    buf[(BC + s) * S + skew(fy)] = c2::mul(b, hb[u]);
   }
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int q = tid + u * NT;
-    const int s = q / NY, fy = q % NY;
-    buf[s * S + skew(fy)] = va[u];
-    buf[(BC + s) * S + skew(fy)] = vb[u];
+    buf[(q / NY) * S + skew(q % NY)] = va[u];
   }
   __syncthreads();
   fft_lds<NY, 2 * BC, NT, +1>(buf, tw, tid);
   TIO* dst = out + t * (long)NY * nx;
   for (int q = tid; q < 2 * BC * NY; q += NT) {
     const int y = q / (2 * BC), i = q % (2 * BC);
-    int c, slot;
+    int c;
     if (i < BC) {
       c = f0 + i;
-      slot = i;
     } else {
       const int fx = f0 + i - BC;
       c = fx == 0 ? nx / 2 : nx - fx;
-      slot = i;
     }
-    store_c(dst + (long)y * nx + c, buf[slot * S + skew(y)]);
+    store_c(dst + (long)y * nx + c, buf[i * S + skew(y)]);
   }
 }
 
@@ -200,7 +260,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const TIN* __restrict__ in, TOUT
                                                 float scale) {
   constexpr int S = lds_stride(NX);
   __shared__ float2 buf[ROWS * S];
-  __shared__ float2 tw[NX];
+  __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
   const int tid = threadIdx.x;
   const long base = ((long)blockIdx.y * ny + (long)blockIdx.x * ROWS) * NX;
   fill_twiddles<NX>(tw, tid, NT);
@@ -220,7 +280,7 @@ __global__ __launch_bounds__(NT) void k_rows_c2c(const TIN* __restrict__ in, TOU
                                                  int ny, float scale) {
   constexpr int S = lds_stride(NX);
   __shared__ float2 buf[ROWS * S];
-  __shared__ float2 tw[NX];
+  __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
   const int tid = threadIdx.x;
   const int y0 = blockIdx.x * ROWS;
   const long t = blockIdx.y;
@@ -255,7 +315,7 @@ __global__ __launch_bounds__(NT) void k_col_full(const TIO* __restrict__ in, TIO
                                                  const float2* __restrict__ ht, int nx) {
   constexpr int S = lds_stride(NY);
   __shared__ float2 buf[BC * S];
-  __shared__ float2 tw[NY];
+  __shared__ float2 tw[tw_size(NY) > 0 ? tw_size(NY) : 1];
   const int tid = threadIdx.x;
   const int p0 = blockIdx.x * BC;
   const long t = blockIdx.y;
@@ -285,7 +345,7 @@ __global__ __launch_bounds__(NT) void k_fresnel_cols(const TIN* __restrict__ in,
                                                      const float2* __restrict__ qy, int nx, float scale) {
   constexpr int S = lds_stride(NY);
   __shared__ float2 buf[BC * S];
-  __shared__ float2 tw[NY];
+  __shared__ float2 tw[tw_size(NY) > 0 ? tw_size(NY) : 1];
   const int tid = threadIdx.x;
   const int p0 = blockIdx.x * BC;
   const long t = blockIdx.y;
@@ -310,8 +370,10 @@ constexpr int cap32(int r) { return r > 32 ? 32 : r; }
 template <int NX, typename TIN, typename TOUT>
 void go_r2c(const void* in, void* out, int n, int ny, float scale, hipStream_t st) {
   constexpr int ROWS = cap64(16384 / NX);
-  hipLaunchKernelGGL((k_row_r2c<NX, ROWS, TIN, TOUT>), dim3(ny / ROWS, n), dim3(NT), 0, st, (const TIN*)in,
-                     (TOUT*)out, ny, scale);
+  const int nunits = n * (ny / ROWS);
+  auto kern = k_row_r2c<NX, ROWS, TIN, TOUT>;
+  hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, nunits)), dim3(NT), 0, st, (const TIN*)in, (TOUT*)out, ny,
+                     nunits, scale);
 }
 
 template <int NY, typename TIO>

@@ -146,27 +146,68 @@ __device__ inline void load_wts(float* wts_lds, const CoefArgs& g, int tid) {
 }
 
 // ------------------------------------------------------------------ fused row inverse + GEMM
+// Unit u = (window u / ny, row u % ny): the W rows y of the window's frames
+// are inverse-transformed in LDS and reduced by the coefficient GEMM.
+//
+// FP16 input: persistent blocks with a register prefetch of the next unit's
+// rows (16 VGPRs) while the current unit is transformed and reduced.
+// FP32 input: one unit per block.  A 32-VGPR prefetch would lift the kernel
+// past 128 VGPRs and halve the resident blocks per CU, which costs more than
+// the prefetch gains (measured at 256 x 256, W = 32).
 template <int NX, int W, bool MIXED, typename TIN>
-__global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, int ny, int stride, CoefArgs g) {
+__global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, int ny, int stride, int nunits,
+                                                    CoefArgs g) {
+  constexpr bool PF = sizeof(TIN) == 4;
   constexpr int S = lds_stride(NX);
+  constexpr int PER = (W * NX) / NT;
+  static_assert((W * NX) % NT == 0, "row block must split evenly");
   __shared__ float2 buf[W * S];
-  __shared__ float2 tw[NX];
+  __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
   __shared__ float wts_lds[3 * MT_MAX * 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int y = blockIdx.x;
-  const long jj = blockIdx.y;
   fill_twiddles<NX>(tw, tid, NT);
   load_wts(wts_lds, g, tid);
-  const TIN* src = z + ((jj * stride) * (long)ny + y) * NX;
-  for (int q = tid; q < W * NX; q += NT) {
-    const int t = q / NX, x = q % NX;
-    buf[t * S + skew(x)] = load_c(src + (long)t * ny * NX + x);
-  }
-  __syncthreads();
-  fft_lds<NX, W, NT, +1>(buf, tw, tid);
   const long npix = (long)ny * NX;
-  for (int nt = wave; nt < NX / 32; nt += NT / 64)
-    coef_pixels<W, MIXED, false>(g, wts_lds, buf, S, nt * 32, lane, jj, (long)y * NX, npix);
+  auto rows = [&](int u) { return z + (((long)(u / ny) * stride) * (long)ny + u % ny) * NX; };
+  auto reduce = [&](int u) {
+    fft_lds<NX, W, NT, +1>(buf, tw, tid);
+    for (int nt = wave; nt < NX / 32; nt += NT / 64)
+      coef_pixels<W, MIXED, false>(g, wts_lds, buf, S, nt * 32, lane, u / ny, (long)(u % ny) * NX, npix);
+  };
+  if constexpr (PF) {
+    TIN pre[PER];
+    auto fetch = [&](int u) {
+      const TIN* src = rows(u);
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int q = tid + i * NT;
+        pre[i] = src[(long)(q / NX) * npix + (q % NX)];
+      }
+    };
+    int u = blockIdx.x;
+    if (u < nunits) fetch(u);
+    for (; u < nunits; u += gridDim.x) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int q = tid + i * NT;
+        buf[(q / NX) * S + skew(q % NX)] = load_c(&pre[i]);
+      }
+      __syncthreads();
+      if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+      reduce(u);
+      __syncthreads();
+    }
+  } else {
+    const int u = blockIdx.x;
+    const TIN* src = rows(u);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + i * NT;
+      buf[(q / NX) * S + skew(q % NX)] = load_c(src + (long)(q / NX) * npix + (q % NX));
+    }
+    __syncthreads();
+    reduce(u);
+  }
 }
 
 // ------------------------------------------------------------------ GEMM from a field in memory
@@ -492,16 +533,33 @@ CoefArgs make_args(const hvi::CoefGemm& g, long a_win_stride, float bsc, float a
   return a;
 }
 
+// Grid of a persistent kernel: every CU filled to the kernel's occupancy.
+template <class K>
+int persistent_grid(K kernel, int nunits) {
+  static int blocks = 0;  // one per kernel instantiation
+  if (!blocks) {
+    int dev = 0, cus = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, NT, 0);
+    blocks = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
+  }
+  return nunits < blocks ? nunits : blocks;
+}
+
 template <int NX, int W, bool MIXED>
 hv_status go_rowinv(const void* z, bool half_in, int ny, int stride, int nwin, const CoefArgs& a,
                     hipStream_t st) {
-  if constexpr (W * NX <= 8192) {
-    if (half_in)
-      hipLaunchKernelGGL((k_rowinv_coef<NX, W, MIXED, hv_h2>), dim3(ny, nwin), dim3(NT), 0, st, (const hv_h2*)z,
-                         ny, stride, a);
-    else
-      hipLaunchKernelGGL((k_rowinv_coef<NX, W, MIXED, float2>), dim3(ny, nwin), dim3(NT), 0, st,
-                         (const float2*)z, ny, stride, a);
+  if constexpr (W * NX <= 8192 && (W * NX) % NT == 0) {
+    const int nunits = ny * nwin;
+    if (half_in) {
+      auto kern = k_rowinv_coef<NX, W, MIXED, hv_h2>;
+      hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, nunits)), dim3(NT), 0, st, (const hv_h2*)z, ny, stride,
+                         nunits, a);
+    } else {
+      hipLaunchKernelGGL((k_rowinv_coef<NX, W, MIXED, float2>), dim3(nunits), dim3(NT), 0, st, (const float2*)z,
+                         ny, stride, nunits, a);
+    }
     return launched("rowinv_coef");
   } else {
     return hvi::fail(HV_ERR_SHAPE, "fused row-inverse GEMM does not fit nx=%d W=%d", NX, W);
@@ -552,7 +610,7 @@ void go_gram(const void* u, bool half_in, long npix, int stride, int nwin, long 
 
 namespace hvi {
 
-bool rowinv_coef_fits(int nx, int window) { return (long)nx * window <= 8192; }
+bool rowinv_coef_fits(int nx, int window) { return (long)nx * window <= 8192 && ((long)nx * window) % NT == 0; }
 
 hv_status launch_rowinv_coef(const void* z, bool half_in, int ny, int nx, int stride, int nwin, const CoefGemm& g,
                              bool mixed, float b_scale, float out_scale, float* out0, float* out1, float* out2,
