@@ -92,20 +92,31 @@ def kernel_profile(ctx, hv, torch, x, opt, tp, prec, outs, steps, frames):
     return res
 
 
-def cpu_baseline(block, spec, z):
-    """The FP64 oracle on a bounded sample of the same workload."""
+def cpu_baseline(block, spec, z, ctx, hv, torch):
+    """The FP64 oracle on a bounded sample of the same workload (timed), and
+    the relative L2 error of both GPU forms against it on that sample."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle import pipeline
     sample = block
     t0 = time.perf_counter()
-    pipeline.stft_moments(sample, pipeline.Optics(852e-9, spec.pitch, spec.pitch, -z), W, W, spec.fs, 3e3, 35e3)
+    ref = pipeline.stft_moments(sample, pipeline.Optics(852e-9, spec.pitch, spec.pitch, -z), W, W, spec.fs,
+                                3e3, 35e3)
     dt = time.perf_counter() - t0
     blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    opt = hv.Optics(852e-9, spec.pitch, spec.pitch, -z, hv.HV_AS)
+    tp = hv.Temporal(W, W, spec.fs, 3e3, 35e3)
+    xd = torch.from_numpy(sample).cuda()
+    err = {}
+    for prec, name in ((hv.HV_PREC_FP32, "fp32"), (hv.HV_PREC_MIXED, "mixed")):
+        got = [t.cpu().numpy().astype(np.float64) for t in ctx.hv_stft_moments(xd, opt, tp, prec)]
+        err[name] = {k: float(np.linalg.norm(g - ref[k]) / np.linalg.norm(ref[k]))
+                     for k, g in zip(("m0", "m1", "m2"), got)}
     return {"value": sample.shape[0] / dt, "unit": "frames/s", "cores": int(blas), "kind": "oracle",
             "sample": f"{sample.shape[0]} frames (64 windows) of the 256x256 stream, numpy float64; "
-                      f"FFTs single-threaded, BLAS {blas} threads", "seconds": dt}
+                      f"FFTs single-threaded, BLAS {blas} threads", "seconds": dt,
+            "gpu_rel_l2_vs_oracle": err}
 
 
 def serving(hv, torch, seconds, prec):
@@ -137,6 +148,19 @@ def serving(hv, torch, seconds, prec):
                     "1024x512 u16 5 kHz W64; Poisson 6/s, Exp(2 s) lifetimes; budget 32 GiB"}
 
 
+def he_normal_init(seed):
+    """Initial network parameters in the library's storage order: per conv
+    layer weight [co][ci][3][3] then bias, per FC layer weight [out][in] then
+    bias; weights N(0, 2 / fan_in), biases zero."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    for co, ci, k in ((32, 1, 3), (32, 32, 3), (32, 32, 3), (32, 32, 3), (64, 32, 1), (2, 64, 1)):
+        fan_in = ci * k * k
+        parts += [rng.standard_normal(co * fan_in) * np.sqrt(2.0 / fan_in), np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
     """Learned autofocus: train the CNN on n_train holograms synthesised on
     the GPU by the project's forward model (z uniform in [0.05, 0.5] m,
@@ -145,7 +169,6 @@ def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
     confident predictions."""
     import numpy as np
 
-    from oracle import autofocus as oaf  # initial weights only (He-normal from a seed)
     lam, pitch = 852e-9, 20e-6
     z_mean, z_scale = 0.275, 0.45 / np.sqrt(12)
     ctx = hv.Context(0)
@@ -167,7 +190,7 @@ def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
     torch.cuda.synchronize()
     t_gen = time.time() - t0
     log(f"autofocus: {n_train} training holograms synthesised and cropped in {t_gen:.1f}s")
-    init = oaf.init_params(7).astype(np.float32)
+    init = he_normal_init(7)
     model = ctx.af_model(init, batch, z_mean, z_scale)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     g = torch.Generator(device="cuda").manual_seed(0)
@@ -317,7 +340,7 @@ def main():
         log(f"autofocus: {line['autofocus']}")
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample ...")
-        line["cpu_baseline"] = cpu_baseline(block, spec, spec.z)
+        line["cpu_baseline"] = cpu_baseline(block, spec, spec.z, ctx, hv, torch)
     ctx.close()
     print(json.dumps(line), flush=True)
 
