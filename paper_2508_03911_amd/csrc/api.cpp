@@ -9,6 +9,7 @@
 // out of the steady state, Sec. VII-C).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -149,7 +150,15 @@ static hv_status build_as_table(size_t* held, AsPlan& p) {
       h[(size_t)cx * ny + cy] = make_float2((float)re, (float)im);
     }
   }
-  return p.ht.upload(h.data(), h.size() * sizeof(float2), held);
+  // the column pass's order: +fx columns, then the -fx column of each fx
+  std::vector<float2> hs((size_t)nx * ny);
+  for (int fx = 0; fx < nx / 2; ++fx) {
+    const int neg = fx == 0 ? nx / 2 : nx - fx;
+    std::copy_n(&h[(size_t)fx * ny], ny, &hs[(size_t)fx * ny]);
+    std::copy_n(&h[(size_t)neg * ny], ny, &hs[(size_t)(nx / 2 + fx) * ny]);
+  }
+  hv_status s = p.ht.upload(h.data(), h.size() * sizeof(float2), held);
+  return s ? s : p.hs.upload(hs.data(), hs.size() * sizeof(float2), held);
 }
 
 static hv_status build_fresnel_tables(size_t* held, FresnelPlan& p) {
@@ -391,7 +400,7 @@ hv_status spatial(Ctx* c, const void* in, int in_t, int nf, int ny, int nx, cons
       DevBuf& tb = c->work(st, 0);
       if ((s = tb.ensure((size_t)nf * (frame / 2) * cplx, &c->held))) return s;
       if ((s = timed(c, "row_r2c", st, [&] { return launch_row_r2c(in, (hv_dtype)in_t, tb.ptr, mixed, nf, ny, nx, s1, st); }))) return s;
-      if ((s = timed(c, "col_as", st, [&] { return launch_col_as(tb.ptr, zb.ptr, mixed, p->ht_ptr(), nf, ny, nx, st); }))) return s;
+      if ((s = timed(c, "col_as", st, [&] { return launch_col_as(tb.ptr, zb.ptr, mixed, p->hs_ptr(), nf, ny, nx, st); }))) return s;
     }
     out.z = zb.ptr;
     out.z_to_field = 1.0f / (nx * s1);

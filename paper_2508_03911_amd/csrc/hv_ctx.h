@@ -34,7 +34,9 @@ struct AsPlan {
   int ny = 0, nx = 0;
   double wavelength = 0, dx = 0, dy = 0, z = 0;
   DevBuf ht;  // [nx][ny] float2: H_z(fx = column, fy) / ny
+  DevBuf hs;  // [2][nx/2][ny] float2: H_z(fx, fy) / ny, then H_z(-fx, fy) / ny (fx = 0: nx/2)
   const float2* ht_ptr() const { return (const float2*)ht.ptr; }
+  const float2* hs_ptr() const { return (const float2*)hs.ptr; }
 };
 
 struct FresnelPlan {

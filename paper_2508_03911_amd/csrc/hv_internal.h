@@ -29,7 +29,7 @@ hv_status launch_row_r2c(const void* in, hv_dtype in_t, void* out, bool half_out
 // by Hermitian symmetry, multiply by ht (column-major [nx][ny], the
 // transfer function divided by ny), inverse column FFT.
 // in: [n][nx/2][ny] (from launch_row_r2c); out: [n][ny][nx].
-hv_status launch_col_as(const void* in, void* out, bool half_io, const float2* ht, int n, int ny, int nx,
+hv_status launch_col_as(const void* in, void* out, bool half_io, const float2* hs, int n, int ny, int nx,
                         hipStream_t st);
 
 // Row inverse FFT to the field: in [n][ny][nx] complex, out [n][ny][nx]

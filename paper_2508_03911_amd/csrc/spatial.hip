@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.h"
+#include "gmem.h"
 #include "hv_ctx.h"
 #include "hv_internal.h"
 
@@ -113,6 +114,21 @@ template <> struct Raw8<uint16_t> {
   }
 };
 
+// Two consecutive outputs of one column of the transposed half spectrum
+// (rows 2b and 2b + 1) as one store.
+__device__ inline void store_pair(float2* p, float2 a, float2 b) {
+  *reinterpret_cast<float4*>(p) = make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ inline void store_pair(hv_h2* p, float2 a, float2 b) {
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  h4 h;
+  h[0] = (_Float16)a.x;
+  h[1] = (_Float16)a.y;
+  h[2] = (_Float16)b.x;
+  h[3] = (_Float16)b.y;
+  *reinterpret_cast<h4*>(p) = h;
+}
+
 template <int NX, int ROWS, typename TIN, typename TOUT>
 __global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT* __restrict__ out, int ny,
                                                 int nunits, float scale) {
@@ -125,16 +141,25 @@ __global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT
   const int tid = threadIdx.x;
   const int tiles = ny / ROWS;
   fill_twiddles<NX>(tw, tid, NT);
+  // load: chunk q = tid + i * NT is row pair b, columns 8c .. 8c + 7
+  using TL = TileSplit<NX / 8, NT>;
+  const int bt = TL::row_thr(tid), ctl = TL::col_thr(tid);
+  const uint32_t off_in = (uint32_t)(2 * bt * NX + 8 * ctl) * (uint32_t)sizeof(TIN);
+  // store: item q = tid + k * NT is row pair b = q % NB of column fx = q / NB
+  constexpr int FPK = NT / NB;  // columns per pass of the threads
+  static_assert(NT % NB == 0 && (NX / 2) % FPK == 0, "store split");
+  const int bs = tid % NB, fs = tid / NB;
+  const uint32_t off_out = (uint32_t)(fs * ny + 2 * bs) * (uint32_t)sizeof(TOUT);
+  const float2* prow = buf + bs * S;
   Raw8<TIN> ra[PER], rb[PER];
   auto fetch = [&](int u) {
     const TIN* src = in + ((long)(u / tiles) * ny + (long)(u % tiles) * ROWS) * NX;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int q = tid + i * NT;
-      if (CH % NT == 0 || q < CH) {
-        const int b = q / (NX / 8), c = q % (NX / 8);
-        ra[i].load(src + (2 * b) * NX + 8 * c);
-        rb[i].load(src + (2 * b + 1) * NX + 8 * c);
+      if (CH % NT == 0 || tid + i * NT < CH) {
+        const TIN* p = src + 2 * TL::row_i(i) * NX + 8 * TL::col_i(i);
+        ra[i].load(reinterpret_cast<const TIN*>(reinterpret_cast<const char*>(p) + off_in));
+        rb[i].load(reinterpret_cast<const TIN*>(reinterpret_cast<const char*>(p + NX) + off_in));
       }
     }
   };
@@ -143,10 +168,9 @@ __global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT
   for (; u < nunits; u += gridDim.x) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int q = tid + i * NT;
-      if (CH % NT == 0 || q < CH) {
-        const int b = q / (NX / 8), c = q % (NX / 8);
-        float2* dst = buf + b * S;
+      if (CH % NT == 0 || tid + i * NT < CH) {
+        float2* dst = buf + (bt + TL::row_i(i)) * S;
+        const int c = ctl + TL::col_i(i);
 #pragma unroll
         for (int e = 0; e < 8; ++e) dst[skew(8 * c + e)] = make_float2(ra[i].get(e), rb[i].get(e));
       }
@@ -154,36 +178,40 @@ __global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT
     __syncthreads();
     if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
     fft_lds<NX, NB, NT, -1>(buf, tw, tid);
-    const long t = u / tiles;
-    const int y0 = (u % tiles) * ROWS;
-    TOUT* dst = out + t * (long)(NX / 2) * ny + y0;
-    for (int q = tid; q < (NX / 2) * ROWS; q += NT) {
-      const int fx = q / ROWS, r = q % ROWS, b = r >> 1;
-      const float2* row = buf + b * S;
-      float2 z1 = row[skew(fx)];
-      float2 v;
+    // The complex FFT Z of rows x (real part) and y (imaginary part) gives
+    // X(f) = (Z(f) + conj Z(-f)) / 2 and Y(f) = (Z(f) - conj Z(-f)) / 2i.
+    TOUT* dst = out + (long)(u / tiles) * (NX / 2) * ny + (u % tiles) * ROWS;
+#pragma unroll 4
+    for (int k = 0; k < (NX / 2) / FPK; ++k) {
+      const int fx = fs + k * FPK;
+      const float2 z1 = prow[skew(fx)];
+      float2 ve, vo;
       if (fx == 0) {
-        float2 zn = row[skew(NX / 2)];
-        v = (r & 1) ? make_float2(z1.y, zn.y) : make_float2(z1.x, zn.x);
+        const float2 zn = prow[skew(NX / 2)];
+        ve = make_float2(z1.x, zn.x);
+        vo = make_float2(z1.y, zn.y);
       } else {
-        float2 z2 = c2::conj(row[skew(NX - fx)]);
-        if (r & 1) {
-          float2 d = c2::sub(z1, z2);
-          v = make_float2(0.5f * d.y, -0.5f * d.x);
-        } else {
-          v = c2::scale(c2::add(z1, z2), 0.5f);
-        }
+        const float2 z2 = c2::conj(prow[skew(NX - fx)]);
+        ve = c2::scale(c2::add(z1, z2), 0.5f);
+        const float2 d = c2::sub(z1, z2);
+        vo = make_float2(0.5f * d.y, -0.5f * d.x);
       }
-      store_c(dst + (long)fx * ny + r, c2::scale(v, scale));
+      store_pair(reinterpret_cast<TOUT*>(reinterpret_cast<char*>(dst + (long)k * FPK * ny) + off_out),
+                 c2::scale(ve, scale), c2::scale(vo, scale));
     }
     __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------ K2
+// Block (f0 / BC, t): half-spectrum columns fx in [f0, f0 + BC) of frame t.
+// Column fx yields output columns fx and -fx (= nx - fx); fx = 0 packs the
+// real DC and Nyquist columns.  hs holds H_z in the order this kernel reads
+// it: hs[0][fx][fy] = H(fx, fy), hs[1][fx][fy] = H(-fx, fy) (H(nx/2, fy) for
+// fx = 0), both / ny.
 template <int NY, int BC, typename TIO>
 __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* __restrict__ out,
-                                               const float2* __restrict__ ht, int nx) {
+                                               const float2* __restrict__ hs, int nx) {
   constexpr int S = lds_stride(NY);
   constexpr int U = BC * NY / NT;
   static_assert(BC * NY % NT == 0, "column tile must split evenly");
@@ -192,20 +220,30 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
   const int tid = threadIdx.x;
   const int f0 = blockIdx.x * BC;
   const long t = blockIdx.y;
+  const int half = nx / 2;
   fill_twiddles<NY>(tw, tid, NT);
-  const TIO* src = in + (t * (nx / 2) + f0) * (long)NY;
-  for (int q = tid; q < BC * NY; q += NT) buf[(q / NY) * S + skew(q % NY)] = load_c(src + q);
-  // Transfer-function values for this thread's outputs, fetched now so that
-  // their latency hides behind the column FFT.  Column fx of the half
-  // spectrum yields output columns fx and nx - fx; fx = 0 packs the DC and
-  // Nyquist columns.
+  // element u of this thread in the BC x NY tile: column s = st + row_i(u),
+  // frequency fy = yt + col_i(u)
+  using TS = TileSplit<NY, NT>;
+  const int st = TS::row_thr(tid), yt = TS::col_thr(tid);
+  const uint32_t off_in = (uint32_t)(st * NY + yt) * (uint32_t)sizeof(TIO);
+  const uint32_t off_h = (uint32_t)(st * NY + yt) * 8u;
+  const TIO* src = in + (t * half + f0) * (long)NY;
+  const float2* hpos = hs + (long)f0 * NY;
+  const float2* hneg = hs + ((long)half + f0) * NY;
+  float2* lds = buf + st * S + skew(yt);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const TIO v = ld_off(src + TS::row_i(u) * NY + TS::col_i(u), off_in);
+    lds[TS::row_i(u) * S + skew(TS::col_i(u))] = load_c(&v);
+  }
+  // transfer-function values of this thread's outputs, fetched now so that
+  // their latency hides behind the column FFT
   float2 ha[U], hb[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int q = tid + u * NT;
-    const int fx = f0 + q / NY, fy = q % NY;
-    ha[u] = ht[(long)fx * NY + fy];
-    hb[u] = ht[(long)(fx == 0 ? nx / 2 : nx - fx) * NY + fy];
+    ha[u] = ld_off(hpos + TS::row_i(u) * NY + TS::col_i(u), off_h);
+    hb[u] = ld_off(hneg + TS::row_i(u) * NY + TS::col_i(u), off_h);
   }
   __syncthreads();
   fft_lds<NY, BC, NT, -1>(buf, tw, tid);
@@ -215,13 +253,12 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
   float2 va[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int q = tid + u * NT;
-    const int s = q / NY, fy = q % NY, fx = f0 + s;
+    const int s = st + TS::row_i(u), fy = yt + TS::col_i(u);
     const float2* col = buf + s * S;
     float2 z1 = col[skew(fy)];
     float2 z2 = c2::conj(col[skew((NY - fy) & (NY - 1))]);
     float2 a, b;
-    if (fx == 0) {
+    if (f0 + s == 0) {
       a = c2::scale(c2::add(z1, z2), 0.5f);
       float2 d = c2::sub(z1, z2);
       b = make_float2(0.5f * d.y, -0.5f * d.x);
@@ -230,27 +267,28 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
       b = z2;
     }
     va[u] = c2::mul(a, ha[u]);
-    buf[(BC + s) * S + skew(fy)] = c2::mul(b, hb[u]);
+    lds[(BC + TS::row_i(u)) * S + skew(TS::col_i(u))] = c2::mul(b, hb[u]);
   }
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int q = tid + u * NT;
-    buf[(q / NY) * S + skew(q % NY)] = va[u];
-  }
+  for (int u = 0; u < U; ++u) lds[TS::row_i(u) * S + skew(TS::col_i(u))] = va[u];
   __syncthreads();
   fft_lds<NY, 2 * BC, NT, +1>(buf, tw, tid);
+  // output row y = yo + k * RPK, sequence i: +fx column f0 + i for i < BC,
+  // else the -fx column of fx = f0 + i - BC
+  constexpr int RPK = NT / (2 * BC);
+  static_assert(NT % (2 * BC) == 0 && NY % RPK == 0, "store split");
+  const int i = tid % (2 * BC), yo = tid / (2 * BC);
+  int c = f0 + i;
+  if (i >= BC) c = f0 + i - BC == 0 ? half : nx - (f0 + i - BC);
+  const uint32_t off_out = (uint32_t)(yo * nx + c) * (uint32_t)sizeof(TIO);
   TIO* dst = out + t * (long)NY * nx;
-  for (int q = tid; q < 2 * BC * NY; q += NT) {
-    const int y = q / (2 * BC), i = q % (2 * BC);
-    int c;
-    if (i < BC) {
-      c = f0 + i;
-    } else {
-      const int fx = f0 + i - BC;
-      c = fx == 0 ? nx / 2 : nx - fx;
-    }
-    store_c(dst + (long)y * nx + c, buf[i * S + skew(y)]);
+  const float2* row = buf + i * S + skew(yo);
+#pragma unroll 4
+  for (int k = 0; k < NY / RPK; ++k) {
+    TIO v;
+    store_c(&v, row[skew(k * RPK)]);
+    st_off(dst + (long)k * RPK * nx, off_out, v);
   }
 }
 
@@ -377,10 +415,10 @@ void go_r2c(const void* in, void* out, int n, int ny, float scale, hipStream_t s
 }
 
 template <int NY, typename TIO>
-void go_col_as(const void* in, void* out, const float2* ht, int n, int nx, hipStream_t st) {
+void go_col_as(const void* in, void* out, const float2* hs, int n, int nx, hipStream_t st) {
   constexpr int BC = cap32(4096 / NY);  // nx/2 >= 32 >= BC, so BC divides nx/2
   hipLaunchKernelGGL((k_col_as<NY, BC, TIO>), dim3((nx / 2) / BC, n), dim3(NT), 0, st, (const TIO*)in,
-                     (TIO*)out, ht, nx);
+                     (TIO*)out, hs, nx);
 }
 
 template <int NX, typename TIN, typename TOUT>
@@ -455,11 +493,11 @@ hv_status launch_row_r2c(const void* in, hv_dtype in_t, void* out, bool half_out
   return launched("row_r2c");
 }
 
-hv_status launch_col_as(const void* in, void* out, bool half_io, const float2* ht, int n, int ny, int nx,
+hv_status launch_col_as(const void* in, void* out, bool half_io, const float2* hs, int n, int ny, int nx,
                         hipStream_t st) {
   if (n <= 0) return HV_OK;
-  if (half_io) { HV_SWITCH_N(ny, (go_col_as<N_, hv_h2>(in, out, ht, n, nx, st))); }
-  else { HV_SWITCH_N(ny, (go_col_as<N_, float2>(in, out, ht, n, nx, st))); }
+  if (half_io) { HV_SWITCH_N(ny, (go_col_as<N_, hv_h2>(in, out, hs, n, nx, st))); }
+  else { HV_SWITCH_N(ny, (go_col_as<N_, float2>(in, out, hs, n, nx, st))); }
   return launched("col_as");
 }
 

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.h"
+#include "gmem.h"
 #include "hv_internal.h"
 
 using namespace hvk;
@@ -168,7 +169,16 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
   fill_twiddles<NX>(tw, tid, NT);
   load_wts(wts_lds, g, tid);
   const long npix = (long)ny * NX;
+  // thread part of every element's position: row rt, column ct of the
+  // W x NX tile; byte offset off in the field (W * ny * NX * 8 B < 4 GiB)
+  using TS = TileSplit<NX, NT>;
+  const int rt = TS::row_thr(tid), ct = TS::col_thr(tid);
+  const uint32_t off = (uint32_t)(rt * ny * NX + ct) * (uint32_t)sizeof(TIN);
+  float2* lds = buf + rt * S + skew(ct);
+  // first element of unit u = (window u / ny, row u % ny): wave-uniform
   auto rows = [&](int u) { return z + (((long)(u / ny) * stride) * (long)ny + u % ny) * NX; };
+  auto at = [&](const TIN* src, int i) { return src + (long)TS::row_i(i) * npix + TS::col_i(i); };
+  auto put = [&](int i, TIN v) { lds[TS::row_i(i) * S + skew(TS::col_i(i))] = load_c(&v); };
   auto reduce = [&](int u) {
     fft_lds<NX, W, NT, +1>(buf, tw, tid);
     for (int nt = wave; nt < NX / 32; nt += NT / 64)
@@ -179,19 +189,13 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
     auto fetch = [&](int u) {
       const TIN* src = rows(u);
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int q = tid + i * NT;
-        pre[i] = src[(long)(q / NX) * npix + (q % NX)];
-      }
+      for (int i = 0; i < PER; ++i) pre[i] = ld_off(at(src, i), off);
     };
     int u = blockIdx.x;
     if (u < nunits) fetch(u);
     for (; u < nunits; u += gridDim.x) {
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int q = tid + i * NT;
-        buf[(q / NX) * S + skew(q % NX)] = load_c(&pre[i]);
-      }
+      for (int i = 0; i < PER; ++i) put(i, pre[i]);
       __syncthreads();
       if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
       reduce(u);
@@ -201,10 +205,7 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
     const int u = blockIdx.x;
     const TIN* src = rows(u);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int q = tid + i * NT;
-      buf[(q / NX) * S + skew(q % NX)] = load_c(src + (long)(q / NX) * npix + (q % NX));
-    }
+    for (int i = 0; i < PER; ++i) put(i, ld_off(at(src, i), off));
     __syncthreads();
     reduce(u);
   }
