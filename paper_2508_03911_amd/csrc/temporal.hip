@@ -40,11 +40,24 @@ __device__ inline float2 load_c(const hv_h2* p) {
   return make_float2((float)h.x, (float)h.y);
 }
 
-// One 32x32 output tile: A fragments from global memory (L1/L2 resident),
-// B from the LDS tile buf[t * S + skew(x)].
+// This lane's A fragments of one 32-row tile (FP32: W floats; mixed: W/8
+// fp16x8 hi and lo parts), held in registers so that their loads can be
+// issued long before the MFMAs need them.
+template <int W, bool MIXED>
+struct AFrag;
+template <int W>
+struct AFrag<W, false> {
+  float a[W];
+};
+template <int W>
+struct AFrag<W, true> {
+  hv_h8 hi[W / 8], lo[W / 8];
+};
+
+// One 32x32 output tile: A from registers, B from the LDS tile
+// buf[t * S + skew(x)].
 template <int W, bool MIXED, bool EXACT_B>
-__device__ inline f32x16 coef_tile(const float* __restrict__ a32, const hv_h8* __restrict__ ahi,
-                                   const hv_h8* __restrict__ alo, const float2* buf, int S, int x0, int lane,
+__device__ inline f32x16 coef_tile(const AFrag<W, MIXED>& f, const float2* buf, int S, int x0, int lane,
                                    float bsc) {
   f32x16 acc;
 #pragma unroll
@@ -53,12 +66,8 @@ __device__ inline f32x16 coef_tile(const float* __restrict__ a32, const hv_h8* _
   const int xs = skew(x0 + (lane & 31));
   if constexpr (!MIXED) {
     const float* col = reinterpret_cast<const float*>(buf + xs) + h;
-#pragma unroll 8
-    for (int kk = 0; kk < W; ++kk) {
-      float a = a32[kk * 64 + lane];
-      float b = col[2 * kk * S];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-    }
+#pragma unroll
+    for (int kk = 0; kk < W; ++kk) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[kk], col[2 * kk * S], acc, 0, 0, 0);
   } else {
 #pragma unroll
     for (int kk = 0; kk < W / 8; ++kk) {
@@ -74,11 +83,9 @@ __device__ inline f32x16 coef_tile(const float* __restrict__ a32, const hv_h8* _
           bl[2 * i + 1] = (_Float16)(y - (float)bh[2 * i + 1]);
         }
       }
-      hv_h8 a_hi = ahi[kk * 64 + lane];
-      hv_h8 a_lo = alo[kk * 64 + lane];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_lo, bh, acc, 0, 0, 0);
-      if constexpr (!EXACT_B) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.hi[kk], bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.lo[kk], bh, acc, 0, 0, 0);
+      if constexpr (!EXACT_B) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.hi[kk], bl, acc, 0, 0, 0);
     }
   }
   return acc;
@@ -97,19 +104,41 @@ struct CoefArgs {
   float2* spec;       // [nwin][npair][npix] or null
 };
 
+template <int W, bool MIXED>
+__device__ inline void load_afrag(AFrag<W, MIXED>& f, const CoefArgs& g, long jj, int mt, int lane) {
+  const long aw = g.a_win_stride * jj;
+  if constexpr (!MIXED) {
+    const float* p = g.a32 + aw + (long)mt * W * 64;
+#pragma unroll
+    for (int kk = 0; kk < W; ++kk) f.a[kk] = p[kk * 64 + lane];
+  } else {
+    const long o = (aw >> 3) + (long)mt * (W / 8) * 64;
+#pragma unroll
+    for (int kk = 0; kk < W / 8; ++kk) {
+      f.hi[kk] = g.a16hi[o + kk * 64 + lane];
+      f.lo[kk] = g.a16lo[o + kk * 64 + lane];
+    }
+  }
+}
+
 // GEMM + epilogue for the wave's pixel tile [x0, x0+32) of the LDS tile.
 // Writes outputs at out[k][obase + x0 + lane] and spec[(jj*npair + pair)*npix + obase + x0 + lane].
-template <int W, bool MIXED, bool EXACT_B>
+// PRE: f0 holds the fragments of tile 0, loaded by the caller; otherwise
+// every tile's fragments are loaded here.
+template <int W, bool MIXED, bool EXACT_B, bool PRE>
 __device__ inline void coef_pixels(const CoefArgs& g, const float* wts_lds, const float2* buf, int S, int x0,
-                                   int lane, long jj, long obase, long npix) {
+                                   int lane, long jj, long obase, long npix, const AFrag<W, MIXED>& f0) {
   const int h = lane >> 5;
   float e0 = 0.f, e1 = 0.f, e2 = 0.f;
-  const long aw = g.a_win_stride * jj;
   for (int mt = 0; mt < g.mtiles; ++mt) {
-    f32x16 acc = coef_tile<W, MIXED, EXACT_B>(g.a32 + aw + (long)mt * W * 64,
-                                              g.a16hi + (aw >> 3) + (long)mt * (W / 8) * 64,
-                                              g.a16lo + (aw >> 3) + (long)mt * (W / 8) * 64, buf, S, x0, lane,
-                                              g.bsc);
+    f32x16 acc;
+    if (PRE && mt == 0) {
+      acc = coef_tile<W, MIXED, EXACT_B>(f0, buf, S, x0, lane, g.bsc);
+    } else {
+      AFrag<W, MIXED> f;
+      load_afrag(f, g, jj, mt, lane);
+      acc = coef_tile<W, MIXED, EXACT_B>(f, buf, S, x0, lane, g.bsc);
+    }
 #pragma unroll
     for (int gq = 0; gq < 4; ++gq) {
 #pragma unroll
@@ -179,10 +208,14 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
   auto rows = [&](int u) { return z + (((long)(u / ny) * stride) * (long)ny + u % ny) * NX; };
   auto at = [&](const TIN* src, int i) { return src + (long)TS::row_i(i) * npix + TS::col_i(i); };
   auto put = [&](int i, TIN v) { lds[TS::row_i(i) * S + skew(TS::col_i(i))] = load_c(&v); };
-  auto reduce = [&](int u) {
+  // FP32 input: the A fragments are loaded before the FFT and consumed
+  // after it.  FP16 input: they are loaded in the GEMM (measured faster
+  // there: the 32 extra VGPRs across the FFT cost more than they hide).
+  auto reduce = [&](int u, const AFrag<W, MIXED>& af) {
     fft_lds<NX, W, NT, +1>(buf, tw, tid);
     for (int nt = wave; nt < NX / 32; nt += NT / 64)
-      coef_pixels<W, MIXED, false>(g, wts_lds, buf, S, nt * 32, lane, u / ny, (long)(u % ny) * NX, npix);
+      coef_pixels<W, MIXED, false, !PF>(g, wts_lds, buf, S, nt * 32, lane, u / ny, (long)(u % ny) * NX, npix,
+                                        af);
   };
   if constexpr (PF) {
     TIN pre[PER];
@@ -198,7 +231,8 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
       for (int i = 0; i < PER; ++i) put(i, pre[i]);
       __syncthreads();
       if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
-      reduce(u);
+      AFrag<W, MIXED> unused;
+      reduce(u, unused);
       __syncthreads();
     }
   } else {
@@ -206,8 +240,10 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
     const TIN* src = rows(u);
 #pragma unroll
     for (int i = 0; i < PER; ++i) put(i, ld_off(at(src, i), off));
+    AFrag<W, MIXED> af;
+    load_afrag(af, g, u / ny, 0, lane);
     __syncthreads();
-    reduce(u);
+    reduce(u, af);
   }
 }
 
@@ -224,13 +260,15 @@ __global__ __launch_bounds__(NT) void k_field_coef(const TIN* __restrict__ u, lo
   const long p0 = (long)blockIdx.x * TPIX;
   const long jj = blockIdx.y;
   load_wts(wts_lds, g, tid);
+  AFrag<W, MIXED> af;
+  load_afrag(af, g, jj, 0, lane);
   const TIN* src = u + (jj * stride) * npix + p0;
   for (int q = tid; q < W * TPIX; q += NT) {
     const int t = q / TPIX, x = q % TPIX;
     buf[t * S + skew(x)] = load_c(src + (long)t * npix + x);
   }
   __syncthreads();
-  coef_pixels<W, MIXED, EXACT>(g, wts_lds, buf, S, wave * 32, lane, jj, p0, npix);
+  coef_pixels<W, MIXED, EXACT, true>(g, wts_lds, buf, S, wave * 32, lane, jj, p0, npix, af);
 }
 
 // ------------------------------------------------------------------ Gram partials (PCA covariance)
