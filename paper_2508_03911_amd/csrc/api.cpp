@@ -301,6 +301,28 @@ DftPlan* Ctx::dft_plan(const hv_temporal& tp, hv_status* st) {
   }, st);
 }
 
+Ctx::~Ctx() {
+  for (auto& kv : lanes) {
+    if (kv.second.s) hipStreamDestroy(kv.second.s);
+    if (kv.second.fork) hipEventDestroy(kv.second.fork);
+    if (kv.second.join) hipEventDestroy(kv.second.join);
+  }
+}
+
+Ctx::Lane2* Ctx::lane2(hipStream_t caller, hv_status* st) {
+  std::lock_guard<std::recursive_mutex> lk(mu);
+  Lane2& l = lanes[(void*)caller];
+  if (!l.s) {
+    if (hipStreamCreateWithFlags(&l.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&l.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&l.join, hipEventDisableTiming) != hipSuccess) {
+      *st = fail(HV_ERR_DEVICE, "could not create the second stream");
+      return nullptr;
+    }
+  }
+  return &l;
+}
+
 DevBuf& Ctx::work(hipStream_t s, int slot) {
   std::lock_guard<std::recursive_mutex> lk(mu);
   return ws[std::make_pair((void*)s, slot)];
@@ -550,9 +572,21 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
 }
 
 // Shared driver of hv_stft_moments and hv_stft_bins.
+static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                           const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
+                           void* hip_stream, bool two_lanes);
+
+// The serving loop's entry: one stream per call (its workspaces are
+// allocated at admission).
 hv_status hvi_stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                           const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
                           void* hip_stream) {
+  return stft_impl(ctx, in, in_t, n, ny, nx, optics, tp, prec, m0, m1, m2, spec, hip_stream, false);
+}
+
+static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                           const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
+                           void* hip_stream, bool two_lanes) {
   hv_status s;
   if ((s = enter(ctx))) return s;
   std::lock_guard<std::recursive_mutex> lock(ctx->mu);
@@ -589,7 +623,19 @@ hv_status hvi_stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int ny, 
   int gw = chunk >= w ? (chunk - w) / stride + 1 : 1;
   if (gw < 1) gw = 1;
   const float fsc = mixed ? fp16_field_scale(in_t, ny, nx) : 1.f;
-  for (int j0 = 0; j0 < nwin_total; j0 += gw) {
+  // Chunks alternate between the caller's stream and a second one; not while
+  // per-kernel timing is on (its events would then time overlapping kernels).
+  Ctx::Lane2* l2 = nullptr;
+  if (two_lanes && !ctx->timing.on && nwin_total > gw) {
+    if (!(l2 = ctx->lane2(st, &s))) return s;
+    hipEventRecord(l2->fork, st);
+    hipStreamWaitEvent(l2->s, l2->fork, 0);
+  }
+  hv_status res = HV_OK;
+  const hipStream_t caller = st;
+  for (int j0 = 0, c = 0; j0 < nwin_total && res == HV_OK; j0 += gw, ++c) {
+    st = (l2 && (c & 1)) ? l2->s : caller;
+    res = [&]() -> hv_status {
     const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
     const int f0 = j0 * stride;
     const int nf = (g_n - 1) * stride + w;
@@ -616,20 +662,26 @@ hv_status hvi_stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int ny, 
            })))
         return s;
     }
+    return HV_OK;
+    }();
   }
-  return HV_OK;
+  if (l2) {  // join, also after an error, so no work of this call outlives it on the second stream
+    hipEventRecord(l2->join, l2->s);
+    hipStreamWaitEvent(caller, l2->join, 0);
+  }
+  return res;
 }
 
 hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                           const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
                           void* hip_stream) {
-  return hvi_stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, m0, m1, m2, nullptr, hip_stream);
+  return stft_impl(ctx, in, in_t, n, ny, nx, optics, temporal, prec, m0, m1, m2, nullptr, hip_stream, true);
 }
 
 hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                        const hv_temporal* temporal, int prec, void* spec, void* hip_stream) {
-  return hvi_stft_common(ctx, in, in_t, n, ny, nx, optics, temporal, prec, nullptr, nullptr, nullptr, (float2*)spec,
-                     hip_stream);
+  return stft_impl(ctx, in, in_t, n, ny, nx, optics, temporal, prec, nullptr, nullptr, nullptr, (float2*)spec,
+                   hip_stream, true);
 }
 
 hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics, int window,

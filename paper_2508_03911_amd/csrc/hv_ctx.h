@@ -90,6 +90,20 @@ struct Ctx {
   std::map<std::pair<void*, int>, DevBuf> ws;
   std::map<std::string, DevBuf> misc;  // other float64-built tables (autofocus)
 
+  // A second stream per caller stream.  The chunks of one call alternate
+  // between the caller's stream and this one (fork and join by events,
+  // default priority), so one chunk's kernels overlap the next chunk's.
+  struct Lane2 {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+  };
+  std::map<void*, Lane2> lanes;
+
+  Ctx() = default;
+  Ctx(const Ctx&) = delete;
+  Ctx& operator=(const Ctx&) = delete;
+  ~Ctx();
+  Lane2* lane2(hipStream_t caller, hv_status* st);
   AsPlan* as_plan(int ny, int nx, const hv_optics& o, hv_status* st);
   FresnelPlan* fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st);
   DftPlan* dft_plan(const hv_temporal& tp, hv_status* st);

@@ -159,6 +159,27 @@ def test_moments_overlap_ragged(ctx, hv, prec, method):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_two_streams_match_one(ctx, hv, prec):
+    """Chunks of one call alternate over two streams unless per-kernel timing
+    is on; both schedules give bit-identical moments."""
+    say(f"two-stream chunk schedule vs one stream, prec={prec}")
+    x = rand_frames(9, 200, 128, 128, np.uint8)
+    opt = hv.Optics(LAM, 20e-6, 20e-6, -0.2, hv.HV_AS)
+    tp = hv.Temporal(16, 16, 20e3, 1.5e3, 9e3)
+    ctx.set_chunk_frames(32)
+    try:
+        two = [host(t) for t in ctx.hv_stft_moments(dev(x), opt, tp, prec)]
+        ctx.set_timing(True)
+        one = [host(t) for t in ctx.hv_stft_moments(dev(x), opt, tp, prec)]
+    finally:
+        ctx.set_timing(False)
+        ctx.set_chunk_frames(0)
+    assert two[0].shape == (12, 128, 128)
+    for a, b in zip(two, one):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("window", [8, 16, 32, 64])
 def test_field_input_moments(ctx, hv, window, prec):
     say(f"field input W={window} prec={prec}")
