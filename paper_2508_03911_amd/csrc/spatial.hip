@@ -211,15 +211,30 @@ __global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT
 // fx = 0), both / ny.
 template <int NY, int BC, typename TIO>
 __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* __restrict__ out,
-                                               const float2* __restrict__ hs, int nx) {
+                                               const float2* __restrict__ hs, int nx, bool frames8) {
   constexpr int S = lds_stride(NY);
   constexpr int U = BC * NY / NT;
   static_assert(BC * NY % NT == 0, "column tile must split evenly");
   __shared__ float2 buf[2 * BC * S];
   __shared__ float2 tw[tw_size(NY) > 0 ? tw_size(NY) : 1];
   const int tid = threadIdx.x;
-  const int f0 = blockIdx.x * BC;
-  const long t = blockIdx.y;
+  // Workgroups go to the 8 XCDs round-robin by linear index.  The mirrored
+  // runs of neighbouring column groups of one frame share 128-byte lines,
+  // so when the frame count allows, all groups of a frame are given indices
+  // of one residue mod 8 (one XCD, one L2) and the partial lines merge there.
+  const int groups = nx / 2 / BC;
+  const int lin = blockIdx.x;
+  int gx, tf;
+  if (frames8) {
+    const int r = lin >> 3;
+    tf = 8 * (r / groups) + (lin & 7);
+    gx = r % groups;
+  } else {
+    tf = lin / groups;
+    gx = lin % groups;
+  }
+  const int f0 = gx * BC;
+  const long t = tf;
   const int half = nx / 2;
   fill_twiddles<NY>(tw, tid, NT);
   // element u of this thread in the BC x NY tile: column s = st + row_i(u),
@@ -417,8 +432,8 @@ void go_r2c(const void* in, void* out, int n, int ny, float scale, hipStream_t s
 template <int NY, typename TIO>
 void go_col_as(const void* in, void* out, const float2* hs, int n, int nx, hipStream_t st) {
   constexpr int BC = cap32(4096 / NY);  // nx/2 >= 32 >= BC, so BC divides nx/2
-  hipLaunchKernelGGL((k_col_as<NY, BC, TIO>), dim3((nx / 2) / BC, n), dim3(NT), 0, st, (const TIO*)in,
-                     (TIO*)out, hs, nx);
+  hipLaunchKernelGGL((k_col_as<NY, BC, TIO>), dim3((nx / 2) / BC * n), dim3(NT), 0, st, (const TIO*)in,
+                     (TIO*)out, hs, nx, n % 8 == 0);
 }
 
 template <int NX, typename TIN, typename TOUT>
