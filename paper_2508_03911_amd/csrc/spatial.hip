@@ -254,11 +254,14 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
   }
   // transfer-function values of this thread's outputs, fetched now so that
   // their latency hides behind the column FFT
+  // The angular-spectrum H depends on fx^2 + fy^2 only, so H(-fx, fy) =
+  // H(fx, fy): the -fx table is read only for the packed column fx = 0,
+  // whose -fx partner is the Nyquist column.
   float2 ha[U], hb[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     ha[u] = ld_off(hpos + TS::row_i(u) * NY + TS::col_i(u), off_h);
-    hb[u] = ld_off(hneg + TS::row_i(u) * NY + TS::col_i(u), off_h);
+    hb[u] = f0 + st + TS::row_i(u) == 0 ? ld_off(hneg + TS::row_i(u) * NY + TS::col_i(u), off_h) : ha[u];
   }
   __syncthreads();
   fft_lds<NY, BC, NT, -1>(buf, tw, tid);
