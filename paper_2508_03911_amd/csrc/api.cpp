@@ -328,11 +328,14 @@ DevBuf& Ctx::work(hipStream_t s, int slot) {
   return ws[std::make_pair((void*)s, slot)];
 }
 
-int Ctx::chunk_frames_for(int ny, int nx) const {
+int Ctx::chunk_frames_for(int ny, int nx, bool mixed) const {
   if (chunk_frames > 0) return chunk_frames;
-  // about 256 MiB of c64 spectrum + field per chunk, at least 64 frames
-  const long per = (long)ny * nx * 8 * 2;
-  long f = (256L << 20) / per;
+  // about 96 MiB of intermediate spectra per chunk (half spectrum + full
+  // spectrum = 1.5 complex values per pixel), at least 64 frames: 128 frames
+  // (FP32) and 256 (fp16) at 256 x 256, the fastest measured with two
+  // streams in flight
+  const long per = (long)ny * nx * (mixed ? 4 : 8) * 3 / 2;
+  long f = (96L << 20) / per;
   if (f < 64) f = 64;
   if (f > 2048) f = 2048;
   return (int)f;
@@ -538,7 +541,7 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
   if (!in || !out) return fail(HV_ERR_ARG, "NULL data pointer");
   hipStream_t st = (hipStream_t)hip_stream;
   const bool mixed = prec == HV_PREC_MIXED;
-  const int chunk = ctx->chunk_frames_for(ny, nx);
+  const int chunk = ctx->chunk_frames_for(ny, nx, mixed);
   const size_t frame = (size_t)ny * nx;
   for (int f0 = 0; f0 < n; f0 += chunk) {
     const int nf = n - f0 < chunk ? n - f0 : chunk;
@@ -619,7 +622,7 @@ static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny,
     return launch_field_coef(in, false, (long)frame, stride, nwin_total, g, mixed, bsc, mixed ? 1.f / bsc : 1.f, m0,
                              m1, m2, spec, st);
   }
-  const int chunk = ctx->chunk_frames_for(ny, nx);
+  const int chunk = ctx->chunk_frames_for(ny, nx, mixed);
   int gw = chunk >= w ? (chunk - w) / stride + 1 : 1;
   if (gw < 1) gw = 1;
   const float fsc = mixed ? fp16_field_scale(in_t, ny, nx) : 1.f;
@@ -711,7 +714,7 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
   const int npair = comp_hi - comp_lo + 1;
   const int mtiles = (npair + 15) / 16;
   const int nblk = (int)std::max<long>(1, std::min<long>(256, (long)frame / 4096));
-  const int chunk = ctx->chunk_frames_for(ny, nx);
+  const int chunk = ctx->chunk_frames_for(ny, nx, mixed);
   int gw = chunk >= w ? (chunk - w) / stride + 1 : 1;
   if (gw < 1) gw = 1;
   // per-window scratch

@@ -108,7 +108,7 @@ struct Ctx {
   FresnelPlan* fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st);
   DftPlan* dft_plan(const hv_temporal& tp, hv_status* st);
   DevBuf& work(hipStream_t s, int slot);
-  int chunk_frames_for(int ny, int nx) const;
+  int chunk_frames_for(int ny, int nx, bool mixed) const;
 };
 
 // Runs f() (a kernel launch), bracketed by timing events when enabled.
