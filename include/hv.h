@@ -111,7 +111,8 @@ size_t hv_ctx_workspace_bytes(const hv_ctx* ctx);
 hv_status hv_ctx_set_chunk_frames(hv_ctx* ctx, int frames);
 
 /* Per-kernel timing for profiling (Sec. VII-D): when on, every kernel launch
- * is bracketed by HIP events on the caller's stream; no work is skipped.
+ * is bracketed by HIP events on the stream it is launched on (the caller's,
+ * or the second stream of hv_stft_moments); no work is skipped.
  * Turning it on or off clears the totals. */
 hv_status hv_ctx_set_timing(hv_ctx* ctx, int on);
 /* Waits for the recorded launches and returns the total milliseconds and the
@@ -143,7 +144,11 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
  *             them may be NULL to skip it (at least one non-NULL).
  * Window j covers frames [j*stride, j*stride + W); S_j[k] =
  * sum_t U[j*stride+t] exp(-2 pi i k t / W) (rectangular, unnormalised).
- * Returns HV_ERR_SHAPE when n < W. */
+ * Returns HV_ERR_SHAPE when n < W.
+ * Ordering: the frames are processed in chunks; when there is more than one,
+ * the chunks alternate between hip_stream and a second stream the context
+ * keeps for it, forked from and joined back into hip_stream by events, so
+ * the call is ordered on hip_stream like a single launch. */
 hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                           const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
                           void* hip_stream);

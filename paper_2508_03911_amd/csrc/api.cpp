@@ -626,10 +626,11 @@ static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny,
   int gw = chunk >= w ? (chunk - w) / stride + 1 : 1;
   if (gw < 1) gw = 1;
   const float fsc = mixed ? fp16_field_scale(in_t, ny, nx) : 1.f;
-  // Chunks alternate between the caller's stream and a second one; not while
-  // per-kernel timing is on (its events would then time overlapping kernels).
+  // Chunks alternate between the caller's stream and a second one (per-kernel
+  // timing events, when on, bracket each launch on its own stream and so
+  // time it as it runs beside the other stream's work).
   Ctx::Lane2* l2 = nullptr;
-  if (two_lanes && !ctx->timing.on && nwin_total > gw) {
+  if (two_lanes && nwin_total > gw) {
     if (!(l2 = ctx->lane2(st, &s))) return s;
     hipEventRecord(l2->fork, st);
     hipStreamWaitEvent(l2->s, l2->fork, 0);

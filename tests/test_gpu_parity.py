@@ -160,19 +160,18 @@ def test_moments_overlap_ragged(ctx, hv, prec, method):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_two_streams_match_one(ctx, hv, prec):
-    """Chunks of one call alternate over two streams unless per-kernel timing
-    is on; both schedules give bit-identical moments."""
-    say(f"two-stream chunk schedule vs one stream, prec={prec}")
+    """Several chunks alternate over two streams; one chunk runs on the
+    caller's stream alone.  Both schedules give bit-identical moments."""
+    say(f"two-stream chunk schedule vs one chunk, prec={prec}")
     x = rand_frames(9, 200, 128, 128, np.uint8)
     opt = hv.Optics(LAM, 20e-6, 20e-6, -0.2, hv.HV_AS)
     tp = hv.Temporal(16, 16, 20e3, 1.5e3, 9e3)
-    ctx.set_chunk_frames(32)
     try:
+        ctx.set_chunk_frames(32)
         two = [host(t) for t in ctx.hv_stft_moments(dev(x), opt, tp, prec)]
-        ctx.set_timing(True)
+        ctx.set_chunk_frames(256)
         one = [host(t) for t in ctx.hv_stft_moments(dev(x), opt, tp, prec)]
     finally:
-        ctx.set_timing(False)
         ctx.set_chunk_frames(0)
     assert two[0].shape == (12, 128, 128)
     for a, b in zip(two, one):
