@@ -242,6 +242,43 @@ def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
     return out
 
 
+def table_iv(hv, torch, steps):
+    """The paper's Table IV Fresnel + PCA pipeline (window 32, stride 32,
+    components 1..31) at its power-of-two frame sizes, file mode (frames
+    resident in device memory), beside the paper's file-mode fps on its own
+    GPU (context, not a target)."""
+    from synth import holograms
+    paper_file_fps = {256: 53090, 512: 25200}
+    out = {}
+    ctx = hv.Context(0)
+    for side, (block, spec), reps in ((256, holograms.config_c2_block(2048), 16),
+                                      (512, holograms.stream_block(1, 1), 8)):
+        xb = torch.from_numpy(block).cuda()
+        x = xb.repeat(reps, 1, 1).contiguous()
+        del xb
+        frames = x.shape[0]
+        opt = hv.Optics(852e-9, spec.pitch, spec.pitch, -spec.z, hv.HV_FRESNEL)
+        res = {}
+        for prec, name in ((hv.HV_PREC_FP32, "fp32"), (hv.HV_PREC_MIXED, "mixed")):
+            ctx.hv_pca(x, opt, 32, 32, 1, 31, prec, want_eig=False)  # warm-up: plans and workspaces
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                ctx.hv_pca(x, opt, 32, 32, 1, 31, prec, want_eig=False)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            res[name] = {"frames_per_s": frames / (ms * 1e-3), "ms_per_pass": ms,
+                         "gigapixels_per_s": frames * side * side / (ms * 1e-3) / 1e9}
+        log(f"table IV Fresnel+PCA32 {side}x{side}: {res}")
+        out[f"{side}x{side}"] = {"frames": frames, "input": f"uint8 {side}x{side}, z = -{spec.z:.4f} m",
+                                 **res, "paper_file_fps_rtx4090": paper_file_fps[side]}
+        del x
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +290,7 @@ def main():
     ap.add_argument("--af-train", type=int, default=200000, help="autofocus training holograms (0 = skip)")
     ap.add_argument("--af-eval", type=int, default=10000)
     ap.add_argument("--af-epochs", type=int, default=3)
+    ap.add_argument("--no-table-iv", action="store_true", help="skip the Table IV Fresnel + PCA32 measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale factor for HBM counters)")
     args = ap.parse_args()
@@ -334,6 +372,9 @@ def main():
         log(f"stream load replay for {args.serve_seconds:.0f}s ...")
         line["serving"] = serving(hv, torch, args.serve_seconds, hv.HV_PREC_FP32)
         log(f"serving: {line['serving']}")
+    if not args.no_table_iv:
+        log("Table IV Fresnel + PCA32 ...")
+        line["table_iv_fresnel_pca32"] = table_iv(hv, torch, max(1, args.steps // 2))
     if args.af_train > 0:
         log("autofocus training and evaluation ...")
         line["autofocus"] = autofocus(hv, torch, args.af_train, args.af_eval, args.af_epochs)

@@ -715,79 +715,112 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
   const int npair = comp_hi - comp_lo + 1;
   const int mtiles = (npair + 15) / 16;
   const int nblk = (int)std::max<long>(1, std::min<long>(256, (long)frame / 4096));
-  const int chunk = ctx->chunk_frames_for(ny, nx, mixed);
+  // The eigensolve runs one workgroup per window, so a chunk should carry
+  // many windows: up to 64 windows, within about 2 GiB of field per stream.
+  int chunk = ctx->chunk_frames_for(ny, nx, mixed);
+  if (ctx->chunk_frames <= 0) {
+    const long by_mem = (2L << 30) / (long)(frame * (mixed ? 4 : 8));
+    const long want = std::min<long>((long)63 * stride + w, by_mem);
+    if (want > chunk) chunk = (int)want;
+  }
   int gw = chunk >= w ? (chunk - w) / stride + 1 : 1;
   if (gw < 1) gw = 1;
-  // per-window scratch
-  DevBuf& part = ctx->work(st, 10);
-  DevBuf& cv = ctx->work(st, 11);
-  DevBuf& ev = ctx->work(st, 12);
-  DevBuf& vec = ctx->work(st, 13);
-  DevBuf& a32 = ctx->work(st, 14);
-  DevBuf& a16h = ctx->work(st, 15);
-  DevBuf& a16l = ctx->work(st, 16);
-  DevBuf& wts = ctx->work(st, 17);
+  // per-window scratch of one chunk, one set per stream
+  struct Scratch {
+    void *part, *cv, *ev, *vec, *a32, *a16h, *a16l;
+  };
   const size_t M = 2 * (size_t)w;
-  if ((s = part.ensure((size_t)gw * nblk * M * M * 4, &ctx->held))) return s;
-  if ((s = cv.ensure((size_t)gw * w * w * 16, &ctx->held))) return s;
-  if ((s = ev.ensure((size_t)gw * w * 8, &ctx->held))) return s;
-  if ((s = vec.ensure((size_t)gw * w * w * 16, &ctx->held))) return s;
-  if ((s = a32.ensure((size_t)gw * mtiles * w * 64 * 4, &ctx->held))) return s;
-  if ((s = a16h.ensure((size_t)gw * mtiles * (w / 8) * 64 * 16, &ctx->held))) return s;
-  if ((s = a16l.ensure((size_t)gw * mtiles * (w / 8) * 64 * 16, &ctx->held))) return s;
+  auto scratch = [&](hipStream_t cs, Scratch* o) -> hv_status {
+    const size_t bytes[7] = {(size_t)gw * nblk * M * M * 4, (size_t)gw * w * w * 16, (size_t)gw * w * 8,
+                             (size_t)gw * w * w * 16, (size_t)gw * mtiles * w * 64 * 4,
+                             (size_t)gw * mtiles * (w / 8) * 64 * 16, (size_t)gw * mtiles * (w / 8) * 64 * 16};
+    void** dst[7] = {&o->part, &o->cv, &o->ev, &o->vec, &o->a32, &o->a16h, &o->a16l};
+    for (int i = 0; i < 7; ++i) {
+      DevBuf& b = ctx->work(cs, 10 + i);
+      hv_status e = b.ensure(bytes[i], &ctx->held);
+      if (e) return e;
+      *dst[i] = b.ptr;
+    }
+    return HV_OK;
+  };
+  DevBuf& wts = ctx->work(st, 17);  // read-only, shared by both streams
   {
     std::vector<float> hw((size_t)3 * mtiles * 16, 0.f);
     for (int i = 0; i < npair; ++i) hw[i] = 1.f;
     if ((s = wts.upload(hw.data(), hw.size() * 4, &ctx->held))) return s;
   }
   const float fsc = mixed ? fp16_field_scale(optics ? in_t : HV_C64, ny, nx) : 1.f;
-  for (int j0 = 0; j0 < nwin_total; j0 += gw) {
-    const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
-    const int f0 = j0 * stride;
-    const int nf = (g_n - 1) * stride + w;
-    const void* field;
-    bool half;
-    float fs;
-    if (optics) {
-      const char* src = (const char*)in + (size_t)f0 * frame * in_elem(in_t);
-      SpatialOut so;
-      if ((s = spatial(ctx, src, in_t, nf, ny, nx, *optics, mixed, true, fsc, st, so))) return s;
-      field = so.f;
-      half = so.half;
-      fs = so.f_scale;
-    } else {
-      field = (const float2*)in + (size_t)f0 * frame;
-      half = false;
-      fs = fsc;
-    }
-    if ((s = timed(ctx, "gram", st, [&] {
-           return launch_gram_partials(field, half, (long)frame, stride, g_n, w, mixed, half ? 1.f : fs,
-                                       (float*)part.ptr, nblk, st);
-         })))
-      return s;
-    if ((s = launch_gram_reduce((const float*)part.ptr, g_n, nblk, w, 1.0 / ((double)fs * fs), (double*)cv.ptr, st)))
-      return s;
-    if ((s = timed(ctx, "jacobi", st, [&] {
-           return launch_jacobi((const double*)cv.ptr, g_n, w, (double*)ev.ptr, (double*)vec.ptr, 40, st);
-         })))
-      return s;
-    if ((s = launch_proj_coefs((const double*)vec.ptr, g_n, w, comp_lo, comp_hi, mtiles, (float*)a32.ptr,
-                               (hv_h8*)a16h.ptr, (hv_h8*)a16l.ptr, st)))
-      return s;
-    if ((s = timed(ctx, "proj_energy", st, [&] {
-           return launch_proj_energy(field, half, (long)frame, stride, g_n, w, mtiles, npair, (const float*)a32.ptr,
-                                     (const hv_h8*)a16h.ptr, (const hv_h8*)a16l.ptr, (const float*)wts.ptr, mixed,
-                                     half ? 1.f : fs, 1.f / fs, m0 + (size_t)j0 * frame, st);
-         })))
-      return s;
-    if (eigvals && hipMemcpyAsync(eigvals + (size_t)j0 * w, ev.ptr, (size_t)g_n * w * 8, hipMemcpyDeviceToDevice,
-                                  st) != hipSuccess)
-      return fail(HV_ERR_DEVICE, "eigenvalue copy failed");
-    if (cov && hipMemcpyAsync(cov + (size_t)j0 * w * w * 2, cv.ptr, (size_t)g_n * w * w * 16,
-                              hipMemcpyDeviceToDevice, st) != hipSuccess)
-      return fail(HV_ERR_DEVICE, "covariance copy failed");
+  // Chunks alternate between the caller's stream and a second one: one
+  // chunk's eigensolve (one workgroup per window) overlaps the next chunk's
+  // transforms.
+  Ctx::Lane2* l2 = nullptr;
+  Scratch sc[2];
+  if ((s = scratch(st, &sc[0]))) return s;
+  if (nwin_total > gw) {
+    if (!(l2 = ctx->lane2(st, &s))) return s;
+    if ((s = scratch(l2->s, &sc[1]))) return s;
+    hipEventRecord(l2->fork, st);
+    hipStreamWaitEvent(l2->s, l2->fork, 0);
   }
-  return HV_OK;
+  hv_status res = HV_OK;
+  const hipStream_t caller = st;
+  for (int j0 = 0, c = 0; j0 < nwin_total && res == HV_OK; j0 += gw, ++c) {
+    const bool second = l2 && (c & 1);
+    st = second ? l2->s : caller;
+    const Scratch& x = sc[second ? 1 : 0];
+    res = [&]() -> hv_status {
+      const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
+      const int f0 = j0 * stride;
+      const int nf = (g_n - 1) * stride + w;
+      const void* field;
+      bool half;
+      float fs;
+      if (optics) {
+        const char* src = (const char*)in + (size_t)f0 * frame * in_elem(in_t);
+        SpatialOut so;
+        if ((s = spatial(ctx, src, in_t, nf, ny, nx, *optics, mixed, true, fsc, st, so))) return s;
+        field = so.f;
+        half = so.half;
+        fs = so.f_scale;
+      } else {
+        field = (const float2*)in + (size_t)f0 * frame;
+        half = false;
+        fs = fsc;
+      }
+      if ((s = timed(ctx, "gram", st, [&] {
+             return launch_gram_partials(field, half, (long)frame, stride, g_n, w, mixed, half ? 1.f : fs,
+                                         (float*)x.part, nblk, st);
+           })))
+        return s;
+      if ((s = launch_gram_reduce((const float*)x.part, g_n, nblk, w, 1.0 / ((double)fs * fs), (double*)x.cv, st)))
+        return s;
+      if ((s = timed(ctx, "jacobi", st, [&] {
+             return launch_jacobi((const double*)x.cv, g_n, w, (double*)x.ev, (double*)x.vec, 40, st);
+           })))
+        return s;
+      if ((s = launch_proj_coefs((const double*)x.vec, g_n, w, comp_lo, comp_hi, mtiles, (float*)x.a32,
+                                 (hv_h8*)x.a16h, (hv_h8*)x.a16l, st)))
+        return s;
+      if ((s = timed(ctx, "proj_energy", st, [&] {
+             return launch_proj_energy(field, half, (long)frame, stride, g_n, w, mtiles, npair, (const float*)x.a32,
+                                       (const hv_h8*)x.a16h, (const hv_h8*)x.a16l, (const float*)wts.ptr, mixed,
+                                       half ? 1.f : fs, 1.f / fs, m0 + (size_t)j0 * frame, st);
+           })))
+        return s;
+      if (eigvals && hipMemcpyAsync(eigvals + (size_t)j0 * w, x.ev, (size_t)g_n * w * 8, hipMemcpyDeviceToDevice,
+                                    st) != hipSuccess)
+        return fail(HV_ERR_DEVICE, "eigenvalue copy failed");
+      if (cov && hipMemcpyAsync(cov + (size_t)j0 * w * w * 2, x.cv, (size_t)g_n * w * w * 16,
+                                hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(HV_ERR_DEVICE, "covariance copy failed");
+      return HV_OK;
+    }();
+  }
+  if (l2) {  // join, also after an error
+    hipEventRecord(l2->join, l2->s);
+    hipStreamWaitEvent(caller, l2->join, 0);
+  }
+  return res;
 }
 
 }  // extern "C"

@@ -388,47 +388,69 @@ __device__ inline dc dadd(dc a, dc b) { return {a.x + b.x, a.y + b.y}; }
 __device__ inline dc dscale(dc a, double s) { return {a.x * s, a.y * s}; }
 __device__ inline dc dconj(dc a) { return {a.x, -a.y}; }
 
+// JT = W^2 / 2 threads per window (one per update of a rotation step), at
+// most 1024.  A and V sit in LDS with a padded row stride W + 1, so the
+// column updates (lanes walking down a column) spread over the banks.  The
+// rotation parameters use reciprocal square roots: 1/|b| once, then t and
+// c = 1/sqrt(t^2 + 1).
 template <int W>
-__global__ __launch_bounds__(NT) void k_jacobi(const double* __restrict__ cov, double* __restrict__ evals,
-                                               double* __restrict__ evecs, int max_sweeps) {
-  __shared__ dc A[W * W];
-  __shared__ dc V[W * W];
+constexpr int jacobi_threads() {
+  return W * W / 2 > 1024 ? 1024 : W * W / 2;
+}
+
+template <int W>
+__device__ inline double jacobi_sum(double v, double* red) {
+  constexpr int JT = jacobi_threads<W>();
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if constexpr (JT <= 64) {
+    return v;
+  } else {
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < JT / 64; ++i) r += red[i];
+    __syncthreads();
+    return r;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(jacobi_threads<W>()) void k_jacobi(const double* __restrict__ cov,
+                                                                double* __restrict__ evals,
+                                                                double* __restrict__ evecs, int max_sweeps) {
+  constexpr int JT = jacobi_threads<W>();
+  constexpr int WP = W + 1;  // padded row stride
+  __shared__ dc A[W * WP];
+  __shared__ dc V[W * WP];
   __shared__ int pp[W / 2], qq[W / 2];
-  __shared__ dc rc[W / 2], rs[W / 2], re[W / 2];  // c, s (real in .x), e^{-i phi}
-  __shared__ double red[NT];
+  __shared__ double rc[W / 2], rs[W / 2];  // c, s
+  __shared__ dc re[W / 2];                  // e^{-i phi}
+  __shared__ double red[JT / 64 > 0 ? JT / 64 : 1];
   __shared__ int perm[W];
   const int tid = threadIdx.x;
   const long jj = blockIdx.x;
   const dc* src = reinterpret_cast<const dc*>(cov) + jj * W * W;
-  for (int i = tid; i < W * W; i += NT) {
-    A[i] = src[i];
-    V[i] = {(i / W == i % W) ? 1.0 : 0.0, 0.0};
+  for (int i = tid; i < W * W; i += JT) {
+    const int r = i / W, c = i % W;
+    A[r * WP + c] = src[i];
+    V[r * WP + c] = {r == c ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // convergence: off-diagonal energy relative to the total
     double off = 0.0, tot = 0.0;
-    for (int i = tid; i < W * W; i += NT) {
-      const double m2 = A[i].x * A[i].x + A[i].y * A[i].y;
+    for (int i = tid; i < W * W; i += JT) {
+      const int r = i / W, c = i % W;
+      const dc v = A[r * WP + c];
+      const double m2 = v.x * v.x + v.y * v.y;
       tot += m2;
-      if (i / W != i % W) off += m2;
+      if (r != c) off += m2;
     }
-    red[tid] = off;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    const double off_all = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    const double tot_all = red[0];
-    __syncthreads();
+    const double off_all = jacobi_sum<W>(off, red);
+    const double tot_all = jacobi_sum<W>(tot, red);
     if (!(off_all > 1e-30 * tot_all)) break;
     for (int step = 0; step < W - 1; ++step) {
       if (tid < W / 2) {
@@ -442,49 +464,50 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double* __restrict__ cov, d
         }
         pp[k] = p;
         qq[k] = q;
-        const double a = A[p * W + p].x, d = A[q * W + q].x;
-        const dc b = A[p * W + q];
-        const double ab = sqrt(b.x * b.x + b.y * b.y);
-        if (ab < 1e-300) {
-          rc[k] = {1.0, 0.0};
-          rs[k] = {0.0, 0.0};
+        const double a = A[p * WP + p].x, d = A[q * WP + q].x;
+        const dc b = A[p * WP + q];
+        const double b2 = b.x * b.x + b.y * b.y;
+        if (b2 == 0.0 || b2 < 1e-300 * (a * a + d * d)) {  // |b| negligible: no rotation
+          rc[k] = 1.0;
+          rs[k] = 0.0;
           re[k] = {1.0, 0.0};
         } else {
-          const double th = (d - a) / (2.0 * ab);
+          const double inv = rsqrt(b2);  // 1 / |b|
+          const double th = 0.5 * (d - a) * inv;
           const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          const double c = 1.0 / sqrt(t * t + 1.0);
-          rc[k] = {c, 0.0};
-          rs[k] = {t * c, 0.0};
-          re[k] = {b.x / ab, -b.y / ab};  // e^{-i phi}
+          const double c = rsqrt(t * t + 1.0);
+          rc[k] = c;
+          rs[k] = t * c;
+          re[k] = {b.x * inv, -b.y * inv};  // e^{-i phi}
         }
       }
       __syncthreads();
       // columns: A[:,p] = c A[:,p] - s e A[:,q];  A[:,q] = s A[:,p] + c e A[:,q]; same for V
-      for (int i = tid; i < (W / 2) * W; i += NT) {
+      for (int i = tid; i < (W / 2) * W; i += JT) {
         const int k = i / W, r = i % W;
         const int p = pp[k], q = qq[k];
-        const double c = rc[k].x, s = rs[k].x;
+        const double c = rc[k], sn = rs[k];
         const dc e = re[k];
-        dc ap = A[r * W + p], aq = A[r * W + q];
+        dc ap = A[r * WP + p], aq = A[r * WP + q];
         dc eq = dmul(e, aq);
-        A[r * W + p] = dadd(dscale(ap, c), dscale(eq, -s));
-        A[r * W + q] = dadd(dscale(ap, s), dscale(eq, c));
-        dc vp = V[r * W + p], vq = V[r * W + q];
+        A[r * WP + p] = dadd(dscale(ap, c), dscale(eq, -sn));
+        A[r * WP + q] = dadd(dscale(ap, sn), dscale(eq, c));
+        dc vp = V[r * WP + p], vq = V[r * WP + q];
         dc ev = dmul(e, vq);
-        V[r * W + p] = dadd(dscale(vp, c), dscale(ev, -s));
-        V[r * W + q] = dadd(dscale(vp, s), dscale(ev, c));
+        V[r * WP + p] = dadd(dscale(vp, c), dscale(ev, -sn));
+        V[r * WP + q] = dadd(dscale(vp, sn), dscale(ev, c));
       }
       __syncthreads();
       // rows: A[p,:] = c A[p,:] - s conj(e) A[q,:];  A[q,:] = s A[p,:] + c conj(e) A[q,:]
-      for (int i = tid; i < (W / 2) * W; i += NT) {
+      for (int i = tid; i < (W / 2) * W; i += JT) {
         const int k = i / W, col = i % W;
         const int p = pp[k], q = qq[k];
-        const double c = rc[k].x, s = rs[k].x;
+        const double c = rc[k], sn = rs[k];
         const dc ec = dconj(re[k]);
-        dc ap = A[p * W + col], aq = A[q * W + col];
+        dc ap = A[p * WP + col], aq = A[q * WP + col];
         dc eq = dmul(ec, aq);
-        A[p * W + col] = dadd(dscale(ap, c), dscale(eq, -s));
-        A[q * W + col] = dadd(dscale(ap, s), dscale(eq, c));
+        A[p * WP + col] = dadd(dscale(ap, c), dscale(eq, -sn));
+        A[q * WP + col] = dadd(dscale(ap, sn), dscale(eq, c));
       }
       __syncthreads();
     }
@@ -495,7 +518,7 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double* __restrict__ cov, d
     for (int i = 0; i < W; ++i) {
       int best = i;
       for (int j = i + 1; j < W; ++j) {
-        const double vj = A[perm[j] * W + perm[j]].x, vb = A[perm[best] * W + perm[best]].x;
+        const double vj = A[perm[j] * WP + perm[j]].x, vb = A[perm[best] * WP + perm[best]].x;
         if (vj > vb || (vj == vb && perm[j] < perm[best])) best = j;
       }
       int t = perm[i];
@@ -504,11 +527,11 @@ __global__ __launch_bounds__(NT) void k_jacobi(const double* __restrict__ cov, d
     }
   }
   __syncthreads();
-  if (tid < W) evals[jj * W + tid] = A[perm[tid] * W + perm[tid]].x;
+  if (tid < W) evals[jj * W + tid] = A[perm[tid] * WP + perm[tid]].x;
   dc* dst = reinterpret_cast<dc*>(evecs) + jj * W * W;
-  for (int i = tid; i < W * W; i += NT) {
+  for (int i = tid; i < W * W; i += JT) {
     const int r = i / W, c = i % W;
-    dst[i] = V[r * W + perm[c]];
+    dst[i] = V[r * WP + perm[c]];
   }
 }
 
@@ -718,9 +741,15 @@ hv_status launch_jacobi(const double* cov, int nwin, int window, double* evals, 
                         hipStream_t st) {
   if (nwin <= 0) return HV_OK;
   switch (window) {
-    case 16: hipLaunchKernelGGL(k_jacobi<16>, dim3(nwin), dim3(NT), 0, st, cov, evals, evecs, max_sweeps); break;
-    case 32: hipLaunchKernelGGL(k_jacobi<32>, dim3(nwin), dim3(NT), 0, st, cov, evals, evecs, max_sweeps); break;
-    case 64: hipLaunchKernelGGL(k_jacobi<64>, dim3(nwin), dim3(NT), 0, st, cov, evals, evecs, max_sweeps); break;
+    case 16:
+      hipLaunchKernelGGL(k_jacobi<16>, dim3(nwin), dim3(jacobi_threads<16>()), 0, st, cov, evals, evecs, max_sweeps);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_jacobi<32>, dim3(nwin), dim3(jacobi_threads<32>()), 0, st, cov, evals, evecs, max_sweeps);
+      break;
+    case 64:
+      hipLaunchKernelGGL(k_jacobi<64>, dim3(nwin), dim3(jacobi_threads<64>()), 0, st, cov, evals, evecs, max_sweeps);
+      break;
     default: return fail(HV_ERR_SHAPE, "PCA window %d not supported", window);
   }
   return launched("jacobi");

@@ -179,6 +179,25 @@ def test_two_streams_match_one(ctx, hv, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_pca_two_streams_match_one(ctx, hv, prec):
+    """PCA chunks alternate over two streams as well; the result equals the
+    single-chunk run bit for bit."""
+    say(f"PCA two-stream chunk schedule vs one chunk, prec={prec}")
+    x = rand_frames(10, 200, 64, 128, np.uint8)
+    opt = hv.Optics(LAM, 20e-6, 20e-6, 0.3, hv.HV_FRESNEL)
+    try:
+        ctx.set_chunk_frames(40)
+        two = ctx.hv_pca(dev(x), opt, 16, 16, 1, 15, prec, want_cov=True)
+        ctx.set_chunk_frames(256)
+        one = ctx.hv_pca(dev(x), opt, 16, 16, 1, 15, prec, want_cov=True)
+    finally:
+        ctx.set_chunk_frames(0)
+    assert two["m0"].shape == (12, 64, 128)
+    for k in ("m0", "eigvals", "cov"):
+        assert torch.equal(two[k], one[k]), k
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("window", [8, 16, 32, 64])
 def test_field_input_moments(ctx, hv, window, prec):
     say(f"field input W={window} prec={prec}")
