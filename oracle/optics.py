@@ -47,15 +47,31 @@ def as_transfer_function(ny: int, nx: int, wavelength: float, dx: float, dy: flo
     return h
 
 
-def angular_spectrum(x, wavelength: float, dx: float, dy: float, z: float) -> np.ndarray:
+def highpass_mask(ny: int, nx: int, radius: float) -> np.ndarray:
+    """The spatial high-pass filter of the paper's angular-spectrum benchmark
+    (Sec. VI-B.1 names it, without a formula).  Reading: an ideal circular
+    mask on the DFT grid that keeps every bin whose frequency, in cycles per
+    pixel, lies at or beyond ``radius`` from the origin:
+    (k_x / nx)^2 + (k_y / ny)^2 >= radius^2 with signed indices k (fftfreq).
+    ``radius = 0`` keeps everything.  Returns a float64 [ny, nx] of 0 and 1."""
+    ux = np.fft.fftfreq(nx)
+    uy = np.fft.fftfreq(ny)
+    return ((ux[None, :] ** 2 + uy[:, None] ** 2) >= radius ** 2).astype(np.float64)
+
+
+def angular_spectrum(x, wavelength: float, dx: float, dy: float, z: float,
+                     highpass: float = 0.0) -> np.ndarray:
     """Propagate each frame of ``x`` ([..., ny, nx], real or complex) by ``z``.
 
     U = IDFT2( DFT2(x) * H_z ), the angular-spectrum method named in the
     Abstract and Sec. II-B.3.  With the 1/(nx ny) on the inverse only, the
-    operator is unitary when no component is evanescent."""
+    operator is unitary when no component is evanescent.  ``highpass > 0``
+    multiplies the spectrum by ``highpass_mask`` as well."""
     x = np.asarray(x)
     ny, nx = x.shape[-2:]
     h = as_transfer_function(ny, nx, wavelength, dx, dy, z)
+    if highpass > 0:
+        h = h * highpass_mask(ny, nx, highpass)
     spectrum = np.fft.fft2(x.astype(np.complex128), axes=(-2, -1))
     return np.fft.ifft2(spectrum * h, axes=(-2, -1))
 

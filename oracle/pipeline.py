@@ -30,6 +30,7 @@ class Optics:
     dy: float
     z: float
     method: int = AS
+    highpass: float = 0.0  # AS only: high-pass radius in cycles per pixel (0 = none)
 
 
 def reconstruct(frames, opt: Optics | None) -> np.ndarray:
@@ -43,8 +44,10 @@ def reconstruct(frames, opt: Optics | None) -> np.ndarray:
     if opt is None:
         return x.astype(np.complex128)
     if opt.method == AS:
-        return _optics.angular_spectrum(x, opt.wavelength, opt.dx, opt.dy, opt.z)
+        return _optics.angular_spectrum(x, opt.wavelength, opt.dx, opt.dy, opt.z, opt.highpass)
     if opt.method == FRESNEL:
+        if opt.highpass:
+            raise ValueError("the high-pass filter belongs to the angular-spectrum path")
         return _optics.fresnel(x, opt.wavelength, opt.dx, opt.dy, opt.z)
     raise ValueError(f"unknown method {opt.method}")
 
@@ -85,3 +88,18 @@ def pca_render(frames, opt: Optics | None, window: int, stride: int, c1: int = 1
     if not res:
         return _pca.pca(np.zeros((0,) + frames.shape[1:], np.complex128), window, stride, c1, c2)
     return {k: np.stack([r[k] for r in res]) for k in res[0]}
+
+
+def stft_volume(frames, opt: Optics | None, window: int, stride: int) -> np.ndarray:
+    """The paper's STFT benchmark output (Sec. VI-B.1: the temporal transform
+    over a whole window, rendered as a volume): |S_j[k]|^2 for every bin
+    k = 0 .. W-1 of every complete window, [J, W, ny, nx] float64.  Reading:
+    the power of each bin, bins in DFT order."""
+    frames = np.asarray(frames)
+    j_count = _temporal.n_windows(frames.shape[0], window, stride)
+    out = np.zeros((j_count, window) + frames.shape[1:])
+    for j in range(j_count):
+        u = reconstruct(frames[j * stride: j * stride + window], opt)
+        s = _temporal.stft(u, window, window)[0]
+        out[j] = s.real ** 2 + s.imag ** 2
+    return out

@@ -202,3 +202,44 @@ def pca_rank1_error(pca_window_fn, w=6, ny=5, nx=7):
     return max(abs(r["eigvals"][0] - lam0) / lam0,
                float(np.max(np.abs(r["eigvals"][1:]))) / lam0,
                float(np.max(r["m0"])) / lam0)
+
+
+# ---------------------------------------------------------------- high-pass filter and power volume
+
+def highpass_plane_wave_error(as_hp_fn, radius=0.12, z=0.07, ny=24, nx=32, dx=20e-6, dy=15e-6):
+    """Plane waves on the DFT grid: the ones inside the radius vanish, the
+    ones outside propagate exactly (closed form), whatever their mix."""
+    y, x = np.mgrid[0:ny, 0:nx]
+    waves = [(0, 0, 1.0), (1, 2, 0.5 - 0.2j), (-2, 1, 0.3j),   # radius < 0.12 cycles/px
+             (5, -7, 0.8), (-8, 11, -0.4 + 0.1j), (12, 0, 0.25)]  # radius > 0.12
+    field = np.zeros((ny, nx), np.complex128)
+    want = np.zeros((ny, nx), np.complex128)
+    for ky, kx, a in waves:
+        e = a * np.exp(2j * math.pi * (kx * x / nx + ky * y / ny))
+        field += e
+        r2 = (kx / nx) ** 2 + (ky / ny) ** 2
+        if r2 >= radius ** 2:
+            fx, fy = kx / (nx * dx), ky / (ny * dy)
+            kz = math.sqrt(LAMBDA ** -2 - fx * fx - fy * fy)
+            want += e * cmath.exp(2j * math.pi * z * kz)
+    return rel(as_hp_fn(field, LAMBDA, dx, dy, z, radius), want)
+
+
+def volume_errors(volume_fn, window=16, ny=3, nx=4):
+    """Closed forms for the per-bin power: a pure tone e^{2 i pi k0 t / W}
+    with amplitude a gives W^2 |a|^2 in bin k0 and 0 elsewhere; random data
+    obeys Parseval per window (sum_k |S_k|^2 = W sum_t |u_t|^2)."""
+    t = np.arange(2 * window)
+    k0 = 3
+    a = (0.7 - 0.4j) * np.ones((ny, nx))
+    u = a[None] * np.exp(2j * math.pi * k0 * t / window)[:, None, None]
+    v = volume_fn(u, window, window)
+    want = np.zeros_like(v)
+    want[:, k0] = window ** 2 * abs(a[0, 0]) ** 2
+    e_tone = float(np.max(np.abs(v - want)) / (window ** 2))
+    rng = np.random.default_rng(12)
+    r = rng.standard_normal((3 * window, ny, nx)) + 1j * rng.standard_normal((3 * window, ny, nx))
+    v = volume_fn(r, window, window)
+    e = np.stack([(np.abs(r[j * window:(j + 1) * window]) ** 2).sum(axis=0) for j in range(3)])
+    e_pars = float(np.max(np.abs(v.sum(axis=1) - window * e)) / np.max(window * e))
+    return e_tone, e_pars

@@ -148,3 +148,38 @@ def pca_range_exclusive(u, c1, c2):
 @pytest.mark.parametrize("mutant", [pca_conj_cov, pca_ascending, pca_range_exclusive])
 def test_pca_mutants_rejected(mutant):
     assert pins.pca_construction_error(mutant) > 1e-6
+
+
+# ---------------------------------------------------------------- high-pass and volume mutants
+
+def hp_lowpass(x, lam, dx, dy, z, radius):
+    """keeps the inside of the circle instead of the outside"""
+    full = optics.angular_spectrum(x, lam, dx, dy, z)
+    return full - optics.angular_spectrum(x, lam, dx, dy, z, radius)
+
+
+def hp_radius_in_index_units(x, lam, dx, dy, z, radius):
+    """radius compared with the index k instead of k / n"""
+    ny, nx = np.shape(x)[-2:]
+    return optics.angular_spectrum(x, lam, dx, dy, z, radius * nx)
+
+
+@pytest.mark.parametrize("mutant", [hp_lowpass, hp_radius_in_index_units])
+def test_highpass_mutants_rejected(mutant):
+    assert pins.highpass_plane_wave_error(mutant) > 1e-6
+
+
+def vol_magnitude(u, w, s):
+    from oracle import pipeline
+    return np.sqrt(pipeline.stft_volume(u, None, w, s))
+
+
+def vol_reversed_bins(u, w, s):
+    from oracle import pipeline
+    return pipeline.stft_volume(u, None, w, s)[:, ::-1]
+
+
+@pytest.mark.parametrize("mutant", [vol_magnitude, vol_reversed_bins])
+def test_volume_mutants_rejected(mutant):
+    e_tone, e_pars = pins.volume_errors(mutant)
+    assert max(e_tone, e_pars) > 1e-6

@@ -225,3 +225,21 @@ def test_empty_and_short_stacks():
     res = pipeline.pca_render(x, None, 16, 16)
     assert res["m0"].shape == (0, 8, 8)
     assert math.isclose(temporal.band_bins(16, 1e3, 0, 500)[1][-1], 500.0)
+
+
+def test_highpass_plane_waves():
+    assert pins.highpass_plane_wave_error(optics.angular_spectrum) < 1e-12
+
+
+def test_highpass_zero_radius_is_plain_as():
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((2, 16, 24))
+    a = optics.angular_spectrum(x, pins.LAMBDA, 20e-6, 20e-6, 0.1)
+    b = optics.angular_spectrum(x, pins.LAMBDA, 20e-6, 20e-6, 0.1, 0.0)
+    assert np.array_equal(a, b)
+
+
+def test_volume_tone_and_parseval():
+    from oracle import pipeline
+    e_tone, e_pars = pins.volume_errors(lambda u, w, s: pipeline.stft_volume(u, None, w, s))
+    assert e_tone < 1e-12 and e_pars < 1e-12
