@@ -75,13 +75,18 @@ typedef enum { HV_PREC_FP32 = 0, HV_PREC_MIXED = 1 } hv_precision;
 
 typedef struct hv_ctx hv_ctx;
 
-/* Spatial step (Abstract; Sec. II-B.3; Sec. III-B.1). */
+/* Spatial step (Abstract; Sec. II-B.3; Sec. III-B.1).  highpass_cpp is the
+ * spatial high-pass filter of the angular-spectrum benchmark (Sec. VI-B.1):
+ * the spectrum keeps the DFT bins with (k_x/nx)^2 + (k_y/ny)^2 >= r^2 (signed
+ * indices k, r in cycles per pixel); 0 = no filter.  AS only (HV_ERR_ARG for
+ * Fresnel); 0 <= r < 1. */
 typedef struct {
   double wavelength_m;
   double pitch_x_m;
   double pitch_y_m;
   double z_m;   /* signed propagation distance, metres; != 0 for Fresnel */
   int method;   /* hv_method */
+  double highpass_cpp;
 } hv_optics;
 
 /* Temporal step (Sec. III-B.1; Sec. VI-B: window and stride).  The band
@@ -157,6 +162,18 @@ hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, 
  *   spec [J][nbins][ny][nx] c64, nbins as returned by hv_band_bins. */
 hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                        const hv_temporal* temporal, int prec, void* spec, void* hip_stream);
+
+/* The full-band STFT volume of the paper's STFT benchmark (Sec. VI-B.1:
+ * angular spectrum with the spatial high-pass filter of hv_optics, then the
+ * temporal transform over whole windows of W = 128, 256 or 512 frames,
+ * every bin rendered): a radix FFT per pixel and window,
+ *   power [J][W][ny][nx] float32 = |S_j[k]|^2, k in DFT order,
+ * J = floor((n - W)/stride) + 1.  in: camera frames (HV_U8/HV_U16) with
+ * optics, or a field (HV_C64) with optics NULL.  Chunks alternate over two
+ * streams as in hv_stft_moments.  HV_ERR_SHAPE when n < W or W is not
+ * supported. */
+hv_status hv_stft_volume(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                         int window, int stride, int prec, float* power, void* hip_stream);
 
 /* The band's bins and frequencies as the library decides them (host call).
  * bins/freqs may be NULL; *nbins receives the count. */

@@ -142,7 +142,10 @@ static hv_status build_as_table(size_t* held, AsPlan& p) {
       const double fy = (cy < (ny + 1) / 2 ? cy : cy - ny) / (ny * p.dy);
       const double rad = inv_l2 - fx * fx - fy * fy;
       double re = 0.0, im = 0.0;
-      if (rad > 0) {
+      const double ux = (cx < (nx + 1) / 2 ? cx : cx - nx) / (double)nx;  // cycles per pixel
+      const double uy = (cy < (ny + 1) / 2 ? cy : cy - ny) / (double)ny;
+      const bool keep = p.highpass <= 0 || ux * ux + uy * uy >= p.highpass * p.highpass;
+      if (rad > 0 && keep) {
         const double ph = 2.0 * M_PI * p.z * std::sqrt(rad);
         re = std::cos(ph) / ny;
         im = std::sin(ph) / ny;
@@ -249,7 +252,7 @@ static auto* plan_lookup(Ctx* c, Map& m, const Key& key, Make make, hv_status* s
 }
 
 AsPlan* Ctx::as_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
-  auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m);
+  auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m, o.highpass_cpp);
   return plan_lookup(this, as_plans, key, [&](size_t* bytes, hv_status* e) {
     auto p = std::make_unique<AsPlan>();
     p->ny = ny;
@@ -258,6 +261,7 @@ AsPlan* Ctx::as_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
     p->dx = o.pitch_x_m;
     p->dy = o.pitch_y_m;
     p->z = o.z_m;
+    p->highpass = o.highpass_cpp;
     *e = build_as_table(bytes, *p);
     if (*e) p.reset();
     return p;
@@ -265,7 +269,7 @@ AsPlan* Ctx::as_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
 }
 
 FresnelPlan* Ctx::fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
-  auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m);
+  auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m, 0.0);
   return plan_lookup(this, fr_plans, key, [&](size_t* bytes, hv_status* e) {
     auto p = std::make_unique<FresnelPlan>();
     p->ny = ny;
@@ -360,6 +364,9 @@ static hv_status check_optics(const hv_optics* o) {
     return fail(HV_ERR_ARG, "wavelength and pitches must be positive, z finite");
   if (o->method != HV_AS && o->method != HV_FRESNEL) return fail(HV_ERR_ARG, "unknown method %d", o->method);
   if (o->method == HV_FRESNEL && o->z_m == 0.0) return fail(HV_ERR_ARG, "Fresnel transform needs z != 0");
+  if (!(o->highpass_cpp >= 0 && o->highpass_cpp < 1)) return fail(HV_ERR_ARG, "high-pass radius outside [0, 1)");
+  if (o->method == HV_FRESNEL && o->highpass_cpp > 0)
+    return fail(HV_ERR_ARG, "the high-pass filter belongs to the angular-spectrum path");
   return HV_OK;
 }
 
@@ -686,6 +693,64 @@ hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
                        const hv_temporal* temporal, int prec, void* spec, void* hip_stream) {
   return stft_impl(ctx, in, in_t, n, ny, nx, optics, temporal, prec, nullptr, nullptr, nullptr, (float2*)spec,
                    hip_stream, true);
+}
+
+hv_status hv_stft_volume(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                         int window, int stride, int prec, float* power, void* hip_stream) {
+  hv_status s;
+  if ((s = enter(ctx))) return s;
+  std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+  if ((s = check_frame(n, ny, nx))) return s;
+  if (window != 128 && window != 256 && window != 512)
+    return fail(HV_ERR_SHAPE, "volume window %d: use 128, 256 or 512", window);
+  if (stride <= 0) return fail(HV_ERR_ARG, "stride must be positive");
+  if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
+  if (optics) {
+    if ((s = check_optics(optics)) || (s = check_dtype(in_t, true))) return s;
+  } else if (in_t != HV_C64) {
+    return fail(HV_ERR_ARG, "without optics the input must be a field (HV_C64)");
+  }
+  if (n < window) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, window);
+  if (!in || !power) return fail(HV_ERR_ARG, "NULL data pointer");
+  const bool mixed = prec == HV_PREC_MIXED;
+  const int w = window;
+  const int nwin_total = (n - w) / stride + 1;
+  const size_t frame = (size_t)ny * nx;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!optics)
+    return timed(ctx, "time_fft", st, [&] {
+      return launch_time_fft(in, false, (long)frame, stride, nwin_total, w, 1.f, power, st);
+    });
+  const int chunk = std::max(ctx->chunk_frames_for(ny, nx, mixed), w);
+  const int gw = (chunk - w) / stride + 1;
+  const float fsc = mixed ? fp16_field_scale(in_t, ny, nx) : 1.f;
+  // chunks alternate between the caller's stream and a second one
+  Ctx::Lane2* l2 = nullptr;
+  if (nwin_total > gw) {
+    if (!(l2 = ctx->lane2(st, &s))) return s;
+    hipEventRecord(l2->fork, st);
+    hipStreamWaitEvent(l2->s, l2->fork, 0);
+  }
+  hv_status res = HV_OK;
+  const hipStream_t caller = st;
+  for (int j0 = 0, c = 0; j0 < nwin_total && res == HV_OK; j0 += gw, ++c) {
+    st = (l2 && (c & 1)) ? l2->s : caller;
+    const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
+    const int nf = (g_n - 1) * stride + w;
+    const char* src = (const char*)in + (size_t)j0 * stride * frame * in_elem(in_t);
+    SpatialOut so;
+    res = spatial(ctx, src, in_t, nf, ny, nx, *optics, mixed, true, fsc, st, so);
+    if (res == HV_OK)
+      res = timed(ctx, "time_fft", st, [&] {
+        return launch_time_fft(so.f, so.half, (long)frame, stride, g_n, w, 1.f / (so.f_scale * so.f_scale),
+                               power + (size_t)j0 * w * frame, st);
+      });
+  }
+  if (l2) {  // join, also after an error
+    hipEventRecord(l2->join, l2->s);
+    hipStreamWaitEvent(caller, l2->join, 0);
+  }
+  return res;
 }
 
 hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics, int window,

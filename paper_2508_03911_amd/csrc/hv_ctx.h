@@ -33,7 +33,8 @@ struct DevBuf {
 struct AsPlan {
   int ny = 0, nx = 0;
   double wavelength = 0, dx = 0, dy = 0, z = 0;
-  DevBuf ht;  // [nx][ny] float2: H_z(fx = column, fy) / ny
+  double highpass = 0;  // radius in cycles per pixel, folded into the tables (0 = none)
+  DevBuf ht;  // [nx][ny] float2: H_z(fx = column, fy) * mask / ny
   DevBuf hs;  // [2][nx/2][ny] float2: H_z(fx, fy) / ny, then H_z(-fx, fy) / ny (fx = 0: nx/2)
   const float2* ht_ptr() const { return (const float2*)ht.ptr; }
   const float2* hs_ptr() const { return (const float2*)hs.ptr; }
@@ -83,7 +84,7 @@ struct Ctx {
   size_t budget = 0;
   size_t held = 0;  // bytes of plans and workspaces
   int chunk_frames = 0;
-  using OptKey = std::tuple<int, int, double, double, double, double>;
+  using OptKey = std::tuple<int, int, double, double, double, double, double>;
   std::map<OptKey, std::unique_ptr<AsPlan>> as_plans;
   std::map<OptKey, std::unique_ptr<FresnelPlan>> fr_plans;
   std::map<std::tuple<int, std::vector<int>, std::vector<double>>, std::unique_ptr<DftPlan>> dft_plans;

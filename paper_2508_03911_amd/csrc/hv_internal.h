@@ -97,4 +97,9 @@ hv_status launch_proj_energy(const void* u, bool half_in, long npix, int stride,
                              const float* wts, bool mixed, float b_scale, float out_scale, float* m0,
                              hipStream_t st);
 
+// Full-band STFT power of every complete window: a radix FFT over W frames
+// (128, 256 or 512) per pixel, out [nwin][W][npix] f32 = |S_k|^2 * amp2.
+hv_status launch_time_fft(const void* u, bool half_in, long npix, int stride, int nwin, int window, float amp2,
+                          float* out, hipStream_t st);
+
 }  // namespace hvi

@@ -386,11 +386,12 @@ hv_status hv_stream_close(hv_stream* s) {
       for (hv_stream* o : sv->streams)
         shared |= o->ny == s->ny && o->nx == s->nx && o->optics.method == s->optics.method &&
                   o->optics.z_m == s->optics.z_m && o->optics.wavelength_m == s->optics.wavelength_m &&
-                  o->optics.pitch_x_m == s->optics.pitch_x_m && o->optics.pitch_y_m == s->optics.pitch_y_m;
+                  o->optics.pitch_x_m == s->optics.pitch_x_m && o->optics.pitch_y_m == s->optics.pitch_y_m &&
+                  o->optics.highpass_cpp == s->optics.highpass_cpp;
     }
     if (!shared) {
       auto key = std::make_tuple(s->ny, s->nx, s->optics.wavelength_m, s->optics.pitch_x_m, s->optics.pitch_y_m,
-                                 s->optics.z_m);
+                                 s->optics.z_m, s->optics.method == HV_AS ? s->optics.highpass_cpp : 0.0);
       auto ia = ctx->as_plans.find(key);
       if (s->optics.method == HV_AS && ia != ctx->as_plans.end()) {
         ctx->held -= ia->second->ht.bytes;

@@ -271,6 +271,47 @@ __global__ __launch_bounds__(NT) void k_field_coef(const TIN* __restrict__ u, lo
   coef_pixels<W, MIXED, EXACT, true>(g, wts_lds, buf, S, wave * 32, lane, jj, p0, npix, af);
 }
 
+// ------------------------------------------------------------------ full-band STFT power (temporal FFT)
+// The paper's STFT benchmark transforms whole windows of W = 128..512 frames
+// and renders every bin (Sec. VI-B.1).  Block (pixel tile, window j): the W
+// samples of PT = 8192 / W pixels sit in LDS as PT sequences; a radix FFT
+// transforms them and |S_k|^2 * amp2 goes out for every bin k:
+// out[(j * W + k) * npix + p].  Element i of a thread is pixel pt and time
+// (or bin) tt + i * TPI, TPI = NT / PT.
+template <int W, typename TIN>
+__global__ __launch_bounds__(NT) void k_time_fft(const TIN* __restrict__ u, int npix, int stride, float amp2,
+                                                 float* __restrict__ out) {
+  constexpr int PT = 8192 / W;
+  constexpr int TPI = NT / PT;
+  constexpr int PER = W / TPI;
+  constexpr int S = lds_stride(W);
+  static_assert(NT % PT == 0 && W % TPI == 0, "tile split");
+  __shared__ float2 buf[PT * S];
+  __shared__ float2 tw[tw_size(W)];
+  const int tid = threadIdx.x;
+  const long p0 = (long)blockIdx.x * PT;
+  const long jj = blockIdx.y;
+  fill_twiddles<W>(tw, tid, NT);
+  const int pt = tid % PT, tt = tid / PT;
+  float2* lds = buf + pt * S + skew(tt);
+  const TIN* src = u + (jj * stride) * (long)npix + p0;
+  const uint32_t off_in = (uint32_t)(tt * npix + pt) * (uint32_t)sizeof(TIN);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const TIN v = ld_off(src + (long)i * TPI * npix, off_in);
+    lds[skew(i * TPI)] = load_c(&v);
+  }
+  __syncthreads();
+  fft_lds<W, PT, NT, -1>(buf, tw, tid);
+  float* dst = out + jj * W * (long)npix + p0;
+  const uint32_t off_out = (uint32_t)(tt * npix + pt) * 4u;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const float2 v = lds[skew(i * TPI)];
+    st_off(dst + (long)i * TPI * npix, off_out, (v.x * v.x + v.y * v.y) * amp2);
+  }
+}
+
 // ------------------------------------------------------------------ Gram partials (PCA covariance)
 // Block (blk, jj) accumulates G = B^T B over its pixel range for window jj.
 // LDS holds the tile transposed, L[m][p] with m = 2t + c, so both MFMA
@@ -770,6 +811,28 @@ hv_status launch_proj_energy(const void* u, bool half_in, long npix, int stride,
   CoefGemm g{window, mtiles, npair, a32, a16hi, a16lo, wts, 1};
   CoefArgs a = make_args(g, (long)mtiles * window * 64, b_scale, out_scale, m0, nullptr, nullptr, nullptr);
   return field_coef(u, half_in, npix, stride, nwin, a, window, mixed, st);
+}
+
+hv_status launch_time_fft(const void* u, bool half_in, long npix, int stride, int nwin, int window, float amp2,
+                          float* out, hipStream_t st) {
+  if (nwin <= 0) return HV_OK;
+  if (npix % (8192 / window) != 0 || npix > (1L << 24)) return fail(HV_ERR_SHAPE, "pixel count %ld", npix);
+  const dim3 grid((unsigned)(npix / (8192 / window)), nwin);
+#define HV_TFFT(WV)                                                                                          \
+  if (half_in)                                                                                                \
+    hipLaunchKernelGGL((k_time_fft<WV, hv_h2>), grid, dim3(NT), 0, st, (const hv_h2*)u, (int)npix, stride,  \
+                       amp2, out);                                                                            \
+  else                                                                                                        \
+    hipLaunchKernelGGL((k_time_fft<WV, float2>), grid, dim3(NT), 0, st, (const float2*)u, (int)npix, stride, \
+                       amp2, out);
+  switch (window) {
+    case 128: HV_TFFT(128) break;
+    case 256: HV_TFFT(256) break;
+    case 512: HV_TFFT(512) break;
+    default: return fail(HV_ERR_SHAPE, "volume window %d: use 128, 256 or 512", window);
+  }
+#undef HV_TFFT
+  return launched("time_fft");
 }
 
 }  // namespace hvi

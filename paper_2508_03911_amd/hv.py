@@ -45,7 +45,7 @@ lib = _load()
 
 class hv_optics(C.Structure):
     _fields_ = [("wavelength_m", C.c_double), ("pitch_x_m", C.c_double), ("pitch_y_m", C.c_double),
-                ("z_m", C.c_double), ("method", C.c_int)]
+                ("z_m", C.c_double), ("method", C.c_int), ("highpass_cpp", C.c_double)]
 
 
 class hv_temporal(C.Structure):
@@ -98,6 +98,7 @@ _sig = {
     "hv_stft_moments": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P, _P,
                              _P]),
     "hv_stft_bins": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P]),
+    "hv_stft_volume": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _P, _P]),
     "hv_stream_open": (_I, [_P, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _I, C.POINTER(_P)]),
     "hv_stream_push": (_I, [_P, _P, _I, C.POINTER(C.c_int64)]),
     "hv_stream_pop": (_I, [_P, _P, _P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -144,9 +145,10 @@ class Optics:
     pitch_y: float
     z: float
     method: int = HV_AS
+    highpass: float = 0.0
 
     def c(self) -> hv_optics:
-        return hv_optics(self.wavelength, self.pitch_x, self.pitch_y, self.z, self.method)
+        return hv_optics(self.wavelength, self.pitch_x, self.pitch_y, self.z, self.method, self.highpass)
 
 
 @dataclass(frozen=True)
@@ -277,6 +279,18 @@ class Context:
         _check(lib.hv_stft_bins(self.handle, _ptr(x), _dtype_code(x), n, ny, nx,
                                 C.byref(op) if op is not None else None, C.byref(tp), prec, _ptr(out),
                                 _stream(x.device)))
+        return out
+
+    def hv_stft_volume(self, x: torch.Tensor, optics: Optics | None, window: int, stride: int,
+                       prec: int = HV_PREC_FP32, out=None) -> torch.Tensor:
+        n, ny, nx = _frames(x)
+        j = 0 if n < window else (n - window) // stride + 1
+        if out is None:
+            out = torch.empty((j, window, ny, nx), dtype=torch.float32, device=x.device)
+        op = optics.c() if optics is not None else None
+        _check(lib.hv_stft_volume(self.handle, _ptr(x), _dtype_code(x), n, ny, nx,
+                                  C.byref(op) if op is not None else None, window, stride, prec, _ptr(out),
+                                  _stream(x.device)))
         return out
 
     # ---------------------------------------------------------------- PCA
