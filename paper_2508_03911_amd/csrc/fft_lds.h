@@ -110,20 +110,19 @@ __device__ inline void dft_reg(float2* v) {
 
 // ---------------------------------------------------------------- passes
 
-constexpr int radix_of_pass(int n, int pass) {
-  // radices: 16 while the remaining factor allows it, then the remainder
-  int rem = n;
-  int r = 1;
-  for (int p = 0; p <= pass; ++p) {
-    r = rem >= 16 ? 16 : rem;
-    rem /= r;
-  }
-  return r;
+// n = 2^L is split into P = ceil(L / 4) passes of nearly equal radix
+// (exponents differ by at most one, the larger ones last): 256 = 16 x 16,
+// 512 = 8 x 8 x 8, 1024 = 8 x 8 x 16, 128 = 8 x 16, 64 = 8 x 8.  A lone
+// radix-2 pass would cost a full LDS round trip for one add per element.
+constexpr int log2_of(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
 }
-constexpr int num_passes(int n) {
-  int p = 0;
-  for (int rem = n; rem > 1; rem /= (rem >= 16 ? 16 : rem)) ++p;
-  return p;
+constexpr int num_passes(int n) { return (log2_of(n) + 3) / 4; }
+constexpr int radix_of_pass(int n, int pass) {
+  const int l = log2_of(n), p = num_passes(n);
+  return 1 << ((l + pass) / p);
 }
 
 // ---------------------------------------------------------------- twiddles

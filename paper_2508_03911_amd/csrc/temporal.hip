@@ -289,8 +289,13 @@ __global__ __launch_bounds__(NT) void k_time_fft(const TIN* __restrict__ u, int 
   __shared__ float2 buf[PT * S];
   __shared__ float2 tw[tw_size(W)];
   const int tid = threadIdx.x;
-  const long p0 = (long)blockIdx.x * PT;
-  const long jj = blockIdx.y;
+  // Workgroups go to the 8 XCDs round-robin by linear index; tiles 2m and
+  // 2m + 1 (whose 64-byte output runs share 128-byte lines) are given
+  // indices of one residue mod 8, so the lines merge in one L2.
+  const int tiles = npix / PT;  // a multiple of 16
+  const int lin = blockIdx.x % tiles, q = lin >> 3;
+  const long p0 = (long)(16 * (q >> 1) + 2 * (lin & 7) + (q & 1)) * PT;
+  const long jj = blockIdx.x / tiles;
   fill_twiddles<W>(tw, tid, NT);
   const int pt = tid % PT, tt = tid / PT;
   float2* lds = buf + pt * S + skew(tt);
@@ -816,8 +821,8 @@ hv_status launch_proj_energy(const void* u, bool half_in, long npix, int stride,
 hv_status launch_time_fft(const void* u, bool half_in, long npix, int stride, int nwin, int window, float amp2,
                           float* out, hipStream_t st) {
   if (nwin <= 0) return HV_OK;
-  if (npix % (8192 / window) != 0 || npix > (1L << 24)) return fail(HV_ERR_SHAPE, "pixel count %ld", npix);
-  const dim3 grid((unsigned)(npix / (8192 / window)), nwin);
+  if (npix % (16L * (8192 / window)) != 0 || npix > (1L << 24)) return fail(HV_ERR_SHAPE, "pixel count %ld", npix);
+  const dim3 grid((unsigned)(npix / (8192 / window) * nwin));
 #define HV_TFFT(WV)                                                                                          \
   if (half_in)                                                                                                \
     hipLaunchKernelGGL((k_time_fft<WV, hv_h2>), grid, dim3(NT), 0, st, (const hv_h2*)u, (int)npix, stride,  \
