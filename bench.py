@@ -321,6 +321,36 @@ def table_iv_volume(hv, torch, steps, highpass=0.05):
     return out
 
 
+def host_ingest(hv, torch, block, spec, frames, steps):
+    """The same 256x256 stream with its frames in pinned host memory and the
+    moment images returned to pinned host memory: every frame crosses PCIe
+    (the paper's camera-side path).  PCIe-inclusive context, not the
+    headline value."""
+    reps = frames // block.shape[0]
+    xh = torch.empty((reps * block.shape[0],) + block.shape[1:], dtype=torch.uint8, pin_memory=True)
+    src = torch.from_numpy(block)
+    for r in range(reps):
+        xh[r * block.shape[0]:(r + 1) * block.shape[0]].copy_(src)
+    ctx = hv.Context(0)
+    opt = hv.Optics(852e-9, spec.pitch, spec.pitch, -spec.z, hv.HV_AS)
+    tp = hv.Temporal(W, W, spec.fs, 3e3, 35e3)
+    res = {}
+    for prec, name in ((hv.HV_PREC_FP32, "fp32"), (hv.HV_PREC_MIXED, "mixed")):
+        out = ctx.hv_stft_moments_host(xh, opt, tp, prec)  # warm-up; allocates the pinned images
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.hv_stft_moments_host(xh, opt, tp, prec, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"frames_per_s": xh.shape[0] / dt, "ms_per_pass": dt * 1e3,
+                     "h2d_GBs": xh.numel() / dt / 1e9}
+    ctx.close()
+    log(f"host ingest: {res}")
+    return {"frames": int(xh.shape[0]), **res,
+            "note": "frames in pinned host memory, images back to pinned host memory; PCIe-inclusive"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +363,7 @@ def main():
     ap.add_argument("--af-eval", type=int, default=10000)
     ap.add_argument("--af-epochs", type=int, default=3)
     ap.add_argument("--no-table-iv", action="store_true", help="skip the Table IV measurements")
+    ap.add_argument("--no-host-ingest", action="store_true", help="skip the pinned-host (PCIe) measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale factor for HBM counters)")
     args = ap.parse_args()
@@ -414,6 +445,9 @@ def main():
         log(f"stream load replay for {args.serve_seconds:.0f}s ...")
         line["serving"] = serving(hv, torch, args.serve_seconds, hv.HV_PREC_FP32)
         log(f"serving: {line['serving']}")
+    if not args.no_host_ingest:
+        log("host ingest (PCIe) ...")
+        line["host_ingest"] = host_ingest(hv, torch, block, spec, frames, max(1, args.steps // 3))
     if not args.no_table_iv:
         log("Table IV Fresnel + PCA32 ...")
         line["table_iv_fresnel_pca32"] = table_iv(hv, torch, max(1, args.steps // 2))

@@ -158,6 +158,19 @@ hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, 
                           const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
                           void* hip_stream);
 
+/* hv_stft_moments from host memory (the paper's camera path: frames arrive
+ * in host memory and cross PCIe, Sec. II-B.4, VII).  host_in is pinned host
+ * memory (hipHostMalloc) [n][ny][nx] HV_U8/HV_U16; host_m0..m2 are pinned
+ * host buffers [J][ny][nx] float32 (NULL = skip, at least one non-NULL).
+ * Chunks of frames are uploaded, processed and their images downloaded on
+ * alternating streams (hip_stream and the context's second stream), so the
+ * copies of one chunk overlap the kernels of the other; the call is ordered
+ * on hip_stream and the images are complete once hip_stream has drained.
+ * Pageable host memory also works but the copies then do not overlap. */
+hv_status hv_stft_moments_host(hv_ctx* ctx, const void* host_in, int in_t, int n, int ny, int nx,
+                               const hv_optics* optics, const hv_temporal* temporal, int prec, float* host_m0,
+                               float* host_m1, float* host_m2, void* hip_stream);
+
 /* The windowed spectrum itself on the band bins, in band order:
  *   spec [J][nbins][ny][nx] c64, nbins as returned by hv_band_bins. */
 hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,

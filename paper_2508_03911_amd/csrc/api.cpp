@@ -695,6 +695,79 @@ hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
                    hip_stream, true);
 }
 
+hv_status hv_stft_moments_host(hv_ctx* ctx, const void* host_in, int in_t, int n, int ny, int nx,
+                               const hv_optics* optics, const hv_temporal* tp, int prec, float* host_m0,
+                               float* host_m1, float* host_m2, void* hip_stream) {
+  hv_status s;
+  if ((s = enter(ctx))) return s;
+  std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+  if ((s = check_frame(n, ny, nx)) || (s = check_optics(optics)) || (s = check_dtype(in_t, false))) return s;
+  if (!tp) return fail(HV_ERR_ARG, "temporal is NULL");
+  const int w = tp->window, stride = tp->stride;
+  if (stride <= 0 || w <= 0) return fail(HV_ERR_ARG, "window and stride must be positive");
+  if (n < w) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, w);
+  if (!host_in) return fail(HV_ERR_ARG, "input is NULL");
+  if (!host_m0 && !host_m1 && !host_m2) return fail(HV_ERR_ARG, "no output requested");
+  const bool mixed = prec == HV_PREC_MIXED;
+  const int nwin_total = (n - w) / stride + 1;
+  const size_t frame = (size_t)ny * nx, fbytes = frame * in_elem(in_t);
+  const int chunk = std::max(ctx->chunk_frames_for(ny, nx, mixed), w);
+  const int gw = (chunk - w) / stride + 1;
+  const int cf = (gw - 1) * stride + w;  // frames staged per chunk
+  hipStream_t st = (hipStream_t)hip_stream;
+  float* const host_out[3] = {host_m0, host_m1, host_m2};
+  // staging per stream: raw frames in, moment images out
+  auto stage = [&](hipStream_t cs, void** in_dev, float** out_dev) -> hv_status {
+    DevBuf& bi = ctx->work(cs, 20);
+    hv_status e = bi.ensure((size_t)cf * fbytes, &ctx->held);
+    if (e) return e;
+    *in_dev = bi.ptr;
+    for (int k = 0; k < 3; ++k) {
+      out_dev[k] = nullptr;
+      if (!host_out[k]) continue;
+      DevBuf& bo = ctx->work(cs, 21 + k);
+      if ((e = bo.ensure((size_t)gw * frame * 4, &ctx->held))) return e;
+      out_dev[k] = (float*)bo.ptr;
+    }
+    return HV_OK;
+  };
+  void* in_dev[2];
+  float* out_dev[2][3];
+  if ((s = stage(st, &in_dev[0], out_dev[0]))) return s;
+  Ctx::Lane2* l2 = nullptr;
+  if (nwin_total > gw) {
+    if (!(l2 = ctx->lane2(st, &s))) return s;
+    if ((s = stage(l2->s, &in_dev[1], out_dev[1]))) return s;
+    hipEventRecord(l2->fork, st);
+    hipStreamWaitEvent(l2->s, l2->fork, 0);
+  }
+  // Each chunk is copied in, processed and copied out on its own stream;
+  // with two streams one chunk's copies overlap the other chunk's kernels.
+  hv_status res = HV_OK;
+  for (int j0 = 0, c = 0; j0 < nwin_total && res == HV_OK; j0 += gw, ++c) {
+    const int lane = (l2 && (c & 1)) ? 1 : 0;
+    const hipStream_t cs = lane ? l2->s : st;
+    const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
+    const int nf = (g_n - 1) * stride + w;
+    if (hipMemcpyAsync(in_dev[lane], (const char*)host_in + (size_t)j0 * stride * fbytes, (size_t)nf * fbytes,
+                       hipMemcpyHostToDevice, cs) != hipSuccess) {
+      res = fail(HV_ERR_DEVICE, "frame upload failed");
+      break;
+    }
+    res = stft_impl(ctx, in_dev[lane], in_t, nf, ny, nx, optics, tp, prec, out_dev[lane][0], out_dev[lane][1],
+                    out_dev[lane][2], nullptr, cs, false);
+    for (int k = 0; k < 3 && res == HV_OK; ++k)
+      if (host_out[k] && hipMemcpyAsync(host_out[k] + (size_t)j0 * frame, out_dev[lane][k],
+                                        (size_t)g_n * frame * 4, hipMemcpyDeviceToHost, cs) != hipSuccess)
+        res = fail(HV_ERR_DEVICE, "image download failed");
+  }
+  if (l2) {  // join, also after an error
+    hipEventRecord(l2->join, l2->s);
+    hipStreamWaitEvent(st, l2->join, 0);
+  }
+  return res;
+}
+
 hv_status hv_stft_volume(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                          int window, int stride, int prec, float* power, void* hip_stream) {
   hv_status s;

@@ -99,6 +99,8 @@ _sig = {
                              _P]),
     "hv_stft_bins": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P]),
     "hv_stft_volume": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _P, _P]),
+    "hv_stft_moments_host": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P,
+                                  _P, _P, _P]),
     "hv_stream_open": (_I, [_P, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _I, C.POINTER(_P)]),
     "hv_stream_push": (_I, [_P, _P, _I, C.POINTER(C.c_int64)]),
     "hv_stream_pop": (_I, [_P, _P, _P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -182,10 +184,13 @@ def _stream(device) -> C.c_void_p:
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def _frames(x: torch.Tensor):
+def _frames(x: torch.Tensor, host: bool = False):
     if x.dim() != 3:
         raise ValueError("expected a [frames, ny, nx] tensor")
-    if not x.is_cuda or not x.is_contiguous():
+    if host:
+        if x.is_cuda or not x.is_pinned() or not x.is_contiguous():
+            raise ValueError("input must be a contiguous pinned host tensor")
+    elif not x.is_cuda or not x.is_contiguous():
         raise ValueError("input must be a contiguous device tensor")
     return x.shape[0], x.shape[1], x.shape[2]
 
@@ -279,6 +284,23 @@ class Context:
         _check(lib.hv_stft_bins(self.handle, _ptr(x), _dtype_code(x), n, ny, nx,
                                 C.byref(op) if op is not None else None, C.byref(tp), prec, _ptr(out),
                                 _stream(x.device)))
+        return out
+
+    def hv_stft_moments_host(self, x: torch.Tensor, optics: Optics, temporal: Temporal,
+                             prec: int = HV_PREC_FP32, out=None, stream=None):
+        """x: pinned host frames; out: pinned host tensors [J][ny][nx] float32
+        (allocated pinned when None).  Synchronise ``stream`` (default: the
+        current device stream) before reading ``out``."""
+        n, ny, nx = _frames(x, host=True)
+        if out is not None and any(o.is_cuda or not o.is_pinned() or not o.is_contiguous() for o in out):
+            raise ValueError("outputs must be contiguous pinned host tensors")
+        j = self.n_windows(n, temporal)
+        if out is None:
+            out = [torch.empty((j, ny, nx), dtype=torch.float32, pin_memory=True) for _ in range(3)]
+        op, tp = optics.c(), temporal.c()
+        st = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _check(lib.hv_stft_moments_host(self.handle, _ptr(x), _dtype_code(x), n, ny, nx, C.byref(op), C.byref(tp),
+                                        prec, _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), C.c_void_p(st)))
         return out
 
     def hv_stft_volume(self, x: torch.Tensor, optics: Optics | None, window: int, stride: int,
