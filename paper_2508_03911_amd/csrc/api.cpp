@@ -351,10 +351,15 @@ using namespace hvi;
 
 // ---------------------------------------------------------------- validation helpers
 
+// Frame sides: powers of two in [64, 1024], or the mixed-radix sides of the
+// paper's Table IV frames (1280 x 800, 512 x 320, 384 x 384).
+static bool side_ok(int n) { return pow2_in(n, 64, 1024) || n == 320 || n == 384 || n == 800 || n == 1280; }
+
 static hv_status check_frame(int n, int ny, int nx) {
   if (n < 0) return fail(HV_ERR_SHAPE, "negative frame count");
-  if (!pow2_in(nx, 64, 1024) || !pow2_in(ny, 64, 1024))
-    return fail(HV_ERR_SHAPE, "frame %dx%d: nx and ny must be powers of two in [64, 1024]", nx, ny);
+  if (!side_ok(nx) || !side_ok(ny))
+    return fail(HV_ERR_SHAPE, "frame %dx%d: sides must be powers of two in [64, 1024] or 320, 384, 800, 1280", nx,
+                ny);
   return HV_OK;
 }
 
@@ -423,7 +428,8 @@ hv_status spatial(Ctx* c, const void* in, int in_t, int nf, int ny, int nx, cons
     if (!p) return s;
     DevBuf& zb = c->work(st, 1);
     if ((s = zb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
-    if (in_t == HV_C64) {
+    if (in_t == HV_C64 || !pow2_in(nx, 64, 1024) || !pow2_in(ny, 64, 1024)) {
+      // complex rows (no real-input packing), full columns: any supported side
       DevBuf& tb = c->work(st, 0);
       if ((s = tb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
       if ((s = timed(c, "rows_c2c", st, [&] { return launch_rows_c2c(in, in_t, tb.ptr, mixed, nullptr, nullptr, -1, nf, ny, nx, s1, st); }))) return s;

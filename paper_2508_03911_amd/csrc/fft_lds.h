@@ -73,6 +73,32 @@ template <int R, int DIR>
 __device__ inline void dft_reg(float2* v) {
   if constexpr (R == 2) {
     dft2<DIR>(v[0], v[1]);
+  } else if constexpr (R == 3) {
+    // X1,2 = a0 - (a1 + a2)/2 +- DIR i (sqrt(3)/2) (a1 - a2)
+    constexpr float H3 = 0.86602540378443865f;  // sqrt(3)/2
+    const float2 t = c2::add(v[1], v[2]);
+    const float2 d = c2::rot<DIR>(c2::scale(c2::sub(v[1], v[2]), H3));
+    const float2 m = make_float2(v[0].x - 0.5f * t.x, v[0].y - 0.5f * t.y);
+    v[0] = c2::add(v[0], t);
+    v[1] = c2::add(m, d);
+    v[2] = c2::sub(m, d);
+  } else if constexpr (R == 5) {
+    // with t1 = a1 + a4, t2 = a2 + a3, t3 = a1 - a4, t4 = a2 - a3:
+    // X1,4 = a0 + c1 t1 + c2 t2 +- DIR i (s1 t3 + s2 t4)
+    // X2,3 = a0 + c2 t1 + c1 t2 +- DIR i (s2 t3 - s1 t4)
+    constexpr float C1 = 0.30901699437494742f, C2 = -0.80901699437494742f;  // cos(2pi/5), cos(4pi/5)
+    constexpr float S1 = 0.95105651629515357f, S2 = 0.58778525229247313f;   // sin(2pi/5), sin(4pi/5)
+    const float2 t1 = c2::add(v[1], v[4]), t2 = c2::add(v[2], v[3]);
+    const float2 t3 = c2::sub(v[1], v[4]), t4 = c2::sub(v[2], v[3]);
+    const float2 m1 = make_float2(v[0].x + C1 * t1.x + C2 * t2.x, v[0].y + C1 * t1.y + C2 * t2.y);
+    const float2 m2 = make_float2(v[0].x + C2 * t1.x + C1 * t2.x, v[0].y + C2 * t1.y + C1 * t2.y);
+    const float2 r1 = c2::rot<DIR>(make_float2(S1 * t3.x + S2 * t4.x, S1 * t3.y + S2 * t4.y));
+    const float2 r2 = c2::rot<DIR>(make_float2(S2 * t3.x - S1 * t4.x, S2 * t3.y - S1 * t4.y));
+    v[0] = c2::add(v[0], c2::add(t1, t2));
+    v[1] = c2::add(m1, r1);
+    v[4] = c2::sub(m1, r1);
+    v[2] = c2::add(m2, r2);
+    v[3] = c2::sub(m2, r2);
   } else if constexpr (R == 4) {
     dft4<DIR>(v[0], v[1], v[2], v[3]);
   } else if constexpr (R == 8) {
@@ -110,19 +136,41 @@ __device__ inline void dft_reg(float2* v) {
 
 // ---------------------------------------------------------------- passes
 
-// n = 2^L is split into P = ceil(L / 4) passes of nearly equal radix
-// (exponents differ by at most one, the larger ones last): 256 = 16 x 16,
-// 512 = 8 x 8 x 8, 1024 = 8 x 8 x 16, 128 = 8 x 16, 64 = 8 x 8.  A lone
-// radix-2 pass would cost a full LDS round trip for one add per element.
+// n = 5^c 3^b 2^L: first one radix-5 pass per factor 5 and one radix-3
+// pass per factor 3, then 2^L split into P = ceil(L / 4) passes of nearly
+// equal radix (exponents differ by at most one, the larger ones last):
+// 256 = 16 x 16, 512 = 8 x 8 x 8, 1024 = 8 x 8 x 16, 128 = 8 x 16,
+// 1280 = 5 x 16 x 16, 800 = 5 x 5 x 4 x 8, 384 = 3 x 8 x 16, 320 = 5 x 8 x 8.
+// A lone radix-2 pass would cost a full LDS round trip for one add per
+// element.
 constexpr int log2_of(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;
   return l;
 }
-constexpr int num_passes(int n) { return (log2_of(n) + 3) / 4; }
+constexpr int count_factor(int n, int f) {
+  int c = 0;
+  while (n % f == 0) {
+    n /= f;
+    ++c;
+  }
+  return c;
+}
+constexpr int pow2_part(int n) {
+  while (n % 5 == 0) n /= 5;
+  while (n % 3 == 0) n /= 3;
+  return n;
+}
+constexpr int num_passes(int n) {
+  const int m = pow2_part(n);
+  return count_factor(n, 5) + count_factor(n, 3) + (m > 1 ? (log2_of(m) + 3) / 4 : 0);
+}
 constexpr int radix_of_pass(int n, int pass) {
-  const int l = log2_of(n), p = num_passes(n);
-  return 1 << ((l + pass) / p);
+  const int c5 = count_factor(n, 5), c3 = count_factor(n, 3);
+  if (pass < c5) return 5;
+  if (pass < c5 + c3) return 3;
+  const int l = log2_of(pow2_part(n)), p = (l + 3) / 4;
+  return 1 << ((l + pass - c5 - c3) / p);
 }
 
 // ---------------------------------------------------------------- twiddles

@@ -422,6 +422,11 @@ __global__ __launch_bounds__(NT) void k_fresnel_cols(const TIN* __restrict__ in,
 
 constexpr int cap64(int r) { return r > 64 ? 64 : r; }
 constexpr int cap32(int r) { return r > 32 ? 32 : r; }
+constexpr int p2floor(int r) {
+  int p = 1;
+  while (2 * p <= r) p *= 2;
+  return p;
+}
 
 template <int NX, typename TIN, typename TOUT>
 void go_r2c(const void* in, void* out, int n, int ny, float scale, hipStream_t st) {
@@ -441,7 +446,7 @@ void go_col_as(const void* in, void* out, const float2* hs, int n, int nx, hipSt
 
 template <int NX, typename TIN, typename TOUT>
 void go_row_inv(const void* in, void* out, int n, int ny, float scale, hipStream_t st) {
-  constexpr int ROWS = cap64(8192 / NX);
+  constexpr int ROWS = cap64(p2floor(8192 / NX));
   hipLaunchKernelGGL((k_row_inv<NX, ROWS, TIN, TOUT>), dim3(ny / ROWS, n), dim3(NT), 0, st, (const TIN*)in,
                      (TOUT*)out, ny, scale);
 }
@@ -449,7 +454,7 @@ void go_row_inv(const void* in, void* out, int n, int ny, float scale, hipStream
 template <int NX, typename TIN, typename TOUT>
 void go_rows(const void* in, void* out, const float2* qx, const float2* qy, int dir, int n, int ny, float scale,
              hipStream_t st) {
-  constexpr int ROWS = cap64(8192 / NX);
+  constexpr int ROWS = cap64(p2floor(8192 / NX));
   if (dir < 0)
     hipLaunchKernelGGL((k_rows_c2c<NX, ROWS, TIN, TOUT, -1>), dim3(ny / ROWS, n), dim3(NT), 0, st,
                        (const TIN*)in, (TOUT*)out, qx, qy, ny, scale);
@@ -460,7 +465,7 @@ void go_rows(const void* in, void* out, const float2* qx, const float2* qy, int 
 
 template <int NY, typename TIO>
 void go_col_full(const void* in, void* out, const float2* ht, int n, int nx, hipStream_t st) {
-  constexpr int BC = cap32(8192 / NY);
+  constexpr int BC = cap32(p2floor(8192 / NY));
   hipLaunchKernelGGL((k_col_full<NY, BC, TIO>), dim3(nx / BC, n), dim3(NT), 0, st, (const TIO*)in, (TIO*)out, ht,
                      nx);
 }
@@ -468,7 +473,7 @@ void go_col_full(const void* in, void* out, const float2* ht, int n, int nx, hip
 template <int NY, typename TIN, typename TOUT>
 void go_fr_cols(const void* in, void* out, const float2* qx, const float2* qy, int dir, int n, int nx,
                 float scale, hipStream_t st) {
-  constexpr int BC = cap32(8192 / NY);
+  constexpr int BC = cap32(p2floor(8192 / NY));
   if (dir < 0)
     hipLaunchKernelGGL((k_fresnel_cols<NY, BC, TIN, TOUT, -1>), dim3(nx / BC, n), dim3(NT), 0, st,
                        (const TIN*)in, (TOUT*)out, qx, qy, nx, scale);
@@ -483,7 +488,9 @@ hv_status launched(const char* what) {
   return HV_OK;
 }
 
-// Calls F<N>(args...) for N in {64, 128, 256, 512, 1024}.
+// Calls F<N>(args...) for N in {64, 128, 256, 512, 1024} (the real-input
+// row pass, the column pass of the angular spectrum and the fused temporal
+// kernel, which rely on power-of-two sides).
 #define HV_SWITCH_N(n, CALL)          \
   switch (n) {                        \
     case 64: { constexpr int N_ = 64; CALL; } break;     \
@@ -491,6 +498,21 @@ hv_status launched(const char* what) {
     case 256: { constexpr int N_ = 256; CALL; } break;   \
     case 512: { constexpr int N_ = 512; CALL; } break;   \
     case 1024: { constexpr int N_ = 1024; CALL; } break; \
+    default: return hvi::fail(HV_ERR_SHAPE, "size %d not supported", n); \
+  }
+// The complex row and column passes also take the mixed-radix sides of the
+// paper's Table IV frames: 320, 384, 800 and 1280.
+#define HV_SWITCH_NG(n, CALL)         \
+  switch (n) {                        \
+    case 64: { constexpr int N_ = 64; CALL; } break;     \
+    case 128: { constexpr int N_ = 128; CALL; } break;   \
+    case 256: { constexpr int N_ = 256; CALL; } break;   \
+    case 320: { constexpr int N_ = 320; CALL; } break;   \
+    case 384: { constexpr int N_ = 384; CALL; } break;   \
+    case 512: { constexpr int N_ = 512; CALL; } break;   \
+    case 800: { constexpr int N_ = 800; CALL; } break;   \
+    case 1024: { constexpr int N_ = 1024; CALL; } break; \
+    case 1280: { constexpr int N_ = 1280; CALL; } break; \
     default: return hvi::fail(HV_ERR_SHAPE, "size %d not supported", n); \
   }
 
@@ -523,11 +545,11 @@ hv_status launch_row_inv(const void* in, bool half_in, void* out, bool half_out,
                          float scale, hipStream_t st) {
   if (n <= 0) return HV_OK;
   if (half_in) {
-    if (half_out) { HV_SWITCH_N(nx, (go_row_inv<N_, hv_h2, hv_h2>(in, out, n, ny, scale, st))); }
-    else { HV_SWITCH_N(nx, (go_row_inv<N_, hv_h2, float2>(in, out, n, ny, scale, st))); }
+    if (half_out) { HV_SWITCH_NG(nx, (go_row_inv<N_, hv_h2, hv_h2>(in, out, n, ny, scale, st))); }
+    else { HV_SWITCH_NG(nx, (go_row_inv<N_, hv_h2, float2>(in, out, n, ny, scale, st))); }
   } else {
-    if (half_out) { HV_SWITCH_N(nx, (go_row_inv<N_, float2, hv_h2>(in, out, n, ny, scale, st))); }
-    else { HV_SWITCH_N(nx, (go_row_inv<N_, float2, float2>(in, out, n, ny, scale, st))); }
+    if (half_out) { HV_SWITCH_NG(nx, (go_row_inv<N_, float2, hv_h2>(in, out, n, ny, scale, st))); }
+    else { HV_SWITCH_NG(nx, (go_row_inv<N_, float2, float2>(in, out, n, ny, scale, st))); }
   }
   return launched("row_inv");
 }
@@ -536,8 +558,8 @@ hv_status launch_rows_c2c(const void* in, int in_t, void* out, bool half_out, co
                           int dir, int n, int ny, int nx, float scale, hipStream_t st) {
   if (n <= 0) return HV_OK;
 #define HV_ROWS_T(TIN)                                                                                     \
-  if (half_out) { HV_SWITCH_N(nx, (go_rows<N_, TIN, hv_h2>(in, out, qx, qy, dir, n, ny, scale, st))); }   \
-  else { HV_SWITCH_N(nx, (go_rows<N_, TIN, float2>(in, out, qx, qy, dir, n, ny, scale, st))); }
+  if (half_out) { HV_SWITCH_NG(nx, (go_rows<N_, TIN, hv_h2>(in, out, qx, qy, dir, n, ny, scale, st))); }   \
+  else { HV_SWITCH_NG(nx, (go_rows<N_, TIN, float2>(in, out, qx, qy, dir, n, ny, scale, st))); }
   if (in_t == HV_U8) {
     HV_ROWS_T(uint8_t)
   } else if (in_t == HV_U16) {
@@ -552,8 +574,8 @@ hv_status launch_rows_c2c(const void* in, int in_t, void* out, bool half_out, co
 hv_status launch_col_full(const void* in, void* out, bool half_io, const float2* ht, int n, int ny, int nx,
                           hipStream_t st) {
   if (n <= 0) return HV_OK;
-  if (half_io) { HV_SWITCH_N(ny, (go_col_full<N_, hv_h2>(in, out, ht, n, nx, st))); }
-  else { HV_SWITCH_N(ny, (go_col_full<N_, float2>(in, out, ht, n, nx, st))); }
+  if (half_io) { HV_SWITCH_NG(ny, (go_col_full<N_, hv_h2>(in, out, ht, n, nx, st))); }
+  else { HV_SWITCH_NG(ny, (go_col_full<N_, float2>(in, out, ht, n, nx, st))); }
   return launched("col_full");
 }
 
@@ -561,11 +583,11 @@ hv_status launch_fresnel_cols(const void* in, bool half_in, void* out, bool half
                               const float2* qy, int dir, int n, int ny, int nx, float scale, hipStream_t st) {
   if (n <= 0) return HV_OK;
   if (half_in) {
-    if (half_out) { HV_SWITCH_N(ny, (go_fr_cols<N_, hv_h2, hv_h2>(in, out, qx, qy, dir, n, nx, scale, st))); }
-    else { HV_SWITCH_N(ny, (go_fr_cols<N_, hv_h2, float2>(in, out, qx, qy, dir, n, nx, scale, st))); }
+    if (half_out) { HV_SWITCH_NG(ny, (go_fr_cols<N_, hv_h2, hv_h2>(in, out, qx, qy, dir, n, nx, scale, st))); }
+    else { HV_SWITCH_NG(ny, (go_fr_cols<N_, hv_h2, float2>(in, out, qx, qy, dir, n, nx, scale, st))); }
   } else {
-    if (half_out) { HV_SWITCH_N(ny, (go_fr_cols<N_, float2, hv_h2>(in, out, qx, qy, dir, n, nx, scale, st))); }
-    else { HV_SWITCH_N(ny, (go_fr_cols<N_, float2, float2>(in, out, qx, qy, dir, n, nx, scale, st))); }
+    if (half_out) { HV_SWITCH_NG(ny, (go_fr_cols<N_, float2, hv_h2>(in, out, qx, qy, dir, n, nx, scale, st))); }
+    else { HV_SWITCH_NG(ny, (go_fr_cols<N_, float2, float2>(in, out, qx, qy, dir, n, nx, scale, st))); }
   }
   return launched("fresnel_cols");
 }

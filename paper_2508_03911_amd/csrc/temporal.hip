@@ -718,7 +718,9 @@ void go_gram(const void* u, bool half_in, long npix, int stride, int nwin, long 
 
 namespace hvi {
 
-bool rowinv_coef_fits(int nx, int window) { return (long)nx * window <= 8192 && ((long)nx * window) % NT == 0; }
+bool rowinv_coef_fits(int nx, int window) {
+  return (nx & (nx - 1)) == 0 && (long)nx * window <= 8192 && ((long)nx * window) % NT == 0;
+}
 
 hv_status launch_rowinv_coef(const void* z, bool half_in, int ny, int nx, int stride, int nwin, const CoefGemm& g,
                              bool mixed, float b_scale, float out_scale, float* out0, float* out1, float* out2,
