@@ -242,81 +242,91 @@ def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
     return out
 
 
-def table_iv(hv, torch, steps):
-    """The paper's Table IV Fresnel + PCA pipeline (window 32, stride 32,
-    components 1..31) at its power-of-two frame sizes, file mode (frames
-    resident in device memory), beside the paper's file-mode fps on its own
-    GPU (context, not a target)."""
+# The paper's Table IV: frame sizes (ny, nx), frames per timed pass, and its
+# file-mode fps on an RTX 4090 for the two pipelines (context, not targets).
+TABLE_IV = (
+    ((256, 256), 16384, {"as_hp_stft512": 88100, "fresnel_pca32": 53090}),
+    ((512, 512), 4096, {"as_hp_stft512": 23100, "fresnel_pca32": 25200}),
+    ((320, 512), 8192, {"as_hp_stft512": 35900, "fresnel_pca32": 37850}),
+    ((384, 384), 8192, {"as_hp_stft512": 39000, "fresnel_pca32": 40270}),
+    ((800, 1280), 2048, {"as_hp_stft512": 6100, "fresnel_pca32": 6650}),
+)
+
+
+def table_iv_inputs(torch):
+    """Synthetic u8 stacks of the Table IV sizes resident in device memory: a
+    base block from the generator (z drawn in [0.1, 0.4] m) replayed to the
+    pass length."""
     from synth import holograms
-    paper_file_fps = {256: 53090, 512: 25200}
+    out = []
+    for k, ((ny, nx), frames, paper) in enumerate(TABLE_IV):
+        t0 = time.time()
+        if (ny, nx) == (256, 256):
+            block, spec = holograms.config_c2_block(2048)
+        else:
+            spec = holograms.HoloSpec(frames=64 if ny * nx <= 512 * 512 else 32, ny=ny, nx=nx,
+                                      z=holograms.drawn_z(20 + k), fs=20e3, seed=20 + k)
+            block = holograms.hologram_stack(spec)
+        xb = torch.from_numpy(block).cuda()
+        x = xb.repeat(frames // block.shape[0], 1, 1).contiguous()
+        del xb
+        log(f"Table IV input {ny}x{nx}: {block.shape[0]}-frame block in {time.time() - t0:.1f}s, {frames} frames")
+        out.append(((ny, nx), x, spec, paper))
+    return out
+
+
+def _timed_passes(torch, fn, steps):
+    fn()  # warm-up: plans and workspaces
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def table_iv(hv, torch, inputs, steps):
+    """The paper's Table IV Fresnel + PCA pipeline (window 32, stride 32,
+    components 1..31) at its five frame sizes, file mode."""
     out = {}
     ctx = hv.Context(0)
-    for side, (block, spec), reps in ((256, holograms.config_c2_block(2048), 16),
-                                      (512, holograms.stream_block(1, 1), 8)):
-        xb = torch.from_numpy(block).cuda()
-        x = xb.repeat(reps, 1, 1).contiguous()
-        del xb
+    for (ny, nx), x, spec, paper in inputs:
         frames = x.shape[0]
         opt = hv.Optics(852e-9, spec.pitch, spec.pitch, -spec.z, hv.HV_FRESNEL)
         res = {}
         for prec, name in ((hv.HV_PREC_FP32, "fp32"), (hv.HV_PREC_MIXED, "mixed")):
-            ctx.hv_pca(x, opt, 32, 32, 1, 31, prec, want_eig=False)  # warm-up: plans and workspaces
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(steps):
-                ctx.hv_pca(x, opt, 32, 32, 1, 31, prec, want_eig=False)
-            b.record()
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / steps
+            ms = _timed_passes(torch, lambda: ctx.hv_pca(x, opt, 32, 32, 1, 31, prec, want_eig=False), steps)
             res[name] = {"frames_per_s": frames / (ms * 1e-3), "ms_per_pass": ms,
-                         "gigapixels_per_s": frames * side * side / (ms * 1e-3) / 1e9}
-        log(f"table IV Fresnel+PCA32 {side}x{side}: {res}")
-        out[f"{side}x{side}"] = {"frames": frames, "input": f"uint8 {side}x{side}, z = -{spec.z:.4f} m",
-                                 **res, "paper_file_fps_rtx4090": paper_file_fps[side]}
-        del x
+                         "gigapixels_per_s": frames * ny * nx / (ms * 1e-3) / 1e9}
+        log(f"table IV Fresnel+PCA32 {nx}x{ny}: {res}")
+        out[f"{nx}x{ny}"] = {"frames": frames, **res, "paper_file_fps_rtx4090": paper["fresnel_pca32"]}
     ctx.close()
     return out
 
 
-def table_iv_volume(hv, torch, steps, highpass=0.05):
+def table_iv_volume(hv, torch, inputs, steps, highpass=0.05):
     """The paper's Table IV angular spectrum + spatial high-pass filter +
     STFT 512/512 pipeline (every bin of every window rendered: |S_k|^2 as a
-    float32 volume) at its power-of-two frame sizes, file mode, beside the
-    paper's file-mode fps on its own GPU (context, not a target).  The
-    high-pass radius is not given in the paper; 0.05 cycles per pixel is used
-    (the filter is a mask in the transfer table, so its value does not
-    change the work)."""
-    from synth import holograms
-    paper_file_fps = {256: 88100, 512: 23100}
+    float32 volume) at its five frame sizes, file mode.  The high-pass radius
+    is not given in the paper; 0.05 cycles per pixel is used (the filter is a
+    mask in the transfer table, so its value does not change the work)."""
     out = {}
     ctx = hv.Context(0)
-    for side, (block, spec), reps in ((256, holograms.config_c2_block(2048), 8),
-                                      (512, holograms.stream_block(1, 1), 4)):
-        xb = torch.from_numpy(block).cuda()
-        x = xb.repeat(reps, 1, 1).contiguous()
-        del xb
+    for (ny, nx), x, spec, paper in inputs:
         frames = x.shape[0]
         opt = hv.Optics(852e-9, spec.pitch, spec.pitch, -spec.z, hv.HV_AS, highpass)
-        vol = torch.empty((frames // 512, 512, side, side), dtype=torch.float32, device="cuda")
+        vol = torch.empty((frames // 512, 512, ny, nx), dtype=torch.float32, device="cuda")
         res = {}
         for prec, name in ((hv.HV_PREC_FP32, "fp32"), (hv.HV_PREC_MIXED, "mixed")):
-            ctx.hv_stft_volume(x, opt, 512, 512, prec, out=vol)  # warm-up: plans and workspaces
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(steps):
-                ctx.hv_stft_volume(x, opt, 512, 512, prec, out=vol)
-            b.record()
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / steps
+            ms = _timed_passes(torch, lambda: ctx.hv_stft_volume(x, opt, 512, 512, prec, out=vol), steps)
             res[name] = {"frames_per_s": frames / (ms * 1e-3), "ms_per_pass": ms,
-                         "gigavoxels_per_s": frames * side * side / (ms * 1e-3) / 1e9}
-        log(f"table IV AS+HP+STFT512 {side}x{side}: {res}")
-        out[f"{side}x{side}"] = {"frames": frames, "input": f"uint8 {side}x{side}, z = -{spec.z:.4f} m",
-                                 "highpass_cycles_per_pixel": highpass, **res,
-                                 "paper_file_fps_rtx4090": paper_file_fps[side]}
-        del x, vol
+                         "gigavoxels_per_s": frames * ny * nx / (ms * 1e-3) / 1e9}
+        log(f"table IV AS+HP+STFT512 {nx}x{ny}: {res}")
+        out[f"{nx}x{ny}"] = {"frames": frames, "highpass_cycles_per_pixel": highpass, **res,
+                             "paper_file_fps_rtx4090": paper["as_hp_stft512"]}
+        del vol
     ctx.close()
     return out
 
@@ -449,10 +459,12 @@ def main():
         log("host ingest (PCIe) ...")
         line["host_ingest"] = host_ingest(hv, torch, block, spec, frames, max(1, args.steps // 3))
     if not args.no_table_iv:
+        inputs = table_iv_inputs(torch)
         log("Table IV Fresnel + PCA32 ...")
-        line["table_iv_fresnel_pca32"] = table_iv(hv, torch, max(1, args.steps // 2))
+        line["table_iv_fresnel_pca32"] = table_iv(hv, torch, inputs, max(1, args.steps // 2))
         log("Table IV AS + high-pass + STFT512 ...")
-        line["table_iv_as_hp_stft512"] = table_iv_volume(hv, torch, max(1, args.steps // 2))
+        line["table_iv_as_hp_stft512"] = table_iv_volume(hv, torch, inputs, max(1, args.steps // 2))
+        del inputs
     if args.af_train > 0:
         log("autofocus training and evaluation ...")
         line["autofocus"] = autofocus(hv, torch, args.af_train, args.af_eval, args.af_epochs)
