@@ -19,8 +19,11 @@
  *   Arrays are row-major [frames][ny][nx]; x is the fast axis.  Complex
  *   values are interleaved (re, im) float32 ("c64").  z is the signed
  *   propagation distance in metres: a hologram recorded at distance z is
- *   reconstructed with -z.  Supported frame sizes: nx, ny powers of two in
- *   [64, 1024] (non-square allowed).  Windows: 8, 16, 32 or 64 frames.
+ *   reconstructed with -z.  Supported frame sides: powers of two in
+ *   [64, 1024], and 320, 384, 800, 1280 (the mixed-radix sides of the
+ *   paper's Table IV frames; non-square allowed).  Windows: 8, 16, 32 or 64
+ *   frames (hv_stft_volume: 128, 256, 512).
+ *   Exception: hv_stft_moments_host takes pinned HOST frames and images.
  *
  * Ownership and asynchrony
  *   Every data pointer is caller-owned DEVICE memory on the context's
