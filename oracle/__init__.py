@@ -20,10 +20,10 @@ Rendering and Short-Time Analysis", arXiv 2508.03911):
 * Sec. VI-B (benchmarks): the two pipelines "angular spectrum + STFT" and
   "Fresnel + PCA", window equal to stride.
 
-The paper gives these operations in words only.  The formulas below are the
-textbook readings listed in the design doc (sign of z, normalisation, band-to-bin
-mapping, PCA conventions); each function's docstring states the reading it
-implements.  Modules:
+The paper gives these operations in words only.  The formulas below are
+textbook readings (sign of z, normalisation, band-to-bin mapping, PCA
+conventions); each function's docstring states the reading it implements.
+Modules:
 
 * ``optics``    -- unpack, angular spectrum, single-FFT Fresnel transform.
 * ``temporal``  -- STFT windows, band-to-bin mapping, Doppler moments.

@@ -4,8 +4,7 @@ small CNN that predicts z from a hologram's spectrum.
 Test infrastructure only (see the package docstring).
 
 The paper names machine-learning inference only as a future plug-in of the
-pipeline (Sec. VIII).  The build target fixes the rest; the readings used
-here (the design doc lists them):
+pipeline (Sec. VIII).  The readings used here:
 
 * Spectrum crop (network input): log(1 + |DFT2(h - mean h)|), centred on DC
   (fftshift), the central 64 x 64 bins, standardised to mean 0 and

@@ -1,4 +1,4 @@
-// Learned autofocus with a brute-force z-scan as fallback and judge.
+// Learned autofocus with a brute-force z-scan as fallback and as a check.
 //
 // The paper lists machine-learning inference as a plug-in for the real-time
 // pipeline (Sec. VIII, future work).  Built here for 256 x 256 holograms:
