@@ -305,7 +305,6 @@ hv_status hv_replay_run(hv_ctx* ctx, const hv_replay_config* cfg, hv_replay_resu
 
 /* ---------------------------------------------------------------- autofocus */
 /* Learned autofocus with a brute-force scan as fallback and as a check (the
-/* Learned autofocus with a brute-force scan as fallback and judge (the
  * paper names machine-learning inference as a plug-in for the pipeline,
  * Sec. VIII).  Holograms are 256 x 256 uint8 off-axis interferograms whose
  * reference carrier is (+1/4, +1/4) cycles/pixel, so the object term sits at
