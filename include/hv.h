@@ -303,6 +303,37 @@ typedef struct {
 
 hv_status hv_replay_run(hv_ctx* ctx, const hv_replay_config* cfg, hv_replay_result* res);
 
+/* ---------------------------------------------------------------- .holo files */
+
+/* The .holo file (Sec. IV, Holofile system) for file-mode replay: a 64-byte
+ * header ("HOLO", version, bits per pixel, width, height, image count, data
+ * size, endianness, data type; little-endian fields, zero padding), the
+ * images as one stream, an optional JSON footer.  Host-side calls on plain
+ * host memory; no device work. */
+typedef struct {
+  uint16_t version;         /* 7; 0 on write means 7 */
+  uint16_t bits_per_pixel;  /* 8 or 16 */
+  uint32_t width, height, image_count;
+  uint64_t data_size;       /* filled on read; computed on write */
+  uint8_t endianness;       /* of the pixel data: 0 little, 1 big */
+  uint8_t data_type;        /* 0 raw, 1 processed */
+} hv_holo_header;
+
+/* Reads and checks the header (HV_ERR_ARG: missing file, bad magic, other bit
+ * depths, inconsistent data size); footer_bytes (nullable) receives the
+ * footer length. */
+hv_status hv_holo_read_header(const char* path, hv_holo_header* out, uint64_t* footer_bytes);
+/* Images [first, first + count) into host_dst (count * width * height *
+ * bits/8 bytes; pinned memory lets the result go straight to the device),
+ * 16-bit pixels in native (little-endian) order. */
+hv_status hv_holo_read_frames(const char* path, int64_t first, int64_t count, void* host_dst);
+/* The footer text, NUL-terminated, truncated to cap - 1 bytes. */
+hv_status hv_holo_read_footer(const char* path, char* dst, uint64_t cap);
+/* Writes header, images (host memory, native order; swapped when
+ * endianness = 1) and the footer (nullable JSON text). */
+hv_status hv_holo_write(const char* path, const hv_holo_header* header, const void* host_frames,
+                        const char* footer_json);
+
 /* ---------------------------------------------------------------- autofocus */
 /* Learned autofocus with a brute-force scan as fallback and as a check (the
  * paper names machine-learning inference as a plug-in for the pipeline,

@@ -48,6 +48,12 @@ class hv_optics(C.Structure):
                 ("z_m", C.c_double), ("method", C.c_int), ("highpass_cpp", C.c_double)]
 
 
+class hv_holo_header(C.Structure):
+    _fields_ = [("version", C.c_uint16), ("bits_per_pixel", C.c_uint16), ("width", C.c_uint32),
+                ("height", C.c_uint32), ("image_count", C.c_uint32), ("data_size", C.c_uint64),
+                ("endianness", C.c_uint8), ("data_type", C.c_uint8)]
+
+
 class hv_temporal(C.Structure):
     _fields_ = [("window", C.c_int), ("stride", C.c_int), ("fs_hz", C.c_double), ("f_lo_hz", C.c_double),
                 ("f_hi_hz", C.c_double), ("symmetric_band", C.c_int)]
@@ -99,6 +105,10 @@ _sig = {
                              _P]),
     "hv_stft_bins": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P]),
     "hv_stft_volume": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _P, _P]),
+    "hv_holo_read_header": (_I, [C.c_char_p, C.POINTER(hv_holo_header), C.POINTER(C.c_uint64)]),
+    "hv_holo_read_frames": (_I, [C.c_char_p, C.c_int64, C.c_int64, _P]),
+    "hv_holo_read_footer": (_I, [C.c_char_p, C.c_char_p, C.c_uint64]),
+    "hv_holo_write": (_I, [C.c_char_p, C.POINTER(hv_holo_header), _P, C.c_char_p]),
     "hv_stft_moments_host": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P,
                                   _P, _P, _P]),
     "hv_stream_open": (_I, [_P, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _I, C.POINTER(_P)]),
@@ -193,6 +203,36 @@ def _frames(x: torch.Tensor, host: bool = False):
     elif not x.is_cuda or not x.is_contiguous():
         raise ValueError("input must be a contiguous device tensor")
     return x.shape[0], x.shape[1], x.shape[2]
+
+
+def holo_read(path, first: int = 0, count: int | None = None, pin: bool = False):
+    """(header dict, uint8/uint16 frames [count][height][width] on the host,
+    footer text or None) of a .holo file; pin=True reads into pinned memory."""
+    h = hv_holo_header()
+    fb = C.c_uint64(0)
+    p = os.fsencode(path)
+    _check(lib.hv_holo_read_header(p, C.byref(h), C.byref(fb)))
+    n = h.image_count - first if count is None else count
+    dt = torch.uint8 if h.bits_per_pixel == 8 else torch.int16
+    frames = torch.empty((n, h.height, h.width), dtype=dt, pin_memory=pin)
+    _check(lib.hv_holo_read_frames(p, first, n, C.c_void_p(frames.data_ptr())))
+    footer = None
+    if fb.value:
+        buf = C.create_string_buffer(fb.value + 1)
+        _check(lib.hv_holo_read_footer(p, buf, fb.value + 1))
+        footer = buf.value.decode()
+    head = {f: getattr(h, f) for f, _ in hv_holo_header._fields_}
+    return head, frames, footer
+
+
+def holo_write(path, frames: torch.Tensor, footer: str | None = None, data_type: int = 0, endianness: int = 0):
+    """Write host frames [n][height][width] (uint8, or 16-bit) as a .holo file."""
+    if frames.is_cuda or frames.dim() != 3 or not frames.is_contiguous():
+        raise ValueError("frames must be a contiguous [n, h, w] host tensor")
+    bits = 8 * frames.element_size()
+    h = hv_holo_header(7, bits, frames.shape[2], frames.shape[1], frames.shape[0], 0, endianness, data_type)
+    _check(lib.hv_holo_write(os.fsencode(path), C.byref(h), C.c_void_p(frames.data_ptr()),
+                             footer.encode() if footer is not None else None))
 
 
 def band_bins(temporal: Temporal):

@@ -31,3 +31,10 @@ def hv():
         pytest.skip("no GPU")
     from paper_2508_03911_amd import hv as _hv
     return _hv
+
+
+@pytest.fixture(scope="session")
+def hv_host():
+    """The binding for its host-only calls (file I/O); needs no GPU."""
+    from paper_2508_03911_amd import hv as _hv
+    return _hv
