@@ -303,6 +303,33 @@ typedef struct {
 
 hv_status hv_replay_run(hv_ctx* ctx, const hv_replay_config* cfg, hv_replay_result* res);
 
+/* ---------------------------------------------------------------- post-processing */
+
+/* Post-processing of rendered images (Sec. III-B.2), in the paper's order:
+ *   convolution: out = in * kernel (2-D linear convolution, same size,
+ *     zero outside the image); kernel_size odd, at most 31 (0 = skip),
+ *     kernel: HOST [k][k] row-major float32;
+ *   renormalise != 0: each image divided by its own spatial mean;
+ *   registration (ref_count > 0): reference = mean of the first ref_count
+ *     images times a centred disk of radius mask_radius * min(nx, ny) / 2;
+ *     each image is shifted circularly by minus the peak of its circular
+ *     cross-correlation c(s) = sum_p img(p + s) ref(p) (ties: lowest flat
+ *     index); sides must be supported frame sides;
+ *   accumulate > 1: moving average out_j = mean(in_max(0, j-A+1) .. in_j).
+ * in, out: device [count][ny][nx] float32 (may not overlap); shifts: device
+ * [count][2] int (dy, dx) of the registration, nullable. */
+typedef struct {
+  int kernel_size;
+  const float* kernel;
+  int renormalise;
+  int ref_count;
+  double mask_radius;
+  int accumulate;
+} hv_post;
+
+hv_status hv_postprocess(hv_ctx* ctx, const float* in, int count, int ny, int nx, const hv_post* cfg, float* out,
+                         int* shifts, void* hip_stream);
+
 /* ---------------------------------------------------------------- .holo files */
 
 /* The .holo file (Sec. IV, Holofile system) for file-mode replay: a 64-byte

@@ -54,6 +54,11 @@ class hv_holo_header(C.Structure):
                 ("endianness", C.c_uint8), ("data_type", C.c_uint8)]
 
 
+class hv_post(C.Structure):
+    _fields_ = [("kernel_size", C.c_int), ("kernel", C.c_void_p), ("renormalise", C.c_int), ("ref_count", C.c_int),
+                ("mask_radius", C.c_double), ("accumulate", C.c_int)]
+
+
 class hv_temporal(C.Structure):
     _fields_ = [("window", C.c_int), ("stride", C.c_int), ("fs_hz", C.c_double), ("f_lo_hz", C.c_double),
                 ("f_hi_hz", C.c_double), ("symmetric_band", C.c_int)]
@@ -105,6 +110,7 @@ _sig = {
                              _P]),
     "hv_stft_bins": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P]),
     "hv_stft_volume": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _P, _P]),
+    "hv_postprocess": (_I, [_P, _P, _I, _I, _I, C.POINTER(hv_post), _P, _P, _P]),
     "hv_holo_read_header": (_I, [C.c_char_p, C.POINTER(hv_holo_header), C.POINTER(C.c_uint64)]),
     "hv_holo_read_frames": (_I, [C.c_char_p, C.c_int64, C.c_int64, _P]),
     "hv_holo_read_footer": (_I, [C.c_char_p, C.c_char_p, C.c_uint64]),
@@ -342,6 +348,25 @@ class Context:
         _check(lib.hv_stft_moments_host(self.handle, _ptr(x), _dtype_code(x), n, ny, nx, C.byref(op), C.byref(tp),
                                         prec, _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), C.c_void_p(st)))
         return out
+
+    def hv_postprocess(self, images: torch.Tensor, kernel=None, renormalise: bool = False, ref_count: int = 0,
+                       mask_radius: float = 1.0, accumulate: int = 1):
+        """Convolution (kernel: host [k][k] array), re-normalisation,
+        registration and moving average of device images [count][ny][nx]
+        float32; returns (images, shifts [count][2] int32 or None)."""
+        if not images.is_cuda or images.dim() != 3 or images.dtype != torch.float32 or not images.is_contiguous():
+            raise ValueError("images must be a contiguous [count, ny, nx] float32 device tensor")
+        count, ny, nx = images.shape
+        k = None
+        if kernel is not None:
+            k = torch.as_tensor(kernel, dtype=torch.float32).contiguous().cpu()
+        cfg = hv_post(0 if k is None else k.shape[0], None if k is None else C.c_void_p(k.data_ptr()),
+                      int(renormalise), ref_count, mask_radius, accumulate)
+        out = torch.empty_like(images)
+        shifts = torch.empty((count, 2), dtype=torch.int32, device=images.device) if ref_count > 0 else None
+        _check(lib.hv_postprocess(self.handle, _ptr(images), count, ny, nx, C.byref(cfg), _ptr(out), _ptr(shifts),
+                                  _stream(images.device)))
+        return out, shifts
 
     def hv_stft_volume(self, x: torch.Tensor, optics: Optics | None, window: int, stride: int,
                        prec: int = HV_PREC_FP32, out=None) -> torch.Tensor:
