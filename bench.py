@@ -27,11 +27,19 @@ METRIC = "input frames/s @256² AS+STFT32+M0 (FP32 vs mixed, % HBM peak); p99 la
 HBM_PEAK_GBS = 8000.0
 NY = NX = 256
 W = 32
-# algorithmic bytes per pixel-frame of each kernel (read + write), W = 32, 3 moments
-BYTES_PER_PXF = {
-    0: {"row_r2c": 1 + 4, "col_as": 4 + 8, "rowinv_coef": 8 + 12 / W},
-    1: {"row_r2c": 1 + 2, "col_as": 2 + 4, "rowinv_coef": 4 + 12 / W},
-}
+
+
+def bytes_per_pxf(prec: int, nb: int) -> dict:
+    """Algorithmic bytes (read + write) per input pixel-frame of each kernel
+    of the two orders, for u8 frames, W = stride = 32, nb band bins and three
+    f32 moment images.  e = bytes of one stored complex value."""
+    e = 8 if prec == 0 else 4
+    return {
+        # frames first: u8 in, half spectrum out; half in, full out; W full in, 3 images out
+        "row_r2c": 1 + e / 2, "col_as": e / 2 + e, "rowinv_coef": e + 12 / W,
+        # band first: W u8 in, nb bin fields out; nb fields in and out; nb in, 3 images out
+        "band_rows": 1 + nb * e / W, "band_cols": 2 * nb * e / W, "band_power": nb * e / W + 12 / W,
+    }
 
 
 def source_sha() -> str:
@@ -79,7 +87,7 @@ def kernel_profile(ctx, hv, torch, x, opt, tp, prec, outs, steps, frames):
         ctx.hv_stft_moments(x, opt, tp, prec, out=outs)
     torch.cuda.synchronize()
     res = {}
-    for name, bpp in BYTES_PER_PXF[prec].items():
+    for name, bpp in bytes_per_pxf(prec, len(hv.band_bins(tp)[0])).items():
         ms, n = ctx.kernel_time(name)
         if n == 0:
             continue
@@ -87,7 +95,7 @@ def kernel_profile(ctx, hv, torch, x, opt, tp, prec, outs, steps, frames):
         pxf_per_launch = frames * steps * NY * NX / n
         gbs = bpp * pxf_per_launch / (avg_ms * 1e-3) / 1e9
         res[name] = {"launches": n, "avg_ms": avg_ms, "total_ms_per_step": ms / steps,
-                     "bytes_per_launch": bpp * pxf_per_launch, "achieved_GBs": gbs}
+                     "bytes_per_pixel_frame": bpp, "bytes_per_launch": bpp * pxf_per_launch, "achieved_GBs": gbs}
     ctx.set_timing(False)
     return res
 
@@ -422,7 +430,8 @@ def main():
 
     fp32, mixed = res[hv.HV_PREC_FP32], res[hv.HV_PREC_MIXED]
     dom_name, dom = max(fp32["kernels"].items(), key=lambda kv: kv[1]["total_ms_per_step"])
-    pass_bytes = sum(BYTES_PER_PXF[0].values()) * NY * NX * frames
+    bpf = sum(k["bytes_per_pixel_frame"] for k in fp32["kernels"].values())
+    pass_bytes = bpf * NY * NX * frames
     line = {
         "metric": METRIC,
         "value": fp32["frames_per_s"],
@@ -445,7 +454,7 @@ def main():
                      "algorithmic_bytes_per_launch": dom["bytes_per_launch"], "avg_launch_ms": dom["avg_ms"]},
         "pass_level_hbm": {"GBs": pass_bytes / (fp32["ms_per_step"] * 1e-3) / 1e9,
                            "frac": pass_bytes / (fp32["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                           "bytes_per_pixel_frame": sum(BYTES_PER_PXF[0].values())},
+                           "bytes_per_pixel_frame": bpf},
         "mixed": {"value": mixed["frames_per_s"], "ms_per_step": mixed["ms_per_step"],
                   "speedup_vs_fp32": mixed["frames_per_s"] / fp32["frames_per_s"],
                   "kernels": mixed["kernels"]},

@@ -118,6 +118,23 @@ size_t hv_ctx_workspace_bytes(const hv_ctx* ctx);
 /* Frames per spatial chunk (workspace size knob; 0 = automatic). */
 hv_status hv_ctx_set_chunk_frames(hv_ctx* ctx, int frames);
 
+/* Order of the angular-spectrum STFT path of hv_stft_moments and
+ * hv_stft_bins (a throughput knob: both orders compute the same values up to
+ * rounding).  The propagation is one linear operator applied to every frame
+ * (Sec. II-B.3) and each band bin is a fixed linear combination of a
+ * window's frames (Sec. III-B.1), so the bins can be formed from the raw
+ * frames and then propagated ("band first"), which transforms nb fields per
+ * window instead of W frames.
+ *   HV_ORDER_AUTO         band first where it moves fewer bytes per window
+ *                         and the shape is supported (u8/u16 frames, nx 256
+ *                         or 512, ny 64, 128, 256, 320, 384 or 512);
+ *   HV_ORDER_FRAMES_FIRST propagate every frame, then the temporal transform;
+ *   HV_ORDER_BAND_FIRST   band first wherever the shape is supported.
+ * Returns HV_ERR_ARG for another value.  A new context starts from the
+ * environment variable HV_STFT_ORDER (1 or 2) when it is set, else AUTO. */
+typedef enum { HV_ORDER_AUTO = 0, HV_ORDER_FRAMES_FIRST = 1, HV_ORDER_BAND_FIRST = 2 } hv_stft_order;
+hv_status hv_ctx_set_stft_order(hv_ctx* ctx, int order);
+
 /* Per-kernel timing for profiling (Sec. VII-D): when on, every kernel launch
  * is bracketed by HIP events on the stream it is launched on (the caller's,
  * or the second stream of hv_stft_moments); no work is skipped.
@@ -126,7 +143,8 @@ hv_status hv_ctx_set_timing(hv_ctx* ctx, int on);
 /* Waits for the recorded launches and returns the total milliseconds and the
  * launch count of kernel `name` ("row_r2c", "col_as", "rowinv_coef",
  * "row_inv", "field_coef", "rows_c2c", "col_full", "fresnel_rows",
- * "fresnel_cols", "gram", "jacobi", "proj_energy"). */
+ * "fresnel_cols", "band_rows", "band_cols", "band_power", "gram", "jacobi",
+ * "proj_energy"). */
 hv_status hv_ctx_kernel_time(hv_ctx* ctx, const char* name, double* total_ms, long* launches);
 
 /* ---------------------------------------------------------------- spatial */

@@ -220,7 +220,25 @@ static hv_status build_dft_plan(size_t* held, DftPlan& p) {
     wts[mt * 16 + b] = (float)p.freqs[b];
     wts[2 * mt * 16 + b] = (float)(p.freqs[b] * p.freqs[b]);
   }
+  const int ks = w >= 16 ? w / 16 : 1;
+  std::vector<hv_h8> rhi((size_t)mt * ks * 64), rlo(rhi.size());
+  for (int m_t = 0; m_t < mt; ++m_t)
+    for (int kk = 0; kk < ks; ++kk)
+      for (int lane = 0; lane < 64; ++lane) {
+        hv_h8 h, l;
+        for (int e = 0; e < 8; ++e) {
+          const int t = 16 * kk + 8 * (lane >> 5) + e;
+          // real input: column 2t of the complex-input matrix
+          const float a = t < w ? (float)coef(32 * m_t + (lane & 31), 2 * t) : 0.f;
+          h[e] = (_Float16)a;
+          l[e] = (_Float16)(a - (float)h[e]);
+        }
+        rhi[((size_t)m_t * ks + kk) * 64 + lane] = h;
+        rlo[((size_t)m_t * ks + kk) * 64 + lane] = l;
+      }
   hv_status st = p.a32.upload(a32.data(), a32.size() * sizeof(float), held);
+  if (!st) st = p.ar_hi.upload(rhi.data(), rhi.size() * sizeof(hv_h8), held);
+  if (!st) st = p.ar_lo.upload(rlo.data(), rlo.size() * sizeof(hv_h8), held);
   if (!st) st = p.a16hi.upload(hi.data(), hi.size() * sizeof(hv_h8), held);
   if (!st) st = p.a16lo.upload(lo.data(), lo.size() * sizeof(hv_h8), held);
   if (!st) st = p.wts.upload(wts.data(), wts.size() * sizeof(float), held);
@@ -493,6 +511,10 @@ hv_status hv_ctx_create(int device, size_t hbm_budget_bytes, hv_ctx** out) {
   c->device = device;
   c->budget = hbm_budget_bytes;
   if (const char* e = std::getenv("HV_CHUNK_FRAMES")) c->chunk_frames = std::atoi(e);
+  if (const char* e = std::getenv("HV_STFT_ORDER")) {
+    const int o = std::atoi(e);
+    if (o == HV_ORDER_FRAMES_FIRST || o == HV_ORDER_BAND_FIRST) c->stft_order = o;
+  }
   *out = c;
   return HV_OK;
 }
@@ -511,6 +533,14 @@ hv_status hv_ctx_set_chunk_frames(hv_ctx* ctx, int frames) {
   if (!ctx) return fail(HV_ERR_ARG, "context is NULL");
   if (frames < 0) return fail(HV_ERR_ARG, "negative chunk");
   ctx->chunk_frames = frames;
+  return HV_OK;
+}
+
+hv_status hv_ctx_set_stft_order(hv_ctx* ctx, int order) {
+  if (!ctx) return fail(HV_ERR_ARG, "context is NULL");
+  if (order != HV_ORDER_AUTO && order != HV_ORDER_FRAMES_FIRST && order != HV_ORDER_BAND_FIRST)
+    return fail(HV_ERR_ARG, "unknown order %d", order);
+  ctx->stft_order = order;
   return HV_OK;
 }
 
@@ -587,6 +617,91 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
   return HV_OK;
 }
 
+// Bytes per pixel and window of the two orders of the AS moments path
+// (camera values read, intermediate spectra written and read, three f32
+// images written): frames first moves every frame through the row pass
+// (in + half spectrum), the column pass (half spectrum in, full out) and
+// the fused temporal kernel (W full spectra); band first reads the window's
+// raw frames once and moves nb bin fields through three passes.
+static bool band_first_cheaper(int w, int stride, int nb, int in_bytes, bool mixed) {
+  const double e = mixed ? 4.0 : 8.0;
+  const double frames_first = stride * (in_bytes + 2.0 * e) + w * e;
+  const double band_first = w * (double)in_bytes + 4.0 * nb * e;
+  return band_first < frames_first;
+}
+
+// Windows per band-first chunk: about 96 MiB of bin fields (13 windows of
+// 14 bins at 256 x 256 FP32), or the frames set by hv_ctx_set_chunk_frames.
+static int band_chunk_windows(const Ctx* c, int ny, int nx, int nb, int w, int stride, bool mixed) {
+  long g;
+  if (c->chunk_frames > 0) {
+    g = c->chunk_frames >= w ? (c->chunk_frames - w) / stride + 1 : 1;
+  } else {
+    g = (96L << 20) / ((long)nb * ny * nx * (mixed ? 4 : 8));
+  }
+  return g < 1 ? 1 : g > 4096 ? 4096 : (int)g;
+}
+
+// Band-first AS moments: per chunk of windows, the bins' row spectra from
+// the raw frames (KA), the AS column pass in place (KB), the inverse row
+// pass with the weighted powers (KC).  Chunks alternate between two
+// streams like the frames-first driver.
+static hv_status stft_band_first(Ctx* ctx, const void* in, int in_t, int ny, int nx, const hv_optics& o,
+                                 const DftPlan& dp, int w, int stride, int nwin_total, int gw, bool mixed,
+                                 float* m0, float* m1, float* m2, float2* spec, hipStream_t caller,
+                                 bool two_lanes) {
+  hv_status s;
+  AsPlan* p = ctx->as_plan(ny, nx, o, &s);
+  if (!p) return s;
+  const int nb = (int)dp.bins.size();
+  const size_t frame = (size_t)ny * nx;
+  const size_t per_win = (size_t)nb * frame * (mixed ? 4 : 8);
+  // fp16 storage: values scaled so that the worst case (every camera value
+  // at full scale, coherent) stays below the fp16 maximum through the passes
+  const float s1 = in_t == HV_U16 ? 1.0f / (16.0f * nx) : 1.0f / nx;
+  const float sc = mixed ? s1 / w : 1.0f;
+  const float amp = 1.0f / (nx * sc);
+  Ctx::Lane2* l2 = nullptr;
+  hipStream_t st = caller;
+  if (two_lanes && nwin_total > gw) {
+    if (!(l2 = ctx->lane2(caller, &s))) return s;
+    hipEventRecord(l2->fork, caller);
+    hipStreamWaitEvent(l2->s, l2->fork, 0);
+  }
+  hv_status res = HV_OK;
+  for (int j0 = 0, c = 0; j0 < nwin_total && res == HV_OK; j0 += gw, ++c) {
+    st = (l2 && (c & 1)) ? l2->s : caller;
+    res = [&]() -> hv_status {
+      const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
+      const char* src = (const char*)in + (size_t)j0 * stride * frame * in_elem(in_t);
+      DevBuf& b = ctx->work(st, 1);
+      if ((s = b.ensure((size_t)g_n * per_win, &ctx->held))) return s;
+      float* o0 = m0 ? m0 + (size_t)j0 * frame : nullptr;
+      float* o1 = m1 ? m1 + (size_t)j0 * frame : nullptr;
+      float* o2 = m2 ? m2 + (size_t)j0 * frame : nullptr;
+      float2* os = spec ? spec + (size_t)j0 * nb * frame : nullptr;
+      if ((s = timed(ctx, "band_rows", st, [&] {
+             return launch_band_rows(src, in_t, b.ptr, mixed, ny, nx, stride, g_n, w, nb, dp.mtiles,
+                                     (const hv_h8*)dp.ar_hi.ptr, (const hv_h8*)dp.ar_lo.ptr, sc, st);
+           })))
+        return s;
+      if ((s = timed(ctx, "band_cols", st, [&] {
+             return launch_band_cols(b.ptr, mixed, p->ht_ptr(), g_n * nb, ny, nx, st);
+           })))
+        return s;
+      return timed(ctx, "band_power", st, [&] {
+        return launch_band_power(b.ptr, mixed, ny, nx, g_n, nb, dp.mtiles, (const float*)dp.wts.ptr, amp, o0, o1,
+                                 o2, os, st);
+      });
+    }();
+  }
+  if (l2) {
+    hipEventRecord(l2->join, l2->s);
+    hipStreamWaitEvent(caller, l2->join, 0);
+  }
+  return res;
+}
+
 // Shared driver of hv_stft_moments and hv_stft_bins.
 static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                            const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
@@ -634,6 +749,17 @@ static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny,
     const float bsc = mixed ? fp16_field_scale(HV_C64, ny, nx) : 1.f;
     return launch_field_coef(in, false, (long)frame, stride, nwin_total, g, mixed, bsc, mixed ? 1.f / bsc : 1.f, m0,
                              m1, m2, spec, st);
+  }
+  if (optics->method == HV_AS && band_first_fits(ny, nx, in_t) && ctx->stft_order != HV_ORDER_FRAMES_FIRST &&
+      (ctx->stft_order == HV_ORDER_BAND_FIRST || band_first_cheaper(w, stride, nb, (int)in_elem(in_t), mixed))) {
+    int gb = band_chunk_windows(ctx, ny, nx, nb, w, stride, mixed);
+    if (gb > nwin_total) gb = nwin_total;
+    // the serving loop's streams run on workspaces sized at admission: take
+    // this order there only when it fits the one already held
+    const bool fits = two_lanes || ctx->work(st, 1).bytes >= (size_t)gb * nb * frame * (mixed ? 4 : 8);
+    if (fits)
+      return stft_band_first(ctx, in, in_t, ny, nx, *optics, *dp, w, stride, nwin_total, gb, mixed, m0, m1, m2,
+                             spec, st, two_lanes);
   }
   const int chunk = ctx->chunk_frames_for(ny, nx, mixed);
   int gw = chunk >= w ? (chunk - w) / stride + 1 : 1;

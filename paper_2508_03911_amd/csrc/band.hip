@@ -1,0 +1,364 @@
+// Band-first order of the angular-spectrum + short-time DFT moments.
+//
+// The angular spectrum applies one linear operator to every frame
+// (Sec. II-B.3), and each bin of the short-time DFT is a fixed linear
+// combination of a window's frames (Sec. III-B.1).  The two commute: the
+// bin-k field of a window is the angular spectrum of the bin-k combination
+// of its raw frames.  When the band holds fewer bins than the window holds
+// frames, propagating the band's combinations instead of the frames moves
+// fewer bytes and runs fewer FFTs (no Hermitian half-spectrum saving is
+// lost: the propagated field is complex either way).
+//
+//   KA band rows : the W raw rows of one row index of a window are reduced
+//                  to the band's bins on MFMA (camera values are exact in
+//                  fp16, the coefficients are split into fp16 high and low
+//                  parts), then every bin's row gets a forward row FFT;
+//                  out [window][bin][ny][nx] (complex, c64 or fp16);
+//   KB band cols : per bin field, column FFT, multiply by H_z / ny, inverse
+//                  column FFT, in place;
+//   KC band power: per (window, row), inverse row FFT of every bin's row,
+//                  then |.|^2 summed with the weights f^0, f^1, f^2 (and the
+//                  bins written out when asked for).
+//
+// MFMA layout (v_mfma_f32_32x32x16_f16, wave64): lane l holds
+// A[l%32][k0 + 8(l/32) + e] and B[k0 + 8(l/32) + e][l%32], e = 0..7; the
+// result register r of lane l is row 8(r/4) + 4(l/32) + r%4 of column l%32.
+// Rows of A come in (real, imaginary) pairs, one pair per bin; k is the
+// frame index t within the window.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fft_lds.h"
+#include "gmem.h"
+#include "hv_internal.h"
+
+using namespace hvk;
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+
+__device__ inline void store_c(float2* p, float2 v) { *p = v; }
+__device__ inline void store_c(hv_h2* p, float2 v) {
+  hv_h2 h;
+  h.x = (_Float16)v.x;
+  h.y = (_Float16)v.y;
+  *p = h;
+}
+__device__ inline float2 load_c(const float2* p) { return *p; }
+__device__ inline float2 load_c(const hv_h2* p) {
+  hv_h2 h = *p;
+  return make_float2((float)h.x, (float)h.y);
+}
+
+// Two neighbouring camera values of type TIN read as one word.
+template <typename TIN>
+using Raw2 = std::conditional_t<sizeof(TIN) == 1, uint16_t, uint32_t>;
+
+template <typename TIN>
+__device__ inline uint32_t pick(uint32_t w, int q) {
+  constexpr int BITS = 8 * sizeof(TIN);
+  return (w >> (BITS * q)) & ((1u << BITS) - 1u);
+}
+
+// ------------------------------------------------------------------ KA
+// Block u = (window u / ny, row u % ny), NX threads.  Wave v owns pixels
+// [64 v, 64 v + 64); lane (c, h) loads the two neighbouring pixels
+// 64 v + 2c + q (q = 0, 1) of frames t = 16 kk + 8 h + e, which make its B
+// fragments of the two column tiles (tile q, column c).  u16 values are
+// split into two exact bytes, reduced separately and recombined as
+// lo + 256 hi.
+template <int NX, int W, typename TIN, typename TOUT>
+__global__ __launch_bounds__(NX) void k_band_rows(const TIN* __restrict__ in, TOUT* __restrict__ out, int ny,
+                                                  int stride, int nb, int mtiles, const hv_h8* __restrict__ ahi,
+                                                  const hv_h8* __restrict__ alo, float scale) {
+  constexpr int NT = NX, PL = 2;
+  static_assert(NX == 256 || NX == 512, "row width 256 or 512");
+  constexpr int KS = W >= 16 ? W / 16 : 1;
+  constexpr int S = lds_stride(NX);
+  constexpr bool U16 = sizeof(TIN) == 2;
+  using R = Raw2<TIN>;
+  __shared__ float2 buf[16 * S];
+  __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31;
+  fill_twiddles<NX>(tw, tid, NT);
+  const int j = blockIdx.x / ny, y = blockIdx.x % ny;
+  const long npix = (long)ny * NX;
+  const int xb = wave * 32 * PL + PL * c;
+  // frame j*stride + t, row y: wave-uniform base + lane offset (8h frames, pixel xb)
+  const TIN* base = in + ((long)j * stride * ny + y) * NX;
+  const uint32_t off = (uint32_t)((8 * h) * npix + xb) * (uint32_t)sizeof(TIN);
+  R raw[KS][8];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (W >= 16 || h == 0)
+        raw[kk][e] = ld_off(reinterpret_cast<const R*>(base + (long)(16 * kk + e) * npix), off);
+      else
+        raw[kk][e] = 0;
+    }
+  TOUT* dst0 = out + ((long)j * nb * ny + y) * NX;
+  for (int mt = 0; mt < mtiles; ++mt) {
+    hv_h8 fh[KS], fl[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      fh[kk] = ahi[(mt * KS + kk) * 64 + lane];
+      fl[kk] = alo[(mt * KS + kk) * 64 + lane];
+    }
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      f32x16 acc, acc2;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = acc2[r] = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        hv_h8 b, bh;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t v = pick<TIN>(raw[kk][e], q);
+          b[e] = (_Float16)(float)(v & 0xffu);
+          if constexpr (U16) bh[e] = (_Float16)(float)(v >> 8);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[kk], b, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[kk], b, acc, 0, 0, 0);
+        if constexpr (U16) {
+          acc2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[kk], bh, acc2, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[kk], bh, acc2, 0, 0, 0);
+        }
+      }
+      if constexpr (U16) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] += 256.f * acc2[r];
+      }
+      const int xs = skew(xb + q);
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) buf[(4 * g + 2 * h + p) * S + xs] = make_float2(acc[4 * g + 2 * p], acc[4 * g + 2 * p + 1]);
+    }
+    __syncthreads();
+    fft_lds<NX, 16, NT, -1>(buf, tw, tid);
+    const int live = nb - 16 * mt < 16 ? nb - 16 * mt : 16;
+    TOUT* dst = dst0 + (long)16 * mt * npix;
+    for (int q = tid; q < live * NX; q += NT) {
+      const int b = q / NX, x = q % NX;
+      TOUT v;
+      store_c(&v, c2::scale(buf[b * S + skew(x)], scale));
+      st_off(dst, (uint32_t)(b * npix + x) * (uint32_t)sizeof(TOUT), v);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ KB
+// Block (column group, field): columns [x0, x0 + BC) of one bin field
+// [ny][nx], transformed in place.  ht is column-major [nx][ny]:
+// H_z(fx, fy) / ny with the high-pass mask folded in.
+template <int NY, int BC, int NTK, typename TIO>
+__global__ __launch_bounds__(NTK) void k_band_cols(TIO* __restrict__ io, const float2* __restrict__ ht, int nx) {
+  constexpr int S = lds_stride(NY);
+  constexpr int U = BC * NY / NTK;
+  constexpr int RS = NTK / BC;  // rows per pass of the threads
+  static_assert(BC * NY % NTK == 0 && NTK % BC == 0 && NY % RS == 0, "column tile split");
+  __shared__ float2 buf[BC * S];
+  __shared__ float2 tw[tw_size(NY) > 0 ? tw_size(NY) : 1];
+  const int tid = threadIdx.x;
+  const int groups = nx / BC;
+  const int x0 = (blockIdx.x % groups) * BC;
+  const long f = blockIdx.x / groups;
+  fill_twiddles<NY>(tw, tid, NTK);
+  TIO* base = io + f * NY * (long)nx + x0;
+  // load / store element u: column s, row yr + u * RS
+  const int s = tid % BC, yr = tid / BC;
+  const uint32_t off = (uint32_t)(yr * nx + s) * (uint32_t)sizeof(TIO);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const TIO v = ld_off(base + (long)u * RS * nx, off);
+    buf[s * S + skew(yr + u * RS)] = load_c(&v);
+  }
+  // multiply element q = tid + u * NTK: sequence q / NY, frequency q % NY
+  // (the table run of one column is contiguous)
+  const float2* hcol = ht + (long)x0 * NY;
+  float2 hv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) hv[u] = ld_off(hcol + u * NTK, (uint32_t)tid * 8u);
+  __syncthreads();
+  fft_lds<NY, BC, NTK, -1>(buf, tw, tid);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * NTK;
+    float2* e = buf + (q / NY) * S + skew(q % NY);
+    *e = c2::mul(*e, hv[u]);
+  }
+  __syncthreads();
+  fft_lds<NY, BC, NTK, +1>(buf, tw, tid);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    TIO v;
+    store_c(&v, buf[s * S + skew(yr + u * RS)]);
+    st_off(base + (long)u * RS * nx, off, v);
+  }
+}
+
+// ------------------------------------------------------------------ KC
+// Block u = (window u / ny, row u % ny), NX threads: bins in groups of 16,
+// each group's rows inverse-transformed in LDS; thread tid owns pixel tid.
+template <int NX, typename TIN>
+__global__ __launch_bounds__(NX) void k_band_power(const TIN* __restrict__ in, int ny, int nb, int mtiles,
+                                                   const float* __restrict__ wts, float amp,
+                                                   float* __restrict__ o0, float* __restrict__ o1,
+                                                   float* __restrict__ o2, float2* __restrict__ spec) {
+  constexpr int NT = NX, PX = 1;
+  constexpr int S = lds_stride(NX);
+  constexpr int PER = 16 * NX / NT;
+  __shared__ float2 buf[16 * S];
+  __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
+  const int tid = threadIdx.x;
+  fill_twiddles<NX>(tw, tid, NT);
+  const int j = blockIdx.x / ny, y = blockIdx.x % ny;
+  const long npix = (long)ny * NX;
+  const TIN* src = in + ((long)j * nb * ny + y) * NX;
+  const int ws = 16 * mtiles;
+  float e0[PX], e1[PX], e2[PX];
+#pragma unroll
+  for (int i = 0; i < PX; ++i) e0[i] = e1[i] = e2[i] = 0.f;
+  for (int mt = 0; mt < mtiles; ++mt) {
+    const int live = nb - 16 * mt < 16 ? nb - 16 * mt : 16;
+    const TIN* s0 = src + (long)16 * mt * npix;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + i * NT, b = q / NX, x = q % NX;
+      float2 v = make_float2(0.f, 0.f);
+      if (b < live) {
+        const TIN t = ld_off(s0, (uint32_t)(b * npix + x) * (uint32_t)sizeof(TIN));
+        v = load_c(&t);
+      }
+      buf[b * S + skew(x)] = v;
+    }
+    __syncthreads();
+    fft_lds<NX, 16, NT, +1>(buf, tw, tid);
+    for (int b = 0; b < live; ++b) {
+      const int wi = 16 * mt + b;
+      const float w0 = wts[wi], w1 = wts[ws + wi], w2 = wts[2 * ws + wi];
+#pragma unroll
+      for (int i = 0; i < PX; ++i) {
+        const int x = tid + i * NT;
+        const float2 v = c2::scale(buf[b * S + skew(x)], amp);
+        const float pw = v.x * v.x + v.y * v.y;
+        e0[i] += w0 * pw;
+        e1[i] += w1 * pw;
+        e2[i] += w2 * pw;
+        if (spec) spec[((long)j * nb + wi) * npix + (long)y * NX + x] = v;
+      }
+    }
+    __syncthreads();
+  }
+  const long o = (long)j * npix + (long)y * NX;
+#pragma unroll
+  for (int i = 0; i < PX; ++i) {
+    const int x = tid + i * NT;
+    if (o0) o0[o + x] = e0[i];
+    if (o1) o1[o + x] = e1[i];
+    if (o2) o2[o + x] = e2[i];
+  }
+}
+
+hv_status launched(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hvi::fail(HV_ERR_DEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+  return HV_OK;
+}
+
+template <int NX, typename TIN, typename TOUT>
+hv_status go_rows(const void* in, void* out, int ny, int stride, int nwin, int window, int nb, int mtiles,
+                  const hv_h8* ahi, const hv_h8* alo, float scale, hipStream_t st) {
+  const dim3 grid((unsigned)nwin * ny), block(NX);
+  switch (window) {
+    case 8: hipLaunchKernelGGL((k_band_rows<NX, 8, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale); break;
+    case 16: hipLaunchKernelGGL((k_band_rows<NX, 16, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale); break;
+    case 32: hipLaunchKernelGGL((k_band_rows<NX, 32, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale); break;
+    case 64: hipLaunchKernelGGL((k_band_rows<NX, 64, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale); break;
+    default: return hvi::fail(HV_ERR_SHAPE, "window %d not supported", window);
+  }
+  return launched("band_rows");
+}
+
+template <int NY, typename TIO>
+hv_status go_cols(void* io, const float2* ht, int nfields, int nx, hipStream_t st) {
+  // 128-byte runs per row of the column tile (64-byte fp16 runs above
+  // 256 rows, where 32 columns would not leave room for two tiles per CU);
+  // 16 (above 256 rows 32) column elements per thread
+  constexpr int BC = (sizeof(TIO) == 4 && NY <= 256) ? 32 : 16;
+  constexpr int NTK = BC * (NY <= 256 ? 16 : 32);
+  hipLaunchKernelGGL((k_band_cols<NY, BC, NTK, TIO>), dim3((unsigned)(nx / BC) * nfields), dim3(NTK), 0, st,
+                     (TIO*)io, ht, nx);
+  return launched("band_cols");
+}
+
+template <int NX, typename TIN>
+hv_status go_power(const void* in, int ny, int nwin, int nb, int mtiles, const float* wts, float amp, float* o0,
+                   float* o1, float* o2, float2* spec, hipStream_t st) {
+  hipLaunchKernelGGL((k_band_power<NX, TIN>), dim3((unsigned)nwin * ny), dim3(NX), 0, st, (const TIN*)in, ny, nb,
+                     mtiles, wts, amp, o0, o1, o2, spec);
+  return launched("band_power");
+}
+
+}  // namespace
+
+namespace hvi {
+
+bool band_first_fits(int ny, int nx, int in_t) {
+  if (in_t != HV_U8 && in_t != HV_U16) return false;
+  if (nx != 256 && nx != 512) return false;
+  switch (ny) {
+    case 64: case 128: case 256: case 320: case 384: case 512: return true;
+    default: return false;
+  }
+}
+
+hv_status launch_band_rows(const void* in, int in_t, void* out, bool half_out, int ny, int nx, int stride, int nwin,
+                           int window, int nb, int mtiles, const hv_h8* ahi, const hv_h8* alo, float scale,
+                           hipStream_t st) {
+  if (!band_first_fits(ny, nx, in_t)) return fail(HV_ERR_SHAPE, "band-first rows: %dx%d type %d", nx, ny, in_t);
+  if (nb <= 0 || nb > 16 * mtiles || mtiles > 4) return fail(HV_ERR_ARG, "band-first rows: %d bins", nb);
+  if (nwin <= 0) return HV_OK;
+#define HV_ROWS(NX_)                                                                                        \
+  if (in_t == HV_U8)                                                                                        \
+    return half_out ? go_rows<NX_, uint8_t, hv_h2>(in, out, ny, stride, nwin, window, nb, mtiles, ahi, alo, scale, st) \
+                    : go_rows<NX_, uint8_t, float2>(in, out, ny, stride, nwin, window, nb, mtiles, ahi, alo, scale, st); \
+  return half_out ? go_rows<NX_, uint16_t, hv_h2>(in, out, ny, stride, nwin, window, nb, mtiles, ahi, alo, scale, st) \
+                  : go_rows<NX_, uint16_t, float2>(in, out, ny, stride, nwin, window, nb, mtiles, ahi, alo, scale, st);
+  if (nx == 256) { HV_ROWS(256) }
+  HV_ROWS(512)
+#undef HV_ROWS
+}
+
+hv_status launch_band_cols(void* io, bool half_io, const float2* ht, int nfields, int ny, int nx, hipStream_t st) {
+  if (nfields <= 0) return HV_OK;
+  if (nx % 32 || !band_first_fits(ny, 256, HV_U8)) return fail(HV_ERR_SHAPE, "band-first columns: nx %d", nx);
+#define HV_COLS(NY_) \
+  case NY_: return half_io ? go_cols<NY_, hv_h2>(io, ht, nfields, nx, st) : go_cols<NY_, float2>(io, ht, nfields, nx, st);
+  switch (ny) {
+    HV_COLS(64) HV_COLS(128) HV_COLS(256) HV_COLS(320) HV_COLS(384) HV_COLS(512)
+    default: return fail(HV_ERR_SHAPE, "band-first columns: ny %d", ny);
+  }
+#undef HV_COLS
+}
+
+hv_status launch_band_power(const void* in, bool half_in, int ny, int nx, int nwin, int nb, int mtiles,
+                            const float* wts, float amp, float* o0, float* o1, float* o2, float2* spec,
+                            hipStream_t st) {
+  if (nwin <= 0) return HV_OK;
+  if (nx == 256)
+    return half_in ? go_power<256, hv_h2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st)
+                   : go_power<256, float2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st);
+  if (nx == 512)
+    return half_in ? go_power<512, hv_h2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st)
+                   : go_power<512, float2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st);
+  return fail(HV_ERR_SHAPE, "band-first power: nx %d", nx);
+}
+
+}  // namespace hvi

@@ -51,6 +51,9 @@ struct DftPlan {
   std::vector<int> bins;
   std::vector<double> freqs;
   DevBuf a32, a16hi, a16lo, wts;
+  // real-input fragments for the band-first order: A[2b + c][t] =
+  // (cos, -sin)(2 pi k_b t / W), [mtiles][max(1, W/16)][64] fp16x8 (hi, lo)
+  DevBuf ar_hi, ar_lo;
 };
 
 int band_bins(const hv_temporal& tp, std::vector<int>& bins, std::vector<double>& freqs);
@@ -84,6 +87,7 @@ struct Ctx {
   size_t budget = 0;
   size_t held = 0;  // bytes of plans and workspaces
   int chunk_frames = 0;
+  int stft_order = 0;  // HV_ORDER_*
   using OptKey = std::tuple<int, int, double, double, double, double, double>;
   std::map<OptKey, std::unique_ptr<AsPlan>> as_plans;
   std::map<OptKey, std::unique_ptr<FresnelPlan>> fr_plans;

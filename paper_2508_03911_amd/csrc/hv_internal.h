@@ -102,4 +102,26 @@ hv_status launch_proj_energy(const void* u, bool half_in, long npix, int stride,
 hv_status launch_time_fft(const void* u, bool half_in, long npix, int stride, int nwin, int window, float amp2,
                           float* out, hipStream_t st);
 
+// ---------------------------------------------------------------- band-first order
+// (angular spectrum of each band bin's combination of raw frames)
+
+// Frame shapes and input types the band-first kernels take: u8/u16 frames,
+// nx 256 or 512, ny in {64, 128, 256, 320, 384, 512}.
+bool band_first_fits(int ny, int nx, int in_t);
+// Window jj of in (frames jj*stride ..) reduced to nb bins (real-input A
+// fragments ahi/alo, mtiles tiles) and row-transformed:
+// out [nwin][nb][ny][nx] complex (c64 or fp16), values * scale.
+hv_status launch_band_rows(const void* in, int in_t, void* out, bool half_out, int ny, int nx, int stride, int nwin,
+                           int window, int nb, int mtiles, const hv_h8* ahi, const hv_h8* alo, float scale,
+                           hipStream_t st);
+// In place on nfields fields [ny][nx]: column FFT, * ht (column-major
+// [nx][ny]), inverse column FFT.
+hv_status launch_band_cols(void* io, bool half_io, const float2* ht, int nfields, int ny, int nx, hipStream_t st);
+// Inverse row FFT of [nwin][nb][ny][nx], values * amp, then the weighted
+// powers (wts [3][16 mtiles]) into o0..o2 [nwin][ny][nx] and, when spec is
+// not null, the values into spec [nwin][nb][ny*nx].
+hv_status launch_band_power(const void* in, bool half_in, int ny, int nx, int nwin, int nb, int mtiles,
+                            const float* wts, float amp, float* o0, float* o1, float* o2, float2* spec,
+                            hipStream_t st);
+
 }  // namespace hvi

@@ -22,6 +22,7 @@ HV_OK, HV_ERR_ARG, HV_ERR_SHAPE, HV_ERR_NOMEM, HV_ERR_BUDGET, HV_ERR_DEVICE, HV_
 HV_U8, HV_U16, HV_C64 = 0, 1, 3
 HV_AS, HV_FRESNEL = 0, 1
 HV_PREC_FP32, HV_PREC_MIXED = 0, 1
+HV_ORDER_AUTO, HV_ORDER_FRAMES_FIRST, HV_ORDER_BAND_FIRST = 0, 1, 2
 
 _STATUS_NAMES = {0: "HV_OK", -1: "HV_ERR_ARG", -2: "HV_ERR_SHAPE", -3: "HV_ERR_NOMEM", -4: "HV_ERR_BUDGET",
                  -5: "HV_ERR_DEVICE", -6: "HV_ERR_OVERFLOW", -7: "HV_ERR_STATE"}
@@ -102,6 +103,7 @@ _sig = {
     "hv_ctx_destroy": (None, [_P]),
     "hv_ctx_workspace_bytes": (C.c_size_t, [_P]),
     "hv_ctx_set_chunk_frames": (_I, [_P, _I]),
+    "hv_ctx_set_stft_order": (_I, [_P, _I]),
     "hv_ctx_set_timing": (_I, [_P, _I]),
     "hv_ctx_kernel_time": (_I, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_long)]),
     "hv_band_bins": (_I, [C.POINTER(hv_temporal), C.POINTER(_I), C.POINTER(_I), C.POINTER(C.c_double)]),
@@ -276,6 +278,10 @@ class Context:
 
     def set_chunk_frames(self, frames: int):
         _check(lib.hv_ctx_set_chunk_frames(self.handle, frames))
+
+    def set_stft_order(self, order: int):
+        """HV_ORDER_AUTO, HV_ORDER_FRAMES_FIRST or HV_ORDER_BAND_FIRST."""
+        _check(lib.hv_ctx_set_stft_order(self.handle, order))
 
     def set_timing(self, on: bool):
         """Bracket every kernel launch with HIP events (clears the totals)."""
