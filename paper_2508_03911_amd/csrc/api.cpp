@@ -345,6 +345,26 @@ Ctx::Lane2* Ctx::lane2(hipStream_t caller, hv_status* st) {
   return &l;
 }
 
+int persistent_blocks(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  int dev = 0;
+  hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_pair(kernel, dev);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0, per = 0;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess) {
+    hipGetLastError();
+    per = 1;
+  }
+  const int b = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
+  cache[key] = b;
+  return b;
+}
+
 DevBuf& Ctx::work(hipStream_t s, int slot) {
   std::lock_guard<std::recursive_mutex> lk(mu);
   return ws[std::make_pair((void*)s, slot)];

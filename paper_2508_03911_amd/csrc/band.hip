@@ -34,6 +34,7 @@
 #include "hv_internal.h"
 
 using namespace hvk;
+using hvi::persistent_grid;
 
 namespace {
 
@@ -64,16 +65,18 @@ __device__ inline uint32_t pick(uint32_t w, int q) {
 }
 
 // ------------------------------------------------------------------ KA
-// Block u = (window u / ny, row u % ny), NX threads.  Wave v owns pixels
-// [64 v, 64 v + 64); lane (c, h) loads the two neighbouring pixels
-// 64 v + 2c + q (q = 0, 1) of frames t = 16 kk + 8 h + e, which make its B
-// fragments of the two column tiles (tile q, column c).  u16 values are
-// split into two exact bytes, reduced separately and recombined as
-// lo + 256 hi.
+// Unit u = (window u / ny, row u % ny); persistent workgroups of NX
+// threads take units u = blockIdx.x, + gridDim.x, ... and load the next
+// unit's camera values into registers while the current one is
+// transformed.  Wave v owns pixels [64 v, 64 v + 64); lane (c, h) loads the
+// two neighbouring pixels 64 v + 2c + q (q = 0, 1) of frames
+// t = 16 kk + 8 h + e, which make its B fragments of the two column tiles
+// (tile q, column c).  u16 values are split into two exact bytes, reduced
+// separately and recombined as lo + 256 hi.
 template <int NX, int W, typename TIN, typename TOUT>
 __global__ __launch_bounds__(NX) void k_band_rows(const TIN* __restrict__ in, TOUT* __restrict__ out, int ny,
                                                   int stride, int nb, int mtiles, const hv_h8* __restrict__ ahi,
-                                                  const hv_h8* __restrict__ alo, float scale) {
+                                                  const hv_h8* __restrict__ alo, float scale, int nunits) {
   constexpr int NT = NX, PL = 2;
   static_assert(NX == 256 || NX == 512, "row width 256 or 512");
   constexpr int KS = W >= 16 ? W / 16 : 1;
@@ -84,72 +87,80 @@ __global__ __launch_bounds__(NX) void k_band_rows(const TIN* __restrict__ in, TO
   __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31;
   fill_twiddles<NX>(tw, tid, NT);
-  const int j = blockIdx.x / ny, y = blockIdx.x % ny;
   const long npix = (long)ny * NX;
   const int xb = wave * 32 * PL + PL * c;
   // frame j*stride + t, row y: wave-uniform base + lane offset (8h frames, pixel xb)
-  const TIN* base = in + ((long)j * stride * ny + y) * NX;
   const uint32_t off = (uint32_t)((8 * h) * npix + xb) * (uint32_t)sizeof(TIN);
   R raw[KS][8];
+  auto fetch = [&](int u) {
+    const TIN* base = in + ((long)(u / ny) * stride * ny + u % ny) * NX;
 #pragma unroll
-  for (int kk = 0; kk < KS; ++kk)
+    for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if (W >= 16 || h == 0)
-        raw[kk][e] = ld_off(reinterpret_cast<const R*>(base + (long)(16 * kk + e) * npix), off);
-      else
-        raw[kk][e] = 0;
-    }
-  TOUT* dst0 = out + ((long)j * nb * ny + y) * NX;
-  for (int mt = 0; mt < mtiles; ++mt) {
-    hv_h8 fh[KS], fl[KS];
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      fh[kk] = ahi[(mt * KS + kk) * 64 + lane];
-      fl[kk] = alo[(mt * KS + kk) * 64 + lane];
-    }
-#pragma unroll
-    for (int q = 0; q < PL; ++q) {
-      f32x16 acc, acc2;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = acc2[r] = 0.f;
+      for (int e = 0; e < 8; ++e) {
+        if (W >= 16 || h == 0)
+          raw[kk][e] = ld_off(reinterpret_cast<const R*>(base + (long)(16 * kk + e) * npix), off);
+        else
+          raw[kk][e] = 0;
+      }
+  };
+  int u = blockIdx.x;
+  if (u < nunits) fetch(u);
+  for (; u < nunits; u += gridDim.x) {
+    TOUT* dst0 = out + ((long)(u / ny) * nb * ny + u % ny) * NX;
+    for (int mt = 0; mt < mtiles; ++mt) {
+      hv_h8 fh[KS], fl[KS];
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk) {
-        hv_h8 b, bh;
+        fh[kk] = ahi[(mt * KS + kk) * 64 + lane];
+        fl[kk] = alo[(mt * KS + kk) * 64 + lane];
+      }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint32_t v = pick<TIN>(raw[kk][e], q);
-          b[e] = (_Float16)(float)(v & 0xffu);
-          if constexpr (U16) bh[e] = (_Float16)(float)(v >> 8);
+      for (int q = 0; q < PL; ++q) {
+        f32x16 acc, acc2;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] = acc2[r] = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+          hv_h8 b, bh;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t v = pick<TIN>(raw[kk][e], q);
+            b[e] = (_Float16)(float)(v & 0xffu);
+            if constexpr (U16) bh[e] = (_Float16)(float)(v >> 8);
+          }
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[kk], b, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[kk], b, acc, 0, 0, 0);
+          if constexpr (U16) {
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[kk], bh, acc2, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[kk], bh, acc2, 0, 0, 0);
+          }
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[kk], b, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[kk], b, acc, 0, 0, 0);
         if constexpr (U16) {
-          acc2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(fh[kk], bh, acc2, 0, 0, 0);
-          acc2 = __builtin_amdgcn_mfma_f32_32x32x16_f16(fl[kk], bh, acc2, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[r] += 256.f * acc2[r];
         }
+        const int xs = skew(xb + q);
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+          for (int p = 0; p < 2; ++p)
+            buf[(4 * g + 2 * h + p) * S + xs] = make_float2(acc[4 * g + 2 * p], acc[4 * g + 2 * p + 1]);
       }
-      if constexpr (U16) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] += 256.f * acc2[r];
+      // the camera values are consumed: fetch the next unit's
+      if (mt == mtiles - 1 && u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+      __syncthreads();
+      fft_lds<NX, 16, NT, -1>(buf, tw, tid);
+      const int live = nb - 16 * mt < 16 ? nb - 16 * mt : 16;
+      TOUT* dst = dst0 + (long)16 * mt * npix;
+      for (int q = tid; q < live * NX; q += NT) {
+        const int b = q / NX, x = q % NX;
+        TOUT v;
+        store_c(&v, c2::scale(buf[b * S + skew(x)], scale));
+        st_off(dst, (uint32_t)(b * npix + x) * (uint32_t)sizeof(TOUT), v);
       }
-      const int xs = skew(xb + q);
-#pragma unroll
-      for (int g = 0; g < 4; ++g)
-#pragma unroll
-        for (int p = 0; p < 2; ++p) buf[(4 * g + 2 * h + p) * S + xs] = make_float2(acc[4 * g + 2 * p], acc[4 * g + 2 * p + 1]);
+      __syncthreads();
     }
-    __syncthreads();
-    fft_lds<NX, 16, NT, -1>(buf, tw, tid);
-    const int live = nb - 16 * mt < 16 ? nb - 16 * mt : 16;
-    TOUT* dst = dst0 + (long)16 * mt * npix;
-    for (int q = tid; q < live * NX; q += NT) {
-      const int b = q / NX, x = q % NX;
-      TOUT v;
-      store_c(&v, c2::scale(buf[b * S + skew(x)], scale));
-      st_off(dst, (uint32_t)(b * npix + x) * (uint32_t)sizeof(TOUT), v);
-    }
-    __syncthreads();
   }
 }
 
@@ -204,65 +215,69 @@ __global__ __launch_bounds__(NTK) void k_band_cols(TIO* __restrict__ io, const f
 }
 
 // ------------------------------------------------------------------ KC
-// Block u = (window u / ny, row u % ny), NX threads: bins in groups of 16,
-// each group's rows inverse-transformed in LDS; thread tid owns pixel tid.
+// Unit u = (window u / ny, row u % ny), persistent workgroups of NX
+// threads: bins in groups of 16, each group's rows inverse-transformed in
+// LDS while the next group's (or next unit's) rows load into registers;
+// thread tid owns pixel tid.
 template <int NX, typename TIN>
 __global__ __launch_bounds__(NX) void k_band_power(const TIN* __restrict__ in, int ny, int nb, int mtiles,
                                                    const float* __restrict__ wts, float amp,
                                                    float* __restrict__ o0, float* __restrict__ o1,
-                                                   float* __restrict__ o2, float2* __restrict__ spec) {
-  constexpr int NT = NX, PX = 1;
+                                                   float* __restrict__ o2, float2* __restrict__ spec, int nunits) {
+  constexpr int NT = NX;
   constexpr int S = lds_stride(NX);
-  constexpr int PER = 16 * NX / NT;
   __shared__ float2 buf[16 * S];
   __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
   const int tid = threadIdx.x;
   fill_twiddles<NX>(tw, tid, NT);
-  const int j = blockIdx.x / ny, y = blockIdx.x % ny;
   const long npix = (long)ny * NX;
-  const TIN* src = in + ((long)j * nb * ny + y) * NX;
   const int ws = 16 * mtiles;
-  float e0[PX], e1[PX], e2[PX];
+  const uint32_t off = (uint32_t)tid * (uint32_t)sizeof(TIN);
+  TIN pre[16];
+  auto live_of = [&](int mt) { return nb - 16 * mt < 16 ? nb - 16 * mt : 16; };
+  auto fetch = [&](int u, int mt) {
+    const TIN* s0 = in + (((long)(u / ny) * nb + 16 * mt) * ny + u % ny) * NX;
+    const int live = live_of(mt);
 #pragma unroll
-  for (int i = 0; i < PX; ++i) e0[i] = e1[i] = e2[i] = 0.f;
-  for (int mt = 0; mt < mtiles; ++mt) {
-    const int live = nb - 16 * mt < 16 ? nb - 16 * mt : 16;
-    const TIN* s0 = src + (long)16 * mt * npix;
+    for (int i = 0; i < 16; ++i)
+      if (i < live) pre[i] = ld_off(s0 + (long)i * npix, off);
+  };
+  float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+  int u = blockIdx.x, mt = 0;
+  if (u < nunits) fetch(u, 0);
+  while (u < nunits) {
+    const int live = live_of(mt);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int q = tid + i * NT, b = q / NX, x = q % NX;
-      float2 v = make_float2(0.f, 0.f);
-      if (b < live) {
-        const TIN t = ld_off(s0, (uint32_t)(b * npix + x) * (uint32_t)sizeof(TIN));
-        v = load_c(&t);
-      }
-      buf[b * S + skew(x)] = v;
-    }
+    for (int i = 0; i < 16; ++i) buf[i * S + skew(tid)] = i < live ? load_c(&pre[i]) : make_float2(0.f, 0.f);
     __syncthreads();
+    int nu = u, nm = mt + 1;
+    if (nm == mtiles) {
+      nu = u + gridDim.x;
+      nm = 0;
+    }
+    if (nu < nunits) fetch(nu, nm);
     fft_lds<NX, 16, NT, +1>(buf, tw, tid);
+    const long pix = (long)(u % ny) * NX + tid;
     for (int b = 0; b < live; ++b) {
       const int wi = 16 * mt + b;
       const float w0 = wts[wi], w1 = wts[ws + wi], w2 = wts[2 * ws + wi];
-#pragma unroll
-      for (int i = 0; i < PX; ++i) {
-        const int x = tid + i * NT;
-        const float2 v = c2::scale(buf[b * S + skew(x)], amp);
-        const float pw = v.x * v.x + v.y * v.y;
-        e0[i] += w0 * pw;
-        e1[i] += w1 * pw;
-        e2[i] += w2 * pw;
-        if (spec) spec[((long)j * nb + wi) * npix + (long)y * NX + x] = v;
-      }
+      const float2 v = c2::scale(buf[b * S + skew(tid)], amp);
+      const float pw = v.x * v.x + v.y * v.y;
+      e0 += w0 * pw;
+      e1 += w1 * pw;
+      e2 += w2 * pw;
+      if (spec) spec[((long)(u / ny) * nb + wi) * npix + pix] = v;
+    }
+    if (mt == mtiles - 1) {
+      const long o = (long)(u / ny) * npix + pix;
+      if (o0) o0[o] = e0;
+      if (o1) o1[o] = e1;
+      if (o2) o2[o] = e2;
+      e0 = e1 = e2 = 0.f;
     }
     __syncthreads();
-  }
-  const long o = (long)j * npix + (long)y * NX;
-#pragma unroll
-  for (int i = 0; i < PX; ++i) {
-    const int x = tid + i * NT;
-    if (o0) o0[o + x] = e0[i];
-    if (o1) o1[o + x] = e1[i];
-    if (o2) o2[o + x] = e2[i];
+    u = nu;
+    mt = nm;
   }
 }
 
@@ -275,12 +290,21 @@ hv_status launched(const char* what) {
 template <int NX, typename TIN, typename TOUT>
 hv_status go_rows(const void* in, void* out, int ny, int stride, int nwin, int window, int nb, int mtiles,
                   const hv_h8* ahi, const hv_h8* alo, float scale, hipStream_t st) {
-  const dim3 grid((unsigned)nwin * ny), block(NX);
+  const int nunits = nwin * ny;
+  const dim3 block(NX);
+  dim3 grid;
   switch (window) {
-    case 8: hipLaunchKernelGGL((k_band_rows<NX, 8, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale); break;
-    case 16: hipLaunchKernelGGL((k_band_rows<NX, 16, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale); break;
-    case 32: hipLaunchKernelGGL((k_band_rows<NX, 32, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale); break;
-    case 64: hipLaunchKernelGGL((k_band_rows<NX, 64, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale); break;
+    case 8: grid = dim3(persistent_grid(k_band_rows<NX, 8, TIN, TOUT>, NX, nunits)); break;
+    case 16: grid = dim3(persistent_grid(k_band_rows<NX, 16, TIN, TOUT>, NX, nunits)); break;
+    case 32: grid = dim3(persistent_grid(k_band_rows<NX, 32, TIN, TOUT>, NX, nunits)); break;
+    case 64: grid = dim3(persistent_grid(k_band_rows<NX, 64, TIN, TOUT>, NX, nunits)); break;
+    default: return hvi::fail(HV_ERR_SHAPE, "window %d not supported", window);
+  }
+  switch (window) {
+    case 8: hipLaunchKernelGGL((k_band_rows<NX, 8, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale, nunits); break;
+    case 16: hipLaunchKernelGGL((k_band_rows<NX, 16, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale, nunits); break;
+    case 32: hipLaunchKernelGGL((k_band_rows<NX, 32, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale, nunits); break;
+    case 64: hipLaunchKernelGGL((k_band_rows<NX, 64, TIN, TOUT>), grid, block, 0, st, (const TIN*)in, (TOUT*)out, ny, stride, nb, mtiles, ahi, alo, scale, nunits); break;
     default: return hvi::fail(HV_ERR_SHAPE, "window %d not supported", window);
   }
   return launched("band_rows");
@@ -301,8 +325,10 @@ hv_status go_cols(void* io, const float2* ht, int nfields, int nx, hipStream_t s
 template <int NX, typename TIN>
 hv_status go_power(const void* in, int ny, int nwin, int nb, int mtiles, const float* wts, float amp, float* o0,
                    float* o1, float* o2, float2* spec, hipStream_t st) {
-  hipLaunchKernelGGL((k_band_power<NX, TIN>), dim3((unsigned)nwin * ny), dim3(NX), 0, st, (const TIN*)in, ny, nb,
-                     mtiles, wts, amp, o0, o1, o2, spec);
+  const int nunits = nwin * ny;
+  auto kern = k_band_power<NX, TIN>;
+  hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, NX, nunits)), dim3(NX), 0, st, (const TIN*)in, ny, nb, mtiles,
+                     wts, amp, o0, o1, o2, spec, nunits);
   return launched("band_power");
 }
 

@@ -16,6 +16,16 @@ hv_status fail(hv_status st, const char* fmt, ...);
 
 inline bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
 
+// Workgroups of a persistent kernel on the current device: every CU filled
+// to the kernel's occupancy at `threads` per workgroup (computed once per
+// kernel and device).
+int persistent_blocks(const void* kernel, int threads);
+template <class K>
+int persistent_grid(K kernel, int threads, int nunits) {
+  const int b = persistent_blocks(reinterpret_cast<const void*>(kernel), threads);
+  return nunits < b ? nunits : b;
+}
+
 // ---------------------------------------------------------------- spatial kernels
 // All launches are asynchronous on `stream`; shapes are validated by the caller.
 

@@ -21,6 +21,7 @@
 #include "hv_internal.h"
 
 using namespace hvk;
+using hvi::persistent_grid;
 
 namespace {
 
@@ -37,20 +38,6 @@ __device__ inline float2 load_c(const float2* p) { return *p; }
 __device__ inline float2 load_c(const hv_h2* p) {
   hv_h2 h = *p;
   return make_float2((float)h.x, (float)h.y);
-}
-
-// Grid of a persistent kernel: every CU filled to the kernel's occupancy.
-template <class K>
-int persistent_grid(K kernel, int nunits) {
-  static int blocks = 0;  // one per kernel instantiation
-  if (!blocks) {
-    int dev = 0, cus = 0, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, NT, 0);
-    blocks = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
-  }
-  return nunits < blocks ? nunits : blocks;
 }
 
 // 8 consecutive camera values as floats (exact).
@@ -433,7 +420,7 @@ void go_r2c(const void* in, void* out, int n, int ny, float scale, hipStream_t s
   constexpr int ROWS = cap64(16384 / NX);
   const int nunits = n * (ny / ROWS);
   auto kern = k_row_r2c<NX, ROWS, TIN, TOUT>;
-  hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, nunits)), dim3(NT), 0, st, (const TIN*)in, (TOUT*)out, ny,
+  hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, NT, nunits)), dim3(NT), 0, st, (const TIN*)in, (TOUT*)out, ny,
                      nunits, scale);
 }
 

@@ -26,6 +26,7 @@
 #include "hv_internal.h"
 
 using namespace hvk;
+using hvi::persistent_grid;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -641,20 +642,6 @@ CoefArgs make_args(const hvi::CoefGemm& g, long a_win_stride, float bsc, float a
   return a;
 }
 
-// Grid of a persistent kernel: every CU filled to the kernel's occupancy.
-template <class K>
-int persistent_grid(K kernel, int nunits) {
-  static int blocks = 0;  // one per kernel instantiation
-  if (!blocks) {
-    int dev = 0, cus = 0, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, NT, 0);
-    blocks = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
-  }
-  return nunits < blocks ? nunits : blocks;
-}
-
 template <int NX, int W, bool MIXED>
 hv_status go_rowinv(const void* z, bool half_in, int ny, int stride, int nwin, const CoefArgs& a,
                     hipStream_t st) {
@@ -662,7 +649,7 @@ hv_status go_rowinv(const void* z, bool half_in, int ny, int stride, int nwin, c
     const int nunits = ny * nwin;
     if (half_in) {
       auto kern = k_rowinv_coef<NX, W, MIXED, hv_h2>;
-      hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, nunits)), dim3(NT), 0, st, (const hv_h2*)z, ny, stride,
+      hipLaunchKernelGGL(kern, dim3(persistent_grid(kern, NT, nunits)), dim3(NT), 0, st, (const hv_h2*)z, ny, stride,
                          nunits, a);
     } else {
       hipLaunchKernelGGL((k_rowinv_coef<NX, W, MIXED, float2>), dim3(nunits), dim3(NT), 0, st, (const float2*)z,
