@@ -165,11 +165,16 @@ __global__ __launch_bounds__(NX) void k_band_rows(const TIN* __restrict__ in, TO
 }
 
 // ------------------------------------------------------------------ KB
-// Block (column group, field): columns [x0, x0 + BC) of one bin field
-// [ny][nx], transformed in place.  ht is column-major [nx][ny]:
+// Unit u = (field u / groups, column group u % groups): columns
+// [x0, x0 + BC) of one bin field [ny][nx], transformed in place.  Persistent
+// workgroups take units u = blockIdx.x, + gridDim.x, ... with gridDim.x a
+// multiple of groups, so a workgroup keeps one column group: its H_z values
+// stay in registers, and the next unit's columns load into registers while
+// the current one is transformed.  ht is column-major [nx][ny]:
 // H_z(fx, fy) / ny with the high-pass mask folded in.
 template <int NY, int BC, int NTK, typename TIO>
-__global__ __launch_bounds__(NTK) void k_band_cols(TIO* __restrict__ io, const float2* __restrict__ ht, int nx) {
+__global__ __launch_bounds__(NTK) void k_band_cols(TIO* __restrict__ io, const float2* __restrict__ ht, int nx,
+                                                   int nunits) {
   constexpr int S = lds_stride(NY);
   constexpr int U = BC * NY / NTK;
   constexpr int RS = NTK / BC;  // rows per pass of the threads
@@ -179,38 +184,47 @@ __global__ __launch_bounds__(NTK) void k_band_cols(TIO* __restrict__ io, const f
   const int tid = threadIdx.x;
   const int groups = nx / BC;
   const int x0 = (blockIdx.x % groups) * BC;
-  const long f = blockIdx.x / groups;
   fill_twiddles<NY>(tw, tid, NTK);
-  TIO* base = io + f * NY * (long)nx + x0;
-  // load / store element u: column s, row yr + u * RS
-  const int s = tid % BC, yr = tid / BC;
-  const uint32_t off = (uint32_t)(yr * nx + s) * (uint32_t)sizeof(TIO);
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const TIO v = ld_off(base + (long)u * RS * nx, off);
-    buf[s * S + skew(yr + u * RS)] = load_c(&v);
-  }
   // multiply element q = tid + u * NTK: sequence q / NY, frequency q % NY
   // (the table run of one column is contiguous)
   const float2* hcol = ht + (long)x0 * NY;
   float2 hv[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) hv[u] = ld_off(hcol + u * NTK, (uint32_t)tid * 8u);
-  __syncthreads();
-  fft_lds<NY, BC, NTK, -1>(buf, tw, tid);
+  // load / store element u: column s, row yr + u * RS
+  const int s = tid % BC, yr = tid / BC;
+  const uint32_t off = (uint32_t)(yr * nx + s) * (uint32_t)sizeof(TIO);
+  auto base_of = [&](int unit) { return io + (long)(unit / groups) * NY * nx + x0; };
+  TIO pre[U];
+  auto fetch = [&](int unit) {
+    const TIO* base = base_of(unit);
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int q = tid + u * NTK;
-    float2* e = buf + (q / NY) * S + skew(q % NY);
-    *e = c2::mul(*e, hv[u]);
-  }
-  __syncthreads();
-  fft_lds<NY, BC, NTK, +1>(buf, tw, tid);
+    for (int u = 0; u < U; ++u) pre[u] = ld_off(base + (long)u * RS * nx, off);
+  };
+  int unit = blockIdx.x;
+  if (unit < nunits) fetch(unit);
+  for (; unit < nunits; unit += gridDim.x) {
+    TIO* base = base_of(unit);
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    TIO v;
-    store_c(&v, buf[s * S + skew(yr + u * RS)]);
-    st_off(base + (long)u * RS * nx, off, v);
+    for (int u = 0; u < U; ++u) buf[s * S + skew(yr + u * RS)] = load_c(&pre[u]);
+    __syncthreads();
+    if (unit + (int)gridDim.x < nunits) fetch(unit + gridDim.x);
+    fft_lds<NY, BC, NTK, -1>(buf, tw, tid);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = tid + u * NTK;
+      float2* e = buf + (q / NY) * S + skew(q % NY);
+      *e = c2::mul(*e, hv[u]);
+    }
+    __syncthreads();
+    fft_lds<NY, BC, NTK, +1>(buf, tw, tid);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      TIO v;
+      store_c(&v, buf[s * S + skew(yr + u * RS)]);
+      st_off(base + (long)u * RS * nx, off, v);
+    }
+    __syncthreads();
   }
 }
 
@@ -317,8 +331,11 @@ hv_status go_cols(void* io, const float2* ht, int nfields, int nx, hipStream_t s
   // 16 (above 256 rows 32) column elements per thread
   constexpr int BC = (sizeof(TIO) == 4 && NY <= 256) ? 32 : 16;
   constexpr int NTK = BC * (NY <= 256 ? 16 : 32);
-  hipLaunchKernelGGL((k_band_cols<NY, BC, NTK, TIO>), dim3((unsigned)(nx / BC) * nfields), dim3(NTK), 0, st,
-                     (TIO*)io, ht, nx);
+  const int groups = nx / BC, nunits = groups * nfields;
+  auto kern = k_band_cols<NY, BC, NTK, TIO>;
+  int grid = persistent_grid(kern, NTK, nunits);
+  if (grid < nunits) grid = grid / groups * groups;  // a whole number of column-group sets
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NTK), 0, st, (TIO*)io, ht, nx, nunits);
   return launched("band_cols");
 }
 
