@@ -126,8 +126,9 @@ hv_status hv_ctx_set_chunk_frames(hv_ctx* ctx, int frames);
  * frames and then propagated ("band first"), which transforms nb fields per
  * window instead of W frames.
  *   HV_ORDER_AUTO         band first where it moves fewer bytes per window
- *                         and the shape is supported (u8/u16 frames, nx 256
- *                         or 512, ny 64, 128, 256, 320, 384 or 512);
+ *                         and the shape is supported (u8/u16 frames, nx a
+ *                         power of two in [64, 512], ny 64, 128, 256, 320,
+ *                         384 or 512);
  *   HV_ORDER_FRAMES_FIRST propagate every frame, then the temporal transform;
  *   HV_ORDER_BAND_FIRST   band first wherever the shape is supported.
  * Returns HV_ERR_ARG for another value.  A new context starts from the

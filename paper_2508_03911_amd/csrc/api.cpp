@@ -725,19 +725,19 @@ static hv_status stft_band_first(Ctx* ctx, const void* in, int in_t, int ny, int
 // Shared driver of hv_stft_moments and hv_stft_bins.
 static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                            const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
-                           void* hip_stream, bool two_lanes);
+                           void* hip_stream, bool two_lanes, bool fixed_ws = false);
 
-// The serving loop's entry: one stream per call (its workspaces are
-// allocated at admission).
+// The serving loop's entry: one stream per call, on workspaces allocated
+// at admission (fixed_ws: nothing grows here).
 hv_status hvi_stft_common(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                           const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
                           void* hip_stream) {
-  return stft_impl(ctx, in, in_t, n, ny, nx, optics, tp, prec, m0, m1, m2, spec, hip_stream, false);
+  return stft_impl(ctx, in, in_t, n, ny, nx, optics, tp, prec, m0, m1, m2, spec, hip_stream, false, true);
 }
 
 static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                            const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
-                           void* hip_stream, bool two_lanes) {
+                           void* hip_stream, bool two_lanes, bool fixed_ws) {
   hv_status s;
   if ((s = enter(ctx))) return s;
   std::lock_guard<std::recursive_mutex> lock(ctx->mu);
@@ -774,9 +774,9 @@ static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny,
       (ctx->stft_order == HV_ORDER_BAND_FIRST || band_first_cheaper(w, stride, nb, (int)in_elem(in_t), mixed))) {
     int gb = band_chunk_windows(ctx, ny, nx, nb, w, stride, mixed);
     if (gb > nwin_total) gb = nwin_total;
-    // the serving loop's streams run on workspaces sized at admission: take
-    // this order there only when it fits the one already held
-    const bool fits = two_lanes || ctx->work(st, 1).bytes >= (size_t)gb * nb * frame * (mixed ? 4 : 8);
+    // the serving loop's streams run on workspaces sized at admission (for
+    // either order): take this order there only when it fits the one held
+    const bool fits = !fixed_ws || ctx->work(st, 1).bytes >= (size_t)gb * nb * frame * (mixed ? 4 : 8);
     if (fits)
       return stft_band_first(ctx, in, in_t, ny, nx, *optics, *dp, w, stride, nwin_total, gb, mixed, m0, m1, m2,
                              spec, st, two_lanes);

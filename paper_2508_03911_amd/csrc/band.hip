@@ -78,7 +78,7 @@ __global__ __launch_bounds__(NX) void k_band_rows(const TIN* __restrict__ in, TO
                                                   int stride, int nb, int mtiles, const hv_h8* __restrict__ ahi,
                                                   const hv_h8* __restrict__ alo, float scale, int nunits) {
   constexpr int NT = NX, PL = 2;
-  static_assert(NX == 256 || NX == 512, "row width 256 or 512");
+  static_assert(NX % 64 == 0 && NX <= 512, "row width: whole waves of 64 pixels");
   constexpr int KS = W >= 16 ? W / 16 : 1;
   constexpr int S = lds_stride(NX);
   constexpr bool U16 = sizeof(TIN) == 2;
@@ -355,7 +355,7 @@ namespace hvi {
 
 bool band_first_fits(int ny, int nx, int in_t) {
   if (in_t != HV_U8 && in_t != HV_U16) return false;
-  if (nx != 256 && nx != 512) return false;
+  if (!pow2_in(nx, 64, 512)) return false;
   switch (ny) {
     case 64: case 128: case 256: case 320: case 384: case 512: return true;
     default: return false;
@@ -374,8 +374,12 @@ hv_status launch_band_rows(const void* in, int in_t, void* out, bool half_out, i
                     : go_rows<NX_, uint8_t, float2>(in, out, ny, stride, nwin, window, nb, mtiles, ahi, alo, scale, st); \
   return half_out ? go_rows<NX_, uint16_t, hv_h2>(in, out, ny, stride, nwin, window, nb, mtiles, ahi, alo, scale, st) \
                   : go_rows<NX_, uint16_t, float2>(in, out, ny, stride, nwin, window, nb, mtiles, ahi, alo, scale, st);
-  if (nx == 256) { HV_ROWS(256) }
-  HV_ROWS(512)
+  switch (nx) {
+    case 64: { HV_ROWS(64) }
+    case 128: { HV_ROWS(128) }
+    case 256: { HV_ROWS(256) }
+    default: { HV_ROWS(512) }
+  }
 #undef HV_ROWS
 }
 
@@ -395,13 +399,15 @@ hv_status launch_band_power(const void* in, bool half_in, int ny, int nx, int nw
                             const float* wts, float amp, float* o0, float* o1, float* o2, float2* spec,
                             hipStream_t st) {
   if (nwin <= 0) return HV_OK;
-  if (nx == 256)
-    return half_in ? go_power<256, hv_h2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st)
-                   : go_power<256, float2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st);
-  if (nx == 512)
-    return half_in ? go_power<512, hv_h2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st)
-                   : go_power<512, float2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st);
-  return fail(HV_ERR_SHAPE, "band-first power: nx %d", nx);
+#define HV_POWER(NX_)                                                                          \
+  case NX_:                                                                                    \
+    return half_in ? go_power<NX_, hv_h2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st) \
+                   : go_power<NX_, float2>(in, ny, nwin, nb, mtiles, wts, amp, o0, o1, o2, spec, st);
+  switch (nx) {
+    HV_POWER(64) HV_POWER(128) HV_POWER(256) HV_POWER(512)
+    default: return fail(HV_ERR_SHAPE, "band-first power: nx %d", nx);
+  }
+#undef HV_POWER
 }
 
 }  // namespace hvi

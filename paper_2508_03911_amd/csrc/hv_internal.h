@@ -116,7 +116,7 @@ hv_status launch_time_fft(const void* u, bool half_in, long npix, int stride, in
 // (angular spectrum of each band bin's combination of raw frames)
 
 // Frame shapes and input types the band-first kernels take: u8/u16 frames,
-// nx 256 or 512, ny in {64, 128, 256, 320, 384, 512}.
+// nx a power of two in [64, 512], ny in {64, 128, 256, 320, 384, 512}.
 bool band_first_fits(int ny, int nx, int in_t);
 // Window jj of in (frames jj*stride ..) reduced to nb bins (real-input A
 // fragments ahi/alo, mtiles tiles) and row-transformed:

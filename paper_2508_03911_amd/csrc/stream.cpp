@@ -245,7 +245,14 @@ hv_status hv_stream_open(hv_ctx* ctx, int ny, int nx, int raw_t, const hv_optics
   const size_t cplx = prec == HV_PREC_MIXED ? 4 : 8;
   const bool fused = optics->method == HV_AS && rowinv_coef_fits(nx, w);
   const size_t ws0 = nf * npix * cplx;  // row pass output (upper bound)
-  const size_t ws1 = nf * npix * cplx;
+  size_t ws1 = nf * npix * cplx;
+  if (optics->method == HV_AS && band_first_fits(ny, nx, raw_t)) {
+    // room for the band-first order too: `group` windows of nb bin fields
+    std::vector<int> bins;
+    std::vector<double> freqs;
+    const size_t nb = (size_t)band_bins(*temporal, bins, freqs);
+    ws1 = std::max(ws1, (size_t)group * nb * npix * cplx);
+  }
   const size_t ws2 = fused ? 0 : nf * npix * cplx;
   const size_t table_b = npix * 8 + 4 * (size_t)(nx + ny) * 8;
   const size_t total = ring_b + 3 * out_b + ws0 + ws1 + ws2 + table_b;

@@ -82,6 +82,10 @@ CASES = [
     (30, 64, 512, np.uint8, 8, 4, 10e3, 1e3, 4e3, False, 0.05, 0),
     # u16 with W = 64 and 384-row columns
     (70, 384, 256, np.uint16, 64, 64, 64e3, 5e3, 20e3, False, 0.0, 0),
+    # one-wave rows (nx = 64)
+    (50, 128, 64, np.uint8, 16, 16, 20e3, 2e3, 8e3, False, 0.0, 0),
+    # two-wave rows (nx = 128), u16, two-sided band, high-pass, stride 8
+    (40, 64, 128, np.uint16, 32, 8, 30e3, 1e3, 14e3, True, 0.02, 0),
 ]
 
 

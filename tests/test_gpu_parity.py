@@ -159,20 +159,24 @@ def test_moments_overlap_ragged(ctx, hv, prec, method):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_two_streams_match_one(ctx, hv, prec):
+@pytest.mark.parametrize("order", [1, 2])
+def test_two_streams_match_one(ctx, hv, prec, order):
     """Several chunks alternate over two streams; one chunk runs on the
-    caller's stream alone.  Both schedules give bit-identical moments."""
-    say(f"two-stream chunk schedule vs one chunk, prec={prec}")
+    caller's stream alone.  Both schedules give bit-identical moments, in
+    either order of the AS moments path (1 frames first, 2 band first)."""
+    say(f"two-stream chunk schedule vs one chunk, order={order} prec={prec}")
     x = rand_frames(9, 200, 128, 128, np.uint8)
     opt = hv.Optics(LAM, 20e-6, 20e-6, -0.2, hv.HV_AS)
     tp = hv.Temporal(16, 16, 20e3, 1.5e3, 9e3)
     try:
+        ctx.set_stft_order(order)
         ctx.set_chunk_frames(32)
         two = [host(t) for t in ctx.hv_stft_moments(dev(x), opt, tp, prec)]
         ctx.set_chunk_frames(256)
         one = [host(t) for t in ctx.hv_stft_moments(dev(x), opt, tp, prec)]
     finally:
         ctx.set_chunk_frames(0)
+        ctx.set_stft_order(0)
     assert two[0].shape == (12, 128, 128)
     for a, b in zip(two, one):
         assert np.array_equal(a, b)
@@ -329,12 +333,17 @@ def c2_block():
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_c2_block_sampled_windows(ctx, hv, c2_block, prec):
+@pytest.mark.parametrize("order", [1, 2])
+def test_c2_block_sampled_windows(ctx, hv, c2_block, prec, order):
     x, spec = c2_block
-    say(f"256^2 headline block: 2048 frames, prec={prec}")
+    say(f"256^2 headline block: 2048 frames, order={order} prec={prec}")
     opt = hv.Optics(LAM, spec.pitch, spec.pitch, -spec.z, hv.HV_AS)
     tp = hv.Temporal(32, 32, spec.fs, 3e3, 35e3)
-    m = [host(t) for t in ctx.hv_stft_moments(dev(x), opt, tp, prec)]
+    ctx.set_stft_order(order)
+    try:
+        m = [host(t) for t in ctx.hv_stft_moments(dev(x), opt, tp, prec)]
+    finally:
+        ctx.set_stft_order(0)
     assert m[0].shape == (64, 256, 256)
     for j in (0, 31, 63):
         ref = _oracle_moments(x[32 * j:32 * j + 32], opt, tp)
