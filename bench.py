@@ -339,6 +339,24 @@ def table_iv_volume(hv, torch, inputs, steps, highpass=0.05):
     return out
 
 
+def copy_rate(torch, reps: int = 10):
+    """Device-to-device copy of 2 GiB by torch: read + write bytes per second,
+    the practical HBM rate that the pass-level figure can be read against."""
+    src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * (1 << 31) * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    return {"GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "note": "torch copy of 2 GiB, read + write bytes"}
+
+
 def host_ingest(hv, torch, block, spec, frames, steps):
     """The same 256x256 stream with its frames in pinned host memory and the
     moment images returned to pinned host memory: every frame crosses PCIe
@@ -459,6 +477,7 @@ def main():
                   "speedup_vs_fp32": mixed["frames_per_s"] / fp32["frames_per_s"],
                   "kernels": mixed["kernels"]},
         "kernels_fp32": fp32["kernels"],
+        "hbm_copy": copy_rate(torch),
     }
     if args.serve_seconds > 0:
         log(f"stream load replay for {args.serve_seconds:.0f}s ...")

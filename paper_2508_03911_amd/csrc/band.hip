@@ -185,12 +185,19 @@ __global__ __launch_bounds__(NTK) void k_band_cols(TIO* __restrict__ io, const f
   const int groups = nx / BC;
   const int x0 = (blockIdx.x % groups) * BC;
   fill_twiddles<NY>(tw, tid, NTK);
-  // multiply element q = tid + u * NTK: sequence q / NY, frequency q % NY
-  // (the table run of one column is contiguous)
+  // H_z of the outputs this thread writes in the last forward FFT pass,
+  // where the multiply is applied (the table run of one column is
+  // contiguous, and so are the lanes' positions)
+  constexpr int UL = fft_last_slots<NY, BC, NTK>(), RL = radix_of_pass(NY, num_passes(NY) - 1);
   const float2* hcol = ht + (long)x0 * NY;
-  float2 hv[U];
+  float2 hv[UL][RL];
 #pragma unroll
-  for (int u = 0; u < U; ++u) hv[u] = ld_off(hcol + u * NTK, (uint32_t)tid * 8u);
+  for (int u = 0; u < UL; ++u)
+#pragma unroll
+    for (int r = 0; r < RL; ++r) {
+      int b, i;
+      hv[u][r] = fft_last_index<NY, BC, NTK>(tid, u, r, &b, &i) ? hcol[b * NY + i] : make_float2(0.f, 0.f);
+    }
   // load / store element u: column s, row yr + u * RS
   const int s = tid % BC, yr = tid / BC;
   const uint32_t off = (uint32_t)(yr * nx + s) * (uint32_t)sizeof(TIO);
@@ -209,14 +216,9 @@ __global__ __launch_bounds__(NTK) void k_band_cols(TIO* __restrict__ io, const f
     for (int u = 0; u < U; ++u) buf[s * S + skew(yr + u * RS)] = load_c(&pre[u]);
     __syncthreads();
     if (unit + (int)gridDim.x < nunits) fetch(unit + gridDim.x);
-    fft_lds<NY, BC, NTK, -1>(buf, tw, tid);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int q = tid + u * NTK;
-      float2* e = buf + (q / NY) * S + skew(q % NY);
-      *e = c2::mul(*e, hv[u]);
-    }
-    __syncthreads();
+    fft_lds_io<NY, BC, NTK, -1, true>(buf, tw, tid, nullptr, [&](int u, int r, int b, int i, float2 v) {
+      buf[b * S + skew(i)] = c2::mul(v, hv[u][r]);
+    });
     fft_lds<NY, BC, NTK, +1>(buf, tw, tid);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -246,31 +248,49 @@ __global__ __launch_bounds__(NX) void k_band_power(const TIN* __restrict__ in, i
   fill_twiddles<NX>(tw, tid, NT);
   const long npix = (long)ny * NX;
   const int ws = 16 * mtiles;
-  const uint32_t off = (uint32_t)tid * (uint32_t)sizeof(TIN);
-  TIN pre[16];
+  // the elements this thread reads in the first inverse FFT pass: slot u,
+  // element r is bin pb[u] at pixel pi[u][r] (16 lanes read 16 consecutive
+  // pixels of one bin row)
+  constexpr int UF = fft_first_slots<NX, 16, NT>(), RF = radix_of_pass(NX, 0);
+  int pb[UF];
+  uint32_t po[UF][RF];
+#pragma unroll
+  for (int u = 0; u < UF; ++u)
+#pragma unroll
+    for (int r = 0; r < RF; ++r) {
+      int b = 16, i = 0;
+      if (!fft_first_index<NX, 16, NT>(tid, u, r, &b, &i)) b = 16;
+      if (r == 0) pb[u] = b;
+      po[u][r] = (uint32_t)(b * npix + i) * (uint32_t)sizeof(TIN);
+    }
+  TIN pre[UF][RF];
   auto live_of = [&](int mt) { return nb - 16 * mt < 16 ? nb - 16 * mt : 16; };
   auto fetch = [&](int u, int mt) {
     const TIN* s0 = in + (((long)(u / ny) * nb + 16 * mt) * ny + u % ny) * NX;
     const int live = live_of(mt);
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if (i < live) pre[i] = ld_off(s0 + (long)i * npix, off);
+    for (int uu = 0; uu < UF; ++uu)
+#pragma unroll
+      for (int r = 0; r < RF; ++r)
+        if (pb[uu] < live) pre[uu][r] = ld_off(s0, po[uu][r]);
   };
   float e0 = 0.f, e1 = 0.f, e2 = 0.f;
   int u = blockIdx.x, mt = 0;
   if (u < nunits) fetch(u, 0);
   while (u < nunits) {
     const int live = live_of(mt);
+    float2 cur[UF][RF];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) buf[i * S + skew(tid)] = i < live ? load_c(&pre[i]) : make_float2(0.f, 0.f);
-    __syncthreads();
+    for (int uu = 0; uu < UF; ++uu)
+#pragma unroll
+      for (int r = 0; r < RF; ++r) cur[uu][r] = pb[uu] < live ? load_c(&pre[uu][r]) : make_float2(0.f, 0.f);
     int nu = u, nm = mt + 1;
     if (nm == mtiles) {
       nu = u + gridDim.x;
       nm = 0;
     }
     if (nu < nunits) fetch(nu, nm);
-    fft_lds<NX, 16, NT, +1>(buf, tw, tid);
+    fft_lds_io<NX, 16, NT, +1>(buf, tw, tid, [&](int uu, int r, int, int) { return cur[uu][r]; }, nullptr);
     const long pix = (long)(u % ny) * NX + tid;
     for (int b = 0; b < live; ++b) {
       const int wi = 16 * mt + b;

@@ -17,6 +17,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+#include <type_traits>
+
 namespace hvk {
 
 struct c2 {
@@ -207,11 +210,21 @@ __device__ inline void fill_twiddles(float2* tw, int tid, int nthreads) {
 }
 
 // One Stockham pass of radix R over NB sequences of length N (in place).
-template <int N, int R, int NS, int NB, int NT, int DIR, int TWOFF>
-__device__ inline void stockham_pass(float2* buf, const float2* tw, int tid) {
+// LD / ST replace the pass's LDS reads / writes when they are not
+// std::nullptr_t: ld(u, r, b, i) returns element i of sequence b for
+// element r of the thread's butterfly slot u, st(u, r, b, i, v) takes output
+// element i of sequence b (u and r are compile-time after unrolling, so a
+// hook can keep its data in registers).  ST_LDS: the store hook itself
+// writes the buffer (in place of the plain write).  The barrier between the
+// reads and the writes is kept when both touch LDS, the barrier after the
+// writes when the writes touch LDS.
+template <int N, int R, int NS, int NB, int NT, int DIR, int TWOFF, bool ST_LDS, class LD, class ST>
+__device__ inline void stockham_pass_io(float2* buf, const float2* tw, int tid, const LD& ld, const ST& st) {
   constexpr int BF = NB * (N / R);             // butterflies in the pass
   constexpr int U = (BF + NT - 1) / NT;        // per thread
   constexpr int S = lds_stride(N);
+  constexpr bool LDS_IN = std::is_same<LD, std::nullptr_t>::value;
+  constexpr bool LDS_OUT = std::is_same<ST, std::nullptr_t>::value;
   float2 v[U][R];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -220,7 +233,12 @@ __device__ inline void stockham_pass(float2* buf, const float2* tw, int tid) {
       int b = q / (N / R), j = q % (N / R);
       const float2* src = buf + b * S;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[u][r] = src[skew(j + r * (N / R))];
+      for (int r = 0; r < R; ++r) {
+        if constexpr (LDS_IN)
+          v[u][r] = src[skew(j + r * (N / R))];
+        else
+          v[u][r] = ld(u, r, b, j + r * (N / R));
+      }
       int k = j % NS;
       if constexpr (NS > 1) {
 #pragma unroll
@@ -233,7 +251,7 @@ __device__ inline void stockham_pass(float2* buf, const float2* tw, int tid) {
       dft_reg<R, DIR>(v[u]);
     }
   }
-  __syncthreads();
+  if constexpr (LDS_IN && (LDS_OUT || ST_LDS)) __syncthreads();
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     int q = tid + u * NT;
@@ -243,10 +261,20 @@ __device__ inline void stockham_pass(float2* buf, const float2* tw, int tid) {
       float2* dst = buf + b * S;
       int base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[skew(base + r * NS)] = v[u][r];
+      for (int r = 0; r < R; ++r) {
+        if constexpr (LDS_OUT)
+          dst[skew(base + r * NS)] = v[u][r];
+        else
+          st(u, r, b, base + r * NS, v[u][r]);
+      }
     }
   }
-  __syncthreads();
+  if constexpr (LDS_OUT || ST_LDS) __syncthreads();
+}
+
+template <int N, int R, int NS, int NB, int NT, int DIR, int TWOFF>
+__device__ inline void stockham_pass(float2* buf, const float2* tw, int tid) {
+  stockham_pass_io<N, R, NS, NB, NT, DIR, TWOFF, false>(buf, tw, tid, nullptr, nullptr);
 }
 
 template <int N, int PASS, int NS, int NB, int NT, int DIR>
@@ -258,12 +286,70 @@ __device__ inline void fft_passes(float2* buf, const float2* tw, int tid) {
   }
 }
 
+template <int N, int PASS, int NS, int NB, int NT, int DIR, bool ST_LDS, class LD, class ST>
+__device__ inline void fft_passes_io(float2* buf, const float2* tw, int tid, const LD& ld, const ST& st) {
+  if constexpr (PASS < num_passes(N)) {
+    constexpr int R = radix_of_pass(N, PASS);
+    constexpr bool FIRST = PASS == 0, LAST = PASS + 1 == num_passes(N);
+    if constexpr (FIRST && LAST)
+      stockham_pass_io<N, R, NS, NB, NT, DIR, tw_offset(N, PASS), ST_LDS>(buf, tw, tid, ld, st);
+    else if constexpr (FIRST)
+      stockham_pass_io<N, R, NS, NB, NT, DIR, tw_offset(N, PASS), false>(buf, tw, tid, ld, nullptr);
+    else if constexpr (LAST)
+      stockham_pass_io<N, R, NS, NB, NT, DIR, tw_offset(N, PASS), ST_LDS>(buf, tw, tid, nullptr, st);
+    else
+      stockham_pass<N, R, NS, NB, NT, DIR, tw_offset(N, PASS)>(buf, tw, tid);
+    fft_passes_io<N, PASS + 1, NS * R, NB, NT, DIR, ST_LDS>(buf, tw, tid, ld, st);
+  }
+}
+
+// Placement of the elements of the first (read) and last (write) pass of
+// fft_lds<N, NB, NT, .> for a thread: butterfly slot u, element r is
+// position *i of sequence *b; false when the slot holds no butterfly.
+template <int N, int NB, int NT>
+__device__ inline bool fft_first_index(int tid, int u, int r, int* b, int* i) {
+  constexpr int R = radix_of_pass(N, 0);
+  const int q = tid + u * NT;
+  *b = q / (N / R);
+  *i = q % (N / R) + r * (N / R);
+  return q < NB * (N / R);
+}
+template <int N, int NB, int NT>
+__device__ inline bool fft_last_index(int tid, int u, int r, int* b, int* i) {
+  constexpr int P = num_passes(N);
+  constexpr int R = radix_of_pass(N, P - 1), NS = ns_of_pass(N, P - 1);
+  const int q = tid + u * NT;
+  const int j = q % (N / R);
+  *b = q / (N / R);
+  *i = (j / NS) * NS * R + j % NS + r * NS;
+  return q < NB * (N / R);
+}
+// Butterfly slots per thread of the first and last pass.
+template <int N, int NB, int NT>
+constexpr int fft_first_slots() {
+  return (NB * (N / radix_of_pass(N, 0)) + NT - 1) / NT;
+}
+template <int N, int NB, int NT>
+constexpr int fft_last_slots() {
+  return (NB * (N / radix_of_pass(N, num_passes(N) - 1)) + NT - 1) / NT;
+}
+
 // NB in-place FFTs of length N held in LDS at buf[b * lds_stride(N) + skew(i)].
 // Requires a barrier before (data written) -- provided by the caller -- and
 // leaves a barrier after.  tw (tw_size(N) entries) must hold fill_twiddles<N>.
 template <int N, int NB, int NT, int DIR>
 __device__ inline void fft_lds(float2* buf, const float2* tw, int tid) {
   fft_passes<N, 0, 1, NB, NT, DIR>(buf, tw, tid);
+}
+
+// fft_lds with the first pass reading through ld and/or the last pass
+// writing through st (std::nullptr_t = LDS), see stockham_pass_io.  With a
+// load hook no barrier is needed before the call for the data (the caller
+// still orders earlier LDS reads of buf); with a store hook that does not
+// write buf (ST_LDS false) the call ends without a barrier.
+template <int N, int NB, int NT, int DIR, bool ST_LDS = false, class LD, class ST>
+__device__ inline void fft_lds_io(float2* buf, const float2* tw, int tid, const LD& ld, const ST& st) {
+  fft_passes_io<N, 0, 1, NB, NT, DIR, ST_LDS>(buf, tw, tid, ld, st);
 }
 
 }  // namespace hvk
