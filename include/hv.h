@@ -119,20 +119,21 @@ size_t hv_ctx_workspace_bytes(const hv_ctx* ctx);
 hv_status hv_ctx_set_chunk_frames(hv_ctx* ctx, int frames);
 
 /* Order of the angular-spectrum STFT path of hv_stft_moments and
- * hv_stft_bins (a throughput knob: both orders compute the same values up to
- * rounding).  The propagation is one linear operator applied to every frame
- * (Sec. II-B.3) and each band bin is a fixed linear combination of a
- * window's frames (Sec. III-B.1), so the bins can be formed from the raw
- * frames and then propagated ("band first"), which transforms nb fields per
- * window instead of W frames.
+ * hv_stft_bins.  Both orders compute the same values up to rounding.  The
+ * propagation is one linear operator applied to every frame (Sec. II-B.3)
+ * and each band bin is a fixed linear combination of a window's frames
+ * (Sec. III-B.1), so the bins can be formed from the raw frames and then
+ * propagated ("band first"), which transforms nb fields per window instead
+ * of W frames.
+ *   HV_ORDER_FRAMES_FIRST the paper's order and the default: every frame is
+ *                         propagated, then the temporal transform;
  *   HV_ORDER_AUTO         band first where it moves fewer bytes per window
  *                         and the shape is supported (u8/u16 frames, nx a
  *                         power of two in [64, 512], ny 64, 128, 256, 320,
- *                         384 or 512);
- *   HV_ORDER_FRAMES_FIRST propagate every frame, then the temporal transform;
+ *                         384 or 512), else frames first;
  *   HV_ORDER_BAND_FIRST   band first wherever the shape is supported.
  * Returns HV_ERR_ARG for another value.  A new context starts from the
- * environment variable HV_STFT_ORDER (1 or 2) when it is set, else AUTO. */
+ * environment variable HV_STFT_ORDER (0, 1 or 2) when it is set. */
 typedef enum { HV_ORDER_AUTO = 0, HV_ORDER_FRAMES_FIRST = 1, HV_ORDER_BAND_FIRST = 2 } hv_stft_order;
 hv_status hv_ctx_set_stft_order(hv_ctx* ctx, int order);
 

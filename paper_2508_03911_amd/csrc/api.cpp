@@ -533,7 +533,7 @@ hv_status hv_ctx_create(int device, size_t hbm_budget_bytes, hv_ctx** out) {
   if (const char* e = std::getenv("HV_CHUNK_FRAMES")) c->chunk_frames = std::atoi(e);
   if (const char* e = std::getenv("HV_STFT_ORDER")) {
     const int o = std::atoi(e);
-    if (o == HV_ORDER_FRAMES_FIRST || o == HV_ORDER_BAND_FIRST) c->stft_order = o;
+    if (o == HV_ORDER_AUTO || o == HV_ORDER_FRAMES_FIRST || o == HV_ORDER_BAND_FIRST) c->stft_order = o;
   }
   *out = c;
   return HV_OK;

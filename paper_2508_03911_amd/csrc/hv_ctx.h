@@ -87,7 +87,7 @@ struct Ctx {
   size_t budget = 0;
   size_t held = 0;  // bytes of plans and workspaces
   int chunk_frames = 0;
-  int stft_order = 0;  // HV_ORDER_*
+  int stft_order = HV_ORDER_FRAMES_FIRST;  // HV_ORDER_*: the paper's per-frame order unless asked
   using OptKey = std::tuple<int, int, double, double, double, double, double>;
   std::map<OptKey, std::unique_ptr<AsPlan>> as_plans;
   std::map<OptKey, std::unique_ptr<FresnelPlan>> fr_plans;

@@ -66,7 +66,7 @@ def run(ctx, hv, order, fn, chunk=0):
     finally:
         ctx.set_timing(False)
         ctx.set_chunk_frames(0)
-        ctx.set_stft_order(hv.HV_ORDER_AUTO)
+        ctx.set_stft_order(hv.HV_ORDER_FRAMES_FIRST)
     return out, band, frames_first
 
 
