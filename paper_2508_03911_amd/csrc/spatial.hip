@@ -228,16 +228,25 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
   // frequency fy = yt + col_i(u)
   using TS = TileSplit<NY, NT>;
   const int st = TS::row_thr(tid), yt = TS::col_thr(tid);
-  const uint32_t off_in = (uint32_t)(st * NY + yt) * (uint32_t)sizeof(TIO);
   const uint32_t off_h = (uint32_t)(st * NY + yt) * 8u;
   const TIO* src = in + (t * half + f0) * (long)NY;
   const float2* hpos = hs + (long)f0 * NY;
   const float2* hneg = hs + ((long)half + f0) * NY;
   float2* lds = buf + st * S + skew(yt);
+  // The forward column FFT's first pass reads straight from registers:
+  // element (u, r) of this thread is column b_u at frequency i_u + r * SP
+  // (16 lanes take 16 consecutive values of one column), so the input is
+  // loaded into exactly those registers and skips the LDS staging.
+  constexpr int UF = fft_first_slots<NY, BC, NT>(), RF = radix_of_pass(NY, 0), SP = NY / RF;
+  TIO v0[UF][RF];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const TIO v = ld_off(src + TS::row_i(u) * NY + TS::col_i(u), off_in);
-    lds[TS::row_i(u) * S + skew(TS::col_i(u))] = load_c(&v);
+  for (int u = 0; u < UF; ++u) {
+    int b, i;
+    if (fft_first_index<NY, BC, NT>(tid, u, 0, &b, &i)) {
+      const uint32_t o = (uint32_t)(b * NY + i) * (uint32_t)sizeof(TIO);
+#pragma unroll
+      for (int r = 0; r < RF; ++r) v0[u][r] = ld_off(src + r * SP, o);
+    }
   }
   // transfer-function values of this thread's outputs, fetched now so that
   // their latency hides behind the column FFT
@@ -250,8 +259,7 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
     ha[u] = ld_off(hpos + TS::row_i(u) * NY + TS::col_i(u), off_h);
     hb[u] = f0 + st + TS::row_i(u) == 0 ? ld_off(hneg + TS::row_i(u) * NY + TS::col_i(u), off_h) : ha[u];
   }
-  __syncthreads();
-  fft_lds<NY, BC, NT, -1>(buf, tw, tid);
+  fft_lds_io<NY, BC, NT, -1>(buf, tw, tid, [&](int u, int r, int, int) { return load_c(&v0[u][r]); }, nullptr);
   // Sequences BC..2BC-1 are free until the inverse transform: the -fx
   // products go there at once, the +fx products after every read of the
   // forward spectrum is done.

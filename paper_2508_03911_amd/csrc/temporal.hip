@@ -190,8 +190,6 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
                                                     CoefArgs g) {
   constexpr bool PF = sizeof(TIN) == 4;
   constexpr int S = lds_stride(NX);
-  constexpr int PER = (W * NX) / NT;
-  static_assert((W * NX) % NT == 0, "row block must split evenly");
   __shared__ float2 buf[W * S];
   __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
   __shared__ float wts_lds[3 * MT_MAX * 16];
@@ -199,52 +197,61 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
   fill_twiddles<NX>(tw, tid, NT);
   load_wts(wts_lds, g, tid);
   const long npix = (long)ny * NX;
-  // thread part of every element's position: row rt, column ct of the
-  // W x NX tile; byte offset off in the field (W * ny * NX * 8 B < 4 GiB)
-  using TS = TileSplit<NX, NT>;
-  const int rt = TS::row_thr(tid), ct = TS::col_thr(tid);
-  const uint32_t off = (uint32_t)(rt * ny * NX + ct) * (uint32_t)sizeof(TIN);
-  float2* lds = buf + rt * S + skew(ct);
+  // The row inverse FFT's first pass reads straight from registers: element
+  // (u, r) of this thread is frame b_u of the window at pixel i_u + r * SP
+  // (16 lanes take 16 consecutive pixels of one frame row), so the rows are
+  // loaded into exactly those registers and skip the LDS staging.
+  // (small tiles leave some threads without a first-pass butterfly)
+  constexpr int UF = fft_first_slots<NX, W, NT>(), RF = radix_of_pass(NX, 0), SP = NX / RF;
+  uint32_t po[UF];  // byte offset of element (u, 0) in the field (W * ny * NX * 8 B < 4 GiB)
+  bool act[UF];
+#pragma unroll
+  for (int u = 0; u < UF; ++u) {
+    int b, i;
+    act[u] = fft_first_index<NX, W, NT>(tid, u, 0, &b, &i);
+    po[u] = act[u] ? (uint32_t)(b * npix + i) * (uint32_t)sizeof(TIN) : 0u;
+  }
   // first element of unit u = (window u / ny, row u % ny): wave-uniform
   auto rows = [&](int u) { return z + (((long)(u / ny) * stride) * (long)ny + u % ny) * NX; };
-  auto at = [&](const TIN* src, int i) { return src + (long)TS::row_i(i) * npix + TS::col_i(i); };
-  auto put = [&](int i, TIN v) { lds[TS::row_i(i) * S + skew(TS::col_i(i))] = load_c(&v); };
+  auto load = [&](int u, TIN (&v)[UF][RF]) {
+    const TIN* src = rows(u);
+#pragma unroll
+    for (int uu = 0; uu < UF; ++uu)
+#pragma unroll
+      for (int r = 0; r < RF; ++r)
+        if (act[uu]) v[uu][r] = ld_off(src + r * SP, po[uu]);
+  };
   // FP32 input: the A fragments are loaded before the FFT and consumed
   // after it.  FP16 input: they are loaded in the GEMM (measured faster
   // there: the 32 extra VGPRs across the FFT cost more than they hide).
-  auto reduce = [&](int u, const AFrag<W, MIXED>& af) {
-    fft_lds<NX, W, NT, +1>(buf, tw, tid);
+  auto reduce = [&](int u, const AFrag<W, MIXED>& af, const auto& src) {
+    fft_lds_io<NX, W, NT, +1>(buf, tw, tid, [&](int uu, int r, int, int) { return load_c(&src[uu][r]); }, nullptr);
     for (int nt = wave; nt < NX / 32; nt += NT / 64)
       coef_pixels<W, MIXED, false, !PF>(g, wts_lds, buf, S, nt * 32, lane, u / ny, (long)(u % ny) * NX, npix,
                                         af);
   };
   if constexpr (PF) {
-    TIN pre[PER];
-    auto fetch = [&](int u) {
-      const TIN* src = rows(u);
-#pragma unroll
-      for (int i = 0; i < PER; ++i) pre[i] = ld_off(at(src, i), off);
-    };
+    TIN pre[UF][RF];
     int u = blockIdx.x;
-    if (u < nunits) fetch(u);
+    if (u < nunits) load(u, pre);
     for (; u < nunits; u += gridDim.x) {
+      TIN cur[UF][RF];
 #pragma unroll
-      for (int i = 0; i < PER; ++i) put(i, pre[i]);
-      __syncthreads();
-      if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+      for (int uu = 0; uu < UF; ++uu)
+#pragma unroll
+        for (int r = 0; r < RF; ++r) cur[uu][r] = pre[uu][r];
+      if (u + (int)gridDim.x < nunits) load(u + gridDim.x, pre);
       AFrag<W, MIXED> unused;
-      reduce(u, unused);
+      reduce(u, unused, cur);
       __syncthreads();
     }
   } else {
     const int u = blockIdx.x;
-    const TIN* src = rows(u);
-#pragma unroll
-    for (int i = 0; i < PER; ++i) put(i, ld_off(at(src, i), off));
+    TIN v[UF][RF];
+    load(u, v);
     AFrag<W, MIXED> af;
     load_afrag(af, g, u / ny, 0, lane);
-    __syncthreads();
-    reduce(u, af);
+    reduce(u, af, v);
   }
 }
 
