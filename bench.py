@@ -360,6 +360,34 @@ def copy_rate(torch, reps: int = 10):
     return {"GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "note": "torch copy of 2 GiB, read + write bytes"}
 
 
+def isolated_kernels(ctx, hv, torch, x, opt, steps, frames=8192):
+    """The per-frame path's row and column kernels timed alone: hv_propagate
+    (K1, K2, row inverse) on one stream over the first `frames` frames, with
+    the same launch shapes as the headline, so no other stream shares the GPU
+    during a launch.  Algorithmic bytes as in bytes_per_pxf."""
+    xs = x[:frames]
+    out = torch.empty((frames, NY, NX), dtype=torch.complex64, device="cuda")
+    ctx.hv_propagate(xs, opt, hv.HV_PREC_FP32, out=out)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for _ in range(steps):
+        ctx.hv_propagate(xs, opt, hv.HV_PREC_FP32, out=out)
+    torch.cuda.synchronize()
+    res = {}
+    bpp = bytes_per_pxf(0, 14)
+    for name in ("row_r2c", "col_as"):
+        ms, n = ctx.kernel_time(name)
+        if n == 0:
+            continue
+        per_launch = bpp[name] * NY * NX * frames * steps / n
+        gbs = per_launch / (ms / n * 1e-3) / 1e9
+        res[name] = {"launches": n, "avg_ms": ms / n, "bytes_per_launch": per_launch, "achieved_GBs": gbs,
+                     "frac": gbs / HBM_PEAK_GBS}
+    ctx.set_timing(False)
+    del out
+    return res
+
+
 def host_ingest(hv, torch, block, spec, frames, steps):
     """The same 256x256 stream with its frames in pinned host memory and the
     moment images returned to pinned host memory: every frame crosses PCIe
@@ -502,6 +530,7 @@ def main():
                       "speedup_vs_fp32": bmix["frames_per_s"] / bf32["frames_per_s"], "kernels": bmix["kernels"]},
             "kernels_fp32": bf32["kernels"]},
         "hbm_copy": copy_rate(torch),
+        "kernels_alone_fp32": isolated_kernels(ctx, hv, torch, x, opt, max(1, args.steps // 2)),
     }
     if args.serve_seconds > 0:
         log(f"stream load replay for {args.serve_seconds:.0f}s ...")
