@@ -176,7 +176,9 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
  * Ordering: the frames are processed in chunks; when there is more than one,
  * the chunks alternate between hip_stream and a second stream the context
  * keeps for it, forked from and joined back into hip_stream by events, so
- * the call is ordered on hip_stream like a single launch. */
+ * the call is ordered on hip_stream like a single launch.  With the angular
+ * spectrum, the order of the spatial and temporal steps follows
+ * hv_ctx_set_stft_order (per frame unless the caller asks otherwise). */
 hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                           const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
                           void* hip_stream);

@@ -1,4 +1,6 @@
-// Band-first order of the angular-spectrum + short-time DFT moments.
+// Band-first order of the angular-spectrum + short-time DFT moments, an
+// alternative to the paper's per-frame order that callers ask for with
+// hv_ctx_set_stft_order.
 //
 // The angular spectrum applies one linear operator to every frame
 // (Sec. II-B.3), and each bin of the short-time DFT is a fixed linear
@@ -6,8 +8,9 @@
 // bin-k field of a window is the angular spectrum of the bin-k combination
 // of its raw frames.  When the band holds fewer bins than the window holds
 // frames, propagating the band's combinations instead of the frames moves
-// fewer bytes and runs fewer FFTs (no Hermitian half-spectrum saving is
-// lost: the propagated field is complex either way).
+// fewer bytes and runs fewer FFTs.  (The bins are complex, so the real-input
+// row pass of the per-frame order has no counterpart here; that order needs
+// the full spectrum after its column pass all the same.)
 //
 //   KA band rows : the W raw rows of one row index of a window are reduced
 //                  to the band's bins on MFMA (camera values are exact in
@@ -39,7 +42,6 @@ using hvi::persistent_grid;
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-
 
 __device__ inline void store_c(float2* p, float2 v) { *p = v; }
 __device__ inline void store_c(hv_h2* p, float2 v) {
