@@ -379,3 +379,75 @@ def test_c3_shape_fresnel_stft_pca(ctx, hv, c3_frames, prec):
         err = rel_l2(got, pr[k])
         say(f"  PCA {k} rel-L2 {err:.3e}")
         assert err < TOL[prec]
+
+
+# ------------------------------------------------------------------ full sizes of the benchmark launches
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("order", [1, 2])
+def test_c2_full_stream(ctx, hv, c2_block, prec, order):
+    """The 65,536-frame stream as the benchmark times it (the 2,048-frame
+    block replayed 32 times, same chunks and streams).  Windows 64 apart see
+    the same frames, so every window must equal its counterpart in the first
+    block bit for bit; three windows are checked against the oracle."""
+    x, spec = c2_block
+    say(f"256^2 full stream: 65536 frames, order={order} prec={prec}")
+    xs = dev(x).repeat(32, 1, 1).contiguous()
+    opt = hv.Optics(LAM, spec.pitch, spec.pitch, -spec.z, hv.HV_AS)
+    tp = hv.Temporal(32, 32, spec.fs, 3e3, 35e3)
+    ctx.set_stft_order(order)
+    try:
+        m = ctx.hv_stft_moments(xs, opt, tp, prec)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_stft_order(1)
+    del xs
+    assert m[0].shape == (2048, 256, 256)
+    for t in m:
+        per = t.view(32, 64, 256, 256)
+        assert torch.equal(per, per[:1].expand_as(per)), "windows over the same frames differ"
+    for j in (0, 1029, 2047):
+        b = j % 64
+        ref = _oracle_moments(x[32 * b:32 * b + 32], opt, tp)
+        for i, k in enumerate(("m0", "m1", "m2")):
+            err = rel_l2(host(m[i][j]), ref[k][0])
+            assert err < TOL[prec], (j, k, err)
+
+
+@pytest.fixture(scope="module")
+def c3_block():
+    return holograms.config_c3(128)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c3_full_size(ctx, hv, c3_block, prec):
+    """4,096 u16 frames of 1024^2 (a 128-frame block replayed 32 times):
+    Fresnel, W = 64 moments and PCA over every window at full size.  Windows
+    two apart see the same frames and must agree bit for bit; windows 0 and
+    63 are checked against the oracle."""
+    x, spec = c3_block
+    say(f"1024^2 u16 full size: 4096 frames, prec={prec}")
+    xs = dev(x).repeat(32, 1, 1).contiguous()
+    opt = hv.Optics(LAM, spec.pitch, spec.pitch, -spec.z, hv.HV_FRESNEL)
+    fs = spec.fs
+    tp = hv.Temporal(64, 64, fs, 2 * fs / 64, 31 * fs / 64)
+    m = ctx.hv_stft_moments(xs, opt, tp, prec)
+    r = ctx.hv_pca(xs, opt, 64, 64, 1, 63, prec, want_cov=True)
+    torch.cuda.synchronize()
+    del xs
+    assert m[0].shape == (64, 1024, 1024) and r["m0"].shape == (64, 1024, 1024)
+    for t in list(m) + [r["m0"], r["eigvals"], r["cov"]]:
+        per = t.view(32, 2, *t.shape[1:])
+        assert torch.equal(per, per[:1].expand_as(per)), "windows over the same frames differ"
+    bins, freqs = otemp.band_bins(64, fs, 2 * fs / 64, 31 * fs / 64)
+    for j in (0, 63):
+        b = j % 2
+        u_ref = oopt.fresnel(x[64 * b:64 * b + 64].astype(np.float64), LAM, spec.pitch, spec.pitch, -spec.z)
+        s_ref = otemp.stft(u_ref, 64, 64)
+        for i, mr in enumerate(otemp.moments(s_ref, bins, freqs)):
+            err = rel_l2(host(m[i][j]), mr[0])
+            assert err < TOL[prec], (j, i, err)
+        pr = opca.pca_window(u_ref, 1, 63)
+        for k, got in (("cov", host(r["cov"][j])), ("eigvals", host(r["eigvals"][j])), ("m0", host(r["m0"][j]))):
+            err = rel_l2(got, pr[k])
+            assert err < TOL[prec], (j, k, err)
