@@ -49,9 +49,19 @@ def _wait_and_pop(stream, want, store, ny, nx, timeout=20.0):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("method,stride", [(0, 8), (1, 16)])
-def test_stream_images_equal_offline(ctx, hv, prec, method, stride):
-    say(f"stream vs offline method={method} stride={stride} prec={prec}")
+@pytest.mark.parametrize("method,stride,order", [(0, 8, 1), (1, 16, 1), (0, 16, 2)])
+def test_stream_images_equal_offline(ctx, hv, prec, method, stride, order):
+    """Images popped from a stream equal the offline call bit for bit (order 2:
+    the band-first order in both, the stream's workspaces sized for it)."""
+    say(f"stream vs offline method={method} stride={stride} order={order} prec={prec}")
+    ctx.set_stft_order(order)
+    try:
+        _stream_vs_offline(ctx, hv, prec, method, stride)
+    finally:
+        ctx.set_stft_order(hv.HV_ORDER_FRAMES_FIRST)
+
+
+def _stream_vs_offline(ctx, hv, prec, method, stride):
     spec = holograms.HoloSpec(frames=100, ny=128, nx=256, z=0.25, fs=20e3, seed=42)
     x = holograms.hologram_stack(spec)
     xd = torch.from_numpy(x).cuda()
