@@ -425,8 +425,14 @@ void hv_af_model_destroy(hv_af_model* model);
 hv_status hv_af_model_state(hv_af_model* model, float* params, float* m, float* v, int64_t* step);
 hv_status hv_af_model_load(hv_af_model* model, const float* params, const float* m, const float* v, int64_t step);
 
-/* Raw network output [batch][2] = (normalised z, log sigma^2) for fp16 crops. */
+/* Raw network output [batch][2] = (normalised z, log sigma^2) for fp16 crops
+ * (FP32 arithmetic: the forward pass of training). */
 hv_status hv_af_forward(hv_af_model* model, const void* crops, int batch, float* out, void* hip_stream);
+/* The same output from the inference kernels that hv_af_predict runs: each
+ * convolution as an implicit GEMM on the matrix cores with fp16 weights and
+ * activations and FP32 accumulation, the pooling fused into the last
+ * convolution.  Agrees with hv_af_forward to fp16 rounding. */
+hv_status hv_af_infer(hv_af_model* model, const void* crops, int batch, float* out, void* hip_stream);
 /* Mean Gaussian NLL 0.5 (s + (z_n - zhat)^2 e^{-s}) over the batch (loss,
  * device float[1], nullable) and its gradient with respect to every parameter
  * (grad, device float32[nparams]); labels z_m in metres. */
@@ -435,7 +441,8 @@ hv_status hv_af_loss_grad(hv_af_model* model, const void* crops, const float* z_
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on that gradient. */
 hv_status hv_af_train_step(hv_af_model* model, const void* crops, const float* z_m, int batch, float lr,
                            float* loss, void* hip_stream);
-/* Predicted z (metres) and sigma for n holograms; every hologram with
+/* Predicted z (metres) and sigma for n holograms (crops, then the inference
+ * kernels of hv_af_infer); every hologram with
  * sigma > tau_m is re-estimated by hv_af_scan (128 candidates in [0.05, 0.5] m)
  * and flagged in used_fallback[n] (nullable).  *n_fallback (host, nullable)
  * receives their count.  Synchronises the stream. */

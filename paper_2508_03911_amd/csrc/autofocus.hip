@@ -283,6 +283,152 @@ __global__ __launch_bounds__(256) void k_conv(const TIN* __restrict__ in, const 
   }
 }
 
+// ------------------------------------------------------------------ CNN: inference on MFMA
+// The forward pass again, for prediction only, as implicit GEMMs on the
+// matrix cores: per layer, [256 pixels of a 16 x 16 output tile] x [9 CIN]
+// times [9 CIN] x [32 output channels] with fp16 operands and FP32
+// accumulation (v_mfma_f32_32x32x16_f16; lane l holds A[l%32][k0 + 8(l/32)
+// + e] and B[k0 + 8(l/32) + e][l%32], and result register r is row
+// 8(r/4) + 4(l/32) + r%4 of column l%32).  Activations are stored NHWC in
+// fp16.  The k index runs over taps, then channels: k = 32 tap + c for the
+// 32-channel layers, k = tap (padded to 16) for the first.
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+
+constexpr int IKS = 1 + 3 * 18;  // k-steps of the four layers' B fragments
+
+// B fragments of all layers from the FP32 parameters: wf[(kstep) * 64 + lane].
+__global__ void k_pack_weights(const float* __restrict__ params, h8v* __restrict__ wf) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= IKS * 64) return;
+  const int ks = q / 64, lane = q % 64, o = lane & 31, h = lane >> 5;
+  h8v v;
+  if (ks == 0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 8 * h + e;
+      v[e] = (_Float16)(k < 9 ? params[OFF_W[0] + o * 9 + k] : 0.f);
+    }
+  } else {
+    const int l = 1 + (ks - 1) / 18, s = (ks - 1) % 18;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 16 * s + 8 * h + e, tap = k / NCH, c = k % NCH;
+      v[e] = (_Float16)params[OFF_W[l] + (o * NCH + c) * 9 + tap];
+    }
+  }
+  wf[q] = v;
+}
+
+// One 16 x 16 output tile of one sample per workgroup of 4 waves; wave w
+// owns tile pixels [64 w, 64 w + 64) as two 32-pixel M tiles.  LAST: no
+// activation is stored; the ReLU outputs of the tile are summed per channel
+// into pooled[sample][tile][32] (the global average pool, finished in the
+// head in a fixed order).
+template <int CIN, bool LAST>
+__global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ in, const h8v* __restrict__ wf,
+                                                   const float* __restrict__ params, int boff,
+                                                   _Float16* __restrict__ out, float* __restrict__ pooled) {
+  constexpr int PS = CIN == 1 ? 1 : CIN + 8;  // halves per LDS pixel (80 B: 16-B reads of 16 lanes hit distinct banks)
+  constexpr int KS = CIN == 1 ? 1 : 9 * CIN / 16;
+  __shared__ __attribute__((aligned(16))) _Float16 tile[18 * 18 * PS];
+  __shared__ float red[4][32];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31;
+  const int ty0 = (blockIdx.x >> 2) * 16, tx0 = (blockIdx.x & 3) * 16;
+  const long b = blockIdx.y;
+  if constexpr (CIN == 1) {
+    for (int q = tid; q < 324; q += 256) {
+      const int r = q / 18, col = q % 18, y = ty0 + r - 1, x = tx0 + col - 1;
+      tile[q] = (y >= 0 && y < CROP && x >= 0 && x < CROP) ? in[(b * CROP + y) * CROP + x] : (_Float16)0.f;
+    }
+  } else {
+    for (int q = tid; q < 324 * (CIN / 8); q += 256) {
+      const int pix = q / (CIN / 8), ch = q % (CIN / 8);
+      const int r = pix / 18, col = pix % 18, y = ty0 + r - 1, x = tx0 + col - 1;
+      h8v v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (_Float16)0.f;
+      if (y >= 0 && y < CROP && x >= 0 && x < CROP)
+        v = *reinterpret_cast<const h8v*>(in + ((b * CROP + y) * CROP + x) * CIN + 8 * ch);
+      *reinterpret_cast<h8v*>(tile + pix * PS + 8 * ch) = v;
+    }
+  }
+  h8v bw[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) bw[s] = wf[s * 64 + lane];
+  const float bias = params[boff + c];
+  __syncthreads();
+  f32x16 acc[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[mt][r] = 0.f;
+    const int p = (2 * wave + mt) * 32 + c, py = p >> 4, px = p & 15;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      h8v a;
+      if constexpr (CIN == 1) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = 8 * h + e;
+          a[e] = k < 9 ? tile[(py + k / 3) * 18 + px + k % 3] : (_Float16)0.f;
+        }
+      } else {
+        const int tap = s >> 1, c0 = 16 * (s & 1) + 8 * h;
+        a = *reinterpret_cast<const h8v*>(tile + ((py + tap / 3) * 18 + px + tap % 3) * PS + c0);
+      }
+      acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bw[s], acc[mt], 0, 0, 0);
+    }
+  }
+  if constexpr (!LAST) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int p = (2 * wave + mt) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const int y = ty0 + (p >> 4), x = tx0 + (p & 15);
+        out[((b * CROP + y) * CROP + x) * NCH + c] = (_Float16)fmaxf(acc[mt][r] + bias, 0.f);
+      }
+  } else {
+    float sum = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) sum += fmaxf(acc[mt][r] + bias, 0.f);
+    sum += __shfl_xor(sum, 32);
+    if (h == 0) red[wave][c] = sum;
+    __syncthreads();
+    if (tid < 32) pooled[(b * 16 + blockIdx.x) * NCH + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  }
+}
+
+// Head for the inference pass: the 16 tile sums of each channel in tile
+// order / HW, FC(32->64) ReLU, FC(64->2); one thread per sample.
+__global__ void k_head_pooled(const float* __restrict__ pooled, const float* __restrict__ params, int bsz,
+                              float* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= bsz) return;
+  float g[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    float s = 0.f;
+    for (int t = 0; t < 16; ++t) s += pooled[((long)b * 16 + t) * NCH + c];
+    g[c] = s / HW;
+  }
+  float o0 = params[OFF_FC2B], o1 = params[OFF_FC2B + 1];
+  for (int j = 0; j < 64; ++j) {
+    float hj = params[OFF_FC1B + j];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) hj += params[OFF_FC1W + j * NCH + c] * g[c];
+    hj = fmaxf(hj, 0.f);
+    o0 += params[OFF_FC2W + j] * hj;
+    o1 += params[OFF_FC2W + 64 + j] * hj;
+  }
+  out[2 * b] = o0;
+  out[2 * b + 1] = o1;
+}
+
 // Weight and bias gradients of one conv layer, partial over a split of the
 // batch: dW[o][c][tap] = sum dZ[b][o][p] X[b][c][p + tap - 1], dZ = dA [A > 0].
 // Threads t < CIN*9 own (c, tap) for CG output channels; the next CG threads
@@ -593,6 +739,9 @@ struct hv_af_model {
   float *d1 = nullptr, *d2 = nullptr;
   float *part_w = nullptr, *part_b = nullptr, *hpart = nullptr, *loss_b = nullptr, *out = nullptr, *zn = nullptr;
   float* loss_tmp = nullptr;
+  _Float16* act16[2] = {nullptr, nullptr};  // inference activations, NHWC fp16
+  float* pooled = nullptr;                   // [max_batch][16 tiles][32]
+  void* wfrag = nullptr;                     // B fragments of the inference pass
   std::vector<void*> owned;
 };
 
@@ -621,6 +770,24 @@ hv_status forward(hv_af_model* md, const _Float16* crops, int bsz, bool train, h
     hipLaunchKernelGGL(k_head<false>, dim3(bsz), dim3(256), 0, st, md->act[3], md->params, nullptr, bsz, md->out,
                        nullptr, nullptr, nullptr);
   return launched("af forward");
+}
+
+// The inference pass on MFMA (fp16 operands), same network and outputs as
+// forward(.., false, ..) up to fp16 rounding.
+hv_status infer(hv_af_model* md, const _Float16* crops, int bsz, hipStream_t st) {
+  const h8v* wf = (const h8v*)md->wfrag;
+  hipLaunchKernelGGL(k_pack_weights, dim3((IKS * 64 + 255) / 256), dim3(256), 0, st, md->params, (h8v*)md->wfrag);
+  const dim3 grid(16, bsz);
+  hipLaunchKernelGGL((k_conv_mfma<1, false>), grid, dim3(256), 0, st, crops, wf, md->params, OFF_B[0],
+                     md->act16[0], nullptr);
+  hipLaunchKernelGGL((k_conv_mfma<NCH, false>), grid, dim3(256), 0, st, md->act16[0], wf + 64, md->params,
+                     OFF_B[1], md->act16[1], nullptr);
+  hipLaunchKernelGGL((k_conv_mfma<NCH, false>), grid, dim3(256), 0, st, md->act16[1], wf + 64 * 19, md->params,
+                     OFF_B[2], md->act16[0], nullptr);
+  hipLaunchKernelGGL((k_conv_mfma<NCH, true>), grid, dim3(256), 0, st, md->act16[0], wf + 64 * 37, md->params,
+                     OFF_B[3], nullptr, md->pooled);
+  hipLaunchKernelGGL(k_head_pooled, dim3((bsz + 63) / 64), dim3(64), 0, st, md->pooled, md->params, bsz, md->out);
+  return launched("af inference");
 }
 
 hv_status backward(hv_af_model* md, const _Float16* crops, int bsz, float* grad, float* loss, hipStream_t st) {
@@ -775,7 +942,11 @@ hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batc
       (s = dev_alloc(md, (void**)&md->hpart, (size_t)max_batch * HEAD_N * 4)) ||
       (s = dev_alloc(md, (void**)&md->loss_b, (size_t)max_batch * 4)) ||
       (s = dev_alloc(md, (void**)&md->out, (size_t)max_batch * 8)) ||
-      (s = dev_alloc(md, (void**)&md->zn, (size_t)max_batch * 4)) || (s = dev_alloc(md, (void**)&md->loss_tmp, 4)))
+      (s = dev_alloc(md, (void**)&md->zn, (size_t)max_batch * 4)) || (s = dev_alloc(md, (void**)&md->loss_tmp, 4)) ||
+      (s = dev_alloc(md, (void**)&md->act16[0], (size_t)max_batch * NCH * HW * 2)) ||
+      (s = dev_alloc(md, (void**)&md->act16[1], (size_t)max_batch * NCH * HW * 2)) ||
+      (s = dev_alloc(md, (void**)&md->pooled, (size_t)max_batch * 16 * NCH * 4)) ||
+      (s = dev_alloc(md, &md->wfrag, (size_t)IKS * 64 * 16)))
     return fail_out(s);
   if (hipMemcpy(md->params, init_params, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(md->m, 0, NPARAM * 4) != hipSuccess || hipMemset(md->v, 0, NPARAM * 4) != hipSuccess)
@@ -828,6 +999,18 @@ hv_status hv_af_forward(hv_af_model* md, const void* crops, int batch, float* ou
   return HV_OK;
 }
 
+hv_status hv_af_infer(hv_af_model* md, const void* crops, int batch, float* out, void* hip_stream) {
+  if (!md || !crops || !out) return fail(HV_ERR_ARG, "NULL argument");
+  if (batch <= 0 || batch > md->max_batch) return fail(HV_ERR_SHAPE, "batch %d outside [1, %d]", batch, md->max_batch);
+  hipSetDevice(md->ctx->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hv_status s = infer(md, (const _Float16*)crops, batch, st);
+  if (s) return s;
+  if (hipMemcpyAsync(out, md->out, (size_t)batch * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return fail(HV_ERR_DEVICE, "output copy failed");
+  return HV_OK;
+}
+
 hv_status hv_af_loss_grad(hv_af_model* md, const void* crops, const float* z_m, int batch, float* loss, float* grad,
                           void* hip_stream) {
   if (!md || !crops || !z_m || !grad) return fail(HV_ERR_ARG, "NULL argument");
@@ -872,7 +1055,7 @@ hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wave
   for (int b0 = 0; b0 < n; b0 += md->max_batch) {
     const int bs = std::min(md->max_batch, n - b0);
     if ((s = hv_af_crops(ctx, holo + (size_t)b0 * AN * AN, bs, AN, AN, cb.ptr, 1, st))) return s;
-    if ((s = forward(md, (const _Float16*)cb.ptr, bs, false, st))) return s;
+    if ((s = infer(md, (const _Float16*)cb.ptr, bs, st))) return s;
     hipLaunchKernelGGL(k_af_denorm, dim3((bs + 255) / 256), dim3(256), 0, st, md->out, bs, (float)md->z_mean,
                        (float)md->z_scale, z_out + b0, sigma + b0);
   }

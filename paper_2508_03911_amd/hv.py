@@ -136,6 +136,7 @@ _sig = {
                                C.POINTER(C.c_int64)]),
     "hv_af_model_load": (_I, [_P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int64]),
     "hv_af_forward": (_I, [_P, _P, _I, _P, _P]),
+    "hv_af_infer": (_I, [_P, _P, _I, _P, _P]),
     "hv_af_loss_grad": (_I, [_P, _P, _P, _I, _P, _P, _P]),
     "hv_af_train_step": (_I, [_P, _P, _P, _I, C.c_float, _P, _P]),
     "hv_af_predict": (_I, [_P, _P, _I, C.c_double, C.c_double, C.c_float, _P, _P, _P, C.POINTER(_I), _P]),
@@ -542,6 +543,12 @@ class AfModel:
     def forward(self, crops: torch.Tensor) -> torch.Tensor:
         out = torch.empty((crops.shape[0], 2), dtype=torch.float32, device=crops.device)
         _check(lib.hv_af_forward(self.handle, _ptr(crops), crops.shape[0], _ptr(out), _stream(crops.device)))
+        return out
+
+    def infer(self, crops: torch.Tensor) -> torch.Tensor:
+        """hv_af_infer: the prediction kernels (fp16 matrix-core convolutions)."""
+        out = torch.empty((crops.shape[0], 2), dtype=torch.float32, device=crops.device)
+        _check(lib.hv_af_infer(self.handle, _ptr(crops), crops.shape[0], _ptr(out), _stream(crops.device)))
         return out
 
     def loss_grad(self, crops: torch.Tensor, z_m: torch.Tensor):

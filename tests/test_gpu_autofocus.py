@@ -94,6 +94,28 @@ def test_forward_loss_grad_match_oracle(ctx, hv, init):
     m.close()
 
 
+@pytest.mark.parametrize("seed", [3, 4])
+def test_inference_kernels_match_oracle(ctx, hv, init, seed):
+    """The prediction path (fp16 operands on the matrix cores, FP32
+    accumulation) against the FP64 oracle forward on the same fp16 crops:
+    within 2e-3 rel-L2 over the outputs, and against the FP32 forward.  The
+    second seed uses trained-size weights (scaled up) and a ragged batch."""
+    say(f"CNN inference kernels vs oracle, seed {seed}")
+    b = 37 if seed == 4 else 8
+    x, _ = _crops_and_labels(seed, b)
+    th = init.astype(np.float64) * (1.0 if seed == 3 else 1.7)
+    m = ctx.af_model(th.astype(np.float32), 64, Z_MEAN, Z_SCALE)
+    xd = torch.from_numpy(x).cuda()
+    fast = m.infer(xd).cpu().numpy()
+    full = m.forward(xd).cpu().numpy()
+    ref_out, _ = oaf.forward(th.astype(np.float32).astype(np.float64), x.astype(np.float64)[:, None])
+    err = rel_l2(fast, ref_out)
+    say(f"  rel-L2 vs oracle {err:.2e}, FP32 forward {rel_l2(full, ref_out):.2e}")
+    assert err < 2e-3
+    assert rel_l2(fast, full) < 2e-3
+    m.close()
+
+
 def test_adam_step_and_checkpoint(ctx, hv, init):
     say("Adam step, state round trip")
     b = 4
