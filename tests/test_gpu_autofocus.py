@@ -162,9 +162,10 @@ def _dataset(ctx, n, seed, base=0, levels=512):
 def test_training_gain_over_scan(ctx, hv, init):
     """Train briefly on holograms of the project's own forward model and
     report what the network gives next to the scan: it must have learned
-    (well below the error of predicting the mean distance) and the scan
-    fallback on its least confident 10 % must improve it.  The printed line
-    compares errors and times of network, network + fallback and scan."""
+    (well below the error of predicting the mean distance), the scan
+    fallback on its least confident 10 % must improve it, and network +
+    fallback must take less time than scanning every hologram.  The printed
+    line compares errors and times of network, network + fallback and scan."""
     say("training the autofocus network (short)")
     holo, crops, z = _dataset(ctx, 16384, seed=123)
     m = ctx.af_model(init, 256, Z_MEAN, Z_SCALE)
@@ -180,6 +181,7 @@ def test_training_gain_over_scan(ctx, hv, init):
     assert losses[-1] < losses[0] - 0.5
     eh, _, ez = _dataset(ctx, 1024, seed=999, base=10 ** 6)
     ez = ez.cpu().numpy()
+    ctx.hv_af_scan(eh[:8], LAM, PITCH)  # tables built outside the timing
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     zs, _ = ctx.hv_af_scan(eh, LAM, PITCH)
@@ -202,4 +204,5 @@ def test_training_gain_over_scan(ctx, hv, init):
     assert np.median(e_net) < 0.7 * base
     assert np.mean(e_fb) < np.mean(e_net)
     assert nfb <= 0.15 * len(ez)
+    assert t_fb < t_scan
     m.close()
