@@ -105,9 +105,11 @@ def kernel_profile(ctx, hv, torch, x, opt, tp, prec, outs, steps, frames):
     return res
 
 
-def cpu_baseline(block, spec, z, ctx, hv, torch):
+def cpu_baseline(block, spec, z, ctx, hv, torch, precision=None):
     """The FP64 oracle on a bounded sample of the same workload (timed), and
-    the relative L2 error of both GPU forms against it on that sample."""
+    the relative L2 error of both GPU forms against it on that sample; with
+    `precision` (from precision_case) also the errors of window 0 of the
+    1024 x 1024 Fresnel case, every output, both forms."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -129,10 +131,23 @@ def cpu_baseline(block, spec, z, ctx, hv, torch):
             err[tag + name] = {k: float(np.linalg.norm(g - ref[k]) / np.linalg.norm(ref[k]))
                                for k, g in zip(("m0", "m1", "m2"), got)}
     ctx.set_stft_order(hv.HV_ORDER_FRAMES_FIRST)
-    return {"value": sample.shape[0] / dt, "unit": "frames/s", "cores": int(blas), "kind": "oracle",
-            "sample": f"{sample.shape[0]} frames (64 windows) of the 256x256 stream, numpy float64; "
-                      f"FFTs single-threaded, BLAS {blas} threads", "seconds": dt,
-            "gpu_rel_l2_vs_oracle": err}
+    res = {"value": sample.shape[0] / dt, "unit": "frames/s", "cores": int(blas), "kind": "oracle",
+           "sample": f"{sample.shape[0]} frames (64 windows) of the 256x256 stream, numpy float64; "
+                     f"FFTs single-threaded, BLAS {blas} threads", "seconds": dt,
+           "gpu_rel_l2_vs_oracle": err}
+    if precision is not None:
+        from oracle import optics as oopt, pca as opca, temporal as otemp
+        pb, ps, w = precision["block"], precision["spec"], precision["window"]
+        u = oopt.fresnel(pb.astype(np.float64), 852e-9, ps.pitch, ps.pitch, -ps.z)
+        bins, freqs = otemp.band_bins(w, ps.fs, 2 * ps.fs / w, 31 * ps.fs / w)
+        mom = [mm[0] for mm in otemp.moments(otemp.stft(u, w, w), bins, freqs)]
+        pr = opca.pca_window(u, 1, 63)
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        res["precision_case_window0_rel_l2"] = {
+            name: {"m0": rel(m[0], mom[0]), "m1": rel(m[1], mom[1]), "m2": rel(m[2], mom[2]),
+                   "pca_m0": rel(pm0, pr["m0"]), "eigvals": rel(ev, pr["eigvals"])}
+            for name, (m, pm0, ev) in precision["gpu"].items()}
+    return res
 
 
 def serving(hv, torch, seconds, prec):
@@ -303,6 +318,70 @@ def _timed_passes(torch, fn, steps):
     return a.elapsed_time(b) / steps
 
 
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "mixed": 2500.0}  # dense matrix peak of the operand type used
+
+
+def precision_case(hv, torch, steps):
+    """The precision-form workload: 4,096 uint16 (12-bit) frames of 1024 x 1024
+    (a 64-frame synthetic block replayed 64 times, resident in HBM), Fresnel at
+    z = 0.5 m, then (a) the STFT over windows of 64 (stride 64, bins 2..31 at
+    fs 5 kHz) with its moments and (b) PCA over the same windows (components
+    1..63).  Reports frames/s per form and the GEMM kernels' useful TFLOP/s
+    against the matrix-core peak of their operand type; returns as well the
+    GPU outputs of window 0 and the block, for the oracle check of the
+    cpu_baseline leg."""
+    import numpy as np
+    from synth import holograms
+    t0 = time.time()
+    block, spec = holograms.config_c3(64)
+    log(f"precision case: block {block.shape} in {time.time() - t0:.1f}s")
+    x = torch.from_numpy(block).cuda().repeat(64, 1, 1).contiguous()
+    n, ny, nx = x.shape
+    w = 64
+    opt = hv.Optics(852e-9, spec.pitch, spec.pitch, -spec.z, hv.HV_FRESNEL)
+    fs = spec.fs
+    tp = hv.Temporal(w, w, fs, 2 * fs / w, 31 * fs / w)
+    nb = len(hv.band_bins(tp)[0])
+    nwin = n // w
+    npix = ny * nx
+    # useful flops per pixel and window of each GEMM (real arithmetic on
+    # (re, im)-interleaved operands, K = 2W)
+    flops = {"field_coef": 2 * (2 * nb) * (2 * w), "gram": 2 * (2 * w) ** 2, "proj_energy": 2 * (2 * 63) * (2 * w)}
+    ctx = hv.Context(0)
+    out = {"workload": f"{n} uint16 frames of {nx}x{ny} (12-bit), Fresnel z={spec.z} m, W={w} stride {w}, "
+                       f"{nb} band bins, PCA components 1..63", "frames": n}
+    res_keep = {}
+    for prec, name in ((hv.HV_PREC_FP32, "fp32"), (hv.HV_PREC_MIXED, "mixed")):
+        stft = lambda: ctx.hv_stft_moments(x, opt, tp, prec)
+        pca = lambda: ctx.hv_pca(x, opt, w, w, 1, 63, prec, want_eig=True)
+        ms_s = _timed_passes(torch, stft, steps)
+        ms_p = _timed_passes(torch, pca, steps)
+        ctx.set_timing(True)
+        stft()
+        pca()
+        torch.cuda.synchronize()
+        kern = {}
+        for k in ("fresnel_rows", "fresnel_cols", "field_coef", "gram", "jacobi", "proj_energy"):
+            ms, cnt = ctx.kernel_time(k)
+            if cnt == 0:
+                continue
+            kern[k] = {"launches": cnt, "avg_ms": ms / cnt}
+            if k in flops:
+                tf = flops[k] * npix * nwin / (ms * 1e-3) / 1e12
+                kern[k].update({"useful_TFLOPs": tf, "mfma_peak_TFLOPs": MFMA_PEAK_TFLOPS[name],
+                                "frac": tf / MFMA_PEAK_TFLOPS[name]})
+        ctx.set_timing(False)
+        out[name] = {"stft_moments_frames_per_s": n / (ms_s * 1e-3), "pca_frames_per_s": n / (ms_p * 1e-3),
+                     "kernels": kern}
+        log(f"precision case {name}: {out[name]}")
+        m = [t[0].cpu().numpy().astype(np.float64) for t in stft()]
+        r = pca()
+        res_keep[name] = (m, r["m0"][0].cpu().numpy().astype(np.float64), r["eigvals"][0].cpu().numpy())
+    ctx.close()
+    del x
+    return out, {"block": block[:w], "spec": spec, "window": w, "gpu": res_keep}
+
+
 def table_iv(hv, torch, inputs, steps):
     """The paper's Table IV Fresnel + PCA pipeline (window 32, stride 32,
     components 1..31) at its five frame sizes, file mode."""
@@ -436,6 +515,9 @@ def main():
     ap.add_argument("--af-epochs", type=int, default=3)
     ap.add_argument("--no-table-iv", action="store_true", help="skip the Table IV measurements")
     ap.add_argument("--no-host-ingest", action="store_true", help="skip the pinned-host (PCIe) measurement")
+    ap.add_argument("--no-precision-case", action="store_true", help="skip the 1024x1024 u16 Fresnel W64 case")
+    ap.add_argument("--precision-case-only", action="store_true",
+                    help="run only the 1024x1024 u16 Fresnel W64 case and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (scale factor for HBM counters)")
     args = ap.parse_args()
@@ -458,6 +540,10 @@ def main():
 
     from paper_2508_03911_amd import hv
     from synth import holograms
+
+    if args.precision_case_only:
+        print(json.dumps({"precision_case": precision_case(hv, torch, max(1, args.steps // 3))[0]}), flush=True)
+        return
 
     t0 = time.time()
     block, spec = holograms.config_c2_block(2048)
@@ -551,13 +637,17 @@ def main():
         log("Table IV AS + high-pass + STFT512 ...")
         line["table_iv_as_hp_stft512"] = table_iv_volume(hv, torch, inputs, max(1, args.steps // 2))
         del inputs
+    precision = None
+    if not args.no_precision_case:
+        log("precision case (1024x1024 u16 Fresnel, W 64, STFT moments and PCA) ...")
+        line["precision_case"], precision = precision_case(hv, torch, max(1, args.steps // 3))
     if args.af_train > 0:
         log("autofocus training and evaluation ...")
         line["autofocus"] = autofocus(hv, torch, args.af_train, args.af_eval, args.af_epochs)
         log(f"autofocus: {line['autofocus']}")
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample ...")
-        line["cpu_baseline"] = cpu_baseline(block, spec, spec.z, ctx, hv, torch)
+        line["cpu_baseline"] = cpu_baseline(block, spec, spec.z, ctx, hv, torch, precision)
     ctx.close()
     print(json.dumps(line), flush=True)
 

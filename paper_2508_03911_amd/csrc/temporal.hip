@@ -271,9 +271,20 @@ __global__ __launch_bounds__(NT) void k_field_coef(const TIN* __restrict__ u, lo
   AFrag<W, MIXED> af;
   load_afrag(af, g, jj, 0, lane);
   const TIN* src = u + (jj * stride) * npix + p0;
-  for (int q = tid; q < W * TPIX; q += NT) {
-    const int t = q / TPIX, x = q % TPIX;
-    buf[t * S + skew(x)] = load_c(src + (long)t * npix + x);
+  // element i of this thread: frame RPI * i + tid / TPIX, pixel tid % TPIX;
+  // loads go out in batches of 8 so that several are in flight at once
+  constexpr int RPI = NT / TPIX, PER = W * TPIX / NT, BATCH = PER < 8 ? PER : 8;
+  static_assert(PER % BATCH == 0, "load batches");
+  const int tr = tid / TPIX, x = tid % TPIX;
+  const uint32_t off = (uint32_t)(tr * npix + x) * (uint32_t)sizeof(TIN);
+  float2* lds = buf + tr * S + skew(x);
+#pragma unroll
+  for (int i0 = 0; i0 < PER; i0 += BATCH) {
+    TIN v[BATCH];
+#pragma unroll
+    for (int i = 0; i < BATCH; ++i) v[i] = ld_off(src + (long)RPI * (i0 + i) * npix, off);
+#pragma unroll
+    for (int i = 0; i < BATCH; ++i) lds[RPI * (i0 + i) * S] = load_c(&v[i]);
   }
   __syncthreads();
   coef_pixels<W, MIXED, EXACT, true>(g, wts_lds, buf, S, wave * 32, lane, jj, p0, npix, af);
