@@ -305,6 +305,25 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
   }
 }
 
+// A tile of E elements from src (element q at src + q, sequence-major) into
+// the LDS rows buf[(q / N) * S + skew(q % N)].  The trip count is fixed at
+// compile time, so every load is issued before the first LDS write.
+template <int N, int E, typename TIN>
+__device__ inline void load_tile(float2* buf, const TIN* __restrict__ src, int tid) {
+  constexpr int S = lds_stride(N), PER = (E + NT - 1) / NT;
+  TIN v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int q = tid + i * NT;
+    if (E % NT == 0 || q < E) v[i] = src[q];
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int q = tid + i * NT;
+    if (E % NT == 0 || q < E) buf[(q / N) * S + skew(q % N)] = load_c(&v[i]);
+  }
+}
+
 // ------------------------------------------------------------------ K3
 template <int NX, int ROWS, typename TIN, typename TOUT>
 __global__ __launch_bounds__(NT) void k_row_inv(const TIN* __restrict__ in, TOUT* __restrict__ out, int ny,
@@ -315,11 +334,20 @@ __global__ __launch_bounds__(NT) void k_row_inv(const TIN* __restrict__ in, TOUT
   const int tid = threadIdx.x;
   const long base = ((long)blockIdx.y * ny + (long)blockIdx.x * ROWS) * NX;
   fill_twiddles<NX>(tw, tid, NT);
-  for (int q = tid; q < ROWS * NX; q += NT) buf[(q / NX) * S + skew(q % NX)] = load_c(in + base + q);
+  load_tile<NX, ROWS * NX>(buf, in + base, tid);
   __syncthreads();
   fft_lds<NX, ROWS, NT, +1>(buf, tw, tid);
   for (int q = tid; q < ROWS * NX; q += NT)
     store_c(out + base + q, c2::scale(buf[(q / NX) * S + skew(q % NX)], scale));
+}
+
+// Workgroups go to the 8 XCDs round-robin by linear index.  The tiles of a
+// frame below write runs of 8 or 16 values, so neighbouring tiles 2m and
+// 2m + 1 share 128-byte lines; when the tile count is a multiple of 16 this
+// numbering gives the two of a pair indices of one residue mod 8 (one XCD,
+// one L2), where the partial lines merge before they reach HBM.
+__device__ inline int xcd_paired(int bx, int tiles) {
+  return (tiles & 15) ? bx : 16 * (bx >> 4) + 2 * (bx & 7) + ((bx >> 3) & 1);
 }
 
 // ------------------------------------------------------------------ K4 rows / complex rows
@@ -333,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_rows_c2c(const TIN* __restrict__ in, TOU
   __shared__ float2 buf[ROWS * S];
   __shared__ float2 tw[tw_size(NX) > 0 ? tw_size(NX) : 1];
   const int tid = threadIdx.x;
-  const int y0 = blockIdx.x * ROWS;
+  const int y0 = xcd_paired(blockIdx.x, gridDim.x) * ROWS;
   const long t = blockIdx.y;
   fill_twiddles<NX>(tw, tid, NT);
   const TIN* src = in + (t * ny + y0) * (long)NX;
@@ -368,11 +396,11 @@ __global__ __launch_bounds__(NT) void k_col_full(const TIO* __restrict__ in, TIO
   __shared__ float2 buf[BC * S];
   __shared__ float2 tw[tw_size(NY) > 0 ? tw_size(NY) : 1];
   const int tid = threadIdx.x;
-  const int p0 = blockIdx.x * BC;
+  const int p0 = xcd_paired(blockIdx.x, gridDim.x) * BC;
   const long t = blockIdx.y;
   fill_twiddles<NY>(tw, tid, NT);
   const TIO* src = in + (t * nx + p0) * (long)NY;
-  for (int q = tid; q < BC * NY; q += NT) buf[(q / NY) * S + skew(q % NY)] = load_c(src + q);
+  load_tile<NY, BC * NY>(buf, src, tid);
   __syncthreads();
   fft_lds<NY, BC, NT, -1>(buf, tw, tid);
   for (int q = tid; q < BC * NY; q += NT) {
@@ -398,11 +426,11 @@ __global__ __launch_bounds__(NT) void k_fresnel_cols(const TIN* __restrict__ in,
   __shared__ float2 buf[BC * S];
   __shared__ float2 tw[tw_size(NY) > 0 ? tw_size(NY) : 1];
   const int tid = threadIdx.x;
-  const int p0 = blockIdx.x * BC;
+  const int p0 = xcd_paired(blockIdx.x, gridDim.x) * BC;
   const long t = blockIdx.y;
   fill_twiddles<NY>(tw, tid, NT);
   const TIN* src = in + (t * nx + p0) * (long)NY;
-  for (int q = tid; q < BC * NY; q += NT) buf[(q / NY) * S + skew(q % NY)] = load_c(src + q);
+  load_tile<NY, BC * NY>(buf, src, tid);
   __syncthreads();
   fft_lds<NY, BC, NT, DIR>(buf, tw, tid);
   TOUT* dst = out + t * (long)NY * nx;
