@@ -365,17 +365,27 @@ __global__ __launch_bounds__(NT) void k_rows_c2c(const TIN* __restrict__ in, TOU
   const long t = blockIdx.y;
   fill_twiddles<NX>(tw, tid, NT);
   const TIN* src = in + (t * ny + y0) * (long)NX;
-  for (int q = tid; q < ROWS * (NX / 8); q += NT) {
+  // Runs of 8 values; every run of the tile is loaded before the first LDS
+  // write.
+  constexpr int E8 = ROWS * (NX / 8), PER = (E8 + NT - 1) / NT;
+  float2 v[PER][8];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int q = tid + k * NT;
+    if (E8 % NT == 0 || q < E8) load8c(src + (q / (NX / 8)) * NX + 8 * (q % (NX / 8)), v[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int q = tid + k * NT;
+    if (E8 % NT != 0 && q >= E8) continue;
     const int r = q / (NX / 8), c = q % (NX / 8);
-    float2 v[8];
-    load8c(src + r * NX + 8 * c, v);
     if (qx) {
       const float2 cy = qy[y0 + r];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = c2::mul(v[e], c2::mul(qx[8 * c + e], cy));
+      for (int e = 0; e < 8; ++e) v[k][e] = c2::mul(v[k][e], c2::mul(qx[8 * c + e], cy));
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) buf[r * S + skew(8 * c + e)] = v[e];
+    for (int e = 0; e < 8; ++e) buf[r * S + skew(8 * c + e)] = v[k][e];
   }
   __syncthreads();
   fft_lds<NX, ROWS, NT, DIR>(buf, tw, tid);
