@@ -411,12 +411,27 @@ __global__ __launch_bounds__(NT) void k_col_full(const TIO* __restrict__ in, TIO
   fill_twiddles<NY>(tw, tid, NT);
   const TIO* src = in + (t * nx + p0) * (long)NY;
   load_tile<NY, BC * NY>(buf, src, tid);
+  // The tile's transfer-function values are one contiguous run
+  // ht[p0 * NY + q], fetched here so they arrive during the forward FFT.
+  // For 1024-point columns the extra registers would cost the second
+  // workgroup per CU, so there they are read after the FFT.
+  constexpr int E = BC * NY, PER = (E + NT - 1) / NT;
+  constexpr bool PRE = NY < 1024;
+  const float2* hp = ht + (long)p0 * NY;
+  float2 h[PRE ? PER : 1];
+  if constexpr (PRE) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (E % NT == 0 || tid + k * NT < E) h[k] = hp[tid + k * NT];
+  }
   __syncthreads();
   fft_lds<NY, BC, NT, -1>(buf, tw, tid);
-  for (int q = tid; q < BC * NY; q += NT) {
-    const int i = q / NY, fy = q % NY;
-    float2* e = &buf[i * S + skew(fy)];
-    *e = c2::mul(*e, ht[(long)(p0 + i) * NY + fy]);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int q = tid + k * NT;
+    if (E % NT != 0 && q >= E) continue;
+    float2* e = &buf[(q / NY) * S + skew(q % NY)];
+    *e = c2::mul(*e, PRE ? h[PRE ? k : 0] : hp[q]);
   }
   __syncthreads();
   fft_lds<NY, BC, NT, +1>(buf, tw, tid);
@@ -441,13 +456,26 @@ __global__ __launch_bounds__(NT) void k_fresnel_cols(const TIN* __restrict__ in,
   fill_twiddles<NY>(tw, tid, NT);
   const TIN* src = in + (t * nx + p0) * (long)NY;
   load_tile<NY, BC * NY>(buf, src, tid);
+  // Output element q = tid + k * NT is (y, i) = (q / BC, q % BC); NT is a
+  // multiple of BC, so each thread keeps one column i and steps y by NT / BC.
+  // Its chirp values are fetched here and arrive during the FFT.
+  constexpr int E = BC * NY, PER = (E + NT - 1) / NT, YS = NT / BC;
+  static_assert(NT % BC == 0, "a thread keeps one column");
+  const int i = tid % BC, yt = tid / BC;
+  const float2 cx = qx[p0 + i];
+  float2 cy[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (E % NT == 0 || yt + k * YS < NY) cy[k] = qy[yt + k * YS];
   __syncthreads();
   fft_lds<NY, BC, NT, DIR>(buf, tw, tid);
-  TOUT* dst = out + t * (long)NY * nx;
-  for (int q = tid; q < BC * NY; q += NT) {
-    const int y = q / BC, i = q % BC;
-    float2 v = c2::mul(buf[i * S + skew(y)], c2::mul(qx[p0 + i], qy[y]));
-    store_c(dst + (long)y * nx + p0 + i, c2::scale(v, scale));
+  TOUT* dst = out + t * (long)NY * nx + p0 + i;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int y = yt + k * YS;
+    if (E % NT != 0 && y >= NY) continue;
+    float2 v = c2::mul(buf[i * S + skew(y)], c2::mul(cx, cy[k]));
+    store_c(dst + (long)y * nx, c2::scale(v, scale));
   }
 }
 
