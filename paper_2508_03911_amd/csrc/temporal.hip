@@ -440,8 +440,9 @@ __global__ void k_gram_reduce(const float* __restrict__ part, int nblk, int W, d
 // ------------------------------------------------------------------ FP64 Jacobi
 // Cyclic Jacobi for a Hermitian W x W matrix, one block per window, with the
 // round-robin (circle) ordering: in each of the W-1 steps of a sweep, W/2
-// disjoint pairs rotate at once; column updates of all pairs, then row
-// updates, then the eigenvector columns.  Pair (p, q) with a = A_pp,
+// disjoint pairs rotate at once, the matrix in independent 2x2 blocks (the
+// column and the row rotation together) and the eigenvector columns in one
+// pass between two barriers.  Pair (p, q) with a = A_pp,
 // d = A_qq, b = A_pq = |b| e^{i phi}: J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
 // with t = sgn(th)/(|th| + sqrt(th^2 + 1)), th = (d - a)/(2|b|),
 // c = 1/sqrt(t^2 + 1), s = t c zeroes A_pq in J^H A J.
@@ -453,9 +454,10 @@ __device__ inline dc dadd(dc a, dc b) { return {a.x + b.x, a.y + b.y}; }
 __device__ inline dc dscale(dc a, double s) { return {a.x * s, a.y * s}; }
 __device__ inline dc dconj(dc a) { return {a.x, -a.y}; }
 
-// JT = W^2 / 2 threads per window (one per update of a rotation step), at
-// most 1024.  A and V sit in LDS with a padded row stride W + 1, so the
-// column updates (lanes walking down a column) spread over the banks.  The
+// JT = W^2 / 2 threads per window (one per eigenvector-pair update of a
+// rotation step; the (W/2)^2 matrix blocks take a half or a quarter of
+// them), at most 1024.  A and V sit in LDS with a padded row stride W + 1, so
+// lanes walking down a column spread over the banks.  The
 // rotation parameters use reciprocal square roots: 1/|b| once, then t and
 // c = 1/sqrt(t^2 + 1).
 template <int W>
@@ -547,32 +549,43 @@ __global__ __launch_bounds__(jacobi_threads<W>()) void k_jacobi(const double* __
         }
       }
       __syncthreads();
-      // columns: A[:,p] = c A[:,p] - s e A[:,q];  A[:,q] = s A[:,p] + c e A[:,q]; same for V
+      // The step's rotations act on disjoint index pairs that cover 0..W-1,
+      // so A' = J^H A J splits into independent 2x2 blocks: rows {p_i, q_i}
+      // by columns {p_j, q_j} take the column rotation of pair j,
+      //   A[:,p] = c A[:,p] - s e A[:,q],  A[:,q] = s A[:,p] + c e A[:,q],
+      // then the row rotation of pair i,
+      //   A[p,:] = c A[p,:] - s conj(e) A[q,:],  A[q,:] = s A[p,:] + c conj(e) A[q,:],
+      // in registers, with one read and one write of each element.
+      for (int b = tid; b < (W / 2) * (W / 2); b += JT) {
+        const int i = b / (W / 2), j = b % (W / 2);
+        const int pi = pp[i], qi = qq[i], pj = pp[j], qj = qq[j];
+        const double cj = rc[j], sj = rs[j], ci = rc[i], si = rs[i];
+        const dc ej = re[j], eci = dconj(re[i]);
+        const dc a_pp = A[pi * WP + pj], a_pq = A[pi * WP + qj];
+        const dc a_qp = A[qi * WP + pj], a_qq = A[qi * WP + qj];
+        dc t = dmul(ej, a_pq);
+        const dc n_pp = dadd(dscale(a_pp, cj), dscale(t, -sj));
+        const dc n_pq = dadd(dscale(a_pp, sj), dscale(t, cj));
+        t = dmul(ej, a_qq);
+        const dc n_qp = dadd(dscale(a_qp, cj), dscale(t, -sj));
+        const dc n_qq = dadd(dscale(a_qp, sj), dscale(t, cj));
+        t = dmul(eci, n_qp);
+        A[pi * WP + pj] = dadd(dscale(n_pp, ci), dscale(t, -si));
+        A[qi * WP + pj] = dadd(dscale(n_pp, si), dscale(t, ci));
+        t = dmul(eci, n_qq);
+        A[pi * WP + qj] = dadd(dscale(n_pq, ci), dscale(t, -si));
+        A[qi * WP + qj] = dadd(dscale(n_pq, si), dscale(t, ci));
+      }
+      // V = V J: the column rotation of every pair on every row
       for (int i = tid; i < (W / 2) * W; i += JT) {
         const int k = i / W, r = i % W;
         const int p = pp[k], q = qq[k];
         const double c = rc[k], sn = rs[k];
         const dc e = re[k];
-        dc ap = A[r * WP + p], aq = A[r * WP + q];
-        dc eq = dmul(e, aq);
-        A[r * WP + p] = dadd(dscale(ap, c), dscale(eq, -sn));
-        A[r * WP + q] = dadd(dscale(ap, sn), dscale(eq, c));
         dc vp = V[r * WP + p], vq = V[r * WP + q];
         dc ev = dmul(e, vq);
         V[r * WP + p] = dadd(dscale(vp, c), dscale(ev, -sn));
         V[r * WP + q] = dadd(dscale(vp, sn), dscale(ev, c));
-      }
-      __syncthreads();
-      // rows: A[p,:] = c A[p,:] - s conj(e) A[q,:];  A[q,:] = s A[p,:] + c conj(e) A[q,:]
-      for (int i = tid; i < (W / 2) * W; i += JT) {
-        const int k = i / W, col = i % W;
-        const int p = pp[k], q = qq[k];
-        const double c = rc[k], sn = rs[k];
-        const dc ec = dconj(re[k]);
-        dc ap = A[p * WP + col], aq = A[q * WP + col];
-        dc eq = dmul(ec, aq);
-        A[p * WP + col] = dadd(dscale(ap, c), dscale(eq, -sn));
-        A[q * WP + col] = dadd(dscale(ap, sn), dscale(eq, c));
       }
       __syncthreads();
     }
