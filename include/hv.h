@@ -276,7 +276,9 @@ hv_status hv_stream_push(hv_stream* s, const void* frames, int n_frames, const i
  * in images_overwritten. */
 hv_status hv_stream_pop(hv_stream* s, float* m0, float* m1, float* m2, int64_t* t_last_arrival_ns,
                         int64_t* t_done_ns);
-/* Finish in-flight windows, free the stream and return its bytes to the budget. */
+/* Finish in-flight windows, free the stream and return its bytes to the budget.
+ * The stream is released even when the device reports an error while its
+ * work drains; that error is returned as HV_ERR_DEVICE. */
 hv_status hv_stream_close(hv_stream* s);
 /* Per-stream counters (nullable outputs). */
 hv_status hv_stream_frames(const hv_stream* s, int64_t* pushed, int64_t* dropped, int64_t* windows_done);

@@ -43,17 +43,20 @@ const char* last_error() { return g_err; }
 
 DevBuf::~DevBuf() { release(); }
 void DevBuf::release() {
-  if (ptr) hipFree(ptr);
+  if (ptr) (void)hipFree(ptr);
   ptr = nullptr;
   bytes = 0;
 }
 hv_status DevBuf::ensure(size_t want, size_t* accounted) {
   if (want <= bytes) return HV_OK;
   if (accounted) *accounted -= bytes;
-  if (ptr) hipDeviceSynchronize();  // queued work may still read the old buffer
+  // queued work may still read the old buffer
+  if (ptr && hipDeviceSynchronize() != hipSuccess)
+    return fail(HV_ERR_DEVICE, "device error before regrowing a workspace: %s",
+                hipGetErrorString(hipGetLastError()));
   release();
   if (hipMalloc(&ptr, want) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     ptr = nullptr;
     return fail(HV_ERR_NOMEM, "hipMalloc of %zu bytes failed", want);
   }
@@ -78,17 +81,22 @@ hipEvent_t Timing::take() {
     return e;
   }
   hipEvent_t e = nullptr;
-  hipEventCreate(&e);
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
   return e;
 }
 void Timing::collect() {
   for (auto& r : pending) {
-    hipEventSynchronize(r.b);
     float ms = 0.f;
-    hipEventElapsedTime(&ms, r.a, r.b);
-    auto& slot = acc[r.name];
-    slot.first += ms;
-    slot.second += 1;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& slot = acc[r.name];
+      slot.first += ms;
+      slot.second += 1;
+    } else {
+      (void)hipGetLastError();  // a sample that cannot be read is left out
+    }
     pool.push_back(r.a);
     pool.push_back(r.b);
   }
@@ -100,7 +108,7 @@ void Timing::reset() {
 }
 Timing::~Timing() {
   collect();
-  for (hipEvent_t e : pool) hipEventDestroy(e);
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
 // ---------------------------------------------------------------- band
@@ -325,9 +333,9 @@ DftPlan* Ctx::dft_plan(const hv_temporal& tp, hv_status* st) {
 
 Ctx::~Ctx() {
   for (auto& kv : lanes) {
-    if (kv.second.s) hipStreamDestroy(kv.second.s);
-    if (kv.second.fork) hipEventDestroy(kv.second.fork);
-    if (kv.second.join) hipEventDestroy(kv.second.join);
+    if (kv.second.s) (void)hipStreamDestroy(kv.second.s);
+    if (kv.second.fork) (void)hipEventDestroy(kv.second.fork);
+    if (kv.second.join) (void)hipEventDestroy(kv.second.join);
   }
 }
 
@@ -335,29 +343,58 @@ Ctx::Lane2* Ctx::lane2(hipStream_t caller, hv_status* st) {
   std::lock_guard<std::recursive_mutex> lk(mu);
   Lane2& l = lanes[(void*)caller];
   if (!l.s) {
-    if (hipStreamCreateWithFlags(&l.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&l.fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&l.join, hipEventDisableTiming) != hipSuccess) {
-      *st = fail(HV_ERR_DEVICE, "could not create the second stream");
+    hipStream_t s2 = nullptr;
+    hipEvent_t f = nullptr, j = nullptr;
+    if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+      const hipError_t e = hipGetLastError();
+      if (j) (void)hipEventDestroy(j);
+      if (f) (void)hipEventDestroy(f);
+      if (s2) (void)hipStreamDestroy(s2);
+      lanes.erase((void*)caller);  // a later call tries again from scratch
+      *st = fail(HV_ERR_DEVICE, "could not create the second stream: %s", hipGetErrorString(e));
       return nullptr;
     }
+    l.s = s2;
+    l.fork = f;
+    l.join = j;
   }
   return &l;
+}
+
+hv_status Ctx::Lane2::fork_from(hipStream_t from) {
+  hipError_t e = hipEventRecord(fork, from);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, fork, 0);
+  if (e == hipSuccess) return HV_OK;
+  (void)hipGetLastError();
+  return fail(HV_ERR_DEVICE, "could not order the second stream after the caller's: %s", hipGetErrorString(e));
+}
+
+hv_status Ctx::Lane2::join_into(hipStream_t to) {
+  hipError_t e = hipEventRecord(join, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(to, join, 0);
+  if (e == hipSuccess) return HV_OK;
+  (void)hipGetLastError();
+  return fail(HV_ERR_DEVICE, "could not order the caller's stream after the second one: %s", hipGetErrorString(e));
 }
 
 int persistent_blocks(const void* kernel, int threads) {
   static std::mutex mu;
   static std::map<std::pair<const void*, int>, int> cache;
   int dev = 0;
-  hipGetDevice(&dev);
+  if (hipGetDevice(&dev) != hipSuccess) (void)hipGetLastError();
   std::lock_guard<std::mutex> lk(mu);
   auto key = std::make_pair(kernel, dev);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   int cus = 0, per = 0;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    cus = 0;
+  }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     per = 1;
   }
   const int b = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
@@ -521,7 +558,7 @@ hv_status hv_ctx_create(int device, size_t hbm_budget_bytes, hv_ctx** out) {
   *out = nullptr;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(HV_ERR_DEVICE, "no HIP device available");
   }
   if (device < 0 || device >= count) return fail(HV_ERR_ARG, "device %d out of range (%d devices)", device, count);
@@ -541,9 +578,11 @@ hv_status hv_ctx_create(int device, size_t hbm_budget_bytes, hv_ctx** out) {
 
 void hv_ctx_destroy(hv_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
+  // teardown cannot report: a failing device still has its host state freed
+  (void)hipSetDevice(ctx->device);
   serve_shutdown(ctx);
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
+  (void)hipGetLastError();
   delete ctx;
 }
 
@@ -685,8 +724,7 @@ static hv_status stft_band_first(Ctx* ctx, const void* in, int in_t, int ny, int
   hipStream_t st = caller;
   if (two_lanes && nwin_total > gw) {
     if (!(l2 = ctx->lane2(caller, &s))) return s;
-    hipEventRecord(l2->fork, caller);
-    hipStreamWaitEvent(l2->s, l2->fork, 0);
+    if ((s = l2->fork_from(caller))) return s;
   }
   hv_status res = HV_OK;
   for (int j0 = 0, c = 0; j0 < nwin_total && res == HV_OK; j0 += gw, ++c) {
@@ -716,8 +754,8 @@ static hv_status stft_band_first(Ctx* ctx, const void* in, int in_t, int ny, int
     }();
   }
   if (l2) {
-    hipEventRecord(l2->join, l2->s);
-    hipStreamWaitEvent(caller, l2->join, 0);
+    const hv_status j = l2->join_into(caller);
+    if (res == HV_OK) res = j;
   }
   return res;
 }
@@ -791,8 +829,7 @@ static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny,
   Ctx::Lane2* l2 = nullptr;
   if (two_lanes && nwin_total > gw) {
     if (!(l2 = ctx->lane2(st, &s))) return s;
-    hipEventRecord(l2->fork, st);
-    hipStreamWaitEvent(l2->s, l2->fork, 0);
+    if ((s = l2->fork_from(st))) return s;
   }
   hv_status res = HV_OK;
   const hipStream_t caller = st;
@@ -829,8 +866,8 @@ static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny,
     }();
   }
   if (l2) {  // join, also after an error, so no work of this call outlives it on the second stream
-    hipEventRecord(l2->join, l2->s);
-    hipStreamWaitEvent(caller, l2->join, 0);
+    const hv_status j = l2->join_into(caller);
+    if (res == HV_OK) res = j;
   }
   return res;
 }
@@ -890,8 +927,7 @@ hv_status hv_stft_moments_host(hv_ctx* ctx, const void* host_in, int in_t, int n
   if (nwin_total > gw) {
     if (!(l2 = ctx->lane2(st, &s))) return s;
     if ((s = stage(l2->s, &in_dev[1], out_dev[1]))) return s;
-    hipEventRecord(l2->fork, st);
-    hipStreamWaitEvent(l2->s, l2->fork, 0);
+    if ((s = l2->fork_from(st))) return s;
   }
   // Each chunk is copied in, processed and copied out on its own stream;
   // with two streams one chunk's copies overlap the other chunk's kernels.
@@ -914,8 +950,8 @@ hv_status hv_stft_moments_host(hv_ctx* ctx, const void* host_in, int in_t, int n
         res = fail(HV_ERR_DEVICE, "image download failed");
   }
   if (l2) {  // join, also after an error
-    hipEventRecord(l2->join, l2->s);
-    hipStreamWaitEvent(st, l2->join, 0);
+    const hv_status j = l2->join_into(st);
+    if (res == HV_OK) res = j;
   }
   return res;
 }
@@ -953,8 +989,7 @@ hv_status hv_stft_volume(hv_ctx* ctx, const void* in, int in_t, int n, int ny, i
   Ctx::Lane2* l2 = nullptr;
   if (nwin_total > gw) {
     if (!(l2 = ctx->lane2(st, &s))) return s;
-    hipEventRecord(l2->fork, st);
-    hipStreamWaitEvent(l2->s, l2->fork, 0);
+    if ((s = l2->fork_from(st))) return s;
   }
   hv_status res = HV_OK;
   const hipStream_t caller = st;
@@ -972,8 +1007,8 @@ hv_status hv_stft_volume(hv_ctx* ctx, const void* in, int in_t, int n, int ny, i
       });
   }
   if (l2) {  // join, also after an error
-    hipEventRecord(l2->join, l2->s);
-    hipStreamWaitEvent(caller, l2->join, 0);
+    const hv_status j = l2->join_into(caller);
+    if (res == HV_OK) res = j;
   }
   return res;
 }
@@ -1049,8 +1084,7 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
   if (nwin_total > gw) {
     if (!(l2 = ctx->lane2(st, &s))) return s;
     if ((s = scratch(l2->s, &sc[1]))) return s;
-    hipEventRecord(l2->fork, st);
-    hipStreamWaitEvent(l2->s, l2->fork, 0);
+    if ((s = l2->fork_from(st))) return s;
   }
   hv_status res = HV_OK;
   const hipStream_t caller = st;
@@ -1107,8 +1141,8 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
     }();
   }
   if (l2) {  // join, also after an error
-    hipEventRecord(l2->join, l2->s);
-    hipStreamWaitEvent(caller, l2->join, 0);
+    const hv_status j = l2->join_into(caller);
+    if (res == HV_OK) res = j;
   }
   return res;
 }

@@ -844,7 +844,7 @@ hv_status hv_af_crops(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, v
   if (!ctx || !holo || !out) return fail(HV_ERR_ARG, "NULL argument");
   if (ny != AN || nx != AN) return fail(HV_ERR_SHAPE, "autofocus works on 256x256 holograms");
   if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
-  hipSetDevice(ctx->device);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   hipStream_t st = (hipStream_t)hip_stream;
   float2* t1;
@@ -865,7 +865,7 @@ hv_status hv_af_scan(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, do
   if (n_candidates < 2 || !(z_hi_m > z_lo_m) || !(wavelength_m > 0) || !(pitch_m > 0))
     return fail(HV_ERR_ARG, "need >= 2 candidates, z_hi > z_lo, positive wavelength and pitch");
   if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
-  hipSetDevice(ctx->device);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   hipStream_t st = (hipStream_t)hip_stream;
   // transfer-function table per candidate, built in float64 once per setting
@@ -916,8 +916,8 @@ hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batc
                              hv_af_model** out) {
   if (!ctx || !init_params || !out) return fail(HV_ERR_ARG, "NULL argument");
   if (max_batch <= 0 || !(z_scale > 0)) return fail(HV_ERR_ARG, "max_batch and z_scale must be positive");
-  hipSetDevice(ctx->device);
   *out = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   auto* md = new hv_af_model();
   md->ctx = ctx;
   md->max_batch = max_batch;
@@ -957,16 +957,17 @@ hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batc
 
 void hv_af_model_destroy(hv_af_model* md) {
   if (!md) return;
-  hipSetDevice(md->ctx->device);
-  hipDeviceSynchronize();
-  for (void* p : md->owned) hipFree(p);
+  (void)hipSetDevice(md->ctx->device);  // teardown cannot report
+  (void)hipDeviceSynchronize();
+  for (void* p : md->owned) (void)hipFree(p);
+  (void)hipGetLastError();
   delete md;
 }
 
 hv_status hv_af_model_state(hv_af_model* md, float* params, float* m, float* v, int64_t* step) {
   if (!md) return fail(HV_ERR_ARG, "NULL model");
-  hipSetDevice(md->ctx->device);
-  hipDeviceSynchronize();
+  if (hipSetDevice(md->ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return fail(HV_ERR_DEVICE, "device error: %s", hipGetErrorString(hipGetLastError()));
   if ((params && hipMemcpy(params, md->params, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
       (m && hipMemcpy(m, md->m, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
       (v && hipMemcpy(v, md->v, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess))
@@ -977,8 +978,8 @@ hv_status hv_af_model_state(hv_af_model* md, float* params, float* m, float* v, 
 
 hv_status hv_af_model_load(hv_af_model* md, const float* params, const float* m, const float* v, int64_t step) {
   if (!md || !params) return fail(HV_ERR_ARG, "NULL argument");
-  hipSetDevice(md->ctx->device);
-  hipDeviceSynchronize();
+  if (hipSetDevice(md->ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return fail(HV_ERR_DEVICE, "device error: %s", hipGetErrorString(hipGetLastError()));
   if (hipMemcpy(md->params, params, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess ||
       (m && hipMemcpy(md->m, m, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess) ||
       (v && hipMemcpy(md->v, v, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess))
@@ -990,7 +991,7 @@ hv_status hv_af_model_load(hv_af_model* md, const float* params, const float* m,
 hv_status hv_af_forward(hv_af_model* md, const void* crops, int batch, float* out, void* hip_stream) {
   if (!md || !crops || !out) return fail(HV_ERR_ARG, "NULL argument");
   if (batch <= 0 || batch > md->max_batch) return fail(HV_ERR_SHAPE, "batch %d outside [1, %d]", batch, md->max_batch);
-  hipSetDevice(md->ctx->device);
+  if (hipSetDevice(md->ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)hip_stream;
   hv_status s = forward(md, (const _Float16*)crops, batch, false, st);
   if (s) return s;
@@ -1002,7 +1003,7 @@ hv_status hv_af_forward(hv_af_model* md, const void* crops, int batch, float* ou
 hv_status hv_af_infer(hv_af_model* md, const void* crops, int batch, float* out, void* hip_stream) {
   if (!md || !crops || !out) return fail(HV_ERR_ARG, "NULL argument");
   if (batch <= 0 || batch > md->max_batch) return fail(HV_ERR_SHAPE, "batch %d outside [1, %d]", batch, md->max_batch);
-  hipSetDevice(md->ctx->device);
+  if (hipSetDevice(md->ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)hip_stream;
   hv_status s = infer(md, (const _Float16*)crops, batch, st);
   if (s) return s;
@@ -1015,7 +1016,7 @@ hv_status hv_af_loss_grad(hv_af_model* md, const void* crops, const float* z_m, 
                           void* hip_stream) {
   if (!md || !crops || !z_m || !grad) return fail(HV_ERR_ARG, "NULL argument");
   if (batch <= 0 || batch > md->max_batch) return fail(HV_ERR_SHAPE, "batch %d outside [1, %d]", batch, md->max_batch);
-  hipSetDevice(md->ctx->device);
+  if (hipSetDevice(md->ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)hip_stream;
   hipLaunchKernelGGL(k_normalize, dim3((batch + 255) / 256), dim3(256), 0, st, z_m, batch, (float)md->z_mean,
                      (float)(1.0 / md->z_scale), md->zn);
@@ -1042,7 +1043,7 @@ hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wave
   if (!md || !holo || !z_out) return fail(HV_ERR_ARG, "NULL argument");
   if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
   hv_ctx* ctx = md->ctx;
-  hipSetDevice(ctx->device);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)hip_stream;
   DevBuf& cb = ctx->work(st, 23);
   DevBuf& sg = ctx->work(st, 24);
@@ -1076,7 +1077,9 @@ hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wave
   if ((s = ib.ensure((size_t)m * 4, &ctx->held)) || (s = gb.ensure((size_t)m * AN * AN, &ctx->held)) ||
       (s = zb.ensure((size_t)m * 4, &ctx->held)))
     return s;
-  if (hipMemcpyAsync(ib.ptr, idx.data(), (size_t)m * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+  // a synchronous copy (m ints): the host vector may go out of scope on any
+  // return below while nothing in flight still reads it
+  if (hipMemcpy(ib.ptr, idx.data(), (size_t)m * 4, hipMemcpyHostToDevice) != hipSuccess)
     return fail(HV_ERR_DEVICE, "index copy failed");
   hipLaunchKernelGGL(k_af_gather, dim3(std::min(4096, (m * AN * AN / 16 + 255) / 256)), dim3(256), 0, st, holo,
                      (const int*)ib.ptr, m, (uint8_t*)gb.ptr);
@@ -1085,15 +1088,18 @@ hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wave
     return s;
   hipLaunchKernelGGL(k_af_scatter, dim3((m + 255) / 256), dim3(256), 0, st, (const float*)zb.ptr,
                      (const int*)ib.ptr, m, z_out, used_fallback);
-  hipStreamSynchronize(st);  // the host index vector must outlive the copy
-  return launched("af_predict");
+  if ((s = launched("af_predict"))) return s;
+  // z_out is complete on return, as on the path without fallback
+  if (hipStreamSynchronize(st) != hipSuccess)
+    return fail(HV_ERR_DEVICE, "af_predict: %s", hipGetErrorString(hipGetLastError()));
+  return HV_OK;
 }
 
 hv_status hv_af_synthesize(hv_ctx* ctx, int n, const double* z_m, double wavelength_m, double pitch_m, uint64_t seed,
                            int64_t index_base, uint8_t* out, void* hip_stream) {
   if (!ctx || !z_m || !out) return fail(HV_ERR_ARG, "NULL argument");
   if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
-  hipSetDevice(ctx->device);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)hip_stream;
   constexpr int CH = 128;  // holograms per chunk
   hv_status s;
@@ -1153,7 +1159,8 @@ hv_status hv_af_synthesize(hv_ctx* ctx, int n, const double* z_m, double wavelen
     hipLaunchKernelGGL(k_af_holo, dim3(cn), dim3(256), 0, st, (const float2*)fb.ptr, out + (size_t)c0 * AN * AN,
                        seed, base);
     if ((s = launched("af_synthesize"))) return s;
-    hipStreamSynchronize(st);  // the host disk table is reused by the next chunk
+    if (hipStreamSynchronize(st) != hipSuccess)  // the host disk table is reused by the next chunk
+      return fail(HV_ERR_DEVICE, "af_synthesize: %s", hipGetErrorString(hipGetLastError()));
   }
   return HV_OK;
 }

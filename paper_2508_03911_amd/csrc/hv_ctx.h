@@ -73,7 +73,10 @@ struct Timing {
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<double, long>> acc;  // total ms, launches
-  hipEvent_t take();
+  hipEvent_t take();  // null if no event could be created
+  void give_back(hipEvent_t e) {
+    if (e) pool.push_back(e);
+  }
   void collect();
   void reset();
   ~Timing();
@@ -101,6 +104,10 @@ struct Ctx {
   struct Lane2 {
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    // The second stream waits for everything queued on `from` so far.
+    hv_status fork_from(hipStream_t from);
+    // `to` waits for everything queued on the second stream so far.
+    hv_status join_into(hipStream_t to);
   };
   std::map<void*, Lane2> lanes;
 
@@ -121,10 +128,17 @@ template <class F>
 hv_status timed(Ctx* c, const char* name, hipStream_t st, F&& f) {
   if (!c->timing.on) return f();
   hipEvent_t a = c->timing.take(), b = c->timing.take();
-  hipEventRecord(a, st);
+  // timing is diagnostic: a launch whose events cannot be recorded runs
+  // untimed
+  const bool ra = a && b && hipEventRecord(a, st) == hipSuccess;
   hv_status s = f();
-  hipEventRecord(b, st);
-  c->timing.pending.push_back({name, a, b});
+  if (ra && hipEventRecord(b, st) == hipSuccess) {
+    c->timing.pending.push_back({name, a, b});
+  } else {
+    (void)hipGetLastError();
+    c->timing.give_back(a);
+    c->timing.give_back(b);
+  }
   return s;
 }
 

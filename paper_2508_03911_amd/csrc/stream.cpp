@@ -86,7 +86,10 @@ struct ServeState {
       return e;
     }
     hipEvent_t e = nullptr;
-    hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
     return e;
   }
   void give_event(hipEvent_t e) {
@@ -133,7 +136,8 @@ static int drain(ServeState* sv, hv_stream* s, bool wait) {
 
 static void poll_loop(hv_ctx* ctx) {
   ServeState* sv = ctx->serve;
-  hipSetDevice(ctx->device);
+  // the context's device was set successfully when the context was created
+  (void)hipSetDevice(ctx->device);
   while (!sv->stop.load()) {
     int done = 0;
     {
@@ -165,7 +169,7 @@ void serve_shutdown(Ctx* c) {
   for (hv_stream* s : left) hv_stream_close(s);
   sv->stop = true;
   if (sv->poller.joinable()) sv->poller.join();
-  for (hipEvent_t e : sv->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : sv->ev_pool) (void)hipEventDestroy(e);
   delete sv;
   ctx->serve = nullptr;
 }
@@ -194,7 +198,11 @@ static hv_status launch_ready(hv_stream* s) {
       slot += run * s->tp.stride;
     }
     hipEvent_t ev = sv->take_event();
-    if (hipEventRecord(ev, s->st) != hipSuccess) return fail(HV_ERR_DEVICE, "event record failed");
+    if (!ev) return fail(HV_ERR_DEVICE, "could not create a completion event");
+    if (hipEventRecord(ev, s->st) != hipSuccess) {
+      sv->give_event(ev);
+      return fail(HV_ERR_DEVICE, "event record failed: %s", hipGetErrorString(hipGetLastError()));
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     s->pending.push_back({ev, g});
   }
@@ -272,10 +280,10 @@ hv_status hv_stream_open(hv_ctx* ctx, int ny, int nx, int raw_t, const hv_optics
       std::lock_guard<std::recursive_mutex> lock(ctx->mu);
       sv->admitted_bytes -= total;
     }
-    if (st->ring_dev) hipFree(st->ring_dev);
+    if (st->ring_dev) (void)hipFree(st->ring_dev);
     for (float* p : st->out_dev)
-      if (p) hipFree(p);
-    if (st->st) hipStreamDestroy(st->st);
+      if (p) (void)hipFree(p);
+    if (st->st) (void)hipStreamDestroy(st->st);
     delete st;
     return e;
   };
@@ -363,12 +371,15 @@ hv_status hv_stream_close(hv_stream* s) {
   if (!s) return fail(HV_ERR_ARG, "NULL stream");
   hv_ctx* ctx = s->ctx;
   ServeState* sv = ctx->serve;
-  hipSetDevice(ctx->device);
+  // A device error is reported, but the stream is released all the same.
+  hv_status res = HV_OK;
+  const bool on_dev = hipSetDevice(ctx->device) == hipSuccess;
   {
     std::lock_guard<std::mutex> g(sv->mu);
     sv->streams.erase(std::remove(sv->streams.begin(), sv->streams.end(), s), sv->streams.end());
   }
-  hipStreamSynchronize(s->st);
+  if (!on_dev || hipStreamSynchronize(s->st) != hipSuccess)
+    res = fail(HV_ERR_DEVICE, "device error while closing a stream: %s", hipGetErrorString(hipGetLastError()));
   drain(sv, s, true);
   std::vector<void*> to_free;
   std::vector<std::unique_ptr<AsPlan>> dead_as;
@@ -413,14 +424,15 @@ hv_status hv_stream_close(hv_stream* s) {
       }
     }
   }
-  for (void* p : to_free) hipFree(p);
+  // teardown of a closed stream: failures here cannot be acted on
+  for (void* p : to_free) (void)hipFree(p);
   dead_as.clear();
   dead_fr.clear();
-  hipFree(s->ring_dev);
-  for (float* p : s->out_dev) hipFree(p);
-  hipStreamDestroy(s->st);
+  (void)hipFree(s->ring_dev);
+  for (float* p : s->out_dev) (void)hipFree(p);
+  (void)hipStreamDestroy(s->st);
   delete s;
-  return HV_OK;
+  return res;
 }
 
 hv_status hv_stream_frames(const hv_stream* s, int64_t* pushed, int64_t* dropped, int64_t* windows_done) {
@@ -530,7 +542,7 @@ hv_status hv_replay_run(hv_ctx* ctx, const hv_replay_config* cfg, hv_replay_resu
     const int64_t t_stop = std::min(t_end, t_start + (int64_t)(lifetime * 1e9));
     const uint64_t sid = stream_id++;
     workers.emplace_back([&, s, c, k, t_start, t_stop, sid]() {
-      hipSetDevice(ctx->device);
+      (void)hipSetDevice(ctx->device);  // set successfully when the context was created
       const size_t fb = (size_t)k.ny * k.nx * (k.raw_t == HV_U8 ? 1 : 2);
       std::vector<int64_t> arr(packet);
       int64_t f = 0;
