@@ -169,8 +169,8 @@ __device__ inline void coef_pixels(const CoefArgs& g, const float* wts_lds, cons
   }
 }
 
-__device__ inline void load_wts(float* wts_lds, const CoefArgs& g, int tid) {
-  for (int i = tid; i < 3 * MT_MAX * 16; i += NT) {
+__device__ inline void load_wts(float* wts_lds, const CoefArgs& g, int tid, int nthreads = NT) {
+  for (int i = tid; i < 3 * MT_MAX * 16; i += nthreads) {
     const int k = i / (MT_MAX * 16), m = i % (MT_MAX * 16);
     wts_lds[i] = (m < g.mtiles * 16 && k < g.nout) ? g.wts[k * g.mtiles * 16 + m] : 0.f;
   }
@@ -256,26 +256,41 @@ __global__ __launch_bounds__(NT) void k_rowinv_coef(const TIN* __restrict__ z, i
 }
 
 // ------------------------------------------------------------------ GEMM from a field in memory
-constexpr int TPIX = NT / 2;  // pixels per block tile (one 32-pixel tile per wave)
+constexpr int TPIX = NT / 2;  // pixel counts must be a multiple of this
 
-template <int W, bool MIXED, typename TIN>
-__global__ __launch_bounds__(NT) void k_field_coef(const TIN* __restrict__ u, long npix, int stride, CoefArgs g) {
-  constexpr int S = lds_stride(TPIX);
+// Threads per block: one 32-pixel tile per wave, so a block covers
+// threads / 2 pixels.  A W = 64 tile of 256 pixels fills 140 KB of LDS and
+// leaves one block per CU, its loads and its MFMAs in turn.  HALF halves it
+// (128 pixels, four waves, 67 KB) so that two blocks share a CU and one's
+// loads run under the other's MFMAs.  Measured on 1024^2 fields: the STFT
+// GEMM 0.50 -> 0.445 ms per window with it; the PCA projection ran faster
+// too, but its pass slower (it shares the chip with the other stream's
+// eigensolve and covariance), so that one keeps the full tile.
+template <int W, bool HALF>
+constexpr int coef_threads() {
+  return HALF && W >= 64 ? NT / 2 : NT;
+}
+
+template <int W, bool MIXED, typename TIN, bool HALF>
+__global__ __launch_bounds__((coef_threads<W, HALF>())) void k_field_coef(const TIN* __restrict__ u, long npix,
+                                                                        int stride, CoefArgs g) {
+  constexpr int NTB = coef_threads<W, HALF>(), TP = NTB / 2;
+  constexpr int S = lds_stride(TP);
   constexpr bool EXACT = MIXED && sizeof(TIN) == 4;  // fp16 storage is exact in fp16
   __shared__ float2 buf[W * S];
   __shared__ float wts_lds[3 * MT_MAX * 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long p0 = (long)blockIdx.x * TPIX;
+  const long p0 = (long)blockIdx.x * TP;
   const long jj = blockIdx.y;
-  load_wts(wts_lds, g, tid);
+  load_wts(wts_lds, g, tid, NTB);
   AFrag<W, MIXED> af;
   load_afrag(af, g, jj, 0, lane);
   const TIN* src = u + (jj * stride) * npix + p0;
-  // element i of this thread: frame RPI * i + tid / TPIX, pixel tid % TPIX;
+  // element i of this thread: frame RPI * i + tid / TP, pixel tid % TP;
   // loads go out in batches of 8 so that several are in flight at once
-  constexpr int RPI = NT / TPIX, PER = W * TPIX / NT, BATCH = PER < 8 ? PER : 8;
+  constexpr int RPI = NTB / TP, PER = W * TP / NTB, BATCH = PER < 8 ? PER : 8;
   static_assert(PER % BATCH == 0, "load batches");
-  const int tr = tid / TPIX, x = tid % TPIX;
+  const int tr = tid / TP, x = tid % TP;
   const uint32_t off = (uint32_t)(tr * npix + x) * (uint32_t)sizeof(TIN);
   float2* lds = buf + tr * S + skew(x);
 #pragma unroll
@@ -710,14 +725,16 @@ hv_status go_rowinv_w(const void* z, bool half_in, int ny, int nx, int stride, i
   return hvi::fail(HV_ERR_SHAPE, "nx=%d not supported", nx);
 }
 
-template <int W, bool MIXED>
+template <int W, bool MIXED, bool HALF = false>
 void go_field(const void* u, bool half_in, long npix, int stride, int nwin, const CoefArgs& a, hipStream_t st) {
-  dim3 grid((unsigned)(npix / TPIX), nwin);
+  constexpr int NTB = coef_threads<W, HALF>();
+  dim3 grid((unsigned)(npix / (NTB / 2)), nwin);
   if (half_in)
-    hipLaunchKernelGGL((k_field_coef<W, MIXED, hv_h2>), grid, dim3(NT), 0, st, (const hv_h2*)u, npix, stride, a);
+    hipLaunchKernelGGL((k_field_coef<W, MIXED, hv_h2, HALF>), grid, dim3(NTB), 0, st, (const hv_h2*)u, npix,
+                       stride, a);
   else
-    hipLaunchKernelGGL((k_field_coef<W, MIXED, float2>), grid, dim3(NT), 0, st, (const float2*)u, npix, stride,
-                       a);
+    hipLaunchKernelGGL((k_field_coef<W, MIXED, float2, HALF>), grid, dim3(NTB), 0, st, (const float2*)u, npix,
+                       stride, a);
 }
 
 template <int W, bool MIXED>
@@ -754,8 +771,10 @@ hv_status launch_rowinv_coef(const void* z, bool half_in, int ny, int nx, int st
   return fail(HV_ERR_SHAPE, "window %d not supported", g.window);
 }
 
+// half_tile: W = 64 runs two 128-pixel blocks per CU (the STFT GEMM) rather
+// than one of 256 pixels (the PCA projection).
 static hv_status field_coef(const void* u, bool half_in, long npix, int stride, int nwin, const CoefArgs& a,
-                            int window, bool mixed, hipStream_t st) {
+                            int window, bool mixed, bool half_tile, hipStream_t st) {
   if (nwin <= 0) return HV_OK;
   if (npix % TPIX) return fail(HV_ERR_SHAPE, "pixel count %ld not a multiple of %d", npix, TPIX);
   switch (window) {
@@ -765,8 +784,14 @@ static hv_status field_coef(const void* u, bool half_in, long npix, int stride, 
                    : go_field<16, false>(u, half_in, npix, stride, nwin, a, st); break;
     case 32: mixed ? go_field<32, true>(u, half_in, npix, stride, nwin, a, st)
                    : go_field<32, false>(u, half_in, npix, stride, nwin, a, st); break;
-    case 64: mixed ? go_field<64, true>(u, half_in, npix, stride, nwin, a, st)
-                   : go_field<64, false>(u, half_in, npix, stride, nwin, a, st); break;
+    case 64:
+      if (half_tile)
+        mixed ? go_field<64, true, true>(u, half_in, npix, stride, nwin, a, st)
+              : go_field<64, false, true>(u, half_in, npix, stride, nwin, a, st);
+      else
+        mixed ? go_field<64, true>(u, half_in, npix, stride, nwin, a, st)
+              : go_field<64, false>(u, half_in, npix, stride, nwin, a, st);
+      break;
     default: return fail(HV_ERR_SHAPE, "window %d not supported", window);
   }
   return launched("field_coef");
@@ -776,7 +801,7 @@ hv_status launch_field_coef(const void* u, bool half_in, long npix, int stride, 
                             bool mixed, float b_scale, float out_scale, float* out0, float* out1, float* out2,
                             float2* spec, hipStream_t st) {
   CoefArgs a = make_args(g, 0, b_scale, out_scale, out0, out1, out2, spec);
-  return field_coef(u, half_in, npix, stride, nwin, a, g.window, mixed, st);
+  return field_coef(u, half_in, npix, stride, nwin, a, g.window, mixed, true, st);
 }
 
 hv_status launch_gram_partials(const void* u, bool half_in, long npix, int stride, int nwin, int window,
@@ -835,7 +860,7 @@ hv_status launch_proj_energy(const void* u, bool half_in, long npix, int stride,
                              hipStream_t st) {
   CoefGemm g{window, mtiles, npair, a32, a16hi, a16lo, wts, 1};
   CoefArgs a = make_args(g, (long)mtiles * window * 64, b_scale, out_scale, m0, nullptr, nullptr, nullptr);
-  return field_coef(u, half_in, npix, stride, nwin, a, window, mixed, st);
+  return field_coef(u, half_in, npix, stride, nwin, a, window, mixed, false, st);
 }
 
 hv_status launch_time_fft(const void* u, bool half_in, long npix, int stride, int nwin, int window, float amp2,
