@@ -19,6 +19,17 @@ accumulation buffer of user-defined size.  Readings:
   integer shifts s (ties: the lowest flat index), and the image is shifted
   circularly by -s;
 * accumulation: out_j = mean(in_{max(0, j - A + 1)} .. in_j).
+
+Besides the statistical moments, the paper renders the magnitude or the
+argument of the windowed spectrum over a range of temporal indices
+(Sec. III-B.1) into the buffer these steps work on.  Readings (the paper
+does not say how the range is combined):
+
+* magnitude: the sum over the range of the moduli, sum_k |S_k| (a sum, as
+  the moments sum their weighted powers);
+* argument: the argument of the sum over the range, arg(sum_k S_k) in
+  [-pi, pi] (a sum of angles would depend on where each one wraps); for a
+  one-index range both are |S_k| and arg(S_k).
 """
 
 from __future__ import annotations
@@ -90,3 +101,14 @@ def postprocess(images, kernel=None, renorm: bool = False, ref_count: int = 0, m
     if accumulate_length > 1:
         x = accumulate(x, accumulate_length)
     return x, shifts
+
+
+def magnitude_image(spec) -> np.ndarray:
+    """out[j, ...] = sum_k |S[j, k, ...]| over the range held in axis 1 of
+    spec (the windowed spectrum restricted to the range)."""
+    return np.abs(np.asarray(spec, dtype=np.complex128)).sum(axis=1)
+
+
+def argument_image(spec) -> np.ndarray:
+    """out[j, ...] = arg(sum_k S[j, k, ...]) over the range held in axis 1."""
+    return np.angle(np.asarray(spec, dtype=np.complex128).sum(axis=1))

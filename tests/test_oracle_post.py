@@ -2,7 +2,7 @@
 
 import numpy as np
 
-from oracle import post
+from oracle import post, temporal
 
 
 def test_delta_kernel_is_identity_and_box_on_constant():
@@ -44,3 +44,38 @@ def test_moving_average_of_a_ramp():
     x = np.arange(6, dtype=np.float64)[:, None, None] * np.ones((1, 2, 3))
     y = post.accumulate(x, 3)
     assert np.allclose(y[:, 0, 0], [0, 0.5, 1, 2, 3, 4])
+
+
+def _tones(window, amps, bins, shape=(3, 4)):
+    """Frames x_t = sum_i a_i exp(2i pi k_i t / W) at every pixel (a_i may vary
+    over the pixels): the oracle's DFT gives S_{k_i} = W a_i, zero elsewhere."""
+    t = np.arange(window)[:, None, None]
+    x = np.zeros((window,) + shape, dtype=np.complex128)
+    for a, k in zip(amps, bins):
+        x += a[None] * np.exp(2j * np.pi * k * t / window)
+    return x
+
+
+def test_magnitude_and_argument_of_tones():
+    rng = np.random.default_rng(4)
+    w = 16
+    a1 = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
+    a2 = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
+    s = temporal.stft(_tones(w, [a1, a2], [3, 5]), w, w)
+    # one-index range: the modulus and the phase of that bin's amplitude
+    assert np.allclose(post.magnitude_image(s[:, [3]])[0], w * np.abs(a1))
+    assert np.allclose(post.argument_image(s[:, [3]])[0], np.angle(a1))
+    # a range over both tones and an empty bin: sum of moduli, phase of the sum
+    assert np.allclose(post.magnitude_image(s[:, [3, 4, 5]])[0], w * (np.abs(a1) + np.abs(a2)))
+    assert np.allclose(post.argument_image(s[:, [3, 4, 5]])[0], np.angle(a1 + a2))
+
+
+def test_argument_rotates_with_a_global_phase():
+    rng = np.random.default_rng(5)
+    s = rng.standard_normal((2, 5, 6, 7)) + 1j * rng.standard_normal((2, 5, 6, 7))
+    phi = 2.2
+    a0, a1 = post.argument_image(s), post.argument_image(s * np.exp(1j * phi))
+    d = np.angle(np.exp(1j * (a1 - a0 - phi)))  # difference wrapped to [-pi, pi]
+    assert np.max(np.abs(d)) < 1e-12
+    assert np.allclose(post.magnitude_image(s * np.exp(1j * phi)), post.magnitude_image(s))
+    assert np.all(np.abs(a0) <= np.pi)
