@@ -444,6 +444,33 @@ def copy_rate(torch, reps: int = 10):
     return {"GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "note": "torch copy of 2 GiB, read + write bytes"}
 
 
+def bins_image_rate(ctx, hv, torch, reps: int = 10):
+    """Magnitude and argument images (hv_bins_image) over the 14 band bins
+    of 64 windows of the 256x256 stream: the spectrum [64][14][256][256] c64
+    (470 MB) is read once and [64][256][256] float32 written, so the
+    algorithmic bytes are 14 * 8 + 4 = 116 per pixel and window.  HIP events
+    on the stream the kernel is launched on."""
+    j, nb = 64, 14
+    spec_t = torch.randn((j, nb, NY, NX), dtype=torch.complex64, device="cuda")
+    out = torch.empty((j, NY, NX), dtype=torch.float32, device="cuda")
+    nbytes = j * NY * NX * (nb * 8 + 4)
+    res = {"workload": f"{j} windows x {nb} bins of {NY}x{NX} c64", "bytes_per_launch": nbytes}
+    for kind, name in ((hv.HV_IMG_MAGNITUDE, "magnitude"), (hv.HV_IMG_ARGUMENT, "argument")):
+        ctx.hv_bins_image(spec_t, kind, out=out)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            ctx.hv_bins_image(spec_t, kind, out=out)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms_per_launch": ms, "GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    del spec_t, out
+    return res
+
+
 def isolated_kernels(ctx, hv, torch, x, opt, steps, frames=8192):
     """The per-frame path's row and column kernels timed alone: hv_propagate
     (K1, K2, row inverse) on one stream over the first `frames` frames, with
@@ -622,6 +649,7 @@ def main():
             "kernels_fp32": bf32["kernels"]},
         "hbm_copy": copy_rate(torch),
         "kernels_alone_fp32": isolated_kernels(ctx, hv, torch, x, opt, max(1, args.steps // 2)),
+        "bins_image": bins_image_rate(ctx, hv, torch),
     }
     if args.serve_seconds > 0:
         log(f"stream load replay for {args.serve_seconds:.0f}s ...")

@@ -354,6 +354,20 @@ typedef struct {
 hv_status hv_postprocess(hv_ctx* ctx, const float* in, int count, int ny, int nx, const hv_post* cfg, float* out,
                          int* shifts, void* hip_stream);
 
+/* Magnitude or argument image of the windowed spectrum over a range of
+ * temporal indices (Sec. III-B.1: besides the moments, the value rendered
+ * per pixel may be the magnitude or the argument over a given index range):
+ *   HV_IMG_MAGNITUDE  out[j][p] = sum_k |spec[j][k][p]|
+ *   HV_IMG_ARGUMENT   out[j][p] = arg(sum_k spec[j][k][p]), in [-pi, pi]
+ * (for a one-bin range, |S_k| and arg(S_k)).  spec: device [nwin][nbins]
+ * [ny][nx] c64 -- the output of hv_stft_bins, or any range of its bins
+ * held contiguously; out: device [nwin][ny][nx] float32.  FP32 arithmetic.
+ * HV_ERR_ARG for an unknown kind or NULL pointers, HV_ERR_SHAPE for
+ * nwin outside [0, 65535] or non-positive sizes; nwin = 0 does nothing. */
+typedef enum { HV_IMG_MAGNITUDE = 0, HV_IMG_ARGUMENT = 1 } hv_image_kind;
+hv_status hv_bins_image(hv_ctx* ctx, const void* spec, int nwin, int nbins, int ny, int nx, int kind, float* out,
+                        void* hip_stream);
+
 /* ---------------------------------------------------------------- .holo files */
 
 /* The .holo file (Sec. IV, Holofile system) for file-mode replay: a 64-byte

@@ -170,6 +170,30 @@ __global__ void k_moving_average(const float* __restrict__ in, float* __restrict
   }
 }
 
+// Magnitude or argument image of the windowed spectrum over a range of
+// temporal indices (Sec. III-B.1): spec [J][nb][npix] c64 -> out [J][npix],
+// magnitude sum_k |S_k|, argument arg(sum_k S_k).  Lanes walk the pixels, so
+// every bin row is read once, coalesced.
+template <bool ARG>
+__global__ __launch_bounds__(CT) void k_bins_image(const float2* __restrict__ spec, int nb, long npix,
+                                                   float* __restrict__ out) {
+  const long j = blockIdx.y;
+  const float2* sj = spec + j * nb * npix;
+  for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < npix; p += (long)gridDim.x * blockDim.x) {
+    float mag = 0.f, re = 0.f, im = 0.f;
+    for (int k = 0; k < nb; ++k) {
+      const float2 v = sj[k * npix + p];
+      if (ARG) {
+        re += v.x;
+        im += v.y;
+      } else {
+        mag += hypotf(v.x, v.y);
+      }
+    }
+    out[j * npix + p] = ARG ? atan2f(im, re) : mag;
+  }
+}
+
 unsigned blocks_for(long n) { return (unsigned)std::min<long>((n + CT - 1) / CT, 4096); }
 
 hv_status launched(const char* what) {
@@ -273,4 +297,24 @@ extern "C" hv_status hv_postprocess(hv_ctx* ctx, const float* in, int count, int
   if (hipMemcpyAsync(out, cur, (size_t)total * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return fail(HV_ERR_DEVICE, "output copy failed");
   return HV_OK;
+}
+
+extern "C" hv_status hv_bins_image(hv_ctx* ctx, const void* spec, int nwin, int nbins, int ny, int nx, int kind,
+                                  float* out, void* hip_stream) {
+  using namespace hvi;
+  if (!ctx) return fail(HV_ERR_ARG, "NULL context");
+  if (kind != HV_IMG_MAGNITUDE && kind != HV_IMG_ARGUMENT) return fail(HV_ERR_ARG, "image kind %d", kind);
+  if (nwin < 0 || nwin > 65535 || nbins <= 0 || ny <= 0 || nx <= 0)
+    return fail(HV_ERR_SHAPE, "%d windows of %d bins of %dx%d", nwin, nbins, ny, nx);
+  if (nwin == 0) return HV_OK;
+  if (!spec || !out) return fail(HV_ERR_ARG, "NULL pointer");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
+  const long npix = (long)ny * nx;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const dim3 grid(blocks_for(npix), (unsigned)nwin);
+  if (kind == HV_IMG_ARGUMENT)
+    hipLaunchKernelGGL(k_bins_image<true>, grid, dim3(CT), 0, st, (const float2*)spec, nbins, npix, out);
+  else
+    hipLaunchKernelGGL(k_bins_image<false>, grid, dim3(CT), 0, st, (const float2*)spec, nbins, npix, out);
+  return launched("bins_image");
 }

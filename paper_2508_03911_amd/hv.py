@@ -23,6 +23,7 @@ HV_U8, HV_U16, HV_C64 = 0, 1, 3
 HV_AS, HV_FRESNEL = 0, 1
 HV_PREC_FP32, HV_PREC_MIXED = 0, 1
 HV_ORDER_AUTO, HV_ORDER_FRAMES_FIRST, HV_ORDER_BAND_FIRST = 0, 1, 2
+HV_IMG_MAGNITUDE, HV_IMG_ARGUMENT = 0, 1
 
 _STATUS_NAMES = {0: "HV_OK", -1: "HV_ERR_ARG", -2: "HV_ERR_SHAPE", -3: "HV_ERR_NOMEM", -4: "HV_ERR_BUDGET",
                  -5: "HV_ERR_DEVICE", -6: "HV_ERR_OVERFLOW", -7: "HV_ERR_STATE"}
@@ -113,6 +114,7 @@ _sig = {
     "hv_stft_bins": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P]),
     "hv_stft_volume": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _P, _P]),
     "hv_postprocess": (_I, [_P, _P, _I, _I, _I, C.POINTER(hv_post), _P, _P, _P]),
+    "hv_bins_image": (_I, [_P, _P, _I, _I, _I, _I, _I, _P, _P]),
     "hv_holo_read_header": (_I, [C.c_char_p, C.POINTER(hv_holo_header), C.POINTER(C.c_uint64)]),
     "hv_holo_read_frames": (_I, [C.c_char_p, C.c_int64, C.c_int64, _P]),
     "hv_holo_read_footer": (_I, [C.c_char_p, C.c_char_p, C.c_uint64]),
@@ -374,6 +376,18 @@ class Context:
         _check(lib.hv_postprocess(self.handle, _ptr(images), count, ny, nx, C.byref(cfg), _ptr(out), _ptr(shifts),
                                   _stream(images.device)))
         return out, shifts
+
+    def hv_bins_image(self, spec: torch.Tensor, kind: int, out=None) -> torch.Tensor:
+        """Magnitude (HV_IMG_MAGNITUDE: sum of moduli) or argument
+        (HV_IMG_ARGUMENT: argument of the sum) over the bins of a device
+        spectrum [J][nbins][ny][nx] complex64; returns [J][ny][nx] float32."""
+        if not spec.is_cuda or spec.dim() != 4 or spec.dtype != torch.complex64 or not spec.is_contiguous():
+            raise ValueError("spec must be a contiguous [J, nbins, ny, nx] complex64 device tensor")
+        j, nb, ny, nx = spec.shape
+        if out is None:
+            out = torch.empty((j, ny, nx), dtype=torch.float32, device=spec.device)
+        _check(lib.hv_bins_image(self.handle, _ptr(spec), j, nb, ny, nx, kind, _ptr(out), _stream(spec.device)))
+        return out
 
     def hv_stft_volume(self, x: torch.Tensor, optics: Optics | None, window: int, stride: int,
                        prec: int = HV_PREC_FP32, out=None) -> torch.Tensor:
