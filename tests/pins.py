@@ -243,3 +243,29 @@ def volume_errors(volume_fn, window=16, ny=3, nx=4):
     e = np.stack([(np.abs(r[j * window:(j + 1) * window]) ** 2).sum(axis=0) for j in range(3)])
     e_pars = float(np.max(np.abs(v.sum(axis=1) - window * e)) / np.max(window * e))
     return e_tone, e_pars
+
+
+# ---------------------------------------------------------------- magnitude / argument images
+
+def tone_image_errors(magnitude_fn, argument_fn, window=16, bins=(3, 5), shape=(3, 4), seed=4):
+    """Two tones a_i exp(2i pi k_i t / W) at every pixel have, in closed form,
+    the spectrum S_{k_i} = W a_i and zero elsewhere.  Over the range
+    k_1 .. k_2 the magnitude image is W (|a_1| + |a_2|) and the argument image
+    arg(a_1 + a_2); over k_1 alone, W |a_1| and arg(a_1).  Returns the largest
+    (magnitude, wrapped argument) errors over both ranges."""
+    rng = np.random.default_rng(seed)
+    a = [rng.standard_normal(shape) + 1j * rng.standard_normal(shape) for _ in bins]
+    spec = np.zeros((1, window) + shape, np.complex128)
+    for ai, k in zip(a, bins):
+        spec[0, k] = window * ai
+    both = list(range(bins[0], bins[1] + 1))
+    one = [bins[0]]
+
+    def wrap(d):
+        return np.abs(np.angle(np.exp(1j * d)))
+
+    em = max(np.max(np.abs(magnitude_fn(spec[:, both])[0] - window * (np.abs(a[0]) + np.abs(a[1])))),
+             np.max(np.abs(magnitude_fn(spec[:, one])[0] - window * np.abs(a[0]))))
+    ea = max(np.max(wrap(argument_fn(spec[:, both])[0] - np.angle(a[0] + a[1]))),
+             np.max(wrap(argument_fn(spec[:, one])[0] - np.angle(a[0]))))
+    return float(em), float(ea)

@@ -11,7 +11,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import optics, pca, temporal
+from oracle import optics, pca, post, temporal
 from tests import pins
 
 
@@ -183,3 +183,32 @@ def vol_reversed_bins(u, w, s):
 def test_volume_mutants_rejected(mutant):
     e_tone, e_pars = pins.volume_errors(mutant)
     assert max(e_tone, e_pars) > 1e-6
+
+
+# ---------------------------------------------------------------- magnitude / argument image mutants
+
+def img_modulus_of_sum(s):
+    return np.abs(np.asarray(s).sum(axis=1))
+
+
+def img_power_sum(s):
+    return (np.abs(np.asarray(s)) ** 2).sum(axis=1)
+
+
+def img_sum_of_angles(s):
+    return np.angle(np.asarray(s)).sum(axis=1)
+
+
+def img_conjugated_argument(s):
+    return -post.argument_image(s)
+
+
+@pytest.mark.parametrize("mag_fn, arg_fn", [
+    (img_modulus_of_sum, post.argument_image),
+    (img_power_sum, post.argument_image),
+    (post.magnitude_image, img_sum_of_angles),
+    (post.magnitude_image, img_conjugated_argument),
+])
+def test_image_mutants_rejected(mag_fn, arg_fn):
+    em, ea = pins.tone_image_errors(mag_fn, arg_fn)
+    assert max(em, ea) > 1e-6

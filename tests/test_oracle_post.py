@@ -3,6 +3,7 @@
 import numpy as np
 
 from oracle import post, temporal
+from tests import pins
 
 
 def test_delta_kernel_is_identity_and_box_on_constant():
@@ -79,3 +80,8 @@ def test_argument_rotates_with_a_global_phase():
     assert np.max(np.abs(d)) < 1e-12
     assert np.allclose(post.magnitude_image(s * np.exp(1j * phi)), post.magnitude_image(s))
     assert np.all(np.abs(a0) <= np.pi)
+
+
+def test_tone_image_pin():
+    em, ea = pins.tone_image_errors(post.magnitude_image, post.argument_image)
+    assert em < 1e-12 and ea < 1e-12
