@@ -30,7 +30,8 @@ Modules:
 * ``pca``       -- covariance, ordered eigendecomposition, projection energy.
 * ``pipeline``  -- the end-to-end compositions used by the tests.
 * ``autofocus`` -- the z-scan sharpness reference and the FP64 CNN.
-* ``stream``    -- windowing/counting rules of the multi-stream loop.
+* ``post``      -- magnitude and argument images, post-processing chain.
+* ``holo``      -- the .holo file layout.
 """
 
 from . import optics, temporal, pca, pipeline  # noqa: F401

@@ -269,3 +269,75 @@ def tone_image_errors(magnitude_fn, argument_fn, window=16, bins=(3, 5), shape=(
     ea = max(np.max(wrap(argument_fn(spec[:, both])[0] - np.angle(a[0] + a[1]))),
              np.max(wrap(argument_fn(spec[:, one])[0] - np.angle(a[0]))))
     return float(em), float(ea)
+
+
+# ---------------------------------------------------------------- post-processing helpers
+
+def disk_mask_errors(disk_fn):
+    """Count of wrong pixels of the registration mask on three grids whose
+    in-disk sets are derived by hand.  A disk of radius r centred on a lattice
+    point holds N(r) lattice points (Gauss's circle problem: N(2) = 13,
+    N(3) = 29).  The mask radius is ``mask_radius * min(nx, ny) / 2`` about
+    the centre pixel (ny/2, nx/2), boundary included:
+
+    * 8 x 8, mask_radius 0.5: r = 2 about (4, 4), all 13 points on the grid;
+    * 6 x 10, mask_radius 1.0: r = 3 about (3, 5); of the 29 points, (6, 5)
+      lies below the last row, so 28 remain;
+    * 8 x 12, mask_radius 0.1: r = 0.4, the centre pixel (4, 6) alone."""
+    def expect(ny, nx, cy, cx, r2):
+        m = np.zeros((ny, nx))
+        for y in range(ny):
+            for x in range(nx):
+                if (y - cy) ** 2 + (x - cx) ** 2 <= r2:
+                    m[y, x] = 1.0
+        return m
+
+    bad = 0
+    for (ny, nx, rad, count, cy, cx, r2) in ((8, 8, 0.5, 13, 4, 4, 4), (6, 10, 1.0, 28, 3, 5, 9),
+                                              (8, 12, 0.1, 1, 4, 6, 0)):
+        got = np.asarray(disk_fn(ny, nx, rad), np.float64)
+        bad += abs(int(round(got.sum())) - count)
+        bad += int(np.sum(got != expect(ny, nx, cy, cx, r2)))
+    return bad
+
+
+def gaussian_kernel_errors(gauss_fn, sigmas=(1.5, 0.4, 2.2)):
+    """A Gaussian of standard deviation sigma, g(i, j) proportional to
+    exp(-(i^2 + j^2) / (2 sigma^2)), truncated at 3 sigma and normalised:
+    the side is 2 ceil(3 sigma) + 1, the sum is 1, and the ratios to the
+    centre value are exp(-1/(2 sigma^2)) one step along an axis,
+    exp(-1/sigma^2) one step along the diagonal and exp(-5/(2 sigma^2)) at
+    (2, 1).  Returns the largest relative error (a wrong side counts as 1)."""
+    worst = 0.0
+    for s in sigmas:
+        g = np.asarray(gauss_fn(s), np.float64)
+        r = math.ceil(3 * s)
+        if g.shape != (2 * r + 1, 2 * r + 1):
+            return 1.0
+        c = g[r, r]
+        checks = [(g.sum(), 1.0), (g[r + 1, r] / c, math.exp(-1 / (2 * s * s))),
+                  (g[r, r - 1] / c, math.exp(-1 / (2 * s * s))),
+                  (g[r + 1, r + 1] / c, math.exp(-1 / (s * s))),
+                  (g[r - 2, r + 1] / c, math.exp(-5 / (2 * s * s)))]
+        for got, want in checks:
+            worst = max(worst, abs(got - want) / want)
+    return worst
+
+
+def convolution_shift_error(conv_fn, shift=(1, 2), size=5, shape=(2, 9, 11), seed=6):
+    """Convolution with a unit impulse displaced by (a, b) from the kernel
+    centre moves the image by +(a, b): (x * k)[i, j] = x[i - a, j - b], zero
+    where that falls outside the image.  A correlation would move it the
+    other way.  Returns the largest absolute error."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(shape)
+    k = np.zeros((size, size))
+    c = size // 2
+    k[c + shift[0], c + shift[1]] = 1.0
+    want = np.zeros_like(x)
+    a, b = shift
+    for i in range(shape[1]):
+        for j in range(shape[2]):
+            if 0 <= i - a < shape[1] and 0 <= j - b < shape[2]:
+                want[:, i, j] = x[:, i - a, j - b]
+    return float(np.max(np.abs(np.asarray(conv_fn(x, k)) - want)))

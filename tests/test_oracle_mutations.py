@@ -212,3 +212,73 @@ def img_conjugated_argument(s):
 def test_image_mutants_rejected(mag_fn, arg_fn):
     em, ea = pins.tone_image_errors(mag_fn, arg_fn)
     assert max(em, ea) > 1e-6
+
+
+# ---------------------------------------------------------------- post-processing helper mutants
+
+def disk_max_side(ny, nx, mask_radius):
+    """radius scaled by the longer side instead of the shorter"""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    r = mask_radius * max(nx, ny) / 2.0
+    return (((yy - ny / 2.0) ** 2 + (xx - nx / 2.0) ** 2) <= r * r).astype(np.float64)
+
+
+def disk_half_pixel_centre(ny, nx, mask_radius):
+    """centre at ((ny - 1) / 2, (nx - 1) / 2) instead of the centre pixel"""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    r = mask_radius * min(nx, ny) / 2.0
+    return (((yy - (ny - 1) / 2.0) ** 2 + (xx - (nx - 1) / 2.0) ** 2) <= r * r).astype(np.float64)
+
+
+def disk_open_boundary(ny, nx, mask_radius):
+    """boundary excluded"""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    r = mask_radius * min(nx, ny) / 2.0
+    return (((yy - ny / 2.0) ** 2 + (xx - nx / 2.0) ** 2) < r * r).astype(np.float64)
+
+
+@pytest.mark.parametrize("mutant", [disk_max_side, disk_half_pixel_centre, disk_open_boundary])
+def test_disk_mask_mutants_rejected(mutant):
+    assert pins.disk_mask_errors(mutant) > 0
+
+
+def gauss_sigma_squared(sigma):
+    """exp(-r^2 / sigma^2): the width of a Gaussian of std sigma / sqrt(2)"""
+    r = int(np.ceil(3 * sigma))
+    i = np.arange(-r, r + 1)
+    g = np.exp(-(i[:, None] ** 2 + i[None, :] ** 2) / (sigma * sigma))
+    return g / g.sum()
+
+
+def gauss_unnormalised(sigma):
+    r = int(np.ceil(3 * sigma))
+    i = np.arange(-r, r + 1)
+    return np.exp(-(i[:, None] ** 2 + i[None, :] ** 2) / (2.0 * sigma * sigma))
+
+
+def gauss_two_sigma_support(sigma):
+    """truncated at 2 sigma"""
+    r = int(np.ceil(2 * sigma))
+    i = np.arange(-r, r + 1)
+    g = np.exp(-(i[:, None] ** 2 + i[None, :] ** 2) / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+@pytest.mark.parametrize("mutant", [gauss_sigma_squared, gauss_unnormalised, gauss_two_sigma_support])
+def test_gaussian_kernel_mutants_rejected(mutant):
+    assert pins.gaussian_kernel_errors(mutant) > 1e-6
+
+
+def conv_as_correlation(images, kernel):
+    from scipy.signal import correlate2d
+    return np.stack([correlate2d(im, kernel, mode="same", boundary="fill") for im in np.asarray(images)])
+
+
+def conv_periodic(images, kernel):
+    from scipy.signal import convolve2d
+    return np.stack([convolve2d(im, kernel, mode="same", boundary="wrap") for im in np.asarray(images)])
+
+
+@pytest.mark.parametrize("mutant", [conv_as_correlation, conv_periodic])
+def test_convolution_mutants_rejected(mutant):
+    assert pins.convolution_shift_error(mutant) > 1e-6

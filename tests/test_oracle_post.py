@@ -85,3 +85,29 @@ def test_argument_rotates_with_a_global_phase():
 def test_tone_image_pin():
     em, ea = pins.tone_image_errors(post.magnitude_image, post.argument_image)
     assert em < 1e-12 and ea < 1e-12
+
+
+def test_disk_mask_pin():
+    assert pins.disk_mask_errors(post.disk_mask) == 0
+
+
+def test_gaussian_kernel_pin():
+    assert pins.gaussian_kernel_errors(post.gaussian_kernel) < 1e-12
+
+
+def test_convolution_orientation_pin():
+    assert pins.convolution_shift_error(post.convolve) < 1e-15
+
+
+def test_registration_with_a_disk_inside_the_image():
+    """A bright off-centre blob inside the mask, moved circularly: the shift
+    is recovered with a mask of half the image (the blob stays inside it)."""
+    ny, nx = 40, 56
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    base = np.exp(-((yy - 17.0) ** 2 + (xx - 31.0) ** 2) / 8.0) + 0.01
+    moves = [(0, 0), (2, -3), (-4, 5)]
+    stack = np.stack([np.roll(base, m, axis=(0, 1)) for m in moves])
+    out, shifts = post.register(stack, ref_count=1, mask_radius=0.5)
+    for j, (my, mx) in enumerate(moves):
+        assert tuple(shifts[j]) == (my % ny, mx % nx)
+        assert np.allclose(out[j], base)
