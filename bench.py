@@ -105,23 +105,70 @@ def kernel_profile(ctx, hv, torch, x, opt, tp, prec, outs, steps, frames):
     return res
 
 
-def cpu_baseline(block, spec, z, ctx, hv, torch, precision=None):
-    """The FP64 oracle on a bounded sample of the same workload (timed), and
-    the relative L2 error of both GPU forms against it on that sample; with
-    `precision` (from precision_case) also the errors of window 0 of the
-    1024 x 1024 Fresnel case, every output, both forms."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
+# ---------------------------------------------------------------- CPU baseline
+# The oracle runs in a pool of worker processes, one window range per task
+# (windows are independent).  The workers are forked before this process
+# touches the GPU and inherit the base block of the stream.
 
+_ORACLE = {}
+
+
+def _oracle_worker_init():
+    from threadpoolctl import threadpool_limits
+    _ORACLE["limits"] = threadpool_limits(1)  # one core per worker
+
+
+def _oracle_ready(_):
+    time.sleep(0.2)  # keep each worker busy so that every one answers
+    return os.getpid()
+
+
+def _oracle_windows(task):
+    """The oracle's moments of windows j0 .. j1-1 of the stream (the base
+    block replayed cyclically); returned only for windows of the first block
+    (the rest repeat them), None otherwise."""
     from oracle import pipeline
-    # the stream replays the base block, so three copies of it are its first
-    # 6,144 frames: about 12 s of oracle work on the 16-core host
-    sample = np.concatenate([block] * 3)
-    t0 = time.perf_counter()
-    ref = pipeline.stft_moments(sample, pipeline.Optics(852e-9, spec.pitch, spec.pitch, -z), W, W, spec.fs,
+    import numpy as np
+    j0, j1 = task
+    block, spec, z = _ORACLE["block"], _ORACLE["spec"], _ORACLE["z"]
+    per = block.shape[0] // W
+    frames = np.concatenate([block[(j % per) * W:(j % per + 1) * W] for j in range(j0, j1)])
+    ref = pipeline.stft_moments(frames, pipeline.Optics(852e-9, spec.pitch, spec.pitch, -z), W, W, spec.fs,
                                 3e3, 35e3)
+    if j0 >= per:
+        return None
+    return j0, {k: ref[k] for k in ("m0", "m1", "m2")}
+
+
+def oracle_pool(block, spec, z):
+    """Fork the oracle workers now (before any GPU call): one per core of
+    this process's CPU set, at most 16."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    _ORACLE.update(block=block, spec=spec, z=z)
+    n = max(1, min(16, len(os.sched_getaffinity(0))))
+    pool = cf.ProcessPoolExecutor(max_workers=n, mp_context=mp.get_context("fork"), initializer=_oracle_worker_init)
+    pids = set(pool.map(_oracle_ready, range(2 * n)))
+    return pool, n, len(pids)
+
+
+def cpu_baseline(pool, workers, frames, block, spec, z, ctx, hv, torch, precision=None):
+    """The FP64 oracle, unchanged, over the whole stream (every window of the
+    `frames`-frame stream, one window range per task across `workers`
+    processes, timed), and the relative L2 error of both GPU forms against
+    it on the first block; with `precision` (from precision_case) also the
+    errors of window 0 of the 1024 x 1024 Fresnel case, every output, both
+    forms."""
+    import numpy as np
+
+    nwin = frames // W
+    per = block.shape[0] // W
+    tasks = [(j, min(nwin, j + 16)) for j in range(0, nwin, 16)]
+    t0 = time.perf_counter()
+    parts = [r for r in pool.map(_oracle_windows, tasks) if r is not None]
     dt = time.perf_counter() - t0
-    blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    ref = {k: np.concatenate([p[1][k] for p in sorted(parts, key=lambda p: p[0])])[:per] for k in ("m0", "m1", "m2")}
+    sample = block
     opt = hv.Optics(852e-9, spec.pitch, spec.pitch, -z, hv.HV_AS)
     tp = hv.Temporal(W, W, spec.fs, 3e3, 35e3)
     xd = torch.from_numpy(sample).cuda()
@@ -133,9 +180,10 @@ def cpu_baseline(block, spec, z, ctx, hv, torch, precision=None):
             err[tag + name] = {k: float(np.linalg.norm(g - ref[k]) / np.linalg.norm(ref[k]))
                                for k, g in zip(("m0", "m1", "m2"), got)}
     ctx.set_stft_order(hv.HV_ORDER_FRAMES_FIRST)
-    res = {"value": sample.shape[0] / dt, "unit": "frames/s", "cores": int(blas), "kind": "oracle",
-           "sample": f"{sample.shape[0]} frames ({sample.shape[0] // W} windows) of the 256x256 stream, numpy float64; "
-                     f"FFTs single-threaded, BLAS {blas} threads", "seconds": dt,
+    res = {"value": nwin * W / dt, "unit": "frames/s", "cores": int(workers), "kind": "oracle",
+           "sample": f"the whole stream: {nwin * W} frames ({nwin} windows) of 256x256, numpy float64, "
+                     f"{workers} worker processes with one BLAS thread each, 16 windows per task; GPU errors on "
+                     f"the first {sample.shape[0]} frames (the rest repeat them)", "seconds": dt,
            "gpu_rel_l2_vs_oracle": err}
     if precision is not None:
         from oracle import optics as oopt, pca as opca, temporal as otemp
@@ -144,11 +192,14 @@ def cpu_baseline(block, spec, z, ctx, hv, torch, precision=None):
         bins, freqs = otemp.band_bins(w, ps.fs, 2 * ps.fs / w, 31 * ps.fs / w)
         mom = [mm[0] for mm in otemp.moments(otemp.stft(u, w, w), bins, freqs)]
         pr = opca.pca_window(u, 1, 63)
-        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        s_ref = otemp.stft(u, w, w)[0]
+        rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
         res["precision_case_window0_rel_l2"] = {
-            name: {"m0": rel(m[0], mom[0]), "m1": rel(m[1], mom[1]), "m2": rel(m[2], mom[2]),
-                   "pca_m0": rel(pm0, pr["m0"]), "eigvals": rel(ev, pr["eigvals"])}
-            for name, (m, pm0, ev) in precision["gpu"].items()}
+            name: {"spectrum_all_64_bins": rel(g["spectrum"], s_ref[g["bins"]]),
+                   "m0": rel(g["m"][0], mom[0]), "m1": rel(g["m"][1], mom[1]), "m2": rel(g["m"][2], mom[2]),
+                   "covariance": rel(g["cov"], pr["cov"]), "eigvals": rel(g["eigvals"], pr["eigvals"]),
+                   "pca_m0": rel(g["pca_m0"], pr["m0"])}
+            for name, g in precision["gpu"].items()}
     return res
 
 
@@ -377,8 +428,14 @@ def precision_case(hv, torch, steps):
                      "kernels": kern}
         log(f"precision case {name}: {out[name]}")
         m = [t[0].cpu().numpy().astype(np.float64) for t in stft()]
-        r = pca()
-        res_keep[name] = (m, r["m0"][0].cpu().numpy().astype(np.float64), r["eigvals"][0].cpu().numpy())
+        r = ctx.hv_pca(x[:w], opt, w, w, 1, 63, prec, want_eig=True, want_cov=True)
+        # every bin of window 0: the band [0, fs/2] taken on both sides
+        tp_all = hv.Temporal(w, w, fs, 0.0, fs / 2, True)
+        s_all = ctx.hv_stft_bins(x[:w], opt, tp_all, prec)[0].cpu().numpy()
+        res_keep[name] = {"m": m, "pca_m0": r["m0"][0].cpu().numpy().astype(np.float64),
+                          "eigvals": r["eigvals"][0].cpu().numpy(), "cov": r["cov"][0].cpu().numpy(),
+                          "spectrum": s_all, "bins": hv.band_bins(tp_all)[0]}
+        del s_all
     ctx.close()
     del x
     return out, {"block": block[:w], "spec": spec, "window": w, "gpu": res_keep}
@@ -579,6 +636,10 @@ def main():
     log(f"generated base block {block.shape} in {time.time() - t0:.1f}s (z = {spec.z:.4f} m)")
     reps = args.frames // block.shape[0]
     frames = reps * block.shape[0]
+    pool = None
+    if not args.no_cpu_baseline:
+        pool, workers, forked = oracle_pool(block, spec, spec.z)
+        log(f"oracle pool: {workers} workers ({forked} answered)")
     xb = torch.from_numpy(block).cuda()
     x = xb.repeat(reps, 1, 1).contiguous()  # the stream replays the base block cyclically
     del xb
@@ -676,8 +737,9 @@ def main():
         line["autofocus"] = autofocus(hv, torch, args.af_train, args.af_eval, args.af_epochs)
         log(f"autofocus: {line['autofocus']}")
     if not args.no_cpu_baseline:
-        log("timing the oracle on a sample ...")
-        line["cpu_baseline"] = cpu_baseline(block, spec, spec.z, ctx, hv, torch, precision)
+        log("timing the oracle over the stream ...")
+        line["cpu_baseline"] = cpu_baseline(pool, workers, frames, block, spec, spec.z, ctx, hv, torch, precision)
+        pool.shutdown()
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -227,10 +227,14 @@ hv_status hv_band_bins(const hv_temporal* temporal, int* nbins, int* bins, doubl
  *   m0       [J][ny][nx] float32
  *   eigvals  [J][W] float64, descending (nullable)
  *   cov      [J][W][W] complex float64 interleaved (nullable)
+ *   offdiag  [J] float64 (nullable): sqrt(sum of |off-diagonal|^2 / sum of
+ *            |all entries|^2) of the rotated matrix when the Jacobi solver
+ *            stopped: below 1e-15 when the window converged, larger when it
+ *            reached the sweep limit (40) first; the call does not fail then
  * 0 <= comp_lo <= comp_hi < W. */
 hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics, int window,
                  int stride, int comp_lo, int comp_hi, int prec, float* m0, double* eigvals, double* cov,
-                 void* hip_stream);
+                 double* offdiag, void* hip_stream);
 
 /* ---------------------------------------------------------------- serving loop */
 
@@ -254,6 +258,7 @@ typedef struct {
   int64_t latency_samples;
   int64_t lat_p50_ns, lat_p99_ns, lat_max_ns; /* image done - arrival of the window's last frame */
   int64_t admitted_bytes;     /* device bytes charged to open streams */
+  int64_t device_errors;      /* completion queries that reported a device error */
 } hv_stats;
 
 /* Open a stream of ny x nx frames (HV_U8 or HV_U16).  ring_frames must be a
@@ -268,7 +273,10 @@ hv_status hv_stream_open(hv_ctx* ctx, int ny, int nx, int raw_t, const hv_optics
  * every window they complete.  arrival_ns[i] (CLOCK_MONOTONIC ns, nullable =
  * now) is the arrival time of frame i, used for latency.  A packet that
  * would overwrite frames still needed returns HV_ERR_OVERFLOW and is counted
- * as dropped; nothing is overwritten silently. */
+ * as dropped; nothing is overwritten silently.  When a window launch fails,
+ * or the device reports an error for a launched window, the stream is
+ * marked failed: that push returns the launch error and every later push
+ * returns HV_ERR_STATE (not counted as drops) until the stream is closed. */
 hv_status hv_stream_push(hv_stream* s, const void* frames, int n_frames, const int64_t* arrival_ns);
 /* Oldest completed, unpopped window: copies its M0/M1/M2 (each ny*nx float32,
  * device pointers, nullable) and returns its timestamps.  HV_ERR_STATE when

@@ -438,7 +438,7 @@ static hv_status check_frame(int n, int ny, int nx) {
   return HV_OK;
 }
 
-static hv_status check_optics(const hv_optics* o) {
+hv_status hvi::check_optics(const hv_optics* o) {
   if (!o) return fail(HV_ERR_ARG, "optics is NULL");
   if (!(o->wavelength_m > 0) || !(o->pitch_x_m > 0) || !(o->pitch_y_m > 0) || !std::isfinite(o->z_m))
     return fail(HV_ERR_ARG, "wavelength and pitches must be positive, z finite");
@@ -475,6 +475,20 @@ static float fp16_field_scale(int in_t, int ny, int nx) {
   return (float)std::ldexp(1.0, -k);
 }
 
+// Power-of-two scale of the row-pass output when spectra are stored as fp16.
+// After the row transform |X| <= nx * maxv; the angular-spectrum column pass
+// is unitary along y, so one column can gather into a single value of at
+// most sqrt(ny) * nx * maxv (a coherent full-scale input).  The scale keeps
+// that below 32768 (fp16 max 65504): 1/nx for 8-bit frames at every side up
+// to 1280, and 2^-k / nx for 16-bit frames (k = 6 at ny = 1024).
+static float fp16_row_scale(int in_t, int ny, int nx) {
+  const double maxv = in_t == HV_U16 ? 65535.0 : 255.0;
+  const double bound = std::sqrt((double)ny) * maxv;
+  int k = 0;
+  while (bound * std::ldexp(1.0, -k) > 32768.0) ++k;
+  return (float)(std::ldexp(1.0, -k) / nx);
+}
+
 // ---------------------------------------------------------------- spatial driver
 
 namespace hvi {
@@ -494,7 +508,7 @@ hv_status spatial(Ctx* c, const void* in, int in_t, int nf, int ny, int nx, cons
                   bool want_field, float f_scale, hipStream_t st, SpatialOut& out) {
   const size_t cplx = mixed ? 4 : 8;
   const size_t frame = (size_t)ny * nx;
-  const float s1 = mixed ? (in_t == HV_U16 ? 1.0f / (16.0f * nx) : 1.0f / nx) : 1.0f;
+  const float s1 = mixed ? fp16_row_scale(in_t, ny, nx) : 1.0f;
   out.half = mixed;
   out.f_scale = f_scale;
   hv_status s;
@@ -664,7 +678,7 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
       if (!p) return s;
       DevBuf& tb = ctx->work(st, 0);
       if ((s = tb.ensure((size_t)nf * frame * (mix ? 4 : 8), &ctx->held))) return s;
-      const float s1 = mix ? (in_t == HV_U16 ? 1.0f / (16.0f * nx) : 1.0f / nx) : 1.0f;
+      const float s1 = mix ? fp16_row_scale(in_t, ny, nx) : 1.0f;
       const float2* q = (const float2*)p->tables.ptr;
       if ((s = launch_rows_c2c(src, in_t, tb.ptr, mix, q, q + nx, dir, nf, ny, nx, s1, st))) return s;
       const float unit = (float)(1.0 / std::sqrt((double)nx * ny));
@@ -717,7 +731,8 @@ static hv_status stft_band_first(Ctx* ctx, const void* in, int in_t, int ny, int
   const size_t per_win = (size_t)nb * frame * (mixed ? 4 : 8);
   // fp16 storage: values scaled so that the worst case (every camera value
   // at full scale, coherent) stays below the fp16 maximum through the passes
-  const float s1 = in_t == HV_U16 ? 1.0f / (16.0f * nx) : 1.0f / nx;
+  // (a bin sums W frames, hence the extra 1/W)
+  const float s1 = fp16_row_scale(in_t, ny, nx);
   const float sc = mixed ? s1 / w : 1.0f;
   const float amp = 1.0f / (nx * sc);
   Ctx::Lane2* l2 = nullptr;
@@ -1013,9 +1028,13 @@ hv_status hv_stft_volume(hv_ctx* ctx, const void* in, int in_t, int n, int ny, i
   return res;
 }
 
+// Sweep limit of the FP64 Jacobi eigensolver (cyclic sweeps converge
+// quadratically; W = 64 windows of camera data take well under 20).
+static constexpr int kJacobiSweeps = 40;
+
 hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics, int window,
                  int stride, int comp_lo, int comp_hi, int prec, float* m0, double* eigvals, double* cov,
-                 void* hip_stream) {
+                 double* offdiag, void* hip_stream) {
   hv_status s;
   if ((s = enter(ctx))) return s;
   std::lock_guard<std::recursive_mutex> lock(ctx->mu);
@@ -1119,7 +1138,8 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
       if ((s = launch_gram_reduce((const float*)x.part, g_n, nblk, w, 1.0 / ((double)fs * fs), (double*)x.cv, st)))
         return s;
       if ((s = timed(ctx, "jacobi", st, [&] {
-             return launch_jacobi((const double*)x.cv, g_n, w, (double*)x.ev, (double*)x.vec, 40, st);
+             return launch_jacobi((const double*)x.cv, g_n, w, (double*)x.ev, (double*)x.vec,
+                                  offdiag ? offdiag + j0 : nullptr, kJacobiSweeps, st);
            })))
         return s;
       if ((s = launch_proj_coefs((const double*)x.vec, g_n, w, comp_lo, comp_hi, mtiles, (float*)x.a32,

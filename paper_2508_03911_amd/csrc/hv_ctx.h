@@ -57,6 +57,9 @@ struct DftPlan {
 };
 
 int band_bins(const hv_temporal& tp, std::vector<int>& bins, std::vector<double>& freqs);
+// Positive wavelength and pitches, finite z, a known method, z != 0 for
+// Fresnel, a high-pass radius in [0, 1) and only with the angular spectrum.
+hv_status check_optics(const hv_optics* o);
 const char* last_error();
 
 struct ServeState;  // serving loop (stream.cpp)

@@ -94,8 +94,10 @@ hv_status launch_gram_partials(const void* u, bool half_in, long npix, int strid
 hv_status launch_gram_reduce(const float* part, int nwin, int nblk, int window, double cscale, double* cov,
                              hipStream_t st);
 // FP64 cyclic Jacobi on each window's C: eigenvalues (descending) and
-// eigenvectors (columns, complex f64 interleaved) [nwin][W][W].
-hv_status launch_jacobi(const double* cov, int nwin, int window, double* evals, double* evecs,
+// eigenvectors (columns, complex f64 interleaved) [nwin][W][W]; offdiag
+// (nullable) [nwin] receives sqrt(off-diagonal / total squared magnitude)
+// when the window stops (converged below 1e-15, or max_sweeps reached).
+hv_status launch_jacobi(const double* cov, int nwin, int window, double* evals, double* evecs, double* offdiag,
                         int max_sweeps, hipStream_t st);
 // Build per-window projection coefficient fragments from eigenvectors
 // columns c1..c2 (A = [Vr^T Vi^T ; ...]) for the coefficient GEMM.

@@ -72,7 +72,7 @@ struct ServeState {
   std::thread poller;
   std::atomic<bool> stop{false};
   std::atomic<int64_t> frames_in{0}, frames_dropped{0}, windows_done{0}, admitted{0}, refused{0},
-      images_overwritten{0};
+      images_overwritten{0}, device_errors{0};
   std::atomic<int64_t> lat_after_ns{0};  // latencies of windows whose last frame arrived before are ignored
   size_t admitted_bytes = 0;
   hvs::LatencyLog lat;
@@ -110,6 +110,20 @@ static int drain(ServeState* sv, hv_stream* s, bool wait) {
     }
     hipError_t q = wait ? hipEventSynchronize(p.ev) : hipEventQuery(p.ev);
     if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) {
+      // a device error: these windows are not complete and are not timed;
+      // the stream is marked failed so pushes report it
+      (void)hipGetLastError();
+      s->ring.set_failed();
+      sv->device_errors++;
+      {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->pending.pop_front();
+      }
+      (void)hipEventDestroy(p.ev);
+      ++n;
+      continue;
+    }
     const int64_t t_done = now_ns();
     const int64_t after = sv->lat_after_ns.load();
     {
@@ -192,15 +206,22 @@ static hv_status launch_ready(hv_stream* s) {
       hv_status st = hvi_stft_common(s->ctx, src, s->raw_t, nf, s->ny, s->nx, &s->optics, &s->tp, s->prec,
                                      s->out_dev[0] + (size_t)os * npix, s->out_dev[1] + (size_t)os * npix,
                                      s->out_dev[2] + (size_t)os * npix, nullptr, s->st);
-      if (st) return st;
+      if (st) {
+        s->ring.abandon(g);
+        return st;
+      }
       j += run;
       left -= run;
       slot += run * s->tp.stride;
     }
     hipEvent_t ev = sv->take_event();
-    if (!ev) return fail(HV_ERR_DEVICE, "could not create a completion event");
+    if (!ev) {
+      s->ring.abandon(g);
+      return fail(HV_ERR_DEVICE, "could not create a completion event");
+    }
     if (hipEventRecord(ev, s->st) != hipSuccess) {
       sv->give_event(ev);
+      s->ring.abandon(g);
       return fail(HV_ERR_DEVICE, "event record failed: %s", hipGetErrorString(hipGetLastError()));
     }
     std::lock_guard<std::mutex> lk(s->mu);
@@ -228,8 +249,17 @@ hv_status hv_stream_open(hv_ctx* ctx, int ny, int nx, int raw_t, const hv_optics
   if (ring_frames % s || ring_frames < 2 * w)
     return fail(HV_ERR_ARG, "ring_frames must be a multiple of the stride and >= 2 W");
   if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
-  if (optics->method != HV_AS && optics->method != HV_FRESNEL) return fail(HV_ERR_ARG, "unknown method");
-  if (optics->method == HV_FRESNEL && optics->z_m == 0.0) return fail(HV_ERR_ARG, "Fresnel needs z != 0");
+  {
+    hv_status e = check_optics(optics);
+    if (e) return e;
+  }
+  if (!(temporal->fs_hz > 0)) return fail(HV_ERR_ARG, "fs must be positive");
+  {
+    // the band must keep at least one bin (the same check as the offline call)
+    std::vector<int> bins;
+    std::vector<double> freqs;
+    if (band_bins(*temporal, bins, freqs) <= 0) return fail(HV_ERR_ARG, "the band holds no bin");
+  }
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   ServeState* sv = serve(ctx);
   const int group = std::max(1, std::min(8, ring_frames / (2 * s)));
@@ -330,7 +360,10 @@ hv_status hv_stream_push(hv_stream* s, const void* frames, int n_frames, const i
   std::lock_guard<std::mutex> lk(s->push_mu);
   std::vector<hvs::Span> copies;
   const int64_t first = s->ring.pushed();
-  if (!s->ring.push(n_frames, arrival_ns, now_ns(), copies)) {
+  const hvs::RingLogic::Push pr = s->ring.push(n_frames, arrival_ns, now_ns(), copies);
+  if (pr == hvs::RingLogic::Push::failed)
+    return fail(HV_ERR_STATE, "stream failed on an earlier launch or device error; close it");
+  if (pr == hvs::RingLogic::Push::full) {
     sv->frames_dropped += n_frames;
     return fail(HV_ERR_OVERFLOW, "ring full: %d frames refused", n_frames);
   }
@@ -412,7 +445,7 @@ hv_status hv_stream_close(hv_stream* s) {
                                  s->optics.z_m, s->optics.method == HV_AS ? s->optics.highpass_cpp : 0.0);
       auto ia = ctx->as_plans.find(key);
       if (s->optics.method == HV_AS && ia != ctx->as_plans.end()) {
-        ctx->held -= ia->second->ht.bytes;
+        ctx->held -= ia->second->ht.bytes + ia->second->hs.bytes;
         dead_as.push_back(std::move(ia->second));
         ctx->as_plans.erase(ia);
       }
@@ -462,6 +495,7 @@ hv_status hv_ctx_stats(hv_ctx* ctx, hv_stats* out) {
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     out->admitted_bytes = (int64_t)sv->admitted_bytes;
   }
+  out->device_errors = sv->device_errors;
   return HV_OK;
 }
 
@@ -476,6 +510,7 @@ hv_status hv_ctx_stats_reset(hv_ctx* ctx) {
   sv->admitted = 0;
   sv->refused = 0;
   sv->images_overwritten = 0;
+  sv->device_errors = 0;
   return HV_OK;
 }
 

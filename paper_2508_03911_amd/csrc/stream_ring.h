@@ -44,17 +44,21 @@ class RingLogic {
   int mirror_frames() const { return W_ - S_; }
   int slots_total() const { return R_ + W_ - S_; }
 
+  enum class Push { ok, full, failed };
+
   // Reserve n frames; on success returns the spans to copy (primary and
-  // mirror) and records the arrival times.  Returns false (and counts the
-  // drop) when the ring has no room.
-  bool push(int n, const int64_t* arrival_ns, int64_t now_ns, std::vector<Span>& copies) {
+  // mirror) and records the arrival times.  Returns full (and counts the
+  // drop) when the ring has no room, failed (nothing counted) once the
+  // stream has been marked failed.
+  Push push(int n, const int64_t* arrival_ns, int64_t now_ns, std::vector<Span>& copies) {
     std::lock_guard<std::mutex> g(mu_);
     copies.clear();
-    if (n <= 0) return true;
+    if (failed_) return Push::failed;
+    if (n <= 0) return Push::ok;
     const int64_t need_from = done_windows_ * S_;
     if (pushed_ + n - need_from > R_) {
       dropped_ += n;
-      return false;
+      return Push::full;
     }
     int64_t f = pushed_;
     int left = n;
@@ -73,13 +77,15 @@ class RingLogic {
     for (int i = 0; i < n; ++i) arrival_[(pushed_ + i) % R_] = arrival_ns ? arrival_ns[i] : now_ns;
     pushed_ += n;
     accepted_ += n;
-    return true;
+    return Push::ok;
   }
 
   // Complete windows not yet launched, grouped so that a group never crosses
-  // the end of the ring and holds at most max_group windows.
+  // the end of the ring and holds at most max_group windows.  Nothing is
+  // handed out once the stream has failed.
   bool take_ready(WindowGroup& out) {
     std::lock_guard<std::mutex> g(mu_);
+    if (failed_) return false;
     const int64_t complete = pushed_ >= W_ ? (pushed_ - W_) / S_ + 1 : 0;
     if (launched_ >= complete) return false;
     const int slot = (int)((launched_ * S_) % R_);
@@ -109,6 +115,22 @@ class RingLogic {
     if (first == done_windows_) done_windows_ += count;
   }
 
+  // The launch of group g (the last one taken) could not be issued: its
+  // windows go back to "not launched" and the stream is marked failed, so
+  // later pushes are refused as a failed stream instead of being counted
+  // as drops of a ring that would never drain.
+  void abandon(const WindowGroup& grp) {
+    std::lock_guard<std::mutex> g(mu_);
+    if (launched_ == grp.first_window + grp.count) launched_ = grp.first_window;
+    failed_ = true;
+  }
+  // A device error was reported for work already launched.
+  void set_failed() {
+    std::lock_guard<std::mutex> g(mu_);
+    failed_ = true;
+  }
+  bool failed() const { std::lock_guard<std::mutex> g(mu_); return failed_; }
+
   int64_t pushed() const { std::lock_guard<std::mutex> g(mu_); return pushed_; }
   int64_t dropped() const { std::lock_guard<std::mutex> g(mu_); return dropped_; }
   int64_t launched() const { std::lock_guard<std::mutex> g(mu_); return launched_; }
@@ -124,6 +146,7 @@ class RingLogic {
   std::vector<int64_t> arrival_;
   int64_t pushed_ = 0, accepted_ = 0, dropped_ = 0;
   int64_t launched_ = 0, done_windows_ = 0;
+  bool failed_ = false;
 };
 
 // Latency samples with percentiles (nearest-rank).

@@ -502,7 +502,8 @@ __device__ inline double jacobi_sum(double v, double* red) {
 template <int W>
 __global__ __launch_bounds__(jacobi_threads<W>()) void k_jacobi(const double* __restrict__ cov,
                                                                 double* __restrict__ evals,
-                                                                double* __restrict__ evecs, int max_sweeps) {
+                                                                double* __restrict__ evecs,
+                                                                double* __restrict__ offdiag, int max_sweeps) {
   constexpr int JT = jacobi_threads<W>();
   constexpr int WP = W + 1;  // padded row stride
   __shared__ dc A[W * WP];
@@ -521,8 +522,10 @@ __global__ __launch_bounds__(jacobi_threads<W>()) void k_jacobi(const double* __
     V[r * WP + c] = {r == c ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // convergence: off-diagonal energy relative to the total
+  for (int sweep = 0;; ++sweep) {
+    // convergence: off-diagonal energy relative to the total; at exit the
+    // ratio sqrt(off / total) is reported, so a window that reached the
+    // sweep limit unconverged is visible to the caller
     double off = 0.0, tot = 0.0;
     for (int i = tid; i < W * W; i += JT) {
       const int r = i / W, c = i % W;
@@ -533,7 +536,10 @@ __global__ __launch_bounds__(jacobi_threads<W>()) void k_jacobi(const double* __
     }
     const double off_all = jacobi_sum<W>(off, red);
     const double tot_all = jacobi_sum<W>(tot, red);
-    if (!(off_all > 1e-30 * tot_all)) break;
+    if (!(off_all > 1e-30 * tot_all) || sweep >= max_sweeps) {
+      if (offdiag && tid == 0) offdiag[jj] = tot_all > 0 ? sqrt(off_all / tot_all) : 0.0;
+      break;
+    }
     for (int step = 0; step < W - 1; ++step) {
       if (tid < W / 2) {
         const int k = tid;
@@ -828,18 +834,21 @@ hv_status launch_gram_reduce(const float* part, int nwin, int nblk, int window, 
   return launched("gram_reduce");
 }
 
-hv_status launch_jacobi(const double* cov, int nwin, int window, double* evals, double* evecs, int max_sweeps,
-                        hipStream_t st) {
+hv_status launch_jacobi(const double* cov, int nwin, int window, double* evals, double* evecs, double* offdiag,
+                        int max_sweeps, hipStream_t st) {
   if (nwin <= 0) return HV_OK;
   switch (window) {
     case 16:
-      hipLaunchKernelGGL(k_jacobi<16>, dim3(nwin), dim3(jacobi_threads<16>()), 0, st, cov, evals, evecs, max_sweeps);
+      hipLaunchKernelGGL(k_jacobi<16>, dim3(nwin), dim3(jacobi_threads<16>()), 0, st, cov, evals, evecs, offdiag,
+                         max_sweeps);
       break;
     case 32:
-      hipLaunchKernelGGL(k_jacobi<32>, dim3(nwin), dim3(jacobi_threads<32>()), 0, st, cov, evals, evecs, max_sweeps);
+      hipLaunchKernelGGL(k_jacobi<32>, dim3(nwin), dim3(jacobi_threads<32>()), 0, st, cov, evals, evecs, offdiag,
+                         max_sweeps);
       break;
     case 64:
-      hipLaunchKernelGGL(k_jacobi<64>, dim3(nwin), dim3(jacobi_threads<64>()), 0, st, cov, evals, evecs, max_sweeps);
+      hipLaunchKernelGGL(k_jacobi<64>, dim3(nwin), dim3(jacobi_threads<64>()), 0, st, cov, evals, evecs, offdiag,
+                         max_sweeps);
       break;
     default: return fail(HV_ERR_SHAPE, "PCA window %d not supported", window);
   }

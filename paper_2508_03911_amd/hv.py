@@ -69,7 +69,8 @@ class hv_temporal(C.Structure):
 class hv_stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "frames_in", "frames_dropped", "windows_done", "streams_admitted", "streams_refused",
-        "images_overwritten", "latency_samples", "lat_p50_ns", "lat_p99_ns", "lat_max_ns", "admitted_bytes")]
+        "images_overwritten", "latency_samples", "lat_p50_ns", "lat_p99_ns", "lat_max_ns", "admitted_bytes",
+        "device_errors")]
 
 
 HV_REPLAY_MAX_CLASSES = 4
@@ -144,7 +145,7 @@ _sig = {
     "hv_af_predict": (_I, [_P, _P, _I, C.c_double, C.c_double, C.c_float, _P, _P, _P, C.POINTER(_I), _P]),
     "hv_af_synthesize": (_I, [_P, _I, C.POINTER(C.c_double), C.c_double, C.c_double, C.c_uint64, C.c_int64, _P,
                               _P]),
-    "hv_pca": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _I, _I, _P, _P, _P, _P]),
+    "hv_pca": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(lib, _name)
@@ -411,11 +412,12 @@ class Context:
         m0 = torch.empty((j, ny, nx), dtype=torch.float32, device=x.device)
         ev = torch.empty((j, window), dtype=torch.float64, device=x.device) if want_eig else None
         cov = torch.empty((j, window, window), dtype=torch.complex128, device=x.device) if want_cov else None
+        off = torch.empty((j,), dtype=torch.float64, device=x.device)
         op = optics.c() if optics is not None else None
         _check(lib.hv_pca(self.handle, _ptr(x), _dtype_code(x), n, ny, nx, C.byref(op) if op is not None else None,
-                          window, stride, comp_lo, comp_hi, prec, _ptr(m0), _ptr(ev), _ptr(cov),
+                          window, stride, comp_lo, comp_hi, prec, _ptr(m0), _ptr(ev), _ptr(cov), _ptr(off),
                           _stream(x.device)))
-        return {"m0": m0, "eigvals": ev, "cov": cov}
+        return {"m0": m0, "eigvals": ev, "cov": cov, "offdiag": off}
 
 
     # ---------------------------------------------------------------- serving loop

@@ -15,6 +15,7 @@
 using hvs::RingLogic;
 using hvs::Span;
 using hvs::WindowGroup;
+using Push = hvs::RingLogic::Push;
 
 static int failures = 0;
 #define CHECK(c)                                                   \
@@ -50,7 +51,7 @@ static void test_contiguity(int R, int W, int S, int G) {
   int64_t windows = 0, refused = 0;
   for (int it = 0; it < 400; ++it) {
     const int n = 1 + (int)(rng() % (unsigned)(S + 5));
-    if (!r.push(n, nullptr, it, copies)) {
+    if (r.push(n, nullptr, it, copies) != Push::ok) {
       refused += n;
       // drain everything launched, then retry
       WindowGroup g;
@@ -59,7 +60,7 @@ static void test_contiguity(int R, int W, int S, int G) {
         r.mark_done(g.first_window, g.count);
         windows += g.count;
       }
-      CHECK(r.push(n, nullptr, it, copies));
+      CHECK(r.push(n, nullptr, it, copies) == Push::ok);
     }
     fr.apply(copies);
     if (rng() % 3 == 0) {
@@ -86,19 +87,19 @@ static void test_contiguity(int R, int W, int S, int G) {
 static void test_overflow_counted() {
   RingLogic r(32, 16, 16, 2);
   std::vector<Span> c;
-  CHECK(!r.push(40, nullptr, 0, c));  // larger than the ring
+  CHECK(r.push(40, nullptr, 0, c) == Push::full);  // larger than the ring
   CHECK(r.dropped() == 40 && r.pushed() == 0);
-  CHECK(r.push(32, nullptr, 0, c));
-  CHECK(!r.push(1, nullptr, 0, c));  // nothing consumed yet
+  CHECK(r.push(32, nullptr, 0, c) == Push::ok);
+  CHECK(r.push(1, nullptr, 0, c) == Push::full);  // nothing consumed yet
   CHECK(r.dropped() == 41);
   WindowGroup g;
   CHECK(r.take_ready(g) && g.first_window == 0 && g.count == 2);
-  CHECK(!r.push(1, nullptr, 0, c));  // launched but not done: still needed
+  CHECK(r.push(1, nullptr, 0, c) == Push::full);  // launched but not done: still needed
   r.mark_done(0, 1);
-  CHECK(r.push(16, nullptr, 0, c));  // window 0's frames are free now
-  CHECK(!r.push(1, nullptr, 0, c));
+  CHECK(r.push(16, nullptr, 0, c) == Push::ok);  // window 0's frames are free now
+  CHECK(r.push(1, nullptr, 0, c) == Push::full);
   r.mark_done(1, 1);
-  CHECK(r.push(16, nullptr, 0, c));
+  CHECK(r.push(16, nullptr, 0, c) == Push::ok);
   CHECK(r.dropped() == 43);
 }
 
@@ -107,7 +108,7 @@ static void test_arrival_and_percentiles() {
   std::vector<Span> c;
   std::vector<int64_t> arr(24);
   for (int i = 0; i < 24; ++i) arr[i] = 1000 + i;
-  CHECK(r.push(24, arr.data(), 0, c));
+  CHECK(r.push(24, arr.data(), 0, c) == Push::ok);
   WindowGroup g;
   CHECK(r.take_ready(g) && g.first_window == 0 && g.count == 2);
   CHECK(r.window_arrival(0) == 1015 && r.window_arrival(1) == 1023 && g.last_arrival_ns == 1023);
@@ -141,7 +142,7 @@ static void test_threads(bool slow) {
         bool ok;
         {
           std::lock_guard<std::mutex> g(fr_mu);
-          ok = r.push(n, nullptr, it, c);
+          ok = r.push(n, nullptr, it, c) == Push::ok;
           if (ok) {
             fr.apply(c);
             accepted += n;
@@ -183,6 +184,30 @@ static void test_threads(bool slow) {
   else CHECK(r.pushed() == accepted.load() && accepted.load() > 0);
 }
 
+// A launch that cannot be issued: the group goes back to "not launched",
+// the stream is marked failed, and later pushes report the failure without
+// being counted as drops; nothing more is handed to the executor.
+static void test_launch_failure() {
+  RingLogic r(64, 16, 16, 2);
+  std::vector<Span> c;
+  CHECK(r.push(32, nullptr, 0, c) == Push::ok);
+  WindowGroup g;
+  CHECK(r.take_ready(g) && g.first_window == 0 && g.count == 2);
+  CHECK(r.launched() == 2);
+  r.abandon(g);
+  CHECK(r.failed() && r.launched() == 0);
+  CHECK(r.push(16, nullptr, 0, c) == Push::failed);
+  CHECK(r.dropped() == 0 && r.pushed() == 32);
+  CHECK(!r.take_ready(g));
+  // a device error on work already in flight also stops the stream
+  RingLogic q(64, 16, 16, 2);
+  CHECK(q.push(16, nullptr, 0, c) == Push::ok);
+  CHECK(q.take_ready(g) && g.count == 1);
+  q.set_failed();
+  CHECK(q.push(16, nullptr, 0, c) == Push::failed && q.dropped() == 0);
+  CHECK(!q.take_ready(g));
+}
+
 int main() {
   test_contiguity(64, 16, 16, 4);
   test_contiguity(48, 16, 8, 3);
@@ -191,6 +216,7 @@ int main() {
   test_contiguity(128, 32, 1, 8);
   test_overflow_counted();
   test_arrival_and_percentiles();
+  test_launch_failure();
   test_threads(false);
   test_threads(true);
   RingLogic bad_cfg(50, 16, 16, 1);

@@ -90,6 +90,73 @@ def _stream_vs_offline(ctx, hv, prec, method, stride):
             assert np.array_equal(got[j][k], ref[k][j]), (j, k)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("cls", [1, 2])
+def test_stream_class_equals_offline(ctx, hv, cls, prec):
+    """The larger serving classes: 512^2 u8 with W = 32 and 1024 x 512
+    (nx x ny) 12-bit u16 with W = stride = 64; every popped image equals the
+    offline call on the same frames bit for bit."""
+    ny, nx, bits, fs, w, _ = holograms.STREAM_CLASSES[cls]
+    say(f"stream class {cls}: {nx}x{ny} {bits}-bit W={w} prec={prec}")
+    n = 3 * w + 7
+    x, spec = holograms.stream_block(cls, 5, frames=n)
+    xd = torch.from_numpy(x).cuda()
+    opt = hv.Optics(LAM, spec.pitch, spec.pitch, -spec.z, hv.HV_AS)
+    tp = hv.Temporal(w, w, fs, 2 * fs / w, (w // 2 - 1) * fs / w)
+    ref = [t.cpu().numpy() for t in ctx.hv_stft_moments(xd, opt, tp, prec)]
+    j_total = ref[0].shape[0]
+    s = ctx.hv_stream_open(ny, nx, xd.dtype, opt, tp, prec, ring_frames=4 * w)
+    got = []
+    pos, i = 0, 0
+    sizes = [8, 13, 5, 16, 1]
+    while pos < n:
+        k = min(sizes[i % len(sizes)], n - pos)
+        s.push(xd[pos:pos + k])
+        pos += k
+        i += 1
+        _wait_and_pop(s, 0 if pos < w else (pos - w) // w + 1, got, ny, nx)
+    c = s.counters()
+    s.close()
+    assert c["pushed"] == n and c["dropped"] == 0 and c["windows_done"] == j_total == 3
+    assert len(got) == j_total
+    for j in range(j_total):
+        for k in range(3):
+            assert np.array_equal(got[j][k], ref[k][j]), (j, k)
+
+
+def test_stream_open_checks_optics(ctx, hv):
+    say("stream open: optics and band checks")
+    tp = hv.Temporal(16, 16, 20e3, 1e3, 9e3)
+    bad = [hv.Optics(-LAM, 20e-6, 20e-6, -0.2), hv.Optics(LAM, 0.0, 20e-6, -0.2),
+           hv.Optics(LAM, 20e-6, 20e-6, -0.2, hv.HV_FRESNEL, highpass=0.1),
+           hv.Optics(LAM, 20e-6, 20e-6, -0.2, hv.HV_AS, highpass=1.5)]
+    for opt in bad:
+        with pytest.raises(hv.HvError) as e:
+            ctx.hv_stream_open(64, 64, torch.uint8, opt, tp)
+        assert e.value.status == hv.HV_ERR_ARG
+    with pytest.raises(hv.HvError) as e:  # a band with no bin
+        ctx.hv_stream_open(64, 64, torch.uint8, hv.Optics(LAM, 20e-6, 20e-6, -0.2),
+                           hv.Temporal(16, 16, 20e3, 9.1e3, 9.2e3))
+    assert e.value.status == hv.HV_ERR_ARG
+
+
+def test_stream_close_returns_table_bytes(hv):
+    """Opening and closing an angular-spectrum stream twice leaves the
+    context's held bytes where the first close left them (both transfer
+    tables are returned)."""
+    say("stream close: held bytes")
+    c = hv.Context(0)
+    opt = hv.Optics(LAM, 20e-6, 20e-6, -0.23)
+    tp = hv.Temporal(16, 16, 20e3, 1e3, 9e3)
+    held = []
+    for _ in range(2):
+        s = c.hv_stream_open(128, 128, torch.uint8, opt, tp)
+        s.close()
+        held.append(c.workspace_bytes())
+    c.close()
+    assert held[0] == held[1]
+
+
 def test_stream_overflow_is_refused(ctx, hv):
     say("stream overflow")
     opt = hv.Optics(LAM, 20e-6, 20e-6, -0.2)
