@@ -28,10 +28,11 @@ Modules:
 * ``optics``    -- unpack, angular spectrum, single-FFT Fresnel transform.
 * ``temporal``  -- STFT windows, band-to-bin mapping, Doppler moments.
 * ``pca``       -- covariance, ordered eigendecomposition, projection energy.
+* ``ssa``       -- the SSA + FFT path: components c1..c2 of each window, then the STFT.
 * ``pipeline``  -- the end-to-end compositions used by the tests.
 * ``autofocus`` -- the z-scan sharpness reference and the FP64 CNN.
 * ``post``      -- magnitude and argument images, post-processing chain.
 * ``holo``      -- the .holo file layout.
 """
 
-from . import optics, temporal, pca, pipeline  # noqa: F401
+from . import optics, temporal, pca, ssa, pipeline  # noqa: F401

@@ -17,6 +17,7 @@ import numpy as np
 
 from . import optics as _optics
 from . import pca as _pca
+from . import ssa as _ssa
 from . import temporal as _temporal
 
 AS = 0
@@ -102,4 +103,23 @@ def stft_volume(frames, opt: Optics | None, window: int, stride: int) -> np.ndar
         u = reconstruct(frames[j * stride: j * stride + window], opt)
         s = _temporal.stft(u, window, window)[0]
         out[j] = s.real ** 2 + s.imag ** 2
+    return out
+
+
+def ssa_render(frames, opt: Optics | None, window: int, stride: int, fs: float, f_lo: float, f_hi: float,
+               c1: int = 1, c2: int | None = None, symmetric: bool = False, keep_spectrum: bool = False):
+    """SSA + FFT path: every window reconstructed, filtered by its components
+    c1..c2 (covariance, eigenpairs, projection and back), transformed in
+    time, reduced to the moments over the band."""
+    frames = np.asarray(frames)
+    j_count = _temporal.n_windows(frames.shape[0], window, stride)
+    res = []
+    for j in range(j_count):
+        u = reconstruct(frames[j * stride: j * stride + window], opt)
+        res.append(_ssa.ssa_moments(u, window, window, fs, f_lo, f_hi, c1, c2, symmetric, keep_spectrum))
+    if not res:
+        return _ssa.ssa_moments(np.zeros((0,) + frames.shape[1:], np.complex128), window, stride, fs, f_lo, f_hi,
+                                c1, c2, symmetric, keep_spectrum)
+    out = {k: np.concatenate([r[k] for r in res]) for k in res[0] if k not in ("bins", "freqs")}
+    out["bins"], out["freqs"] = res[0]["bins"], res[0]["freqs"]
     return out

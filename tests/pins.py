@@ -341,3 +341,51 @@ def convolution_shift_error(conv_fn, shift=(1, 2), size=5, shape=(2, 9, 11), see
             if 0 <= i - a < shape[1] and 0 <= j - b < shape[2]:
                 want[:, i, j] = x[:, i - a, j - b]
     return float(np.max(np.abs(np.asarray(conv_fn(x, k)) - want)))
+
+
+# ---------------------------------------------------------------- SSA + FFT
+
+def _orthogonal_pixel_vectors(shape, count, norms, seed):
+    """`count` complex pixel images, mutually orthogonal (as vectors over the
+    pixels), with the given norms (Gram-Schmidt on random draws)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        v = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+        for o in out:
+            v = v - np.vdot(o, v) / np.vdot(o, o) * o
+        out.append(v / np.linalg.norm(v) * norms[i])
+    return out
+
+
+def ssa_tone_errors(ssa_stft_fn, window=16, shape=(5, 6), seed=21):
+    """Closed forms of the filter's action on windows whose components are
+    known.  A window u_t = b + a_1 e^{2i pi k_1 t/W} + a_2 e^{2i pi k_2 t/W}
+    with pixel images b, a_1, a_2 mutually orthogonal and
+    |b| > |a_1| > |a_2| has exactly three non-zero eigenpairs of C = X^H X:
+    W|b|^2 (the constant time vector), W|a_1|^2 (tone k_1) and W|a_2|^2
+    (tone k_2), the time vectors being orthogonal over a whole window.  So
+    the spectrum S of the filtered window is, in closed form:
+
+    * components 0..W-1 (everything): S_0 = W b, S_k1 = W a_1, S_k2 = W a_2;
+    * components 1..W-1 (the static part removed): S_k1 = W a_1, S_k2 = W a_2;
+    * component 1 alone: S_k1 = W a_1;   component 0 alone: S_0 = W b;
+    * components 2..W-1: S_k2 = W a_2;
+    every other bin zero.  Returns the largest error over the five ranges,
+    relative to W |b|."""
+    k1, k2 = 3, 11
+    b, a1, a2 = _orthogonal_pixel_vectors(shape, 3, (3.0, 2.0, 1.0), seed)
+    t = np.arange(window)[:, None, None]
+    u = (b[None] + a1[None] * np.exp(2j * np.pi * k1 * t / window)
+         + a2[None] * np.exp(2j * np.pi * k2 * t / window))
+    cases = [((0, window - 1), {0: b, k1: a1, k2: a2}), ((1, window - 1), {k1: a1, k2: a2}),
+             ((1, 1), {k1: a1}), ((0, 0), {0: b}), ((2, window - 1), {k2: a2})]
+    worst = 0.0
+    scale = window * np.linalg.norm(b)
+    for (c1, c2), want in cases:
+        s = np.asarray(ssa_stft_fn(u, c1, c2))
+        ref = np.zeros((window,) + shape, np.complex128)
+        for k, amp in want.items():
+            ref[k] = window * amp
+        worst = max(worst, float(np.linalg.norm((s - ref).ravel()) / scale))
+    return worst

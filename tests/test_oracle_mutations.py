@@ -282,3 +282,33 @@ def conv_periodic(images, kernel):
 @pytest.mark.parametrize("mutant", [conv_as_correlation, conv_periodic])
 def test_convolution_mutants_rejected(mutant):
     assert pins.convolution_shift_error(mutant) > 1e-6
+
+
+# ---------------------------------------------------------------- SSA + FFT mutants
+
+def _ssa_variant(u, c1, c2, how):
+    from oracle import pca as opca
+    w = u.shape[0]
+    x = opca.window_matrix(u)
+    lam, v = opca.eig_descending(opca.covariance(x))
+    if how == "ascending":
+        v = v[:, ::-1]
+    vs = v[:, c1:c2] if how == "exclusive" else v[:, c1:c2 + 1]
+    if how == "no_conj":
+        xf = x @ vs @ vs.T
+    elif how == "spectrum_filtered":
+        s = temporal.stft(u, w, w)[0]
+        sm = opca.window_matrix(s)
+        return (sm @ vs @ vs.conj().T).T.reshape(u.shape)
+    elif how == "conj_cov":
+        lam2, v2 = opca.eig_descending(opca.covariance(x).conj())
+        vs = v2[:, c1:c2 + 1]
+        xf = x @ vs @ vs.conj().T
+    else:
+        xf = x @ vs @ vs.conj().T
+    return temporal.stft(xf.T.reshape(u.shape), w, w)[0]
+
+
+@pytest.mark.parametrize("how", ["ascending", "exclusive", "no_conj", "spectrum_filtered", "conj_cov"])
+def test_ssa_mutants_rejected(how):
+    assert pins.ssa_tone_errors(lambda u, c1, c2: _ssa_variant(u, c1, c2, how)) > 1e-6
