@@ -183,6 +183,29 @@ hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, 
                           const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
                           void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * moments as hv_stft_moments, same arguments, layout and results, with
+ * every workspace taken from a static device array of the library (256 MiB,
+ * one copy per GPU, held until the process ends) instead of allocated.  The
+ * call allocates nothing and creates no stream or event:
+ *   - the transfer-function or chirp tables and the DFT coefficients must
+ *     already be in the context: one call of hv_stft_moments (or
+ *     hv_stft_bins) with the same frame shape, optics and temporal settings
+ *     builds them; otherwise HV_ERR_STATE;
+ *   - it always takes the per-frame order on hip_stream alone, in chunks of
+ *     as many windows as the scratch holds;
+ *   - a shape whose single window needs more than 256 MiB of workspace
+ *     (ny*nx*W*(1.5 or 2)*(8 FP32 or 4 mixed) bytes; 1024 x 1024 FP32 at
+ *     W = 32 is one) returns HV_ERR_SHAPE.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (two host threads, or two streams whose work overlaps) race and
+ * corrupt each other's results; serialise them.  Nothing in the scratch
+ * needs clearing: every workspace byte is written before it is read. */
+hv_status hv_stft_moments_noalloc(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx,
+                                  const hv_optics* optics, const hv_temporal* temporal, int prec, float* m0,
+                                  float* m1, float* m2, void* hip_stream);
+
 /* hv_stft_moments from host memory (the paper's camera path: frames arrive
  * in host memory and cross PCIe, Sec. II-B.4, VII).  host_in is pinned host
  * memory (hipHostMalloc) [n][ny][nx] HV_U8/HV_U16; host_m0..m2 are pinned

@@ -259,11 +259,16 @@ static hv_status build_dft_plan(size_t* held, DftPlan& p) {
 // float64 tables of a large frame take milliseconds), so a stream being
 // opened never stalls the launches of the streams already running.
 template <class Map, class Key, class Make>
-static auto* plan_lookup(Ctx* c, Map& m, const Key& key, Make make, hv_status* st) {
+static auto* plan_lookup(Ctx* c, Map& m, const Key& key, Make make, hv_status* st, bool build) {
   {
     std::lock_guard<std::recursive_mutex> lk(c->mu);
     auto it = m.find(key);
     if (it != m.end()) return it->second.get();
+  }
+  if (!build) {
+    *st = fail(HV_ERR_STATE, "no plan for these settings in the context: one call of the allocating entry point "
+                             "with the same frame shape, optics and temporal settings builds it");
+    return (decltype(make(nullptr, nullptr).get())) nullptr;
   }
   size_t bytes = 0;
   auto p = make(&bytes, st);
@@ -277,7 +282,7 @@ static auto* plan_lookup(Ctx* c, Map& m, const Key& key, Make make, hv_status* s
   return raw;
 }
 
-AsPlan* Ctx::as_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
+AsPlan* Ctx::as_plan(int ny, int nx, const hv_optics& o, hv_status* st, bool build) {
   auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m, o.highpass_cpp);
   return plan_lookup(this, as_plans, key, [&](size_t* bytes, hv_status* e) {
     auto p = std::make_unique<AsPlan>();
@@ -291,10 +296,10 @@ AsPlan* Ctx::as_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
     *e = build_as_table(bytes, *p);
     if (*e) p.reset();
     return p;
-  }, st);
+  }, st, build);
 }
 
-FresnelPlan* Ctx::fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st) {
+FresnelPlan* Ctx::fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st, bool build) {
   auto key = std::make_tuple(ny, nx, o.wavelength_m, o.pitch_x_m, o.pitch_y_m, o.z_m, 0.0);
   return plan_lookup(this, fr_plans, key, [&](size_t* bytes, hv_status* e) {
     auto p = std::make_unique<FresnelPlan>();
@@ -307,10 +312,10 @@ FresnelPlan* Ctx::fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st
     *e = build_fresnel_tables(bytes, *p);
     if (*e) p.reset();
     return p;
-  }, st);
+  }, st, build);
 }
 
-DftPlan* Ctx::dft_plan(const hv_temporal& tp, hv_status* st) {
+DftPlan* Ctx::dft_plan(const hv_temporal& tp, hv_status* st, bool build) {
   std::vector<int> bins;
   std::vector<double> freqs;
   band_bins(tp, bins, freqs);
@@ -328,7 +333,7 @@ DftPlan* Ctx::dft_plan(const hv_temporal& tp, hv_status* st) {
     *e = build_dft_plan(bytes, *p);
     if (*e) p.reset();
     return p;
-  }, st);
+  }, st, build);
 }
 
 Ctx::~Ctx() {
@@ -496,6 +501,14 @@ namespace hvi {
 // Spatial transform of nf frames starting at `in` into either the AS column
 // output Z (as_z_only, real AS input: row inverse left to the caller) or the
 // field F.  Returns the buffers used through zbuf/fbuf.
+// Fixed workspaces for the entry point that allocates nothing: regions of
+// the library's static device scratch, one per workspace slot.
+struct FixedWs {
+  static constexpr int kSlots = 3;
+  void* ptr[kSlots];
+  size_t cap[kSlots];
+};
+
 struct SpatialOut {
   void* z = nullptr;   // [nf][ny][nx] after the AS column pass (AS only)
   void* f = nullptr;   // [nf][ny][nx] field
@@ -504,62 +517,126 @@ struct SpatialOut {
   float f_scale = 1.f;     // stored field = f_scale * U
 };
 
+// A workspace of `bytes` for `slot`: the context's per-stream buffer (grown
+// on demand), or, for the entry point that allocates nothing, a fixed region
+// of the library's static device scratch (too small: HV_ERR_SHAPE).
+static hv_status ws_get(Ctx* c, hipStream_t st, int slot, size_t bytes, const FixedWs* fixed, void** out) {
+  if (fixed) {
+    if (slot < 0 || slot >= FixedWs::kSlots || bytes > fixed->cap[slot])
+      return fail(HV_ERR_SHAPE, "workspace slot %d needs %zu bytes, the fixed scratch holds %zu", slot, bytes,
+                  slot >= 0 && slot < FixedWs::kSlots ? fixed->cap[slot] : (size_t)0);
+    *out = fixed->ptr[slot];
+    return HV_OK;
+  }
+  DevBuf& b = c->work(st, slot);
+  hv_status s = b.ensure(bytes, &c->held);
+  if (s) return s;
+  *out = b.ptr;
+  return HV_OK;
+}
+
+// A launch, timed by events when timing is on, untimed with fixed
+// workspaces (that path creates no events).
+template <class F>
+static hv_status run(Ctx* c, const char* name, hipStream_t st, const FixedWs* fixed, F&& f) {
+  return fixed ? f() : timed(c, name, st, std::forward<F>(f));
+}
+
 hv_status spatial(Ctx* c, const void* in, int in_t, int nf, int ny, int nx, const hv_optics& o, bool mixed,
-                  bool want_field, float f_scale, hipStream_t st, SpatialOut& out) {
+                  bool want_field, float f_scale, hipStream_t st, SpatialOut& out, const FixedWs* fixed = nullptr) {
   const size_t cplx = mixed ? 4 : 8;
   const size_t frame = (size_t)ny * nx;
   const float s1 = mixed ? fp16_row_scale(in_t, ny, nx) : 1.0f;
+  const bool build = fixed == nullptr;
   out.half = mixed;
   out.f_scale = f_scale;
   hv_status s;
   if (o.method == HV_AS) {
-    AsPlan* p = c->as_plan(ny, nx, o, &s);
+    AsPlan* p = c->as_plan(ny, nx, o, &s, build);
     if (!p) return s;
-    DevBuf& zb = c->work(st, 1);
-    if ((s = zb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
+    void *zb = nullptr, *tb = nullptr;
+    if ((s = ws_get(c, st, 1, (size_t)nf * frame * cplx, fixed, &zb))) return s;
     if (in_t == HV_C64 || !pow2_in(nx, 64, 1024) || !pow2_in(ny, 64, 1024)) {
       // complex rows (no real-input packing), full columns: any supported side
-      DevBuf& tb = c->work(st, 0);
-      if ((s = tb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
-      if ((s = timed(c, "rows_c2c", st, [&] { return launch_rows_c2c(in, in_t, tb.ptr, mixed, nullptr, nullptr, -1, nf, ny, nx, s1, st); }))) return s;
-      if ((s = timed(c, "col_full", st, [&] { return launch_col_full(tb.ptr, zb.ptr, mixed, p->ht_ptr(), nf, ny, nx, st); }))) return s;
+      if ((s = ws_get(c, st, 0, (size_t)nf * frame * cplx, fixed, &tb))) return s;
+      if ((s = run(c, "rows_c2c", st, fixed, [&] { return launch_rows_c2c(in, in_t, tb, mixed, nullptr, nullptr, -1, nf, ny, nx, s1, st); }))) return s;
+      if ((s = run(c, "col_full", st, fixed, [&] { return launch_col_full(tb, zb, mixed, p->ht_ptr(), nf, ny, nx, st); }))) return s;
     } else {
-      DevBuf& tb = c->work(st, 0);
-      if ((s = tb.ensure((size_t)nf * (frame / 2) * cplx, &c->held))) return s;
-      if ((s = timed(c, "row_r2c", st, [&] { return launch_row_r2c(in, (hv_dtype)in_t, tb.ptr, mixed, nf, ny, nx, s1, st); }))) return s;
-      if ((s = timed(c, "col_as", st, [&] { return launch_col_as(tb.ptr, zb.ptr, mixed, p->hs_ptr(), nf, ny, nx, st); }))) return s;
+      if ((s = ws_get(c, st, 0, (size_t)nf * (frame / 2) * cplx, fixed, &tb))) return s;
+      if ((s = run(c, "row_r2c", st, fixed, [&] { return launch_row_r2c(in, (hv_dtype)in_t, tb, mixed, nf, ny, nx, s1, st); }))) return s;
+      if ((s = run(c, "col_as", st, fixed, [&] { return launch_col_as(tb, zb, mixed, p->hs_ptr(), nf, ny, nx, st); }))) return s;
     }
-    out.z = zb.ptr;
+    out.z = zb;
     out.z_to_field = 1.0f / (nx * s1);
     if (want_field) {
-      DevBuf& fb = c->work(st, 2);
-      if ((s = fb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
-      if ((s = timed(c, "row_inv", st, [&] { return launch_row_inv(zb.ptr, mixed, fb.ptr, mixed, nf, ny, nx, out.z_to_field * f_scale, st); }))) return s;
-      out.f = fb.ptr;
+      void* fb = nullptr;
+      if ((s = ws_get(c, st, 2, (size_t)nf * frame * cplx, fixed, &fb))) return s;
+      if ((s = run(c, "row_inv", st, fixed, [&] { return launch_row_inv(zb, mixed, fb, mixed, nf, ny, nx, out.z_to_field * f_scale, st); }))) return s;
+      out.f = fb;
     }
     return HV_OK;
   }
-  FresnelPlan* p = c->fresnel_plan(ny, nx, o, &s);
+  FresnelPlan* p = c->fresnel_plan(ny, nx, o, &s, build);
   if (!p) return s;
   const int dir = o.z_m > 0 ? -1 : +1;
-  DevBuf& tb = c->work(st, 0);
-  if ((s = tb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
-  DevBuf& fb = c->work(st, 2);
-  if ((s = fb.ensure((size_t)nf * frame * cplx, &c->held))) return s;
+  void *tb = nullptr, *fb = nullptr;
+  if ((s = ws_get(c, st, 0, (size_t)nf * frame * cplx, fixed, &tb))) return s;
+  if ((s = ws_get(c, st, 2, (size_t)nf * frame * cplx, fixed, &fb))) return s;
   const float2* q = (const float2*)p->tables.ptr;
-  if ((s = timed(c, "fresnel_rows", st, [&] { return launch_rows_c2c(in, in_t, tb.ptr, mixed, q, q + nx, dir, nf, ny, nx, s1, st); })))
+  if ((s = run(c, "fresnel_rows", st, fixed, [&] { return launch_rows_c2c(in, in_t, tb, mixed, q, q + nx, dir, nf, ny, nx, s1, st); })))
     return s;
   const float unit = (float)(1.0 / std::sqrt((double)nx * ny));
-  if ((s = timed(c, "fresnel_cols", st, [&] {
-         return launch_fresnel_cols(tb.ptr, mixed, fb.ptr, mixed, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
+  if ((s = run(c, "fresnel_cols", st, fixed, [&] {
+         return launch_fresnel_cols(tb, mixed, fb, mixed, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
                                     unit / s1 * f_scale, st);
        })))
     return s;
-  out.f = fb.ptr;
+  out.f = fb;
   return HV_OK;
 }
 
 }  // namespace hvi
+
+// ---------------------------------------------------------------- static scratch
+
+// Static device scratch of hv_stft_moments_noalloc.  In host code the name
+// `scratch` is a host-side stand-in, not a device address: the address of
+// each GPU's copy is taken once per device by hipGetSymbolAddress at
+// context creation (that device current), kept in g_scratch, and used
+// wherever host code needs the array.
+static constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+struct ScratchAddr {
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+std::mutex g_scratch_mu;
+std::map<int, ScratchAddr> g_scratch;  // device -> its copy of the scratch
+}  // namespace
+
+static void scratch_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch.count(device) && g_scratch[device].ptr) return;
+  ScratchAddr a;
+  a.err = hipGetSymbolAddress(&a.ptr, HIP_SYMBOL(scratch));
+  if (a.err != hipSuccess) {
+    (void)hipGetLastError();
+    a.ptr = nullptr;
+  }
+  g_scratch[device] = a;
+}
+
+static hv_status scratch_of(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(device);
+  if (it == g_scratch.end() || !it->second.ptr)
+    return fail(HV_ERR_DEVICE, "the static scratch of device %d could not be located: %s", device,
+                it == g_scratch.end() ? "no context was created on it" : hipGetErrorString(it->second.err));
+  *out = it->second.ptr;
+  return HV_OK;
+}
 
 // ---------------------------------------------------------------- C-ABI
 
@@ -586,6 +663,8 @@ hv_status hv_ctx_create(int device, size_t hbm_budget_bytes, hv_ctx** out) {
     const int o = std::atoi(e);
     if (o == HV_ORDER_AUTO || o == HV_ORDER_FRAMES_FIRST || o == HV_ORDER_BAND_FIRST) c->stft_order = o;
   }
+  // the device address of this device's static scratch (no-allocation entry point)
+  scratch_setup(device);
   *out = c;
   return HV_OK;
 }
@@ -775,6 +854,39 @@ static hv_status stft_band_first(Ctx* ctx, const void* in, int in_t, int ny, int
   return res;
 }
 
+// One chunk of the frames-first order: windows j0 .. j0 + g_n - 1 of the
+// call (frames from j0 * stride), spatial passes then the temporal GEMM with
+// the moment epilogue; outputs at window j0 of m0/m1/m2/spec.
+static hv_status frames_first_chunk(Ctx* ctx, const void* in, int in_t, int ny, int nx, const hv_optics& o,
+                                    const CoefGemm& g, int nb, int w, int stride, int j0, int g_n, bool mixed,
+                                    float* m0, float* m1, float* m2, float2* spec, hipStream_t st,
+                                    const FixedWs* fixed) {
+  hv_status s;
+  const size_t frame = (size_t)ny * nx;
+  const float fsc = mixed ? fp16_field_scale(in_t, ny, nx) : 1.f;
+  const int nf = (g_n - 1) * stride + w;
+  const char* src = (const char*)in + (size_t)j0 * stride * frame * in_elem(in_t);
+  float* o0 = m0 ? m0 + (size_t)j0 * frame : nullptr;
+  float* o1 = m1 ? m1 + (size_t)j0 * frame : nullptr;
+  float* o2 = m2 ? m2 + (size_t)j0 * frame : nullptr;
+  float2* os = spec ? spec + (size_t)j0 * nb * frame : nullptr;
+  const bool fused = o.method == HV_AS && rowinv_coef_fits(nx, w);
+  SpatialOut so;
+  if ((s = spatial(ctx, src, in_t, nf, ny, nx, o, mixed, !fused, fsc, st, so, fixed))) return s;
+  if (fused) {
+    // B = z_to_field * IDFT_x(z) * bsc with bsc keeping fp16 in range
+    const float bsc = mixed ? so.z_to_field * fsc : 1.f;
+    const float amp = mixed ? 1.f / fsc : so.z_to_field;
+    return run(ctx, "rowinv_coef", st, fixed, [&] {
+      return launch_rowinv_coef(so.z, so.half, ny, nx, stride, g_n, g, mixed, bsc, amp, o0, o1, o2, os, st);
+    });
+  }
+  return run(ctx, "field_coef", st, fixed, [&] {
+    return launch_field_coef(so.f, so.half, (long)frame, stride, g_n, g, mixed, 1.f, 1.f / so.f_scale, o0, o1, o2,
+                             os, st);
+  });
+}
+
 // Shared driver of hv_stft_moments and hv_stft_bins.
 static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
                            const hv_temporal* tp, int prec, float* m0, float* m1, float* m2, float2* spec,
@@ -837,7 +949,6 @@ static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny,
   const int chunk = ctx->chunk_frames_for(ny, nx, mixed);
   int gw = chunk >= w ? (chunk - w) / stride + 1 : 1;
   if (gw < 1) gw = 1;
-  const float fsc = mixed ? fp16_field_scale(in_t, ny, nx) : 1.f;
   // Chunks alternate between the caller's stream and a second one (per-kernel
   // timing events, when on, bracket each launch on its own stream and so
   // time it as it runs beside the other stream's work).
@@ -850,35 +961,9 @@ static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny,
   const hipStream_t caller = st;
   for (int j0 = 0, c = 0; j0 < nwin_total && res == HV_OK; j0 += gw, ++c) {
     st = (l2 && (c & 1)) ? l2->s : caller;
-    res = [&]() -> hv_status {
     const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
-    const int f0 = j0 * stride;
-    const int nf = (g_n - 1) * stride + w;
-    const char* src = (const char*)in + (size_t)f0 * frame * in_elem(in_t);
-    float* o0 = m0 ? m0 + (size_t)j0 * frame : nullptr;
-    float* o1 = m1 ? m1 + (size_t)j0 * frame : nullptr;
-    float* o2 = m2 ? m2 + (size_t)j0 * frame : nullptr;
-    float2* os = spec ? spec + (size_t)j0 * nb * frame : nullptr;
-    const bool fused = optics->method == HV_AS && rowinv_coef_fits(nx, w);
-    SpatialOut so;
-    if ((s = spatial(ctx, src, in_t, nf, ny, nx, *optics, mixed, !fused, fsc, st, so))) return s;
-    if (fused) {
-      // B = z_to_field * IDFT_x(z) * bsc with bsc keeping fp16 in range
-      const float bsc = mixed ? so.z_to_field * fsc : 1.f;
-      const float amp = mixed ? 1.f / fsc : so.z_to_field;
-      if ((s = timed(ctx, "rowinv_coef", st, [&] {
-             return launch_rowinv_coef(so.z, so.half, ny, nx, stride, g_n, g, mixed, bsc, amp, o0, o1, o2, os, st);
-           })))
-        return s;
-    } else {
-      if ((s = timed(ctx, "field_coef", st, [&] {
-             return launch_field_coef(so.f, so.half, (long)frame, stride, g_n, g, mixed, 1.f, 1.f / so.f_scale, o0,
-                                      o1, o2, os, st);
-           })))
-        return s;
-    }
-    return HV_OK;
-    }();
+    res = frames_first_chunk(ctx, in, in_t, ny, nx, *optics, g, nb, w, stride, j0, g_n, mixed, m0, m1, m2, spec, st,
+                             nullptr);
   }
   if (l2) {  // join, also after an error, so no work of this call outlives it on the second stream
     const hv_status j = l2->join_into(caller);
@@ -891,6 +976,82 @@ hv_status hv_stft_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, 
                           const hv_temporal* temporal, int prec, float* m0, float* m1, float* m2,
                           void* hip_stream) {
   return stft_impl(ctx, in, in_t, n, ny, nx, optics, temporal, prec, m0, m1, m2, nullptr, hip_stream, true);
+}
+
+// ---------------------------------------------------------------- the entry point that allocates nothing
+
+hv_status hv_stft_moments_noalloc(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx,
+                                  const hv_optics* optics, const hv_temporal* tp, int prec, float* m0, float* m1,
+                                  float* m2, void* hip_stream) {
+  hv_status s;
+  if ((s = enter(ctx))) return s;
+  std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+  if ((s = check_frame(n, ny, nx))) return s;
+  if (!tp) return fail(HV_ERR_ARG, "temporal is NULL");
+  const int w = tp->window, stride = tp->stride;
+  if (w != 8 && w != 16 && w != 32 && w != 64) return fail(HV_ERR_SHAPE, "window %d: use 8, 16, 32 or 64", w);
+  if (stride <= 0) return fail(HV_ERR_ARG, "stride must be positive");
+  if (!(tp->fs_hz > 0)) return fail(HV_ERR_ARG, "fs must be positive");
+  if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
+  if (optics) {
+    if ((s = check_optics(optics)) || (s = check_dtype(in_t, true))) return s;
+  } else if (in_t != HV_C64) {
+    return fail(HV_ERR_ARG, "without optics the input must be a field (HV_C64)");
+  }
+  if (n < w) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, w);
+  if (!in) return fail(HV_ERR_ARG, "input is NULL");
+  if (!m0 && !m1 && !m2) return fail(HV_ERR_ARG, "no output requested");
+  DftPlan* dp = ctx->dft_plan(*tp, &s, false);
+  if (!dp) return s;
+  const int nwin_total = (n - w) / stride + 1;
+  const bool mixed = prec == HV_PREC_MIXED;
+  const size_t frame = (size_t)ny * nx;
+  hipStream_t st = (hipStream_t)hip_stream;
+  CoefGemm g{w, dp->mtiles, (int)dp->bins.size(), (const float*)dp->a32.ptr, (const hv_h8*)dp->a16hi.ptr,
+             (const hv_h8*)dp->a16lo.ptr, (const float*)dp->wts.ptr, 3};
+  const int nb = (int)dp->bins.size();
+  if (!optics) {  // a field in memory: the temporal kernel alone, no workspace
+    const float bsc = mixed ? fp16_field_scale(HV_C64, ny, nx) : 1.f;
+    return launch_field_coef(in, false, (long)frame, stride, nwin_total, g, mixed, bsc, mixed ? 1.f / bsc : 1.f, m0,
+                             m1, m2, nullptr, st);
+  }
+  void* base = nullptr;
+  if ((s = scratch_of(ctx->device, &base))) return s;
+  // bytes per frame of the three workspaces of the frames-first order (the
+  // same sizes the spatial passes ask for)
+  const size_t cplx = mixed ? 4 : 8;
+  const bool as = optics->method == HV_AS;
+  const bool real_rows = as && in_t != HV_C64 && pow2_in(nx, 64, 1024) && pow2_in(ny, 64, 1024);
+  const bool fused = as && rowinv_coef_fits(nx, w);
+  const size_t per[3] = {real_rows ? frame / 2 * cplx : frame * cplx, as ? frame * cplx : 0,
+                         fused ? 0 : frame * cplx};
+  const size_t per_frame = per[0] + per[1] + per[2];
+  auto fits = [&](long frames) {
+    size_t used = 0;
+    for (size_t b : per) used += (b * (size_t)frames + 255) / 256 * 256;
+    return used <= kScratchBytes;
+  };
+  if (!fits(w))
+    return fail(HV_ERR_SHAPE,
+                "one window of %d frames of %dx%d needs %zu bytes of workspace; the fixed scratch holds %zu", w, nx,
+                ny, per_frame * (size_t)w, kScratchBytes);
+  int gw = 1;
+  while (gw < nwin_total && fits((long)gw * stride + w)) ++gw;  // windows per chunk
+  const long nf_max = (long)(gw - 1) * stride + w;
+  FixedWs fx{};
+  char* at = (char*)base;
+  for (int k = 0; k < FixedWs::kSlots; ++k) {
+    fx.ptr[k] = at;
+    fx.cap[k] = per[k] * (size_t)nf_max;
+    at += (fx.cap[k] + 255) / 256 * 256;
+  }
+  for (int j0 = 0; j0 < nwin_total; j0 += gw) {
+    const int g_n = nwin_total - j0 < gw ? nwin_total - j0 : gw;
+    if ((s = frames_first_chunk(ctx, in, in_t, ny, nx, *optics, g, nb, w, stride, j0, g_n, mixed, m0, m1, m2,
+                                nullptr, st, &fx)))
+      return s;
+  }
+  return HV_OK;
 }
 
 hv_status hv_stft_bins(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,

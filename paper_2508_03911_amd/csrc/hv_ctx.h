@@ -119,9 +119,11 @@ struct Ctx {
   Ctx& operator=(const Ctx&) = delete;
   ~Ctx();
   Lane2* lane2(hipStream_t caller, hv_status* st);
-  AsPlan* as_plan(int ny, int nx, const hv_optics& o, hv_status* st);
-  FresnelPlan* fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st);
-  DftPlan* dft_plan(const hv_temporal& tp, hv_status* st);
+  // Plans are built on first use; with build = false a missing plan is an
+  // HV_ERR_STATE error instead (nothing is allocated).
+  AsPlan* as_plan(int ny, int nx, const hv_optics& o, hv_status* st, bool build = true);
+  FresnelPlan* fresnel_plan(int ny, int nx, const hv_optics& o, hv_status* st, bool build = true);
+  DftPlan* dft_plan(const hv_temporal& tp, hv_status* st, bool build = true);
   DevBuf& work(hipStream_t s, int slot);
   int chunk_frames_for(int ny, int nx, bool mixed) const;
 };

@@ -112,6 +112,8 @@ _sig = {
     "hv_propagate": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _P, _P]),
     "hv_stft_moments": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P, _P,
                              _P]),
+    "hv_stft_moments_noalloc": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P,
+                                     _P, _P, _P]),
     "hv_stft_bins": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P]),
     "hv_stft_volume": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _P, _P]),
     "hv_postprocess": (_I, [_P, _P, _I, _I, _I, C.POINTER(hv_post), _P, _P, _P]),
@@ -326,6 +328,19 @@ class Context:
         _check(lib.hv_stft_moments(self.handle, _ptr(x), _dtype_code(x), n, ny, nx,
                                    C.byref(op) if op is not None else None, C.byref(tp), prec,
                                    _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream(x.device)))
+        return out
+
+    def hv_stft_moments_noalloc(self, x: torch.Tensor, optics: Optics | None, temporal: Temporal,
+                                prec: int, out):
+        """The moments into caller-allocated out = [m0, m1, m2] (each
+        [J][ny][nx] float32 or None) with the library's static scratch as
+        workspace: nothing is allocated by this call."""
+        n, ny, nx = _frames(x)
+        op = optics.c() if optics is not None else None
+        tp = temporal.c()
+        _check(lib.hv_stft_moments_noalloc(self.handle, _ptr(x), _dtype_code(x), n, ny, nx,
+                                           C.byref(op) if op is not None else None, C.byref(tp), prec,
+                                           _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream(x.device)))
         return out
 
     def hv_stft_bins(self, x: torch.Tensor, optics: Optics | None, temporal: Temporal,
