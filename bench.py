@@ -193,12 +193,16 @@ def cpu_baseline(pool, workers, frames, block, spec, z, ctx, hv, torch, precisio
         mom = [mm[0] for mm in otemp.moments(otemp.stft(u, w, w), bins, freqs)]
         pr = opca.pca_window(u, 1, 63)
         s_ref = otemp.stft(u, w, w)[0]
+        from oracle import ssa as ossa
+        sr = ossa.ssa_moments(u, w, w, ps.fs, 2 * ps.fs / w, 31 * ps.fs / w, 1, 63)
         rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
         res["precision_case_window0_rel_l2"] = {
             name: {"spectrum_all_64_bins": rel(g["spectrum"], s_ref[g["bins"]]),
                    "m0": rel(g["m"][0], mom[0]), "m1": rel(g["m"][1], mom[1]), "m2": rel(g["m"][2], mom[2]),
                    "covariance": rel(g["cov"], pr["cov"]), "eigvals": rel(g["eigvals"], pr["eigvals"]),
-                   "pca_m0": rel(g["pca_m0"], pr["m0"])}
+                   "pca_m0": rel(g["pca_m0"], pr["m0"]),
+                   "ssa_m0": rel(g["ssa"][0], sr["m0"][0]), "ssa_m1": rel(g["ssa"][1], sr["m1"][0]),
+                   "ssa_m2": rel(g["ssa"][2], sr["m2"][0])}
             for name, g in precision["gpu"].items()}
     return res
 
@@ -307,6 +311,9 @@ def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
     (zn, sig, _, _), t_net = timed(lambda: model.predict(eh, lam, pitch, tau=1e9))
     tau = float(np.quantile(sig.cpu().numpy(), 0.9))
     (zf, _, used, nfb), t_fb = timed(lambda: model.predict(eh, lam, pitch, tau=tau))
+    model.predict(eh[:8], lam, pitch, tau=1e9, refine=16)  # the local scan's table, outside the timing
+    (zl, _, _, _), t_loc = timed(lambda: model.predict(eh, lam, pitch, tau=1e9, refine=16))
+    (zlf, _, _, nlf), t_lf = timed(lambda: model.predict(eh, lam, pitch, tau=tau, refine=16))
 
     def err(zhat):
         e = np.abs(zhat.cpu().numpy() - ez) * 1e3
@@ -320,6 +327,10 @@ def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
            "cnn": {**err(zn), "holograms_per_s": n_eval / t_net},
            "cnn_fallback": {**err(zf), "holograms_per_s": n_eval / t_fb, "fallback_fraction": nfb / n_eval,
                             "tau_m": tau},
+           "cnn_local_scan": {**err(zl), "holograms_per_s": n_eval / t_loc, "candidates": 16, "k_sigma": 2.5,
+                              "speedup_vs_scan": t_scan / t_loc},
+           "cnn_local_scan_fallback": {**err(zlf), "holograms_per_s": n_eval / t_lf,
+                                       "fallback_fraction": nlf / n_eval, "speedup_vs_scan": t_scan / t_lf},
            "scan": {**err(zs), "holograms_per_s": n_eval / t_scan, "candidates": 128}}
     model.close()
     ctx.close()
@@ -378,8 +389,9 @@ def precision_case(hv, torch, steps):
     """The precision-form workload: 4,096 uint16 (12-bit) frames of 1024 x 1024
     (a 64-frame synthetic block replayed 64 times, resident in HBM), Fresnel at
     z = 0.5 m, then (a) the STFT over windows of 64 (stride 64, bins 2..31 at
-    fs 5 kHz) with its moments and (b) PCA over the same windows (components
-    1..63).  Reports frames/s per form and the GEMM kernels' useful TFLOP/s
+    fs 5 kHz) with its moments, (b) PCA over the same windows (components
+    1..63) and (c) SSA + FFT over them (components 1..63, then the band
+    moments).  Reports frames/s per form and the GEMM kernels' useful TFLOP/s
     against the matrix-core peak of their operand type; returns as well the
     GPU outputs of window 0 and the block, for the oracle check of the
     cpu_baseline leg."""
@@ -399,7 +411,8 @@ def precision_case(hv, torch, steps):
     npix = ny * nx
     # useful flops per pixel and window of each GEMM (real arithmetic on
     # (re, im)-interleaved operands, K = 2W)
-    flops = {"field_coef": 2 * (2 * nb) * (2 * w), "gram": 2 * (2 * w) ** 2, "proj_energy": 2 * (2 * 63) * (2 * w)}
+    flops = {"field_coef": 2 * (2 * nb) * (2 * w), "gram": 2 * (2 * w) ** 2, "proj_energy": 2 * (2 * 63) * (2 * w),
+             "ssa_moments": 2 * (2 * nb) * (2 * w)}
     ctx = hv.Context(0)
     out = {"workload": f"{n} uint16 frames of {nx}x{ny} (12-bit), Fresnel z={spec.z} m, W={w} stride {w}, "
                        f"{nb} band bins, PCA components 1..63", "frames": n}
@@ -407,14 +420,17 @@ def precision_case(hv, torch, steps):
     for prec, name in ((hv.HV_PREC_FP32, "fp32"), (hv.HV_PREC_MIXED, "mixed")):
         stft = lambda: ctx.hv_stft_moments(x, opt, tp, prec)
         pca = lambda: ctx.hv_pca(x, opt, w, w, 1, 63, prec, want_eig=True)
+        ssa = lambda: ctx.hv_ssa_moments(x, opt, tp, 1, 63, prec)
         ms_s = _timed_passes(torch, stft, steps)
         ms_p = _timed_passes(torch, pca, steps)
+        ms_a = _timed_passes(torch, ssa, steps)
         ctx.set_timing(True)
         stft()
         pca()
+        ssa()
         torch.cuda.synchronize()
         kern = {}
-        for k in ("fresnel_rows", "fresnel_cols", "field_coef", "gram", "jacobi", "proj_energy"):
+        for k in ("fresnel_rows", "fresnel_cols", "field_coef", "gram", "jacobi", "proj_energy", "ssa_moments"):
             ms, cnt = ctx.kernel_time(k)
             if cnt == 0:
                 continue
@@ -425,14 +441,16 @@ def precision_case(hv, torch, steps):
                                 "frac": tf / MFMA_PEAK_TFLOPS[name]})
         ctx.set_timing(False)
         out[name] = {"stft_moments_frames_per_s": n / (ms_s * 1e-3), "pca_frames_per_s": n / (ms_p * 1e-3),
-                     "kernels": kern}
+                     "ssa_fft_moments_frames_per_s": n / (ms_a * 1e-3), "kernels": kern}
         log(f"precision case {name}: {out[name]}")
         m = [t[0].cpu().numpy().astype(np.float64) for t in stft()]
         r = ctx.hv_pca(x[:w], opt, w, w, 1, 63, prec, want_eig=True, want_cov=True)
         # every bin of window 0: the band [0, fs/2] taken on both sides
         tp_all = hv.Temporal(w, w, fs, 0.0, fs / 2, True)
         s_all = ctx.hv_stft_bins(x[:w], opt, tp_all, prec)[0].cpu().numpy()
+        ra = ctx.hv_ssa_moments(x[:w], opt, tp, 1, 63, prec)
         res_keep[name] = {"m": m, "pca_m0": r["m0"][0].cpu().numpy().astype(np.float64),
+                          "ssa": [ra[k][0].cpu().numpy().astype(np.float64) for k in ("m0", "m1", "m2")],
                           "eigvals": r["eigvals"][0].cpu().numpy(), "cov": r["cov"][0].cpu().numpy(),
                           "spectrum": s_all, "bins": hv.band_bins(tp_all)[0]}
         del s_all

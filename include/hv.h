@@ -259,6 +259,27 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
                  int stride, int comp_lo, int comp_hi, int prec, float* m0, double* eigvals, double* cov,
                  double* offdiag, void* hip_stream);
 
+/* SSA + FFT (Sec. III-B.1: the temporal transform "SSA and FFT", its SVD
+ * obtained by eigen-decomposition of the data: covariance of the window,
+ * eigen-decomposition, projection onto a sub-basis).  Per window X_j
+ * ([P x W] as for hv_pca; C_j = X_j^H X_j; FP64 Jacobi; eigenvalues
+ * descending), the window is rebuilt from its components
+ * comp_lo..comp_hi, X_f = X_j V_S V_S^H, and transformed in time as in
+ * hv_stft_moments: S_k = sum_t X_f[:, t] exp(-2 pi i k t / W), with
+ * M_n = sum_{k in band} f_k^n |S_k|^2 over the band of `temporal` (window
+ * W = temporal->window in {16, 32, 64}, stride temporal->stride).  The
+ * projection, the back-projection and the DFT are folded into one set of
+ * coefficients per window (FP64-built), so the field is read once by the
+ * coefficient GEMM after the Gram GEMM.
+ *   in       frames (HV_U8/HV_U16 with optics) or field (HV_C64, optics NULL)
+ *   m0..m2   [J][ny][nx] float32 (nullable, not all)
+ *   eigvals  [J][W] float64 (nullable), offdiag [J] (nullable) as in hv_pca
+ * The default comp_lo = 1, comp_hi = W - 1 removes the dominant (static)
+ * component; comp_lo = 0, comp_hi = W - 1 gives hv_stft_moments' moments. */
+hv_status hv_ssa_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                         const hv_temporal* temporal, int comp_lo, int comp_hi, int prec, float* m0, float* m1,
+                         float* m2, double* eigvals, double* offdiag, void* hip_stream);
+
 /* ---------------------------------------------------------------- serving loop */
 
 /* Camera streams processed as their frames arrive (Sec. II-B.1 and III-A:
@@ -488,14 +509,26 @@ hv_status hv_af_loss_grad(hv_af_model* model, const void* crops, const float* z_
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on that gradient. */
 hv_status hv_af_train_step(hv_af_model* model, const void* crops, const float* z_m, int batch, float lr,
                            float* loss, void* hip_stream);
+/* The scan of hv_af_scan over per-hologram ranges: n_candidates distances
+ * evenly spaced in [z_lo[i], z_hi[i]] (device float32 [n] each) for
+ * hologram i; transfer functions from an FP64 table of
+ * 2 pi sqrt(1/lambda^2 - |f|^2), phase and sine/cosine in FP64 on the device.
+ * z_out[n], scores_out [n][n_candidates] (nullable). */
+hv_status hv_af_scan_ranges(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, double wavelength_m,
+                            double pitch_m, const float* z_lo, const float* z_hi, int n_candidates, float* z_out,
+                            float* scores_out, void* hip_stream);
 /* Predicted z (metres) and sigma for n holograms (crops, then the inference
- * kernels of hv_af_infer); every hologram with
- * sigma > tau_m is re-estimated by hv_af_scan (128 candidates in [0.05, 0.5] m)
- * and flagged in used_fallback[n] (nullable).  *n_fallback (host, nullable)
- * receives their count.  Synchronises the stream. */
+ * kernels of hv_af_infer).  With refine_candidates > 0 (>= 4) the network
+ * seeds a local scan from the same spectrum: refine_candidates / 2
+ * candidates over z +- refine_k sigma (clipped to [0.05, 0.5] m, at least
+ * 10 mm wide), then the rest over one coarse step on each side of the best;
+ * z_out is that scan's best candidate.  Every hologram with sigma > tau_m is
+ * re-estimated by hv_af_scan (128 candidates in [0.05, 0.5] m) and flagged
+ * in used_fallback[n] (nullable).  *n_fallback (host, nullable) receives
+ * their count.  Synchronises the stream. */
 hv_status hv_af_predict(hv_af_model* model, const uint8_t* holo, int n, double wavelength_m, double pitch_m,
-                        float tau_m, float* z_out, float* sigma_out, int* used_fallback, int* n_fallback,
-                        void* hip_stream);
+                        float tau_m, int refine_candidates, float refine_k, float* z_out, float* sigma_out,
+                        int* used_fallback, int* n_fallback, void* hip_stream);
 /* Training holograms from the project's own forward model: counter-based
  * complex noise band-limited to a 0.09 cycles/pixel pupil, times 3-8 soft
  * disks (parameters drawn from seed and the hologram index), propagated by

@@ -1193,32 +1193,27 @@ hv_status hv_stft_volume(hv_ctx* ctx, const void* in, int in_t, int n, int ny, i
 // quadratically; W = 64 windows of camera data take well under 20).
 static constexpr int kJacobiSweeps = 40;
 
-hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics, int window,
-                 int stride, int comp_lo, int comp_hi, int prec, float* m0, double* eigvals, double* cov,
-                 double* offdiag, void* hip_stream) {
+// Outputs of the eigen-decomposition paths (each nullable except as noted).
+struct EigOut {
+  float *m0, *m1, *m2;  // PCA: m0 (required) = projection energy; SSA: the moments
+  double *eigvals, *cov, *offdiag;
+};
+
+// Shared driver of the PCA and SSA + FFT paths (Sec. III-B.1: covariance of
+// the window, eigen-decomposition, projection onto a sub-basis).  Per chunk
+// of windows: the field (spatial passes), the Gram partials and their FP64
+// reduction, the FP64 Jacobi; then, for PCA (ssa == nullptr), the
+// projection energy of components comp_lo..comp_hi, and for SSA the
+// coefficients of "project onto those components and back, then the DFT of
+// the band bins" and the coefficient GEMM with the moment epilogue.
+static hv_status eig_path(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                          int w, int stride, int comp_lo, int comp_hi, bool mixed, const DftPlan* ssa,
+                          const EigOut& o, hipStream_t st) {
   hv_status s;
-  if ((s = enter(ctx))) return s;
-  std::lock_guard<std::recursive_mutex> lock(ctx->mu);
-  if ((s = check_frame(n, ny, nx))) return s;
-  if (window != 16 && window != 32 && window != 64) return fail(HV_ERR_SHAPE, "PCA window %d: use 16, 32 or 64", window);
-  if (stride <= 0) return fail(HV_ERR_ARG, "stride must be positive");
-  if (!(0 <= comp_lo && comp_lo <= comp_hi && comp_hi < window))
-    return fail(HV_ERR_ARG, "component range [%d, %d] outside [0, %d)", comp_lo, comp_hi, window);
-  if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
-  if (optics) {
-    if ((s = check_optics(optics)) || (s = check_dtype(in_t, true))) return s;
-  } else if (in_t != HV_C64) {
-    return fail(HV_ERR_ARG, "without optics the input must be a field (HV_C64)");
-  }
-  if (n < window) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, window);
-  if (!in || !m0) return fail(HV_ERR_ARG, "NULL data pointer");
-  const bool mixed = prec == HV_PREC_MIXED;
-  const int w = window;
   const int nwin_total = (n - w) / stride + 1;
   const size_t frame = (size_t)ny * nx;
-  hipStream_t st = (hipStream_t)hip_stream;
-  const int npair = comp_hi - comp_lo + 1;
-  const int mtiles = (npair + 15) / 16;
+  const int npair = ssa ? (int)ssa->bins.size() : comp_hi - comp_lo + 1;
+  const int mtiles = ssa ? ssa->mtiles : (npair + 15) / 16;
   const int nblk = (int)std::max<long>(1, std::min<long>(256, (long)frame / 4096));
   // The eigensolve runs one workgroup per window, so a chunk should carry
   // many windows: up to 64 windows, within about 2 GiB of field per stream.
@@ -1235,11 +1230,11 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
     void *part, *cv, *ev, *vec, *a32, *a16h, *a16l;
   };
   const size_t M = 2 * (size_t)w;
-  auto scratch = [&](hipStream_t cs, Scratch* o) -> hv_status {
+  auto scratch = [&](hipStream_t cs, Scratch* x) -> hv_status {
     const size_t bytes[7] = {(size_t)gw * nblk * M * M * 4, (size_t)gw * w * w * 16, (size_t)gw * w * 8,
                              (size_t)gw * w * w * 16, (size_t)gw * mtiles * w * 64 * 4,
                              (size_t)gw * mtiles * (w / 8) * 64 * 16, (size_t)gw * mtiles * (w / 8) * 64 * 16};
-    void** dst[7] = {&o->part, &o->cv, &o->ev, &o->vec, &o->a32, &o->a16h, &o->a16l};
+    void** dst[7] = {&x->part, &x->cv, &x->ev, &x->vec, &x->a32, &x->a16h, &x->a16l};
     for (int i = 0; i < 7; ++i) {
       DevBuf& b = ctx->work(cs, 10 + i);
       hv_status e = b.ensure(bytes[i], &ctx->held);
@@ -1248,11 +1243,15 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
     }
     return HV_OK;
   };
-  DevBuf& wts = ctx->work(st, 17);  // read-only, shared by both streams
-  {
+  const float* wts = nullptr;
+  if (ssa) {
+    wts = (const float*)ssa->wts.ptr;  // f_k^n of the band bins, as the STFT path
+  } else {
+    DevBuf& wb = ctx->work(st, 17);  // read-only, shared by both streams
     std::vector<float> hw((size_t)3 * mtiles * 16, 0.f);
     for (int i = 0; i < npair; ++i) hw[i] = 1.f;
-    if ((s = wts.upload(hw.data(), hw.size() * 4, &ctx->held))) return s;
+    if ((s = wb.upload(hw.data(), hw.size() * 4, &ctx->held))) return s;
+    wts = (const float*)wb.ptr;
   }
   const float fsc = mixed ? fp16_field_scale(optics ? in_t : HV_C64, ny, nx) : 1.f;
   // Chunks alternate between the caller's stream and a second one: one
@@ -1300,23 +1299,37 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
         return s;
       if ((s = timed(ctx, "jacobi", st, [&] {
              return launch_jacobi((const double*)x.cv, g_n, w, (double*)x.ev, (double*)x.vec,
-                                  offdiag ? offdiag + j0 : nullptr, kJacobiSweeps, st);
+                                  o.offdiag ? o.offdiag + j0 : nullptr, kJacobiSweeps, st);
            })))
         return s;
-      if ((s = launch_proj_coefs((const double*)x.vec, g_n, w, comp_lo, comp_hi, mtiles, (float*)x.a32,
-                                 (hv_h8*)x.a16h, (hv_h8*)x.a16l, st)))
-        return s;
-      if ((s = timed(ctx, "proj_energy", st, [&] {
-             return launch_proj_energy(field, half, (long)frame, stride, g_n, w, mtiles, npair, (const float*)x.a32,
-                                       (const hv_h8*)x.a16h, (const hv_h8*)x.a16l, (const float*)wts.ptr, mixed,
-                                       half ? 1.f : fs, 1.f / fs, m0 + (size_t)j0 * frame, st);
-           })))
-        return s;
-      if (eigvals && hipMemcpyAsync(eigvals + (size_t)j0 * w, x.ev, (size_t)g_n * w * 8, hipMemcpyDeviceToDevice,
-                                    st) != hipSuccess)
+      const size_t at = (size_t)j0 * frame;
+      if (ssa) {
+        if ((s = launch_ssa_coefs((const double*)x.vec, g_n, w, comp_lo, comp_hi, ssa->bins.data(), npair, mtiles,
+                                  (float*)x.a32, (hv_h8*)x.a16h, (hv_h8*)x.a16l, st)))
+          return s;
+        if ((s = timed(ctx, "ssa_moments", st, [&] {
+               return launch_coef_moments(field, half, (long)frame, stride, g_n, w, mtiles, npair,
+                                          (const float*)x.a32, (const hv_h8*)x.a16h, (const hv_h8*)x.a16l, wts,
+                                          mixed, half ? 1.f : fs, 1.f / fs, o.m0 ? o.m0 + at : nullptr,
+                                          o.m1 ? o.m1 + at : nullptr, o.m2 ? o.m2 + at : nullptr, st);
+             })))
+          return s;
+      } else {
+        if ((s = launch_proj_coefs((const double*)x.vec, g_n, w, comp_lo, comp_hi, mtiles, (float*)x.a32,
+                                   (hv_h8*)x.a16h, (hv_h8*)x.a16l, st)))
+          return s;
+        if ((s = timed(ctx, "proj_energy", st, [&] {
+               return launch_proj_energy(field, half, (long)frame, stride, g_n, w, mtiles, npair,
+                                         (const float*)x.a32, (const hv_h8*)x.a16h, (const hv_h8*)x.a16l, wts,
+                                         mixed, half ? 1.f : fs, 1.f / fs, o.m0 + at, st);
+             })))
+          return s;
+      }
+      if (o.eigvals && hipMemcpyAsync(o.eigvals + (size_t)j0 * w, x.ev, (size_t)g_n * w * 8,
+                                      hipMemcpyDeviceToDevice, st) != hipSuccess)
         return fail(HV_ERR_DEVICE, "eigenvalue copy failed");
-      if (cov && hipMemcpyAsync(cov + (size_t)j0 * w * w * 2, x.cv, (size_t)g_n * w * w * 16,
-                                hipMemcpyDeviceToDevice, st) != hipSuccess)
+      if (o.cov && hipMemcpyAsync(o.cov + (size_t)j0 * w * w * 2, x.cv, (size_t)g_n * w * w * 16,
+                                  hipMemcpyDeviceToDevice, st) != hipSuccess)
         return fail(HV_ERR_DEVICE, "covariance copy failed");
       return HV_OK;
     }();
@@ -1326,6 +1339,55 @@ hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, c
     if (res == HV_OK) res = j;
   }
   return res;
+}
+
+// Checks shared by hv_pca and hv_ssa_moments.
+static hv_status check_eig_call(int n, int ny, int nx, const hv_optics* optics, int in_t, const void* in, int window,
+                                int stride, int comp_lo, int comp_hi, int prec) {
+  hv_status s;
+  if ((s = check_frame(n, ny, nx))) return s;
+  if (window != 16 && window != 32 && window != 64) return fail(HV_ERR_SHAPE, "window %d: use 16, 32 or 64", window);
+  if (stride <= 0) return fail(HV_ERR_ARG, "stride must be positive");
+  if (!(0 <= comp_lo && comp_lo <= comp_hi && comp_hi < window))
+    return fail(HV_ERR_ARG, "component range [%d, %d] outside [0, %d)", comp_lo, comp_hi, window);
+  if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
+  if (optics) {
+    if ((s = check_optics(optics)) || (s = check_dtype(in_t, true))) return s;
+  } else if (in_t != HV_C64) {
+    return fail(HV_ERR_ARG, "without optics the input must be a field (HV_C64)");
+  }
+  if (n < window) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, window);
+  if (!in) return fail(HV_ERR_ARG, "input is NULL");
+  return HV_OK;
+}
+
+hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics, int window,
+                 int stride, int comp_lo, int comp_hi, int prec, float* m0, double* eigvals, double* cov,
+                 double* offdiag, void* hip_stream) {
+  hv_status s;
+  if ((s = enter(ctx))) return s;
+  std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+  if ((s = check_eig_call(n, ny, nx, optics, in_t, in, window, stride, comp_lo, comp_hi, prec))) return s;
+  if (!m0) return fail(HV_ERR_ARG, "m0 is NULL");
+  return eig_path(ctx, in, in_t, n, ny, nx, optics, window, stride, comp_lo, comp_hi, prec == HV_PREC_MIXED, nullptr,
+                  EigOut{m0, nullptr, nullptr, eigvals, cov, offdiag}, (hipStream_t)hip_stream);
+}
+
+hv_status hv_ssa_moments(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
+                         const hv_temporal* temporal, int comp_lo, int comp_hi, int prec, float* m0, float* m1,
+                         float* m2, double* eigvals, double* offdiag, void* hip_stream) {
+  hv_status s;
+  if ((s = enter(ctx))) return s;
+  std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+  if (!temporal) return fail(HV_ERR_ARG, "temporal is NULL");
+  if ((s = check_eig_call(n, ny, nx, optics, in_t, in, temporal->window, temporal->stride, comp_lo, comp_hi, prec)))
+    return s;
+  if (!(temporal->fs_hz > 0)) return fail(HV_ERR_ARG, "fs must be positive");
+  if (!m0 && !m1 && !m2) return fail(HV_ERR_ARG, "no output requested");
+  DftPlan* dp = ctx->dft_plan(*temporal, &s);
+  if (!dp) return s;
+  return eig_path(ctx, in, in_t, n, ny, nx, optics, temporal->window, temporal->stride, comp_lo, comp_hi,
+                  prec == HV_PREC_MIXED, dp, EigOut{m0, m1, m2, eigvals, nullptr, offdiag}, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

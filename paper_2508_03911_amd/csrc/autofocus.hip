@@ -148,10 +148,16 @@ __global__ __launch_bounds__(512) void k_af_subband(const float2* __restrict__ t
   }
 }
 
-// Sharpness of the reconstruction for CPB candidates per block.
+// Sharpness of the reconstruction for CPB candidates per block.  Transfer
+// functions: from htab [nc][SUB][SUB] (candidates shared by every hologram),
+// or, when zlo is not null, candidate c of hologram n at
+// z = zlo[n] + (zhi[n] - zlo[n]) c / (nc - 1), H = exp(-i z kz) with
+// kz = 2 pi sqrt(1/lambda^2 - |f|^2) from the FP64 table kz (negative:
+// evanescent, H = 0), phase and sine/cosine in FP64.
 template <int CPB>
 __global__ __launch_bounds__(256) void k_af_scan(const float2* __restrict__ sub, const float2* __restrict__ htab,
-                                                 int nc, float* __restrict__ scores) {
+                                                 const double* __restrict__ kz, const float* __restrict__ zlo,
+                                                 const float* __restrict__ zhi, int nc, float* __restrict__ scores) {
   constexpr int NT = 256, S = lds_stride(SUB);
   __shared__ float2 A[SUB * S];
   __shared__ float2 B[SUB * S];
@@ -164,8 +170,23 @@ __global__ __launch_bounds__(256) void k_af_scan(const float2* __restrict__ sub,
   for (int cc = 0; cc < CPB; ++cc) {
     const int c = blockIdx.y * CPB + cc;
     if (c >= nc) break;
-    const float2* h = htab + (long)c * SUB * SUB;
-    for (int q = tid; q < SUB * SUB; q += NT) A[(q / SUB) * S + skew(q % SUB)] = c2::mul(sv[q], h[q]);
+    if (zlo) {
+      const double z0 = zlo[n], z1 = zhi[n];
+      const double zc = z0 + (z1 - z0) * c / (nc - 1);
+      for (int q = tid; q < SUB * SUB; q += NT) {
+        const double k = kz[q];
+        float2 h = make_float2(0.f, 0.f);
+        if (k >= 0.0) {
+          double sn, cs;
+          sincos(-zc * k, &sn, &cs);
+          h = make_float2((float)cs, (float)sn);
+        }
+        A[(q / SUB) * S + skew(q % SUB)] = c2::mul(sv[q], h);
+      }
+    } else {
+      const float2* h = htab + (long)c * SUB * SUB;
+      for (int q = tid; q < SUB * SUB; q += NT) A[(q / SUB) * S + skew(q % SUB)] = c2::mul(sv[q], h[q]);
+    }
     __syncthreads();
     fft_lds<SUB, SUB, NT, +1>(A, tw, tid);  // rows
     for (int q = tid; q < SUB * SUB; q += NT) {
@@ -197,8 +218,13 @@ __global__ __launch_bounds__(256) void k_af_scan(const float2* __restrict__ sub,
   }
 }
 
+// Argmax over each hologram's candidates (ties to the lowest z); the range
+// is [z_lo, z_hi] for all, or [zlo[i], zhi[i]] when zlo is not null.  With
+// `refine`, [zlo, zhi] is then narrowed to one candidate step on each side
+// of the best (within the old range) for a finer scan.
 __global__ void k_af_argmax(const float* __restrict__ scores, int n, int nc, double z_lo, double z_hi,
-                            float* __restrict__ z_out, float* __restrict__ best) {
+                            float* __restrict__ zlo, float* __restrict__ zhi, float* __restrict__ z_out,
+                            float* __restrict__ best, int refine) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int arg = 0;
@@ -210,8 +236,34 @@ __global__ void k_af_argmax(const float* __restrict__ scores, int n, int nc, dou
       arg = c;
     }
   }
-  z_out[i] = (float)(z_lo + (z_hi - z_lo) * arg / (nc - 1));
+  const double a = zlo ? (double)zlo[i] : z_lo, b = zlo ? (double)zhi[i] : z_hi;
+  const double step = (b - a) / (nc - 1);
+  z_out[i] = (float)(a + step * arg);
   if (best) best[i] = bs;
+  if (refine && zlo) {
+    zlo[i] = (float)(a + step * (arg > 0 ? arg - 1 : 0));
+    zhi[i] = (float)(a + step * (arg < nc - 1 ? arg + 1 : nc - 1));
+  }
+}
+
+// Local scan ranges from the network: [z - k sigma, z + k sigma] clipped to
+// [lo, hi], at least `minw` wide.
+__global__ void k_af_ranges(const float* __restrict__ z, const float* __restrict__ sigma, int n, float k, float lo,
+                            float hi, float minw, float* __restrict__ zlo, float* __restrict__ zhi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float half = fmaxf(k * sigma[i], 0.5f * minw);
+  float a = z[i] - half, b = z[i] + half;
+  if (a < lo) {
+    b = fminf(hi, b + (lo - a));
+    a = lo;
+  }
+  if (b > hi) {
+    a = fmaxf(lo, a - (b - hi));
+    b = hi;
+  }
+  zlo[i] = a;
+  zhi[i] = b;
 }
 
 // ------------------------------------------------------------------ CNN: convolution
@@ -903,13 +955,82 @@ hv_status hv_af_scan(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, do
   hipLaunchKernelGGL(k_af_subband, dim3(n), dim3(512), 0, st, t1, (float2*)sb.ptr);
   constexpr int CPB = 8;
   hipLaunchKernelGGL(k_af_scan<CPB>, dim3(n, (n_candidates + CPB - 1) / CPB), dim3(256), 0, st,
-                     (const float2*)sb.ptr, (const float2*)tab.ptr, n_candidates, (float*)sc.ptr);
+                     (const float2*)sb.ptr, (const float2*)tab.ptr, (const double*)nullptr, (const float*)nullptr,
+                     (const float*)nullptr, n_candidates, (float*)sc.ptr);
   hipLaunchKernelGGL(k_af_argmax, dim3((n + 255) / 256), dim3(256), 0, st, (const float*)sc.ptr, n, n_candidates,
-                     z_lo_m, z_hi_m, z_out, (float*)nullptr);
+                     z_lo_m, z_hi_m, (float*)nullptr, (float*)nullptr, z_out, (float*)nullptr, 0);
   if (scores_out &&
       hipMemcpyAsync(scores_out, sc.ptr, (size_t)n * n_candidates * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return fail(HV_ERR_DEVICE, "score copy failed");
   return launched("af_scan");
+}
+
+}  // extern "C"
+
+// kz = 2 pi sqrt(1/lambda^2 - |f|^2) at the demodulated object frequencies
+// of the scan sub-band (FP64, -1 where evanescent), once per setting.
+static hv_status af_kz_table(hv_ctx* ctx, double wavelength_m, double pitch_m, const double** out) {
+  char key[96];
+  snprintf(key, sizeof key, "afkz %.17g %.17g", wavelength_m, pitch_m);
+  DevBuf& tab = ctx->misc[key];
+  if (!tab.ptr) {
+    std::vector<double> k((size_t)SUB * SUB);
+    const double il2 = 1.0 / (wavelength_m * wavelength_m);
+    for (int i = 0; i < SUB; ++i)
+      for (int j = 0; j < SUB; ++j) {
+        const double fy = (i - SUB / 2) / (AN * pitch_m), fx = (j - SUB / 2) / (AN * pitch_m);
+        const double rad = il2 - fx * fx - fy * fy;
+        k[(size_t)i * SUB + j] = rad > 0 ? 2.0 * M_PI * std::sqrt(rad) : -1.0;
+      }
+    hv_status s = tab.upload(k.data(), k.size() * sizeof(double), &ctx->held);
+    if (s) return s;
+  }
+  *out = (const double*)tab.ptr;
+  return HV_OK;
+}
+
+// Scan of the sub-bands sub [n][SUB][SUB] over per-hologram ranges
+// [zlo[i], zhi[i]] with nc candidates; z_out[i] the best candidate.  With
+// `refine`, zlo / zhi are narrowed to one step around the best on return.
+static hv_status af_scan_ranges(hv_ctx* ctx, const float2* sub, int n, const double* kz, float* zlo, float* zhi,
+                                int nc, float* z_out, float* scores_out, bool refine, hipStream_t st) {
+  DevBuf& sc = ctx->work(st, 28);
+  hv_status s;
+  if ((s = sc.ensure((size_t)n * nc * 4, &ctx->held))) return s;
+  constexpr int CPB = 8;
+  hipLaunchKernelGGL(k_af_scan<CPB>, dim3(n, (nc + CPB - 1) / CPB), dim3(256), 0, st, sub, (const float2*)nullptr,
+                     kz, (const float*)zlo, (const float*)zhi, nc, (float*)sc.ptr);
+  hipLaunchKernelGGL(k_af_argmax, dim3((n + 255) / 256), dim3(256), 0, st, (const float*)sc.ptr, n, nc, 0.0, 0.0,
+                     zlo, zhi, z_out, (float*)nullptr, refine ? 1 : 0);
+  if (scores_out && hipMemcpyAsync(scores_out, sc.ptr, (size_t)n * nc * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return fail(HV_ERR_DEVICE, "score copy failed");
+  return launched("af_scan_ranges");
+}
+
+extern "C" {
+
+hv_status hv_af_scan_ranges(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, double wavelength_m,
+                            double pitch_m, const float* z_lo, const float* z_hi, int n_candidates, float* z_out,
+                            float* scores_out, void* hip_stream) {
+  if (!ctx || !holo || !z_lo || !z_hi || !z_out) return fail(HV_ERR_ARG, "NULL argument");
+  if (ny != AN || nx != AN) return fail(HV_ERR_SHAPE, "autofocus works on 256x256 holograms");
+  if (n_candidates < 2 || !(wavelength_m > 0) || !(pitch_m > 0))
+    return fail(HV_ERR_ARG, "need >= 2 candidates, positive wavelength and pitch");
+  if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hv_status s;
+  const double* kz;
+  if ((s = af_kz_table(ctx, wavelength_m, pitch_m, &kz))) return s;
+  float2* t1;
+  if ((s = af_spectrum(ctx, holo, n, st, &t1))) return s;
+  DevBuf& sb = ctx->work(st, 21);
+  if ((s = sb.ensure((size_t)n * SUB * SUB * 8, &ctx->held))) return s;
+  hipLaunchKernelGGL(k_af_subband, dim3(n), dim3(512), 0, st, t1, (float2*)sb.ptr);
+  // the ranges are read, never written, on this path
+  return af_scan_ranges(ctx, (const float2*)sb.ptr, n, kz, const_cast<float*>(z_lo), const_cast<float*>(z_hi),
+                        n_candidates, z_out, scores_out, false, st);
 }
 
 hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batch, double z_mean, double z_scale,
@@ -1039,28 +1160,62 @@ hv_status hv_af_train_step(hv_af_model* md, const void* crops, const float* z_m,
 }
 
 hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wavelength_m, double pitch_m, float tau_m,
-                        float* z_out, float* sigma_out, int* used_fallback, int* n_fallback, void* hip_stream) {
+                        int refine_candidates, float refine_k, float* z_out, float* sigma_out, int* used_fallback,
+                        int* n_fallback, void* hip_stream) {
   if (!md || !holo || !z_out) return fail(HV_ERR_ARG, "NULL argument");
   if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  const bool refine = refine_candidates > 0;
+  if (refine && (refine_candidates < 4 || !(refine_k > 0)))
+    return fail(HV_ERR_ARG, "a local scan needs >= 4 candidates and a positive width in sigma");
   hv_ctx* ctx = md->ctx;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   hipStream_t st = (hipStream_t)hip_stream;
   DevBuf& cb = ctx->work(st, 23);
   DevBuf& sg = ctx->work(st, 24);
   hv_status s;
   if ((s = cb.ensure((size_t)md->max_batch * HW * 2, &ctx->held))) return s;
   if ((s = sg.ensure((size_t)n * 4, &ctx->held))) return s;
+  float2* subs = nullptr;
+  const double* kz = nullptr;
+  if (refine) {
+    DevBuf& sb = ctx->work(st, 29);
+    if ((s = sb.ensure((size_t)n * SUB * SUB * 8, &ctx->held))) return s;
+    subs = (float2*)sb.ptr;
+    if ((s = af_kz_table(ctx, wavelength_m, pitch_m, &kz))) return s;
+  }
   float* sigma = sigma_out ? sigma_out : (float*)sg.ptr;
   if (used_fallback && hipMemsetAsync(used_fallback, 0, (size_t)n * sizeof(int), st) != hipSuccess)
     return fail(HV_ERR_DEVICE, "memset failed");
   for (int b0 = 0; b0 < n; b0 += md->max_batch) {
     const int bs = std::min(md->max_batch, n - b0);
     if ((s = hv_af_crops(ctx, holo + (size_t)b0 * AN * AN, bs, AN, AN, cb.ptr, 1, st))) return s;
+    if (refine)  // the +1-order sub-band from the same spectrum the crops came from
+      hipLaunchKernelGGL(k_af_subband, dim3(bs), dim3(512), 0, st, (const float2*)ctx->work(st, 20).ptr,
+                         subs + (size_t)b0 * SUB * SUB);
     if ((s = infer(md, (const _Float16*)cb.ptr, bs, st))) return s;
     hipLaunchKernelGGL(k_af_denorm, dim3((bs + 255) / 256), dim3(256), 0, st, md->out, bs, (float)md->z_mean,
                        (float)md->z_scale, z_out + b0, sigma + b0);
   }
-  // fallback: the scan for every hologram whose predicted sigma exceeds tau
+  if (refine) {
+    // local scan seeded by the network: refine_candidates / 2 candidates over
+    // z +- refine_k sigma, then the rest over one coarse step on each side
+    // of the best
+    DevBuf& rl = ctx->work(st, 30);
+    DevBuf& rh = ctx->work(st, 31);
+    DevBuf& rz = ctx->work(st, 32);
+    if ((s = rl.ensure((size_t)n * 4, &ctx->held)) || (s = rh.ensure((size_t)n * 4, &ctx->held)) ||
+        (s = rz.ensure((size_t)n * 4, &ctx->held)))
+      return s;
+    const int n1 = refine_candidates / 2, n2 = refine_candidates - n1;
+    hipLaunchKernelGGL(k_af_ranges, dim3((n + 255) / 256), dim3(256), 0, st, (const float*)z_out,
+                       (const float*)sigma, n, refine_k, 0.05f, 0.5f, 0.01f, (float*)rl.ptr, (float*)rh.ptr);
+    if ((s = af_scan_ranges(ctx, subs, n, kz, (float*)rl.ptr, (float*)rh.ptr, n1, (float*)rz.ptr, nullptr, true, st)))
+      return s;
+    if ((s = af_scan_ranges(ctx, subs, n, kz, (float*)rl.ptr, (float*)rh.ptr, n2, z_out, nullptr, false, st)))
+      return s;
+  }
+  // fallback: the full scan for every hologram whose predicted sigma exceeds tau
   std::vector<float> hs(n);
   if (hipMemcpyAsync(hs.data(), sigma, (size_t)n * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)

@@ -103,6 +103,17 @@ hv_status launch_jacobi(const double* cov, int nwin, int window, double* evals, 
 // columns c1..c2 (A = [Vr^T Vi^T ; ...]) for the coefficient GEMM.
 hv_status launch_proj_coefs(const double* evecs, int nwin, int window, int c1, int c2, int mtiles,
                             float* a32, hv_h8* a16hi, hv_h8* a16lo, hipStream_t st);
+// SSA + FFT: per-window coefficient fragments A[k][t'] = sum_t (V_S V_S^H)[t', t]
+// exp(-2 pi i k t / W) for the nb band bins (bins[0..nb), host array) and
+// components c1..c2, in the layout of the DFT coefficients (mtiles tiles).
+hv_status launch_ssa_coefs(const double* evecs, int nwin, int window, int c1, int c2, const int* bins, int nb,
+                           int mtiles, float* a32, hv_h8* a16hi, hv_h8* a16lo, hipStream_t st);
+// Coefficient GEMM with per-window A and the three weighted-power outputs
+// (wts [3][16 mtiles]) into m0/m1/m2 [nwin][npix] (each nullable).
+hv_status launch_coef_moments(const void* u, bool half_in, long npix, int stride, int nwin, int window, int mtiles,
+                              int npair, const float* a32, const hv_h8* a16hi, const hv_h8* a16lo, const float* wts,
+                              bool mixed, float b_scale, float out_scale, float* m0, float* m1, float* m2,
+                              hipStream_t st);
 // Projection energy M0_pca per pixel per window, with per-window A.
 hv_status launch_proj_energy(const void* u, bool half_in, long npix, int stride, int nwin, int window,
                              int mtiles, int npair, const float* a32, const hv_h8* a16hi, const hv_h8* a16lo,

@@ -668,6 +668,73 @@ __global__ void k_proj_coefs(const double* __restrict__ evecs, int W, int c1, in
   }
 }
 
+// ------------------------------------------------------------------ SSA + FFT coefficients
+// The SSA filter keeps components c1..c2 of the window, X_f = X V_S V_S^H,
+// and the FFT follows, S_k = sum_t d_k[t] X_f[:, t] with d_k[t] =
+// exp(-2 pi i k t / W).  Both steps are linear in the window's frames, so
+// S_k = sum_t' A[k][t'] X[:, t'] with A[k][t'] = sum_i V_S[t', i] G[k][i]
+// and G[k][i] = sum_t conj(V_S[t, i]) d_k[t]; A (FP64) goes into the same
+// MFMA fragment layout as the DFT coefficients, one set per window, and
+// the field is read once by the coefficient GEMM with the moment epilogue.
+struct SsaBins {
+  int n;
+  int k[64];
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void k_ssa_coefs(const double* __restrict__ evecs, int c1, int ns, SsaBins bins,
+                                                   int mtiles, float* __restrict__ a32, hv_h8* __restrict__ a16hi,
+                                                   hv_h8* __restrict__ a16lo) {
+  __shared__ dc G[W * W];  // [bin][component]
+  __shared__ dc A[W * W];  // [bin][frame]
+  const long jj = blockIdx.x;
+  const dc* v = reinterpret_cast<const dc*>(evecs) + jj * W * W;  // v[t * W + c]
+  const int nb = bins.n;
+  for (int e = threadIdx.x; e < nb * ns; e += blockDim.x) {
+    const int b = e / ns, i = e % ns;
+    const int k = bins.k[b];
+    dc acc = {0.0, 0.0};
+    for (int t = 0; t < W; ++t) {
+      double sn, cs;
+      sincospi(2.0 * (double)((k * t) % W) / W, &sn, &cs);
+      acc = dadd(acc, dmul(dconj(v[t * W + c1 + i]), dc{cs, -sn}));
+    }
+    G[b * W + i] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nb * W; e += blockDim.x) {
+    const int b = e / W, t = e % W;
+    dc acc = {0.0, 0.0};
+    for (int i = 0; i < ns; ++i) acc = dadd(acc, dmul(v[t * W + c1 + i], G[b * W + i]));
+    A[b * W + t] = acc;
+  }
+  __syncthreads();
+  // row m = 2b + (0: Re S, 1: Im S), column q = 2t + (0: Re u, 1: Im u)
+  auto coef = [&](int m, int q) -> float {
+    const int b = m >> 1, t = q >> 1;
+    if (b >= nb) return 0.f;
+    const dc a = A[b * W + t];
+    const double val = (m & 1) == 0 ? ((q & 1) == 0 ? a.x : -a.y) : ((q & 1) == 0 ? a.y : a.x);
+    return (float)val;
+  };
+  const long per_win = (long)mtiles * W * 64;
+  for (int i = threadIdx.x; i < mtiles * W * 64; i += blockDim.x) {
+    const int lane = i % 64, kk = (i / 64) % W, mt = i / (64 * W);
+    a32[jj * per_win + i] = coef(32 * mt + (lane & 31), 2 * kk + (lane >> 5));
+  }
+  for (int i = threadIdx.x; i < mtiles * (W / 8) * 64; i += blockDim.x) {
+    const int lane = i % 64, kk = (i / 64) % (W / 8), mt = i / (64 * (W / 8));
+    hv_h8 hi, lo;
+    for (int e = 0; e < 8; ++e) {
+      const float a = coef(32 * mt + (lane & 31), 16 * kk + 8 * (lane >> 5) + e);
+      hi[e] = (_Float16)a;
+      lo[e] = (_Float16)(a - (float)hi[e]);
+    }
+    a16hi[jj * (per_win / 8) + i] = hi;
+    a16lo[jj * (per_win / 8) + i] = lo;
+  }
+}
+
 hv_status launched(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hvi::fail(HV_ERR_DEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
@@ -861,6 +928,36 @@ hv_status launch_proj_coefs(const double* evecs, int nwin, int window, int c1, i
   hipLaunchKernelGGL(k_proj_coefs, dim3(nwin), dim3(256), 0, st, evecs, window, c1, c2 - c1 + 1, mtiles, a32,
                      a16hi, a16lo);
   return launched("proj_coefs");
+}
+
+hv_status launch_ssa_coefs(const double* evecs, int nwin, int window, int c1, int c2, const int* bins, int nb,
+                           int mtiles, float* a32, hv_h8* a16hi, hv_h8* a16lo, hipStream_t st) {
+  if (nwin <= 0) return HV_OK;
+  if (nb <= 0 || nb > window || mtiles * 16 < nb) return fail(HV_ERR_ARG, "SSA band of %d bins", nb);
+  if (!(0 <= c1 && c1 <= c2 && c2 < window)) return fail(HV_ERR_ARG, "component range [%d, %d]", c1, c2);
+  SsaBins b{};
+  b.n = nb;
+  for (int i = 0; i < nb; ++i) {
+    if (bins[i] < 0 || bins[i] >= window) return fail(HV_ERR_ARG, "bin %d outside the window", bins[i]);
+    b.k[i] = bins[i];
+  }
+  const int ns = c2 - c1 + 1;
+  switch (window) {
+    case 16: hipLaunchKernelGGL(k_ssa_coefs<16>, dim3(nwin), dim3(256), 0, st, evecs, c1, ns, b, mtiles, a32, a16hi, a16lo); break;
+    case 32: hipLaunchKernelGGL(k_ssa_coefs<32>, dim3(nwin), dim3(256), 0, st, evecs, c1, ns, b, mtiles, a32, a16hi, a16lo); break;
+    case 64: hipLaunchKernelGGL(k_ssa_coefs<64>, dim3(nwin), dim3(256), 0, st, evecs, c1, ns, b, mtiles, a32, a16hi, a16lo); break;
+    default: return fail(HV_ERR_SHAPE, "SSA window %d not supported (16, 32 or 64)", window);
+  }
+  return launched("ssa_coefs");
+}
+
+hv_status launch_coef_moments(const void* u, bool half_in, long npix, int stride, int nwin, int window, int mtiles,
+                              int npair, const float* a32, const hv_h8* a16hi, const hv_h8* a16lo, const float* wts,
+                              bool mixed, float b_scale, float out_scale, float* m0, float* m1, float* m2,
+                              hipStream_t st) {
+  CoefGemm g{window, mtiles, npair, a32, a16hi, a16lo, wts, 3};
+  CoefArgs a = make_args(g, (long)mtiles * window * 64, b_scale, out_scale, m0, m1, m2, nullptr);
+  return field_coef(u, half_in, npix, stride, nwin, a, window, mixed, false, st);
 }
 
 hv_status launch_proj_energy(const void* u, bool half_in, long npix, int stride, int nwin, int window, int mtiles,

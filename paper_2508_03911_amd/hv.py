@@ -144,10 +144,14 @@ _sig = {
     "hv_af_infer": (_I, [_P, _P, _I, _P, _P]),
     "hv_af_loss_grad": (_I, [_P, _P, _P, _I, _P, _P, _P]),
     "hv_af_train_step": (_I, [_P, _P, _P, _I, C.c_float, _P, _P]),
-    "hv_af_predict": (_I, [_P, _P, _I, C.c_double, C.c_double, C.c_float, _P, _P, _P, C.POINTER(_I), _P]),
+    "hv_af_predict": (_I, [_P, _P, _I, C.c_double, C.c_double, C.c_float, _I, C.c_float, _P, _P, _P, C.POINTER(_I),
+                           _P]),
+    "hv_af_scan_ranges": (_I, [_P, _P, _I, _I, _I, C.c_double, C.c_double, _P, _P, _I, _P, _P, _P]),
     "hv_af_synthesize": (_I, [_P, _I, C.POINTER(C.c_double), C.c_double, C.c_double, C.c_uint64, C.c_int64, _P,
                               _P]),
     "hv_pca": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
+    "hv_ssa_moments": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _I, _I, _P,
+                            _P, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(lib, _name)
@@ -434,6 +438,27 @@ class Context:
                           _stream(x.device)))
         return {"m0": m0, "eigvals": ev, "cov": cov, "offdiag": off}
 
+    def hv_ssa_moments(self, x: torch.Tensor, optics: Optics | None, temporal: Temporal, comp_lo: int = 1,
+                       comp_hi: int | None = None, prec: int = HV_PREC_FP32, out=None, want_eig=True):
+        """SSA + FFT moments: dict with m0, m1, m2 [J][ny][nx], eigvals [J][W]
+        and the Jacobi off-diagonal ratio [J]."""
+        n, ny, nx = _frames(x)
+        w = temporal.window
+        if comp_hi is None:
+            comp_hi = w - 1
+        j = self.n_windows(n, temporal)
+        if out is None:
+            out = [torch.empty((j, ny, nx), dtype=torch.float32, device=x.device) for _ in range(3)]
+        ev = torch.empty((j, w), dtype=torch.float64, device=x.device) if want_eig else None
+        off = torch.empty((j,), dtype=torch.float64, device=x.device)
+        op = optics.c() if optics is not None else None
+        tp = temporal.c()
+        _check(lib.hv_ssa_moments(self.handle, _ptr(x), _dtype_code(x), n, ny, nx,
+                                  C.byref(op) if op is not None else None, C.byref(tp), comp_lo, comp_hi, prec,
+                                  _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(ev), _ptr(off),
+                                  _stream(x.device)))
+        return {"m0": out[0], "m1": out[1], "m2": out[2], "eigvals": ev, "offdiag": off}
+
 
     # ---------------------------------------------------------------- serving loop
     def stats(self) -> dict:
@@ -489,6 +514,16 @@ class Context:
         sc = torch.empty((n, n_candidates), dtype=torch.float32, device=holo.device) if want_scores else None
         _check(lib.hv_af_scan(self.handle, _ptr(holo), n, ny, nx, wavelength, pitch, z_lo, z_hi, n_candidates,
                               _ptr(z), _ptr(sc), _stream(holo.device)))
+        return z, sc
+
+    def hv_af_scan_ranges(self, holo: torch.Tensor, wavelength: float, pitch: float, z_lo: torch.Tensor,
+                          z_hi: torch.Tensor, n_candidates: int, want_scores: bool = False):
+        """The scan over per-hologram ranges [z_lo[i], z_hi[i]] (device float32)."""
+        n, ny, nx = _frames(holo)
+        z = torch.empty(n, dtype=torch.float32, device=holo.device)
+        sc = torch.empty((n, n_candidates), dtype=torch.float32, device=holo.device) if want_scores else None
+        _check(lib.hv_af_scan_ranges(self.handle, _ptr(holo), n, ny, nx, wavelength, pitch, _ptr(z_lo), _ptr(z_hi),
+                                     n_candidates, _ptr(z), _ptr(sc), _stream(holo.device)))
         return z, sc
 
     def hv_af_synthesize(self, z_m, wavelength: float, pitch: float, seed: int, index_base: int = 0):
@@ -610,12 +645,15 @@ class AfModel:
         arrs = [np.ascontiguousarray(np.asarray(state[k], np.float32)) for k in ("params", "m", "v")]
         _check(lib.hv_af_model_load(self.handle, *[a.ctypes.data_as(f) for a in arrs], int(state["step"])))
 
-    def predict(self, holo: torch.Tensor, wavelength: float, pitch: float, tau: float):
+    def predict(self, holo: torch.Tensor, wavelength: float, pitch: float, tau: float, refine: int = 0,
+                refine_k: float = 2.5):
+        """(z, sigma, used_fallback, n_fallback); refine > 0 adds the local
+        scan of `refine` candidates seeded by the network (z +- refine_k sigma)."""
         n = holo.shape[0]
         z = torch.empty(n, dtype=torch.float32, device=holo.device)
         sig = torch.empty(n, dtype=torch.float32, device=holo.device)
         used = torch.empty(n, dtype=torch.int32, device=holo.device)
         nf = C.c_int(0)
-        _check(lib.hv_af_predict(self.handle, _ptr(holo), n, wavelength, pitch, tau, _ptr(z), _ptr(sig),
-                                 _ptr(used), C.byref(nf), _stream(holo.device)))
+        _check(lib.hv_af_predict(self.handle, _ptr(holo), n, wavelength, pitch, tau, refine, refine_k, _ptr(z),
+                                 _ptr(sig), _ptr(used), C.byref(nf), _stream(holo.device)))
         return z, sig, used, nf.value
