@@ -424,24 +424,55 @@ def precision_case(hv, torch, steps):
         ms_s = _timed_passes(torch, stft, steps)
         ms_p = _timed_passes(torch, pca, steps)
         ms_a = _timed_passes(torch, ssa, steps)
-        ctx.set_timing(True)
-        stft()
-        pca()
-        ssa()
-        torch.cuda.synchronize()
         kern = {}
-        for k in ("fresnel_rows", "fresnel_cols", "field_coef", "gram", "jacobi", "proj_energy", "ssa_moments"):
-            ms, cnt = ctx.kernel_time(k)
-            if cnt == 0:
-                continue
-            kern[k] = {"launches": cnt, "avg_ms": ms / cnt}
-            if k in flops:
-                tf = flops[k] * npix * nwin / (ms * 1e-3) / 1e12
-                kern[k].update({"useful_TFLOPs": tf, "mfma_peak_TFLOPs": MFMA_PEAK_TFLOPS[name],
-                                "frac": tf / MFMA_PEAK_TFLOPS[name]})
+        # per path: the launches of one pass, timed by events on their own
+        # streams (two streams share the GPU, so a launch's time includes the
+        # time it shares it)
+        for path, fn in (("stft", stft), ("pca", pca), ("ssa", ssa)):
+            ctx.set_timing(True)
+            fn()
+            torch.cuda.synchronize()
+            kp = {}
+            for k in ("fresnel_rows", "fresnel_cols", "field_coef", "gram", "jacobi", "proj_energy", "ssa_moments"):
+                ms, cnt = ctx.kernel_time(k)
+                if cnt == 0:
+                    continue
+                kp[k] = {"launches": cnt, "avg_ms": ms / cnt}
+                if k in flops:
+                    tf = flops[k] * npix * nwin / (ms * 1e-3) / 1e12
+                    kp[k].update({"useful_TFLOPs": tf, "mfma_peak_TFLOPs": MFMA_PEAK_TFLOPS[name],
+                                  "frac": tf / MFMA_PEAK_TFLOPS[name]})
+            kern[path] = kp
         ctx.set_timing(False)
+        # alone on one stream: the Fresnel passes (hv_propagate of one window's
+        # frames, field written) and the DFT GEMM on that field in memory
+        fld = torch.empty((w, ny, nx), dtype=torch.complex64, device="cuda")
+        ctx.hv_propagate(x[:w], opt, prec, out=fld)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        for _ in range(steps):
+            ctx.hv_propagate(x[:w], opt, prec, out=fld)
+        torch.cuda.synchronize()
+        alone = {}
+        in_b = 2  # u16 camera values
+        cb = 8 if prec == hv.HV_PREC_FP32 else 4
+        for k, bpp in (("fresnel_rows", in_b + cb), ("fresnel_cols", cb + 8)):
+            ms, cnt = ctx.kernel_time(k)
+            if cnt:
+                gbs = bpp * npix * w / (ms / cnt * 1e-3) / 1e9
+                alone[k] = {"avg_ms": ms / cnt, "bytes_per_launch": bpp * npix * w, "GBs": gbs,
+                            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+        ctx.set_timing(False)
+        tp_f = hv.Temporal(w, w, fs, 2 * fs / w, 31 * fs / w)
+        mo = [torch.empty((1, ny, nx), dtype=torch.float32, device="cuda") for _ in range(3)]
+        ms_g = _timed_passes(torch, lambda: ctx.hv_stft_moments(fld, None, tp_f, prec, out=mo), steps)
+        gemm_b = 8 * npix * w + 12 * npix
+        alone["field_coef_c64_field"] = {"avg_ms": ms_g, "field_GBs": gemm_b / (ms_g * 1e-3) / 1e9,
+                                         "frac_of_hbm_peak": gemm_b / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                         "useful_TFLOPs": flops["field_coef"] * npix / (ms_g * 1e-3) / 1e12}
+        del fld, mo
         out[name] = {"stft_moments_frames_per_s": n / (ms_s * 1e-3), "pca_frames_per_s": n / (ms_p * 1e-3),
-                     "ssa_fft_moments_frames_per_s": n / (ms_a * 1e-3), "kernels": kern}
+                     "ssa_fft_moments_frames_per_s": n / (ms_a * 1e-3), "kernels": kern, "kernels_alone": alone}
         log(f"precision case {name}: {out[name]}")
         m = [t[0].cpu().numpy().astype(np.float64) for t in stft()]
         r = ctx.hv_pca(x[:w], opt, w, w, 1, 63, prec, want_eig=True, want_cov=True)
@@ -680,6 +711,27 @@ def main():
         ctx.set_stft_order(hv.HV_ORDER_FRAMES_FIRST)
         return res
 
+    def large_chunks():
+        """The headline pass with chunks of 512 and 1,024 frames: 384 / 768 MiB
+        (FP32) of intermediate spectra per chunk, two chunks in flight, so
+        every intermediate is evicted from the 256 MiB Infinity Cache before
+        it is read back and the pass-level rate is a rate to and from HBM."""
+        res = {}
+        for chunk in (512, 1024):
+            ctx.set_chunk_frames(chunk)
+            for prec, name in ((hv.HV_PREC_FP32, "fp32"), (hv.HV_PREC_MIXED, "mixed")):
+                ctx.hv_stft_moments(x, opt, tp, prec, out=outs)
+                ms = time_steps(ctx, hv, torch, x, opt, tp, prec, outs, max(3, args.steps // 2))
+                bpf = 25.375 if prec == hv.HV_PREC_FP32 else 13.375
+                gbs = bpf * NY * NX * frames / (ms * 1e-3) / 1e9
+                res[f"{name}_chunk{chunk}"] = {"frames_per_s": frames / (ms * 1e-3), "ms_per_step": ms,
+                                               "pass_level_GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                                               "intermediate_MiB_per_chunk": chunk * NY * NX * 1.5 *
+                                               (8 if prec == hv.HV_PREC_FP32 else 4) / 2 ** 20}
+            log(f"chunk {chunk}: {res}")
+        ctx.set_chunk_frames(0)
+        return res
+
     def roofline(r):
         name, k = max(r["kernels"].items(), key=lambda kv: kv[1]["total_ms_per_step"])
         return {"bound": "hbm", "kernel": name, "achieved": k["achieved_GBs"], "peak": HBM_PEAK_GBS,
@@ -728,6 +780,7 @@ def main():
             "mixed": {"value": bmix["frames_per_s"], "ms_per_step": bmix["ms_per_step"],
                       "speedup_vs_fp32": bmix["frames_per_s"] / bf32["frames_per_s"], "kernels": bmix["kernels"]},
             "kernels_fp32": bf32["kernels"]},
+        "pass_level_hbm_large_chunks": large_chunks(),
         "hbm_copy": copy_rate(torch),
         "kernels_alone_fp32": isolated_kernels(ctx, hv, torch, x, opt, max(1, args.steps // 2)),
         "bins_image": bins_image_rate(ctx, hv, torch),

@@ -512,7 +512,8 @@ hv_status hv_af_train_step(hv_af_model* model, const void* crops, const float* z
 /* The scan of hv_af_scan over per-hologram ranges: n_candidates distances
  * evenly spaced in [z_lo[i], z_hi[i]] (device float32 [n] each) for
  * hologram i; transfer functions from an FP64 table of
- * 2 pi sqrt(1/lambda^2 - |f|^2), phase and sine/cosine in FP64 on the device.
+ * 2 pi sqrt(1/lambda^2 - |f|^2); the phase is reduced modulo 2 pi in FP64 on
+ * the device and its sine and cosine taken in FP32.
  * z_out[n], scores_out [n][n_candidates] (nullable). */
 hv_status hv_af_scan_ranges(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, double wavelength_m,
                             double pitch_m, const float* z_lo, const float* z_hi, int n_candidates, float* z_out,

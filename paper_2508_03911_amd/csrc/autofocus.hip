@@ -153,7 +153,8 @@ __global__ __launch_bounds__(512) void k_af_subband(const float2* __restrict__ t
 // or, when zlo is not null, candidate c of hologram n at
 // z = zlo[n] + (zhi[n] - zlo[n]) c / (nc - 1), H = exp(-i z kz) with
 // kz = 2 pi sqrt(1/lambda^2 - |f|^2) from the FP64 table kz (negative:
-// evanescent, H = 0), phase and sine/cosine in FP64.
+// evanescent, H = 0), the phase reduced modulo 2 pi in FP64, its sine and
+// cosine in FP32.
 template <int CPB>
 __global__ __launch_bounds__(256) void k_af_scan(const float2* __restrict__ sub, const float2* __restrict__ htab,
                                                  const double* __restrict__ kz, const float* __restrict__ zlo,
@@ -177,9 +178,13 @@ __global__ __launch_bounds__(256) void k_af_scan(const float2* __restrict__ sub,
         const double k = kz[q];
         float2 h = make_float2(0.f, 0.f);
         if (k >= 0.0) {
-          double sn, cs;
-          sincos(-zc * k, &sn, &cs);
-          h = make_float2((float)cs, (float)sn);
+          // the phase (millions of radians) reduced modulo 2 pi in FP64, then
+          // the sine and cosine of the reduced angle in FP32
+          const double ph = -zc * k;
+          const double r = ph - 6.283185307179586 * rint(ph * 0.15915494309189535);
+          float sn, cs;
+          sincosf((float)r, &sn, &cs);
+          h = make_float2(cs, sn);
         }
         A[(q / SUB) * S + skew(q % SUB)] = c2::mul(sv[q], h);
       }
@@ -791,9 +796,12 @@ struct hv_af_model {
   float *d1 = nullptr, *d2 = nullptr;
   float *part_w = nullptr, *part_b = nullptr, *hpart = nullptr, *loss_b = nullptr, *out = nullptr, *zn = nullptr;
   float* loss_tmp = nullptr;
-  _Float16* act16[2] = {nullptr, nullptr};  // inference activations, NHWC fp16
-  float* pooled = nullptr;                   // [max_batch][16 tiles][32]
+  int infer_batch = 0;                       // batch of the inference kernels (>= max_batch)
+  _Float16* act16[2] = {nullptr, nullptr};  // inference activations, NHWC fp16 [infer_batch]
+  float* pooled = nullptr;                   // [infer_batch][16 tiles][32]
+  float* iout = nullptr;                     // [infer_batch][2] inference outputs
   void* wfrag = nullptr;                     // B fragments of the inference pass
+  int64_t version = 0, packed = -1;          // parameter version, and the one wfrag was packed from
   std::vector<void*> owned;
 };
 
@@ -828,7 +836,10 @@ hv_status forward(hv_af_model* md, const _Float16* crops, int bsz, bool train, h
 // forward(.., false, ..) up to fp16 rounding.
 hv_status infer(hv_af_model* md, const _Float16* crops, int bsz, hipStream_t st) {
   const h8v* wf = (const h8v*)md->wfrag;
-  hipLaunchKernelGGL(k_pack_weights, dim3((IKS * 64 + 255) / 256), dim3(256), 0, st, md->params, (h8v*)md->wfrag);
+  if (md->packed != md->version) {  // weights repacked only after they change
+    hipLaunchKernelGGL(k_pack_weights, dim3((IKS * 64 + 255) / 256), dim3(256), 0, st, md->params, (h8v*)md->wfrag);
+    md->packed = md->version;
+  }
   const dim3 grid(16, bsz);
   hipLaunchKernelGGL((k_conv_mfma<1, false>), grid, dim3(256), 0, st, crops, wf, md->params, OFF_B[0],
                      md->act16[0], nullptr);
@@ -838,7 +849,7 @@ hv_status infer(hv_af_model* md, const _Float16* crops, int bsz, hipStream_t st)
                      OFF_B[2], md->act16[0], nullptr);
   hipLaunchKernelGGL((k_conv_mfma<NCH, true>), grid, dim3(256), 0, st, md->act16[0], wf + 64 * 37, md->params,
                      OFF_B[3], nullptr, md->pooled);
-  hipLaunchKernelGGL(k_head_pooled, dim3((bsz + 63) / 64), dim3(64), 0, st, md->pooled, md->params, bsz, md->out);
+  hipLaunchKernelGGL(k_head_pooled, dim3((bsz + 63) / 64), dim3(64), 0, st, md->pooled, md->params, bsz, md->iout);
   return launched("af inference");
 }
 
@@ -1044,6 +1055,10 @@ hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batc
   md->max_batch = max_batch;
   md->z_mean = z_mean;
   md->z_scale = z_scale;
+  // inference runs in larger batches than training: its fp16 activations
+  // are a quarter of the training set's per sample
+  md->infer_batch = std::max(max_batch, 1024);
+  const size_t ib = (size_t)md->infer_batch;
   hv_status s;
   const size_t act = (size_t)max_batch * NCH * HW * 4;
   // any batch <= max_batch uses at most SPLITS splits (ceil(b / ceil(b / SPLITS)) <= SPLITS)
@@ -1064,9 +1079,9 @@ hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batc
       (s = dev_alloc(md, (void**)&md->loss_b, (size_t)max_batch * 4)) ||
       (s = dev_alloc(md, (void**)&md->out, (size_t)max_batch * 8)) ||
       (s = dev_alloc(md, (void**)&md->zn, (size_t)max_batch * 4)) || (s = dev_alloc(md, (void**)&md->loss_tmp, 4)) ||
-      (s = dev_alloc(md, (void**)&md->act16[0], (size_t)max_batch * NCH * HW * 2)) ||
-      (s = dev_alloc(md, (void**)&md->act16[1], (size_t)max_batch * NCH * HW * 2)) ||
-      (s = dev_alloc(md, (void**)&md->pooled, (size_t)max_batch * 16 * NCH * 4)) ||
+      (s = dev_alloc(md, (void**)&md->act16[0], ib * NCH * HW * 2)) ||
+      (s = dev_alloc(md, (void**)&md->act16[1], ib * NCH * HW * 2)) ||
+      (s = dev_alloc(md, (void**)&md->pooled, ib * 16 * NCH * 4)) || (s = dev_alloc(md, (void**)&md->iout, ib * 8)) ||
       (s = dev_alloc(md, &md->wfrag, (size_t)IKS * 64 * 16)))
     return fail_out(s);
   if (hipMemcpy(md->params, init_params, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess ||
@@ -1106,6 +1121,7 @@ hv_status hv_af_model_load(hv_af_model* md, const float* params, const float* m,
       (v && hipMemcpy(md->v, v, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess))
     return fail(HV_ERR_DEVICE, "state upload failed");
   md->step = step;
+  md->version += 1;
   return HV_OK;
 }
 
@@ -1123,12 +1139,13 @@ hv_status hv_af_forward(hv_af_model* md, const void* crops, int batch, float* ou
 
 hv_status hv_af_infer(hv_af_model* md, const void* crops, int batch, float* out, void* hip_stream) {
   if (!md || !crops || !out) return fail(HV_ERR_ARG, "NULL argument");
-  if (batch <= 0 || batch > md->max_batch) return fail(HV_ERR_SHAPE, "batch %d outside [1, %d]", batch, md->max_batch);
+  if (batch <= 0 || batch > md->infer_batch)
+    return fail(HV_ERR_SHAPE, "batch %d outside [1, %d]", batch, md->infer_batch);
   if (hipSetDevice(md->ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)hip_stream;
   hv_status s = infer(md, (const _Float16*)crops, batch, st);
   if (s) return s;
-  if (hipMemcpyAsync(out, md->out, (size_t)batch * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+  if (hipMemcpyAsync(out, md->iout, (size_t)batch * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return fail(HV_ERR_DEVICE, "output copy failed");
   return HV_OK;
 }
@@ -1152,6 +1169,7 @@ hv_status hv_af_train_step(hv_af_model* md, const void* crops, const float* z_m,
   if (s) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   md->step += 1;
+  md->version += 1;
   const float c1 = (float)(1.0 - std::pow(0.9, (double)md->step));
   const float c2 = (float)(1.0 - std::pow(0.999, (double)md->step));
   hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, md->params, md->m, md->v, md->grad,
@@ -1174,7 +1192,7 @@ hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wave
   DevBuf& cb = ctx->work(st, 23);
   DevBuf& sg = ctx->work(st, 24);
   hv_status s;
-  if ((s = cb.ensure((size_t)md->max_batch * HW * 2, &ctx->held))) return s;
+  if ((s = cb.ensure((size_t)md->infer_batch * HW * 2, &ctx->held))) return s;
   if ((s = sg.ensure((size_t)n * 4, &ctx->held))) return s;
   float2* subs = nullptr;
   const double* kz = nullptr;
@@ -1187,14 +1205,14 @@ hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wave
   float* sigma = sigma_out ? sigma_out : (float*)sg.ptr;
   if (used_fallback && hipMemsetAsync(used_fallback, 0, (size_t)n * sizeof(int), st) != hipSuccess)
     return fail(HV_ERR_DEVICE, "memset failed");
-  for (int b0 = 0; b0 < n; b0 += md->max_batch) {
-    const int bs = std::min(md->max_batch, n - b0);
+  for (int b0 = 0; b0 < n; b0 += md->infer_batch) {
+    const int bs = std::min(md->infer_batch, n - b0);
     if ((s = hv_af_crops(ctx, holo + (size_t)b0 * AN * AN, bs, AN, AN, cb.ptr, 1, st))) return s;
     if (refine)  // the +1-order sub-band from the same spectrum the crops came from
       hipLaunchKernelGGL(k_af_subband, dim3(bs), dim3(512), 0, st, (const float2*)ctx->work(st, 20).ptr,
                          subs + (size_t)b0 * SUB * SUB);
     if ((s = infer(md, (const _Float16*)cb.ptr, bs, st))) return s;
-    hipLaunchKernelGGL(k_af_denorm, dim3((bs + 255) / 256), dim3(256), 0, st, md->out, bs, (float)md->z_mean,
+    hipLaunchKernelGGL(k_af_denorm, dim3((bs + 255) / 256), dim3(256), 0, st, md->iout, bs, (float)md->z_mean,
                        (float)md->z_scale, z_out + b0, sigma + b0);
   }
   if (refine) {
