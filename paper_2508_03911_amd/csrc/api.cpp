@@ -759,10 +759,15 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
       if ((s = tb.ensure((size_t)nf * frame * (mix ? 4 : 8), &ctx->held))) return s;
       const float s1 = mix ? fp16_row_scale(in_t, ny, nx) : 1.0f;
       const float2* q = (const float2*)p->tables.ptr;
-      if ((s = launch_rows_c2c(src, in_t, tb.ptr, mix, q, q + nx, dir, nf, ny, nx, s1, st))) return s;
+      if ((s = timed(ctx, "fresnel_rows", st, [&] {
+             return launch_rows_c2c(src, in_t, tb.ptr, mix, q, q + nx, dir, nf, ny, nx, s1, st);
+           })))
+        return s;
       const float unit = (float)(1.0 / std::sqrt((double)nx * ny));
-      if ((s = launch_fresnel_cols(tb.ptr, mix, dst, false, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
-                                   unit / s1, st)))
+      if ((s = timed(ctx, "fresnel_cols", st, [&] {
+             return launch_fresnel_cols(tb.ptr, mix, dst, false, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
+                                        unit / s1, st);
+           })))
         return s;
     }
   }

@@ -260,21 +260,21 @@ constexpr int TPIX = NT / 2;  // pixel counts must be a multiple of this
 
 // Threads per block: one 32-pixel tile per wave, so a block covers
 // threads / 2 pixels.  A W = 64 tile of 256 pixels fills 140 KB of LDS and
-// leaves one block per CU, its loads and its MFMAs in turn.  HALF halves it
+// leaves one block per CU, its loads and its MFMAs in turn.  DIV = 2 halves it
 // (128 pixels, four waves, 67 KB) so that two blocks share a CU and one's
 // loads run under the other's MFMAs.  Measured on 1024^2 fields: the STFT
 // GEMM 0.50 -> 0.445 ms per window with it; the PCA projection ran faster
 // too, but its pass slower (it shares the chip with the other stream's
 // eigensolve and covariance), so that one keeps the full tile.
-template <int W, bool HALF>
+template <int W, int DIV>
 constexpr int coef_threads() {
-  return HALF && W >= 64 ? NT / 2 : NT;
+  return W >= 64 ? NT / DIV : NT;
 }
 
-template <int W, bool MIXED, typename TIN, bool HALF>
-__global__ __launch_bounds__((coef_threads<W, HALF>())) void k_field_coef(const TIN* __restrict__ u, long npix,
+template <int W, bool MIXED, typename TIN, int DIV>
+__global__ __launch_bounds__((coef_threads<W, DIV>())) void k_field_coef(const TIN* __restrict__ u, long npix,
                                                                         int stride, CoefArgs g) {
-  constexpr int NTB = coef_threads<W, HALF>(), TP = NTB / 2;
+  constexpr int NTB = coef_threads<W, DIV>(), TP = NTB / 2;
   constexpr int S = lds_stride(TP);
   constexpr bool EXACT = MIXED && sizeof(TIN) == 4;  // fp16 storage is exact in fp16
   __shared__ float2 buf[W * S];
@@ -798,15 +798,15 @@ hv_status go_rowinv_w(const void* z, bool half_in, int ny, int nx, int stride, i
   return hvi::fail(HV_ERR_SHAPE, "nx=%d not supported", nx);
 }
 
-template <int W, bool MIXED, bool HALF = false>
+template <int W, bool MIXED, int DIV = 1>
 void go_field(const void* u, bool half_in, long npix, int stride, int nwin, const CoefArgs& a, hipStream_t st) {
-  constexpr int NTB = coef_threads<W, HALF>();
+  constexpr int NTB = coef_threads<W, DIV>();
   dim3 grid((unsigned)(npix / (NTB / 2)), nwin);
   if (half_in)
-    hipLaunchKernelGGL((k_field_coef<W, MIXED, hv_h2, HALF>), grid, dim3(NTB), 0, st, (const hv_h2*)u, npix,
+    hipLaunchKernelGGL((k_field_coef<W, MIXED, hv_h2, DIV>), grid, dim3(NTB), 0, st, (const hv_h2*)u, npix,
                        stride, a);
   else
-    hipLaunchKernelGGL((k_field_coef<W, MIXED, float2, HALF>), grid, dim3(NTB), 0, st, (const float2*)u, npix,
+    hipLaunchKernelGGL((k_field_coef<W, MIXED, float2, DIV>), grid, dim3(NTB), 0, st, (const float2*)u, npix,
                        stride, a);
 }
 
@@ -859,8 +859,8 @@ static hv_status field_coef(const void* u, bool half_in, long npix, int stride, 
                    : go_field<32, false>(u, half_in, npix, stride, nwin, a, st); break;
     case 64:
       if (half_tile)
-        mixed ? go_field<64, true, true>(u, half_in, npix, stride, nwin, a, st)
-              : go_field<64, false, true>(u, half_in, npix, stride, nwin, a, st);
+        mixed ? go_field<64, true, 2>(u, half_in, npix, stride, nwin, a, st)
+              : go_field<64, false, 2>(u, half_in, npix, stride, nwin, a, st);
       else
         mixed ? go_field<64, true>(u, half_in, npix, stride, nwin, a, st)
               : go_field<64, false>(u, half_in, npix, stride, nwin, a, st);
