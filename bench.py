@@ -651,6 +651,8 @@ def main():
     ap.add_argument("--no-table-iv", action="store_true", help="skip the Table IV measurements")
     ap.add_argument("--no-host-ingest", action="store_true", help="skip the pinned-host (PCIe) measurement")
     ap.add_argument("--no-precision-case", action="store_true", help="skip the 1024x1024 u16 Fresnel W64 case")
+    ap.add_argument("--no-large-chunks", action="store_true",
+                    help="skip the headline pass with chunks larger than the Infinity Cache")
     ap.add_argument("--precision-case-only", action="store_true",
                     help="run only the 1024x1024 u16 Fresnel W64 case and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -780,7 +782,7 @@ def main():
             "mixed": {"value": bmix["frames_per_s"], "ms_per_step": bmix["ms_per_step"],
                       "speedup_vs_fp32": bmix["frames_per_s"] / bf32["frames_per_s"], "kernels": bmix["kernels"]},
             "kernels_fp32": bf32["kernels"]},
-        "pass_level_hbm_large_chunks": large_chunks(),
+        "pass_level_hbm_large_chunks": None if args.no_large_chunks else large_chunks(),
         "hbm_copy": copy_rate(torch),
         "kernels_alone_fp32": isolated_kernels(ctx, hv, torch, x, opt, max(1, args.steps // 2)),
         "bins_image": bins_image_rate(ctx, hv, torch),
