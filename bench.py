@@ -54,9 +54,10 @@ def source_sha() -> str:
     return hashlib.sha256(b"".join(open(os.path.join(d, f), "rb").read() for f in PROFILED_SOURCES)).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, prec: str):
-    """HBM bytes per dispatch from the committed rocprofv3 counter summary,
-    or None when the library sources changed since it was taken."""
+def measured_traffic(kernel: str, prec: str, field: str = "traffic_bytes_per_dispatch"):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, or the DRAM-labelled request counters), or
+    None when the library sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_as_stft32_256x256.json")
     try:
         d = json.load(open(path))
@@ -65,7 +66,13 @@ def measured_traffic(kernel: str, prec: str):
     if d.get("source_sha") != source_sha():
         return None
     k = d.get("kernels", {}).get(kernel, {}).get(prec)
-    return None if k is None else k.get("traffic_bytes_per_dispatch")
+    return None if k is None else k.get(field)
+
+
+TRAFFIC_SOURCE = ("rocprofv3 FETCH_SIZE + WRITE_SIZE per dispatch (profiles/hbm_traffic_as_stft32_256x256.json), "
+                  "scaled by the counts of a 1 GiB device copy; these count L2-to-fabric traffic, Infinity-Cache "
+                  "hits included (no counter on this GPU separates them: the DRAM-labelled request counters "
+                  "TCC_EA0_RDREQ_DRAM_32B / TCC_EA0_WRREQ_WRITE_DRAM_32B read the same bytes)")
 
 
 def log(msg):
@@ -736,8 +743,12 @@ def main():
 
     def roofline(r):
         name, k = max(r["kernels"].items(), key=lambda kv: kv[1]["total_ms_per_step"])
+        dram = measured_traffic(name, "fp32", "dram_read_bytes_per_dispatch")
+        dramw = measured_traffic(name, "fp32", "dram_write_bytes_per_dispatch")
         return {"bound": "hbm", "kernel": name, "achieved": k["achieved_GBs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": k["achieved_GBs"] / HBM_PEAK_GBS, "traffic": measured_traffic(name, "fp32"),
+                "traffic_source": TRAFFIC_SOURCE,
+                "dram_labelled_bytes": None if dram is None or dramw is None else dram + dramw,
                 "algorithmic_bytes_per_launch": k["bytes_per_launch"], "avg_launch_ms": k["avg_ms"]}
 
     def pass_level(r):
