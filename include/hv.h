@@ -27,7 +27,8 @@
  *
  * Ownership and asynchrony
  *   Every data pointer is caller-owned DEVICE memory on the context's
- *   device; the library never frees it.  Plans (FP64-built tables,
+ *   device; the library never frees it.  Input arrays must be 16-byte
+ *   aligned (hipMalloc and torch allocations are; HV_ERR_ARG otherwise).  Plans (FP64-built tables,
  *   coefficient fragments) and workspaces belong to the context and are
  *   allocated on first use for a given shape/setting and stream, then
  *   reused; hv_ctx_destroy frees them.  Calls enqueue work on `hip_stream`
@@ -65,7 +66,8 @@ typedef enum {
 typedef enum {
   HV_U8 = 0,   /* camera frames, 8 bit */
   HV_U16 = 1,  /* camera frames, up to 16 bit (12-bit data low-bit aligned) */
-  HV_C64 = 3   /* complex field, interleaved float32 */
+  HV_C64 = 3,  /* complex field, interleaved float32 */
+  HV_C32H = 4  /* complex field, interleaved fp16, holding U * hv_field_scale(...) */
 } hv_dtype;
 
 typedef enum { HV_AS = 0, HV_FRESNEL = 1 } hv_method;
@@ -152,15 +154,27 @@ hv_status hv_ctx_kernel_time(hv_ctx* ctx, const char* name, double* total_ms, lo
 /* ---------------------------------------------------------------- spatial */
 
 /* Reconstruct n frames (Sec. III-B.1 spatial transformation).
- *   in   [n][ny][nx] of in_t (HV_U8, HV_U16 or HV_C64)
- *   out  [n][ny][nx] c64: angular spectrum U = IDFT2(DFT2(x) H_z) with
- *        H_z = exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)) (0 if
- *        evanescent), or the single-FFT Fresnel transform
- *        U = Q_out DFT_c(x Q_in) / sqrt(nx ny) on the output grid of pitch
- *        lambda|z|/(n pitch) (centred DFT of sign sgn(z)).
- *   prec selects the intermediate storage (see hv_precision). */
+ *   in    [n][ny][nx] of in_t (HV_U8, HV_U16 or HV_C64)
+ *   out   [n][ny][nx] of out_t: angular spectrum U = IDFT2(DFT2(x) H_z)
+ *         with H_z = exp(2 pi i z sqrt(1/lambda^2 - fx^2 - fy^2)) (0 if
+ *         evanescent), or the single-FFT Fresnel transform
+ *         U = Q_out DFT_c(x Q_in) / sqrt(nx ny) on the output grid of pitch
+ *         lambda|z|/(n pitch) (centred DFT of sign sgn(z)).
+ *   out_t HV_C64 (U as float32 pairs) or HV_C32H (U * hv_field_scale(in_t,
+ *         ny, nx) as fp16 pairs: half the bytes, about 3 significant
+ *         digits; the scale keeps every field of a camera input in range,
+ *         a HV_C64 input is taken as |U| < 32768).
+ *   prec  selects the intermediate storage (see hv_precision); any prec
+ *         goes with either out_t. */
 hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
-                       int prec, void* out, void* hip_stream);
+                       int prec, int out_t, void* out, void* hip_stream);
+
+/* The power of two by which an HV_C32H field is multiplied (host call, no
+ * device work): 2^-k with k the smallest integer such that
+ * sqrt(ny nx) * max input value * 2^-k <= 32768, where the max input value
+ * is 255 (HV_U8) or 65535 (HV_U16); a unitary propagation of such frames
+ * cannot exceed sqrt(ny nx) times it.  1 for a HV_C64 input. */
+hv_status hv_field_scale(int in_t, int ny, int nx, float* scale);
 
 /* ---------------------------------------------------------------- temporal */
 
@@ -313,12 +327,18 @@ typedef struct {
  * charged to the context's HBM budget: HV_ERR_BUDGET refuses the stream. */
 hv_status hv_stream_open(hv_ctx* ctx, int ny, int nx, int raw_t, const hv_optics* optics,
                          const hv_temporal* temporal, int prec, int ring_frames, hv_stream** out);
-/* Copy n_frames consecutive frames (device memory) into the ring and launch
- * every window they complete.  arrival_ns[i] (CLOCK_MONOTONIC ns, nullable =
+/* Copy n_frames consecutive frames into the ring and launch every window
+ * they complete.  frames is device memory (copied on the stream's queue,
+ * ordered before the windows; the caller's producer work must be complete)
+ * or host memory: pinned (hipHostMalloc) at the PCIe rate, pageable at a
+ * lower one; host frames are uploaded on a queue of their own and waited
+ * for, so the buffer may be reused on return (Sec. II-B.1, the packet
+ * path from the camera).  arrival_ns[i] (CLOCK_MONOTONIC ns, nullable =
  * now) is the arrival time of frame i, used for latency.  A packet that
  * would overwrite frames still needed returns HV_ERR_OVERFLOW and is counted
- * as dropped; nothing is overwritten silently.  When a window launch fails,
- * or the device reports an error for a launched window, the stream is
+ * as dropped; nothing is overwritten silently.  When a ring copy or a
+ * window launch fails, or the device reports an error for a launched
+ * window, the stream is
  * marked failed: that push returns the launch error and every later push
  * returns HV_ERR_STATE (not counted as drops) until the stream is closed. */
 hv_status hv_stream_push(hv_stream* s, const void* frames, int n_frames, const int64_t* arrival_ns);

@@ -463,6 +463,13 @@ static hv_status check_dtype(int t, bool allow_field) {
 
 static size_t in_elem(int t) { return t == HV_U8 ? 1 : t == HV_U16 ? 2 : 8; }
 
+// The kernels read their inputs in 8- and 16-byte vectors.
+static hv_status check_aligned(const void* p) {
+  if (reinterpret_cast<uintptr_t>(p) % 16)
+    return fail(HV_ERR_ARG, "input pointer %p is not 16-byte aligned", p);
+  return HV_OK;
+}
+
 static hv_status enter(hv_ctx* ctx) {
   if (!ctx) return fail(HV_ERR_ARG, "context is NULL");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice(%d) failed", ctx->device);
@@ -725,28 +732,44 @@ hv_status hv_band_bins(const hv_temporal* tp, int* nbins, int* bins, double* fre
   return HV_OK;
 }
 
+hv_status hv_field_scale(int in_t, int ny, int nx, float* scale) {
+  if (!scale) return fail(HV_ERR_ARG, "NULL argument");
+  if (ny <= 0 || nx <= 0) return fail(HV_ERR_SHAPE, "frame %d x %d", ny, nx);
+  hv_status s;
+  if ((s = check_dtype(in_t, true))) return s;
+  *scale = fp16_field_scale(in_t, ny, nx);
+  return HV_OK;
+}
+
 hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics,
-                       int prec, void* out, void* hip_stream) {
+                       int prec, int out_t, void* out, void* hip_stream) {
   hv_status s;
   if ((s = enter(ctx))) return s;
   std::lock_guard<std::recursive_mutex> lock(ctx->mu);
   if ((s = check_frame(n, ny, nx)) || (s = check_optics(optics)) || (s = check_dtype(in_t, true))) return s;
   if (prec != HV_PREC_FP32 && prec != HV_PREC_MIXED) return fail(HV_ERR_ARG, "unknown precision %d", prec);
+  if (out_t != HV_C64 && out_t != HV_C32H) return fail(HV_ERR_ARG, "output dtype %d is not a field type", out_t);
   if (n == 0) return HV_OK;
   if (!in || !out) return fail(HV_ERR_ARG, "NULL data pointer");
+  if ((s = check_aligned(in))) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   const bool mixed = prec == HV_PREC_MIXED;
+  // an fp16 field holds U * osc, a power of two that keeps every field the
+  // input type can give inside the fp16 range
+  const bool half_out = out_t == HV_C32H;
+  const float osc = half_out ? fp16_field_scale(in_t, ny, nx) : 1.f;
+  const size_t out_elem = half_out ? 4 : 8;
   const int chunk = ctx->chunk_frames_for(ny, nx, mixed);
   const size_t frame = (size_t)ny * nx;
   for (int f0 = 0; f0 < n; f0 += chunk) {
     const int nf = n - f0 < chunk ? n - f0 : chunk;
     const char* src = (const char*)in + (size_t)f0 * frame * in_elem(in_t);
-    float2* dst = (float2*)out + (size_t)f0 * frame;
+    void* dst = (char*)out + (size_t)f0 * frame * out_elem;
     SpatialOut so;
     if (optics->method == HV_AS) {
       if ((s = spatial(ctx, src, in_t, nf, ny, nx, *optics, mixed, false, 1.f, st, so))) return s;
       if ((s = timed(ctx, "row_inv", st, [&] {
-             return launch_row_inv(so.z, so.half, dst, false, nf, ny, nx, so.z_to_field, st);
+             return launch_row_inv(so.z, so.half, dst, half_out, nf, ny, nx, so.z_to_field * osc, st);
            })))
         return s;
     } else {
@@ -765,8 +788,8 @@ hv_status hv_propagate(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int
         return s;
       const float unit = (float)(1.0 / std::sqrt((double)nx * ny));
       if ((s = timed(ctx, "fresnel_cols", st, [&] {
-             return launch_fresnel_cols(tb.ptr, mix, dst, false, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
-                                        unit / s1, st);
+             return launch_fresnel_cols(tb.ptr, mix, dst, half_out, q + nx + ny, q + 2 * nx + ny, dir, nf, ny, nx,
+                                        unit / s1 * osc, st);
            })))
         return s;
     }
@@ -925,6 +948,7 @@ static hv_status stft_impl(hv_ctx* ctx, const void* in, int in_t, int n, int ny,
   }
   if (n < w) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, w);
   if (!in) return fail(HV_ERR_ARG, "input is NULL");
+  if ((s = check_aligned(in))) return s;
   if (!m0 && !m1 && !m2 && !spec) return fail(HV_ERR_ARG, "no output requested");
   DftPlan* dp = ctx->dft_plan(*tp, &s);
   if (!dp) return s;
@@ -1005,6 +1029,7 @@ hv_status hv_stft_moments_noalloc(hv_ctx* ctx, const void* in, int in_t, int n, 
   }
   if (n < w) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, w);
   if (!in) return fail(HV_ERR_ARG, "input is NULL");
+  if ((s = check_aligned(in))) return s;
   if (!m0 && !m1 && !m2) return fail(HV_ERR_ARG, "no output requested");
   DftPlan* dp = ctx->dft_plan(*tp, &s, false);
   if (!dp) return s;
@@ -1154,6 +1179,7 @@ hv_status hv_stft_volume(hv_ctx* ctx, const void* in, int in_t, int n, int ny, i
   }
   if (n < window) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, window);
   if (!in || !power) return fail(HV_ERR_ARG, "NULL data pointer");
+  if ((s = check_aligned(in))) return s;
   const bool mixed = prec == HV_PREC_MIXED;
   const int w = window;
   const int nwin_total = (n - w) / stride + 1;
@@ -1363,7 +1389,7 @@ static hv_status check_eig_call(int n, int ny, int nx, const hv_optics* optics, 
   }
   if (n < window) return fail(HV_ERR_SHAPE, "%d frames hold no complete window of %d", n, window);
   if (!in) return fail(HV_ERR_ARG, "input is NULL");
-  return HV_OK;
+  return check_aligned(in);
 }
 
 hv_status hv_pca(hv_ctx* ctx, const void* in, int in_t, int n, int ny, int nx, const hv_optics* optics, int window,

@@ -1325,7 +1325,7 @@ hv_status hv_af_synthesize(hv_ctx* ctx, int n, const double* z_m, double wavelen
       while (j < cn && z_m[c0 + j] == z_m[c0 + i]) ++j;
       hv_optics op{wavelength_m, pitch_m, pitch_m, z_m[c0 + i], HV_AS};
       if ((s = hv_propagate(ctx, (const float2*)fa.ptr + (size_t)i * AN * AN, HV_C64, j - i, AN, AN, &op,
-                            HV_PREC_FP32, (float2*)fb.ptr + (size_t)i * AN * AN, st)))
+                            HV_PREC_FP32, HV_C64, (float2*)fb.ptr + (size_t)i * AN * AN, st)))
         return s;
       i = j;
     }

@@ -46,6 +46,7 @@ struct hv_stream {
   int keep_ready = 4;    // completed, unpopped images kept
   hvs::RingLogic ring;
   hipStream_t st = nullptr;
+  hipStream_t up = nullptr;  // uploads of frames pushed from host memory
   void* ring_dev = nullptr;
   float* out_dev[3] = {nullptr, nullptr, nullptr};
   size_t admitted_bytes = 0;
@@ -314,10 +315,12 @@ hv_status hv_stream_open(hv_ctx* ctx, int ny, int nx, int raw_t, const hv_optics
     for (float* p : st->out_dev)
       if (p) (void)hipFree(p);
     if (st->st) (void)hipStreamDestroy(st->st);
+    if (st->up) (void)hipStreamDestroy(st->up);
     delete st;
     return e;
   };
-  if (hipStreamCreateWithFlags(&st->st, hipStreamNonBlocking) != hipSuccess)
+  if (hipStreamCreateWithFlags(&st->st, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&st->up, hipStreamNonBlocking) != hipSuccess)
     return undo(fail(HV_ERR_DEVICE, "hipStreamCreate failed"));
   if (hipMalloc(&st->ring_dev, ring_b) != hipSuccess) return undo(fail(HV_ERR_NOMEM, "ring allocation failed"));
   for (int i = 0; i < 3; ++i)
@@ -367,11 +370,32 @@ hv_status hv_stream_push(hv_stream* s, const void* frames, int n_frames, const i
     sv->frames_dropped += n_frames;
     return fail(HV_ERR_OVERFLOW, "ring full: %d frames refused", n_frames);
   }
+  // Device frames are copied on the stream's own queue, ahead of the
+  // windows they complete.  Host frames (pinned, or pageable at a lower
+  // rate) go up on the upload queue and are waited for, so the caller may
+  // reuse the buffer on return and the windows launched below see them.
+  // Either way the slots written hold no frame of an unfinished window.
+  bool on_host = true;
+  if (!copies.empty()) {
+    hipPointerAttribute_t pa{};
+    if (hipPointerGetAttributes(&pa, frames) == hipSuccess)
+      on_host = !(pa.type == hipMemoryTypeDevice || pa.type == hipMemoryTypeManaged);
+    else
+      (void)hipGetLastError();  // not known to HIP: pageable host memory
+  }
   for (const hvs::Span& c : copies) {
     const char* src = (const char*)frames + (size_t)(c.first_frame - first) * s->frame_bytes;
     char* dst = (char*)s->ring_dev + (size_t)c.slot * s->frame_bytes;
-    if (hipMemcpyAsync(dst, src, (size_t)c.count * s->frame_bytes, hipMemcpyDeviceToDevice, s->st) != hipSuccess)
+    if (hipMemcpyAsync(dst, src, (size_t)c.count * s->frame_bytes,
+                       on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, on_host ? s->up : s->st) !=
+        hipSuccess) {
+      s->ring.set_failed();
       return fail(HV_ERR_DEVICE, "ring copy failed");
+    }
+  }
+  if (on_host && !copies.empty() && hipStreamSynchronize(s->up) != hipSuccess) {
+    s->ring.set_failed();
+    return fail(HV_ERR_DEVICE, "ring upload failed: %s", hipGetErrorString(hipGetLastError()));
   }
   sv->frames_in += n_frames;
   return launch_ready(s);
@@ -464,6 +488,7 @@ hv_status hv_stream_close(hv_stream* s) {
   (void)hipFree(s->ring_dev);
   for (float* p : s->out_dev) (void)hipFree(p);
   (void)hipStreamDestroy(s->st);
+  (void)hipStreamDestroy(s->up);
   delete s;
   return res;
 }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhv.so")
 
 HV_OK, HV_ERR_ARG, HV_ERR_SHAPE, HV_ERR_NOMEM, HV_ERR_BUDGET, HV_ERR_DEVICE, HV_ERR_OVERFLOW, HV_ERR_STATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
-HV_U8, HV_U16, HV_C64 = 0, 1, 3
+HV_U8, HV_U16, HV_C64, HV_C32H = 0, 1, 3, 4
 HV_AS, HV_FRESNEL = 0, 1
 HV_PREC_FP32, HV_PREC_MIXED = 0, 1
 HV_ORDER_AUTO, HV_ORDER_FRAMES_FIRST, HV_ORDER_BAND_FIRST = 0, 1, 2
@@ -109,7 +109,8 @@ _sig = {
     "hv_ctx_set_timing": (_I, [_P, _I]),
     "hv_ctx_kernel_time": (_I, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_long)]),
     "hv_band_bins": (_I, [C.POINTER(hv_temporal), C.POINTER(_I), C.POINTER(_I), C.POINTER(C.c_double)]),
-    "hv_propagate": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _P, _P]),
+    "hv_propagate": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), _I, _I, _P, _P]),
+    "hv_field_scale": (_I, [_I, _I, _I, C.POINTER(C.c_float)]),
     "hv_stft_moments": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P, _P, _P,
                              _P]),
     "hv_stft_moments_noalloc": (_I, [_P, _P, _I, _I, _I, _I, C.POINTER(hv_optics), C.POINTER(hv_temporal), _I, _P,
@@ -263,6 +264,13 @@ def band_bins(temporal: Temporal):
     return list(bins)[:n.value], list(freqs)[:n.value]
 
 
+def field_scale(in_t: int, ny: int, nx: int) -> float:
+    """The power of two an HV_C32H field holds U multiplied by."""
+    v = C.c_float(0)
+    _check(lib.hv_field_scale(in_t, ny, nx, C.byref(v)))
+    return v.value
+
+
 class Context:
     """One hv_ctx on a HIP device (plans and workspaces live here)."""
 
@@ -308,13 +316,24 @@ class Context:
         return torch.device("cuda", self.device)
 
     # ---------------------------------------------------------------- spatial
-    def hv_propagate(self, x: torch.Tensor, optics: Optics, prec: int = HV_PREC_FP32, out=None) -> torch.Tensor:
+    def hv_propagate(self, x: torch.Tensor, optics: Optics, prec: int = HV_PREC_FP32, out=None,
+                     out_dtype: int = HV_C64) -> torch.Tensor:
+        """The field as complex64 [n, ny, nx] (HV_C64), or as float16
+        [n, ny, nx, 2] (re, im) holding U * field_scale(...) (HV_C32H)."""
         n, ny, nx = _frames(x)
         if out is None:
-            out = torch.empty((n, ny, nx), dtype=torch.complex64, device=x.device)
+            if out_dtype == HV_C32H:
+                out = torch.empty((n, ny, nx, 2), dtype=torch.float16, device=x.device)
+            else:
+                out = torch.empty((n, ny, nx), dtype=torch.complex64, device=x.device)
+        want = (n, ny, nx, 2) if out_dtype == HV_C32H else (n, ny, nx)
+        want_t = torch.float16 if out_dtype == HV_C32H else torch.complex64
+        if out_dtype in (HV_C64, HV_C32H) and (tuple(out.shape) != want or out.dtype != want_t
+                                               or not out.is_contiguous()):
+            raise ValueError(f"out must be a contiguous {want_t} tensor of shape {want}")
         op = optics.c()
-        _check(lib.hv_propagate(self.handle, _ptr(x), _dtype_code(x), n, ny, nx, C.byref(op), prec, _ptr(out),
-                                _stream(x.device)))
+        _check(lib.hv_propagate(self.handle, _ptr(x), _dtype_code(x), n, ny, nx, C.byref(op), prec, out_dtype,
+                                _ptr(out), _stream(x.device)))
         return out
 
     # ---------------------------------------------------------------- temporal
@@ -545,17 +564,26 @@ class Stream:
     def __init__(self, ctx: Context, handle, ny: int, nx: int):
         self.ctx, self.handle, self.ny, self.nx = ctx, handle, ny, nx
 
+    @staticmethod
+    def _ready(frames: torch.Tensor):
+        if not frames.is_contiguous():
+            raise ValueError("frames must be contiguous")
+        # a device copy is ordered on the stream's queue: the caller's
+        # producer work must be complete; host frames (pinned or pageable)
+        # are uploaded and waited for inside the push
+        if frames.is_cuda:
+            torch.cuda.current_stream(frames.device).synchronize()
+
     def push(self, frames: torch.Tensor, arrival_ns=None):
         n = frames.shape[0]
         arr = None
         if arrival_ns is not None:
             arr = (C.c_int64 * n)(*[int(a) for a in arrival_ns])
-        # the copy is ordered on the stream; the caller's producer work must be complete
-        torch.cuda.current_stream(frames.device).synchronize()
+        self._ready(frames)
         _check(lib.hv_stream_push(self.handle, _ptr(frames), n, arr))
 
     def try_push(self, frames: torch.Tensor) -> int:
-        torch.cuda.current_stream(frames.device).synchronize()
+        self._ready(frames)
         return lib.hv_stream_push(self.handle, _ptr(frames), frames.shape[0], None)
 
     def pop(self, m0=None, m1=None, m2=None):

@@ -51,3 +51,26 @@ def test_context_without_device_fails_cleanly():
         assert e.status in (hv.HV_ERR_DEVICE, hv.HV_ERR_ARG)
     else:
         raise AssertionError("context creation must fail without a device")
+
+
+def test_field_scale_host_call():
+    # the fp16 field scale is the largest power of two that keeps the bound
+    # sqrt(ny nx) * max camera value of a unitary propagation below 32768
+    import math
+    from paper_2508_03911_amd import hv
+    for t, maxv in [(hv.HV_U8, 255.0), (hv.HV_U16, 65535.0)]:
+        for ny, nx in [(64, 64), (256, 256), (800, 1280), (1024, 1024), (320, 512)]:
+            s = hv.field_scale(t, ny, nx)
+            k = -math.log2(s)
+            assert k == int(k) and k >= 0
+            assert math.sqrt(ny * nx) * maxv * s <= 32768.0
+            assert k == 0 or math.sqrt(ny * nx) * maxv * 2 * s > 32768.0
+    assert hv.field_scale(hv.HV_C64, 1024, 1024) == 1.0
+    assert hv.field_scale(hv.HV_U8, 256, 256) == 0.5
+    for bad in [(7, 64, 64), (hv.HV_C32H, 64, 64), (hv.HV_U8, 0, 64)]:
+        try:
+            hv.field_scale(*bad)
+        except hv.HvError:
+            pass
+        else:
+            raise AssertionError(f"field_scale{bad} must fail")

@@ -91,6 +91,50 @@ def _stream_vs_offline(ctx, hv, prec, method, stride):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("source", ["pinned", "pageable", "alternating"])
+def test_stream_host_push_equals_offline(ctx, hv, source, prec):
+    """Frames pushed from host memory: every packet goes through one staging
+    buffer that is overwritten with the next packet as soon as the push
+    returns (pinned or pageable; "alternating" mixes pinned and device
+    packets); the images equal the offline call on the same frames bit for
+    bit."""
+    say(f"stream host push {source} prec={prec}")
+    spec = holograms.HoloSpec(frames=90, ny=128, nx=256, z=0.25, fs=20e3, seed=43)
+    x = holograms.hologram_stack(spec)
+    xd = torch.from_numpy(x).cuda()
+    opt = hv.Optics(LAM, spec.pitch, spec.pitch, -spec.z, hv.HV_AS)
+    tp = hv.Temporal(16, 8, spec.fs, 1e3, 9e3)
+    ref = [t.cpu().numpy() for t in ctx.hv_stft_moments(xd, opt, tp, prec)]
+    j_total = ref[0].shape[0]
+    stage = torch.empty((16, 128, 256), dtype=torch.uint8)
+    if source != "pageable":
+        stage = stage.pin_memory()
+    s = ctx.hv_stream_open(128, 256, torch.uint8, opt, tp, prec, ring_frames=64)
+    got = []
+    pos, i = 0, 0
+    sizes = [5, 7, 13, 1, 16, 3, 9]
+    while pos < 90:
+        n = min(sizes[i % len(sizes)], 90 - pos)
+        if source == "alternating" and i % 2:
+            s.push(xd[pos:pos + n])
+        else:
+            stage[:n].copy_(torch.from_numpy(x[pos:pos + n]))
+            s.push(stage[:n])
+            stage.fill_(0)  # the push has returned: the buffer is the caller's again
+        pos += n
+        i += 1
+        want = 0 if pos < 16 else (pos - 16) // 8 + 1
+        _wait_and_pop(s, want, got, 128, 256)
+    c = s.counters()
+    s.close()
+    assert c["pushed"] == 90 and c["dropped"] == 0 and c["windows_done"] == j_total
+    assert len(got) == j_total
+    for j in range(j_total):
+        for k in range(3):
+            assert np.array_equal(got[j][k], ref[k][j]), (j, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("cls", [1, 2])
 def test_stream_class_equals_offline(ctx, hv, cls, prec):
     """The larger serving classes: 512^2 u8 with W = 32 and 1024 x 512
