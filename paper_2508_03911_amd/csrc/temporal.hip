@@ -354,8 +354,55 @@ __global__ __launch_bounds__(NT) void k_time_fft(const TIN* __restrict__ u, int 
 // ------------------------------------------------------------------ Gram partials (PCA covariance)
 // Block (blk, jj) accumulates G = B^T B over its pixel range for window jj.
 // LDS holds the tile transposed, L[m][p] with m = 2t + c, so both MFMA
-// operands read contiguous pixel runs of one row.
+// operands read contiguous pixel runs of one row.  Each thread loads runs
+// of 4 pixels of one frame (16 bytes of fp16 pairs, 32 of float pairs), and
+// the next tile's runs are loaded into registers before the current tile's
+// MFMAs, so the loads are in flight while the matrix cores work.  Pixel
+// ranges are multiples of GP and frames a multiple of 4 pixels, so a run
+// lies wholly inside or wholly outside the range.
 constexpr int GP = 64;  // pixels per LDS tile
+
+template <typename TIN> struct Run4;
+template <> struct Run4<hv_h2> {  // 4 fp16 pairs: re/im of 4 pixels
+  uint4 w;
+  __device__ void load(const hv_h2* p) { w = *reinterpret_cast<const uint4*>(p); }
+  __device__ void zero() { w = make_uint4(0u, 0u, 0u, 0u); }
+  __device__ hv_h2 pair(int e) const {
+    const uint32_t v = e == 0 ? w.x : e == 1 ? w.y : e == 2 ? w.z : w.w;
+    hv_h2 h;
+    __builtin_memcpy(&h, &v, 4);
+    return h;
+  }
+  __device__ float2 get(int e) const {
+    const hv_h2 h = pair(e);
+    return make_float2((float)h.x, (float)h.y);
+  }
+  // the re (c = 0) or im (c = 1) halves of the 4 pixels, as bit copies
+  __device__ uint2 part4(int c) const {
+    const hv_h2 a = pair(0), b = pair(1), d = pair(2), e = pair(3);
+    hv_h2 lo, hi;
+    lo.x = c ? a.y : a.x;
+    lo.y = c ? b.y : b.x;
+    hi.x = c ? d.y : d.x;
+    hi.y = c ? e.y : e.x;
+    uint2 r;
+    __builtin_memcpy(&r.x, &lo, 4);
+    __builtin_memcpy(&r.y, &hi, 4);
+    return r;
+  }
+};
+template <> struct Run4<float2> {  // 4 float pairs
+  float4 a, b;
+  __device__ void load(const float2* p) {
+    a = reinterpret_cast<const float4*>(p)[0];
+    b = reinterpret_cast<const float4*>(p)[1];
+  }
+  __device__ void zero() { a = b = make_float4(0.f, 0.f, 0.f, 0.f); }
+  __device__ float2 get(int e) const {
+    return e == 0 ? make_float2(a.x, a.y) : e == 1 ? make_float2(a.z, a.w) : e == 2 ? make_float2(b.x, b.y)
+                                                                                   : make_float2(b.z, b.w);
+  }
+};
 
 template <int W, bool MIXED, typename TIN>
 __global__ __launch_bounds__(NT) void k_gram(const TIN* __restrict__ u, long npix, int stride, long pix_per_blk,
@@ -366,6 +413,10 @@ __global__ __launch_bounds__(NT) void k_gram(const TIN* __restrict__ u, long npi
   constexpr int TPW = (T * T + NW - 1) / NW;  // tiles per wave
   constexpr int LS32 = GP + 1;          // f32 row stride (odd)
   constexpr int LS16 = GP + 8;          // fp16 row stride (keeps 16-byte reads aligned)
+  constexpr int RUNS = W * GP / 4;      // 4-pixel runs per tile
+  constexpr int PER = (RUNS + NT - 1) / NT;
+  // fp16 pairs at unit scale go to LDS as bit copies
+  constexpr bool COPY16 = MIXED && sizeof(TIN) == 4;
   __shared__ float l32[MIXED ? 1 : M * LS32];
   __shared__ __attribute__((aligned(16))) _Float16 l16[MIXED ? M * LS16 : 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5;
@@ -379,20 +430,49 @@ __global__ __launch_bounds__(NT) void k_gram(const TIN* __restrict__ u, long npi
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
   const TIN* src = u + (jj * stride) * npix;
+  // run q = tid + i * NT of a tile: frame q / (GP / 4), pixels 4 (q % (GP / 4)) + 0..3
+  Run4<TIN> nxt[PER];
+  auto fetch = [&](long p0) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + i * NT;
+      if (RUNS % NT == 0 || q < RUNS) {
+        const int t = q / (GP / 4), x = 4 * (q % (GP / 4));
+        if (p0 + x < pend)
+          nxt[i].load(src + (long)t * npix + p0 + x);
+        else
+          nxt[i].zero();
+      }
+    }
+  };
+  if (pbeg < pend) fetch(pbeg);
   for (long p0 = pbeg; p0 < pend; p0 += GP) {
-    __syncthreads();
-    for (int q = tid; q < W * GP; q += NT) {
-      const int t = q / GP, x = q % GP;
-      float2 v = (p0 + x < pend) ? load_c(src + (long)t * npix + p0 + x) : make_float2(0.f, 0.f);
-      if constexpr (MIXED) {
-        l16[(2 * t) * LS16 + x] = (_Float16)(v.x * bsc);
-        l16[(2 * t + 1) * LS16 + x] = (_Float16)(v.y * bsc);
-      } else {
-        l32[(2 * t) * LS32 + x] = v.x;
-        l32[(2 * t + 1) * LS32 + x] = v.y;
+    __syncthreads();  // every wave is done reading the previous tile
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + i * NT;
+      if (RUNS % NT == 0 || q < RUNS) {
+        const int t = q / (GP / 4), x = 4 * (q % (GP / 4));
+        if constexpr (COPY16) {
+          *reinterpret_cast<uint2*>(&l16[(2 * t) * LS16 + x]) = nxt[i].part4(0);
+          *reinterpret_cast<uint2*>(&l16[(2 * t + 1) * LS16 + x]) = nxt[i].part4(1);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float2 v = nxt[i].get(e);
+            if constexpr (MIXED) {
+              l16[(2 * t) * LS16 + x + e] = (_Float16)(v.x * bsc);
+              l16[(2 * t + 1) * LS16 + x + e] = (_Float16)(v.y * bsc);
+            } else {
+              l32[(2 * t) * LS32 + x + e] = v.x;
+              l32[(2 * t + 1) * LS32 + x + e] = v.y;
+            }
+          }
+        }
       }
     }
     __syncthreads();
+    if (p0 + GP < pend) fetch(p0 + GP);
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int tile = wave + NW * i;
@@ -880,7 +960,9 @@ hv_status launch_field_coef(const void* u, bool half_in, long npix, int stride, 
 hv_status launch_gram_partials(const void* u, bool half_in, long npix, int stride, int nwin, int window,
                                bool mixed, float b_scale, float* part, int nblk, hipStream_t st) {
   if (nwin <= 0) return HV_OK;
-  const long ppb = (npix + nblk - 1) / nblk;
+  if (npix % 4) return fail(HV_ERR_SHAPE, "frame of %ld pixels: a multiple of 4 is needed", npix);
+  // pixel ranges in whole tiles (the last blocks may get fewer pixels, or none)
+  const long ppb = ((npix + nblk - 1) / nblk + GP - 1) / GP * GP;
   switch (window) {
     case 16: mixed ? go_gram<16, true>(u, half_in, npix, stride, nwin, ppb, b_scale, part, nblk, st)
                    : go_gram<16, false>(u, half_in, npix, stride, nwin, ppb, b_scale, part, nblk, st); break;
