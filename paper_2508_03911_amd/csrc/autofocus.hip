@@ -150,16 +150,18 @@ __global__ __launch_bounds__(512) void k_af_subband(const float2* __restrict__ t
 
 // Sharpness of the reconstruction for CPB candidates per block.  Transfer
 // functions: from htab [nc][SUB][SUB] (candidates shared by every hologram),
-// or, when zlo is not null, candidate c of hologram n at
+// or, with RANGES, candidate c of hologram n at
 // z = zlo[n] + (zhi[n] - zlo[n]) c / (nc - 1), H = exp(-i z kz) with
 // kz = 2 pi sqrt(1/lambda^2 - |f|^2) from the FP64 table kz (negative:
-// evanescent, H = 0), the phase reduced modulo 2 pi in FP64, its sine and
-// cosine in FP32.
-template <int CPB>
+// evanescent, H = 0).  The candidates of a block are equally spaced, so H
+// of the first one and the step factor exp(-i dz kz) are formed once per
+// pixel (phase reduced modulo 2 pi in FP64, sine and cosine of the reduced
+// angle in FP32) and H advances by one complex product per candidate.
+template <int CPB, bool RANGES>
 __global__ __launch_bounds__(256) void k_af_scan(const float2* __restrict__ sub, const float2* __restrict__ htab,
                                                  const double* __restrict__ kz, const float* __restrict__ zlo,
                                                  const float* __restrict__ zhi, int nc, float* __restrict__ scores) {
-  constexpr int NT = 256, S = lds_stride(SUB);
+  constexpr int NT = 256, S = lds_stride(SUB), QT = SUB * SUB / NT;
   __shared__ float2 A[SUB * S];
   __shared__ float2 B[SUB * S];
   __shared__ float2 tw[tw_size(SUB) > 0 ? tw_size(SUB) : 1];
@@ -168,25 +170,35 @@ __global__ __launch_bounds__(256) void k_af_scan(const float2* __restrict__ sub,
   const long n = blockIdx.x;
   fill_twiddles<SUB>(tw, tid, NT);
   const float2* sv = sub + n * SUB * SUB;
+  // RANGES: H of this block's current candidate and the step factor at the
+  // pixels q = tid + NT j of this thread
+  float2 hcur[RANGES ? QT : 1], hstep[RANGES ? QT : 1];
+  if constexpr (RANGES) {
+    const double z0 = zlo[n], z1 = zhi[n];
+    const double dz = (z1 - z0) / (nc - 1);
+    const double zc = z0 + dz * (blockIdx.y * CPB);
+    auto unit = [](double ph) {
+      const double r = ph - 6.283185307179586 * rint(ph * 0.15915494309189535);
+      float sn, cs;
+      sincosf((float)r, &sn, &cs);
+      return make_float2(cs, sn);
+    };
+#pragma unroll
+    for (int j = 0; j < QT; ++j) {
+      const double k = kz[tid + NT * j];
+      hcur[j] = k >= 0.0 ? unit(-zc * k) : make_float2(0.f, 0.f);
+      hstep[j] = k >= 0.0 ? unit(-dz * k) : make_float2(0.f, 0.f);
+    }
+  }
   for (int cc = 0; cc < CPB; ++cc) {
     const int c = blockIdx.y * CPB + cc;
     if (c >= nc) break;
-    if (zlo) {
-      const double z0 = zlo[n], z1 = zhi[n];
-      const double zc = z0 + (z1 - z0) * c / (nc - 1);
-      for (int q = tid; q < SUB * SUB; q += NT) {
-        const double k = kz[q];
-        float2 h = make_float2(0.f, 0.f);
-        if (k >= 0.0) {
-          // the phase (millions of radians) reduced modulo 2 pi in FP64, then
-          // the sine and cosine of the reduced angle in FP32
-          const double ph = -zc * k;
-          const double r = ph - 6.283185307179586 * rint(ph * 0.15915494309189535);
-          float sn, cs;
-          sincosf((float)r, &sn, &cs);
-          h = make_float2(cs, sn);
-        }
-        A[(q / SUB) * S + skew(q % SUB)] = c2::mul(sv[q], h);
+    if constexpr (RANGES) {
+#pragma unroll
+      for (int j = 0; j < QT; ++j) {
+        const int q = tid + NT * j;
+        A[(q / SUB) * S + skew(q % SUB)] = c2::mul(sv[q], hcur[j]);
+        hcur[j] = c2::mul(hcur[j], hstep[j]);
       }
     } else {
       const float2* h = htab + (long)c * SUB * SUB;
@@ -378,85 +390,115 @@ __global__ void k_pack_weights(const float* __restrict__ params, h8v* __restrict
   wf[q] = v;
 }
 
-// One 16 x 16 output tile of one sample per workgroup of 4 waves; wave w
-// owns tile pixels [64 w, 64 w + 64) as two 32-pixel M tiles.  LAST: no
-// activation is stored; the ReLU outputs of the tile are summed per channel
-// into pooled[sample][tile][32] (the global average pool, finished in the
-// head in a fixed order).
+// Persistent: workgroup g takes units g, g + gridDim.x, ... (unit = one
+// 16 x 16 output tile of one sample) with the layer's B fragments held in
+// registers across units, and loads the next unit's input tile into
+// registers while the current unit's MFMAs run.  Wave w owns tile pixels
+// [64 w, 64 w + 64) as two 32-pixel M tiles.  LAST: no activation is
+// stored; the ReLU outputs of the tile are summed per channel into
+// pooled[sample][tile][32] (the global average pool, finished in the head
+// in a fixed order).
 template <int CIN, bool LAST>
 __global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ in, const h8v* __restrict__ wf,
                                                    const float* __restrict__ params, int boff,
-                                                   _Float16* __restrict__ out, float* __restrict__ pooled) {
+                                                   _Float16* __restrict__ out, float* __restrict__ pooled,
+                                                   int nunits) {
   constexpr int PS = CIN == 1 ? 1 : CIN + 8;  // halves per LDS pixel (80 B: 16-B reads of 16 lanes hit distinct banks)
   constexpr int KS = CIN == 1 ? 1 : 9 * CIN / 16;
+  // input items per unit: 18 x 18 pixels of one half (CIN = 1) or of CIN/8 chunks of 8 channels
+  constexpr int ITEMS = CIN == 1 ? 324 : 324 * (CIN / 8);
+  constexpr int PER = (ITEMS + 255) / 256;
+  using Item = typename std::conditional<CIN == 1, _Float16, h8v>::type;
   __shared__ __attribute__((aligned(16))) _Float16 tile[18 * 18 * PS];
   __shared__ float red[4][32];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31;
-  const int ty0 = (blockIdx.x >> 2) * 16, tx0 = (blockIdx.x & 3) * 16;
-  const long b = blockIdx.y;
-  if constexpr (CIN == 1) {
-    for (int q = tid; q < 324; q += 256) {
-      const int r = q / 18, col = q % 18, y = ty0 + r - 1, x = tx0 + col - 1;
-      tile[q] = (y >= 0 && y < CROP && x >= 0 && x < CROP) ? in[(b * CROP + y) * CROP + x] : (_Float16)0.f;
-    }
-  } else {
-    for (int q = tid; q < 324 * (CIN / 8); q += 256) {
-      const int pix = q / (CIN / 8), ch = q % (CIN / 8);
-      const int r = pix / 18, col = pix % 18, y = ty0 + r - 1, x = tx0 + col - 1;
-      h8v v;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (_Float16)0.f;
-      if (y >= 0 && y < CROP && x >= 0 && x < CROP)
-        v = *reinterpret_cast<const h8v*>(in + ((b * CROP + y) * CROP + x) * CIN + 8 * ch);
-      *reinterpret_cast<h8v*>(tile + pix * PS + 8 * ch) = v;
-    }
-  }
   h8v bw[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s) bw[s] = wf[s * 64 + lane];
   const float bias = params[boff + c];
-  __syncthreads();
-  f32x16 acc[2];
+  Item nxt[PER];
+  auto fetch = [&](int u) {
+    const long b = u >> 4;
+    const int ty0 = ((u & 15) >> 2) * 16, tx0 = (u & 3) * 16;
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + 256 * i;
+      if (ITEMS % 256 == 0 || q < ITEMS) {
+        const int pix = CIN == 1 ? q : q / (CIN / 8), ch = CIN == 1 ? 0 : q % (CIN / 8);
+        const int r = pix / 18, col = pix % 18, y = ty0 + r - 1, x = tx0 + col - 1;
+        const bool inside = y >= 0 && y < CROP && x >= 0 && x < CROP;
+        if constexpr (CIN == 1) {
+          nxt[i] = inside ? in[(b * CROP + y) * CROP + x] : (_Float16)0.f;
+        } else {
+          h8v v;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[mt][r] = 0.f;
-    const int p = (2 * wave + mt) * 32 + c, py = p >> 4, px = p & 15;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      h8v a;
-      if constexpr (CIN == 1) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = 8 * h + e;
-          a[e] = k < 9 ? tile[(py + k / 3) * 18 + px + k % 3] : (_Float16)0.f;
+          for (int e = 0; e < 8; ++e) v[e] = (_Float16)0.f;
+          if (inside) v = *reinterpret_cast<const h8v*>(in + ((b * CROP + y) * CROP + x) * CIN + 8 * ch);
+          nxt[i] = v;
         }
-      } else {
-        const int tap = s >> 1, c0 = 16 * (s & 1) + 8 * h;
-        a = *reinterpret_cast<const h8v*>(tile + ((py + tap / 3) * 18 + px + tap % 3) * PS + c0);
       }
-      acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bw[s], acc[mt], 0, 0, 0);
     }
-  }
-  if constexpr (!LAST) {
+  };
+  int u = blockIdx.x;
+  if (u < nunits) fetch(u);
+  for (; u < nunits; u += gridDim.x) {
+    const long b = u >> 4;
+    const int t16 = u & 15, ty0 = (t16 >> 2) * 16, tx0 = (t16 & 3) * 16;
+    __syncthreads();  // the previous unit's reads of tile and red are done
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int p = (2 * wave + mt) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        const int y = ty0 + (p >> 4), x = tx0 + (p & 15);
-        out[((b * CROP + y) * CROP + x) * NCH + c] = (_Float16)fmaxf(acc[mt][r] + bias, 0.f);
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + 256 * i;
+      if (ITEMS % 256 == 0 || q < ITEMS) {
+        if constexpr (CIN == 1)
+          tile[q] = nxt[i];
+        else
+          *reinterpret_cast<h8v*>(tile + (q / (CIN / 8)) * PS + 8 * (q % (CIN / 8))) = nxt[i];
       }
-  } else {
-    float sum = 0.f;
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) sum += fmaxf(acc[mt][r] + bias, 0.f);
-    sum += __shfl_xor(sum, 32);
-    if (h == 0) red[wave][c] = sum;
+    }
     __syncthreads();
-    if (tid < 32) pooled[(b * 16 + blockIdx.x) * NCH + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+    f32x16 acc[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mt][r] = 0.f;
+      const int p = (2 * wave + mt) * 32 + c, py = p >> 4, px = p & 15;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        h8v a;
+        if constexpr (CIN == 1) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int k = 8 * h + e;
+            a[e] = k < 9 ? tile[(py + k / 3) * 18 + px + k % 3] : (_Float16)0.f;
+          }
+        } else {
+          const int tap = s >> 1, c0 = 16 * (s & 1) + 8 * h;
+          a = *reinterpret_cast<const h8v*>(tile + ((py + tap / 3) * 18 + px + tap % 3) * PS + c0);
+        }
+        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bw[s], acc[mt], 0, 0, 0);
+      }
+    }
+    if constexpr (!LAST) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int p = (2 * wave + mt) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+          const int y = ty0 + (p >> 4), x = tx0 + (p & 15);
+          out[((b * CROP + y) * CROP + x) * NCH + c] = (_Float16)fmaxf(acc[mt][r] + bias, 0.f);
+        }
+    } else {
+      float sum = 0.f;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sum += fmaxf(acc[mt][r] + bias, 0.f);
+      sum += __shfl_xor(sum, 32);
+      if (h == 0) red[wave][c] = sum;
+      __syncthreads();
+      if (tid < 32) pooled[(b * 16 + t16) * NCH + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    }
   }
 }
 
@@ -840,15 +882,16 @@ hv_status infer(hv_af_model* md, const _Float16* crops, int bsz, hipStream_t st)
     hipLaunchKernelGGL(k_pack_weights, dim3((IKS * 64 + 255) / 256), dim3(256), 0, st, md->params, (h8v*)md->wfrag);
     md->packed = md->version;
   }
-  const dim3 grid(16, bsz);
-  hipLaunchKernelGGL((k_conv_mfma<1, false>), grid, dim3(256), 0, st, crops, wf, md->params, OFF_B[0],
-                     md->act16[0], nullptr);
-  hipLaunchKernelGGL((k_conv_mfma<NCH, false>), grid, dim3(256), 0, st, md->act16[0], wf + 64, md->params,
-                     OFF_B[1], md->act16[1], nullptr);
-  hipLaunchKernelGGL((k_conv_mfma<NCH, false>), grid, dim3(256), 0, st, md->act16[1], wf + 64 * 19, md->params,
-                     OFF_B[2], md->act16[0], nullptr);
-  hipLaunchKernelGGL((k_conv_mfma<NCH, true>), grid, dim3(256), 0, st, md->act16[0], wf + 64 * 37, md->params,
-                     OFF_B[3], nullptr, md->pooled);
+  const int nu = 16 * bsz;
+  hipLaunchKernelGGL((k_conv_mfma<1, false>), dim3(hvi::persistent_grid(k_conv_mfma<1, false>, 256, nu)), dim3(256),
+                     0, st, crops, wf, md->params, OFF_B[0], md->act16[0], nullptr, nu);
+  const int g32 = hvi::persistent_grid(k_conv_mfma<NCH, false>, 256, nu);
+  hipLaunchKernelGGL((k_conv_mfma<NCH, false>), dim3(g32), dim3(256), 0, st, md->act16[0], wf + 64, md->params,
+                     OFF_B[1], md->act16[1], nullptr, nu);
+  hipLaunchKernelGGL((k_conv_mfma<NCH, false>), dim3(g32), dim3(256), 0, st, md->act16[1], wf + 64 * 19, md->params,
+                     OFF_B[2], md->act16[0], nullptr, nu);
+  hipLaunchKernelGGL((k_conv_mfma<NCH, true>), dim3(hvi::persistent_grid(k_conv_mfma<NCH, true>, 256, nu)),
+                     dim3(256), 0, st, md->act16[0], wf + 64 * 37, md->params, OFF_B[3], nullptr, md->pooled, nu);
   hipLaunchKernelGGL(k_head_pooled, dim3((bsz + 63) / 64), dim3(64), 0, st, md->pooled, md->params, bsz, md->iout);
   return launched("af inference");
 }
@@ -965,7 +1008,7 @@ hv_status hv_af_scan(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, do
   if ((s = sc.ensure((size_t)n * n_candidates * 4, &ctx->held))) return s;
   hipLaunchKernelGGL(k_af_subband, dim3(n), dim3(512), 0, st, t1, (float2*)sb.ptr);
   constexpr int CPB = 8;
-  hipLaunchKernelGGL(k_af_scan<CPB>, dim3(n, (n_candidates + CPB - 1) / CPB), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_af_scan<CPB, false>), dim3(n, (n_candidates + CPB - 1) / CPB), dim3(256), 0, st,
                      (const float2*)sb.ptr, (const float2*)tab.ptr, (const double*)nullptr, (const float*)nullptr,
                      (const float*)nullptr, n_candidates, (float*)sc.ptr);
   hipLaunchKernelGGL(k_af_argmax, dim3((n + 255) / 256), dim3(256), 0, st, (const float*)sc.ptr, n, n_candidates,
@@ -1009,7 +1052,7 @@ static hv_status af_scan_ranges(hv_ctx* ctx, const float2* sub, int n, const dou
   hv_status s;
   if ((s = sc.ensure((size_t)n * nc * 4, &ctx->held))) return s;
   constexpr int CPB = 8;
-  hipLaunchKernelGGL(k_af_scan<CPB>, dim3(n, (nc + CPB - 1) / CPB), dim3(256), 0, st, sub, (const float2*)nullptr,
+  hipLaunchKernelGGL((k_af_scan<CPB, true>), dim3(n, (nc + CPB - 1) / CPB), dim3(256), 0, st, sub, (const float2*)nullptr,
                      kz, (const float*)zlo, (const float*)zhi, nc, (float*)sc.ptr);
   hipLaunchKernelGGL(k_af_argmax, dim3((n + 255) / 256), dim3(256), 0, st, (const float*)sc.ptr, n, nc, 0.0, 0.0,
                      zlo, zhi, z_out, (float*)nullptr, refine ? 1 : 0);
