@@ -126,14 +126,25 @@ __device__ inline void load_afrag(AFrag<W, MIXED>& f, const CoefArgs& g, long jj
 // Writes outputs at out[k][obase + x0 + lane] and spec[(jj*npair + pair)*npix + obase + x0 + lane].
 // PRE: f0 holds the fragments of tile 0, loaded by the caller; otherwise
 // every tile's fragments are loaded here.
-template <int W, bool MIXED, bool EXACT_B, bool PRE>
+// PIPE (with PRE): the next tile's fragments are loaded into a second set of
+// registers before the current tile's MFMAs, so their latency hides behind
+// them (W more VGPRs: for kernels with registers to spare).
+template <int W, bool MIXED, bool EXACT_B, bool PRE, bool PIPE = false>
 __device__ inline void coef_pixels(const CoefArgs& g, const float* wts_lds, const float2* buf, int S, int x0,
                                    int lane, long jj, long obase, long npix, const AFrag<W, MIXED>& f0) {
+  static_assert(!PIPE || PRE, "the pipelined form starts from the caller's first fragments");
   const int h = lane >> 5;
   float e0 = 0.f, e1 = 0.f, e2 = 0.f;
+  AFrag<W, MIXED> cur;
+  if constexpr (PIPE) cur = f0;
   for (int mt = 0; mt < g.mtiles; ++mt) {
     f32x16 acc;
-    if (PRE && mt == 0) {
+    if constexpr (PIPE) {
+      AFrag<W, MIXED> nxt;
+      if (mt + 1 < g.mtiles) load_afrag(nxt, g, jj, mt + 1, lane);
+      acc = coef_tile<W, MIXED, EXACT_B>(cur, buf, S, x0, lane, g.bsc);
+      cur = nxt;
+    } else if (PRE && mt == 0) {
       acc = coef_tile<W, MIXED, EXACT_B>(f0, buf, S, x0, lane, g.bsc);
     } else {
       AFrag<W, MIXED> f;
@@ -302,7 +313,7 @@ __global__ __launch_bounds__((coef_threads<W, DIV>())) void k_field_coef(const T
     for (int i = 0; i < BATCH; ++i) lds[RPI * (i0 + i) * S] = load_c(&v[i]);
   }
   __syncthreads();
-  coef_pixels<W, MIXED, EXACT, true>(g, wts_lds, buf, S, wave * 32, lane, jj, p0, npix, af);
+  coef_pixels<W, MIXED, EXACT, true, true>(g, wts_lds, buf, S, wave * 32, lane, jj, p0, npix, af);
 }
 
 // ------------------------------------------------------------------ full-band STFT power (temporal FFT)
