@@ -118,33 +118,32 @@ __global__ __launch_bounds__(512) void k_af_crop(const float2* __restrict__ t1, 
 
 // ------------------------------------------------------------------ scan
 // Masked +1-order sub-band: bins ky = i - 96, kx = j - 96 (i, j < 64), read
-// through Hermitian symmetry from columns 96 - j and rows 96 - i.
+// through Hermitian symmetry from columns 96 - j and rows 96 - i.  Block
+// (n, half) transforms the 32 columns 33 + 32 half .. of hologram n and
+// writes the sub-band values that come from them.
 __global__ __launch_bounds__(512) void k_af_subband(const float2* __restrict__ t1, float2* __restrict__ sub) {
   constexpr int NT = 512, NB = 32, S = lds_stride(AN);
   __shared__ float2 buf[NB * S];
   __shared__ float2 tw[tw_size(AN) > 0 ? tw_size(AN) : 1];
   const int tid = threadIdx.x;
   const long n = blockIdx.x;
+  const int c0 = 33 + 32 * blockIdx.y;
   fill_twiddles<AN>(tw, tid, NT);
-  for (int half = 0; half < 2; ++half) {
-    const int c0 = 33 + 32 * half;
-    const float2* src = t1 + n * (AN / 2) * AN + (long)c0 * AN;
-    for (int q = tid; q < NB * AN; q += NT) buf[(q / AN) * S + skew(q % AN)] = src[q];
-    __syncthreads();
-    fft_lds<AN, NB, NT, -1>(buf, tw, tid);
-    for (int q = tid; q < SUB * SUB; q += NT) {
-      const int i = q / SUB, j = q % SUB;
-      const int col = 96 - j;
-      if (col < c0 || col >= c0 + NB) continue;
-      const int di = i - SUB / 2, dj = j - SUB / 2;
-      float2 v = make_float2(0.f, 0.f);
-      if (100 * (di * di + dj * dj) <= AN * AN) {  // radius 0.1 cycles/pixel
-        const float2 a = buf[(col - c0) * S + skew(96 - i)];
-        v = make_float2(a.x, -a.y);
-      }
-      sub[n * SUB * SUB + q] = v;
+  const float2* src = t1 + n * (AN / 2) * AN + (long)c0 * AN;
+  for (int q = tid; q < NB * AN; q += NT) buf[(q / AN) * S + skew(q % AN)] = src[q];
+  __syncthreads();
+  fft_lds<AN, NB, NT, -1>(buf, tw, tid);
+  for (int q = tid; q < SUB * SUB; q += NT) {
+    const int i = q / SUB, j = q % SUB;
+    const int col = 96 - j;
+    if (col < c0 || col >= c0 + NB) continue;
+    const int di = i - SUB / 2, dj = j - SUB / 2;
+    float2 v = make_float2(0.f, 0.f);
+    if (100 * (di * di + dj * dj) <= AN * AN) {  // radius 0.1 cycles/pixel
+      const float2 a = buf[(col - c0) * S + skew(96 - i)];
+      v = make_float2(a.x, -a.y);
     }
-    __syncthreads();
+    sub[n * SUB * SUB + q] = v;
   }
 }
 
@@ -502,30 +501,37 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ 
   }
 }
 
-// Head for the inference pass: the 16 tile sums of each channel in tile
-// order / HW, FC(32->64) ReLU, FC(64->2); one thread per sample.
-__global__ void k_head_pooled(const float* __restrict__ pooled, const float* __restrict__ params, int bsz,
-                              float* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= bsz) return;
-  float g[NCH];
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) {
+// Head for the inference pass, one wave per sample (four per workgroup):
+// lane c < 32 sums channel c's 16 tile sums in tile order and divides by
+// HW, lane j forms hidden unit j of FC(32->64) + ReLU, and lanes 0 and 1
+// form the two outputs of FC(64->2) over j in order -- each value with the
+// operations, in the order, of a single-thread evaluation.
+__global__ __launch_bounds__(256) void k_head_pooled(const float* __restrict__ pooled,
+                                                     const float* __restrict__ params, int bsz,
+                                                     float* __restrict__ out) {
+  __shared__ float g[4][NCH];
+  __shared__ float hid[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long b = (long)blockIdx.x * 4 + w;
+  const bool live = b < bsz;
+  if (live && lane < NCH) {
     float s = 0.f;
-    for (int t = 0; t < 16; ++t) s += pooled[((long)b * 16 + t) * NCH + c];
-    g[c] = s / HW;
+    for (int t = 0; t < 16; ++t) s += pooled[(b * 16 + t) * NCH + lane];
+    g[w][lane] = s / HW;
   }
-  float o0 = params[OFF_FC2B], o1 = params[OFF_FC2B + 1];
-  for (int j = 0; j < 64; ++j) {
-    float hj = params[OFF_FC1B + j];
+  __syncthreads();
+  if (live) {
+    float hj = params[OFF_FC1B + lane];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) hj += params[OFF_FC1W + j * NCH + c] * g[c];
-    hj = fmaxf(hj, 0.f);
-    o0 += params[OFF_FC2W + j] * hj;
-    o1 += params[OFF_FC2W + 64 + j] * hj;
+    for (int c = 0; c < NCH; ++c) hj += params[OFF_FC1W + lane * NCH + c] * g[w][c];
+    hid[w][lane] = fmaxf(hj, 0.f);
   }
-  out[2 * b] = o0;
-  out[2 * b + 1] = o1;
+  __syncthreads();
+  if (live && lane < 2) {
+    float o = params[OFF_FC2B + lane];
+    for (int j = 0; j < 64; ++j) o += params[OFF_FC2W + 64 * lane + j] * hid[w][j];
+    out[2 * b + lane] = o;
+  }
 }
 
 // Weight and bias gradients of one conv layer, partial over a split of the
@@ -892,7 +898,7 @@ hv_status infer(hv_af_model* md, const _Float16* crops, int bsz, hipStream_t st)
                      OFF_B[2], md->act16[0], nullptr, nu);
   hipLaunchKernelGGL((k_conv_mfma<NCH, true>), dim3(hvi::persistent_grid(k_conv_mfma<NCH, true>, 256, nu)),
                      dim3(256), 0, st, md->act16[0], wf + 64 * 37, md->params, OFF_B[3], nullptr, md->pooled, nu);
-  hipLaunchKernelGGL(k_head_pooled, dim3((bsz + 63) / 64), dim3(64), 0, st, md->pooled, md->params, bsz, md->iout);
+  hipLaunchKernelGGL(k_head_pooled, dim3((bsz + 3) / 4), dim3(256), 0, st, md->pooled, md->params, bsz, md->iout);
   return launched("af inference");
 }
 
@@ -1006,7 +1012,7 @@ hv_status hv_af_scan(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, do
   DevBuf& sc = ctx->work(st, 22);
   if ((s = sb.ensure((size_t)n * SUB * SUB * 8, &ctx->held))) return s;
   if ((s = sc.ensure((size_t)n * n_candidates * 4, &ctx->held))) return s;
-  hipLaunchKernelGGL(k_af_subband, dim3(n), dim3(512), 0, st, t1, (float2*)sb.ptr);
+  hipLaunchKernelGGL(k_af_subband, dim3(n, 2), dim3(512), 0, st, t1, (float2*)sb.ptr);
   constexpr int CPB = 8;
   hipLaunchKernelGGL((k_af_scan<CPB, false>), dim3(n, (n_candidates + CPB - 1) / CPB), dim3(256), 0, st,
                      (const float2*)sb.ptr, (const float2*)tab.ptr, (const double*)nullptr, (const float*)nullptr,
@@ -1081,7 +1087,7 @@ hv_status hv_af_scan_ranges(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int
   if ((s = af_spectrum(ctx, holo, n, st, &t1))) return s;
   DevBuf& sb = ctx->work(st, 21);
   if ((s = sb.ensure((size_t)n * SUB * SUB * 8, &ctx->held))) return s;
-  hipLaunchKernelGGL(k_af_subband, dim3(n), dim3(512), 0, st, t1, (float2*)sb.ptr);
+  hipLaunchKernelGGL(k_af_subband, dim3(n, 2), dim3(512), 0, st, t1, (float2*)sb.ptr);
   // the ranges are read, never written, on this path
   return af_scan_ranges(ctx, (const float2*)sb.ptr, n, kz, const_cast<float*>(z_lo), const_cast<float*>(z_hi),
                         n_candidates, z_out, scores_out, false, st);
@@ -1252,7 +1258,7 @@ hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wave
     const int bs = std::min(md->infer_batch, n - b0);
     if ((s = hv_af_crops(ctx, holo + (size_t)b0 * AN * AN, bs, AN, AN, cb.ptr, 1, st))) return s;
     if (refine)  // the +1-order sub-band from the same spectrum the crops came from
-      hipLaunchKernelGGL(k_af_subband, dim3(bs), dim3(512), 0, st, (const float2*)ctx->work(st, 20).ptr,
+      hipLaunchKernelGGL(k_af_subband, dim3(bs, 2), dim3(512), 0, st, (const float2*)ctx->work(st, 20).ptr,
                          subs + (size_t)b0 * SUB * SUB);
     if ((s = infer(md, (const _Float16*)cb.ptr, bs, st))) return s;
     hipLaunchKernelGGL(k_af_denorm, dim3((bs + 255) / 256), dim3(256), 0, st, md->iout, bs, (float)md->z_mean,
