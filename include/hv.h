@@ -529,6 +529,11 @@ hv_status hv_af_loss_grad(hv_af_model* model, const void* crops, const float* z_
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on that gradient. */
 hv_status hv_af_train_step(hv_af_model* model, const void* crops, const float* z_m, int batch, float lr,
                            float* loss, void* hip_stream);
+/* The same step from 256 x 256 u8 holograms (device [batch][256][256]): their
+ * crops (hv_af_crops, fp16) into a workspace of the context, then
+ * hv_af_train_step.  batch <= the model's max_batch (HV_ERR_SHAPE). */
+hv_status hv_af_train_step_holo(hv_af_model* model, const uint8_t* holo, const float* z_m, int batch, float lr,
+                                float* loss, void* hip_stream);
 /* The scan of hv_af_scan over per-hologram ranges: n_candidates distances
  * evenly spaced in [z_lo[i], z_hi[i]] (device float32 [n] each) for
  * hologram i; transfer functions from an FP64 table of

@@ -1226,6 +1226,21 @@ hv_status hv_af_train_step(hv_af_model* md, const void* crops, const float* z_m,
   return launched("adam");
 }
 
+hv_status hv_af_train_step_holo(hv_af_model* md, const uint8_t* holo, const float* z_m, int batch, float lr,
+                                float* loss, void* hip_stream) {
+  if (!md || !holo || !z_m) return fail(HV_ERR_ARG, "NULL argument");
+  if (batch <= 0 || batch > md->max_batch) return fail(HV_ERR_SHAPE, "batch %d outside [1, %d]", batch, md->max_batch);
+  hv_ctx* ctx = md->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  hipStream_t st = (hipStream_t)hip_stream;
+  DevBuf& cb = ctx->work(st, 34);
+  hv_status s;
+  if ((s = cb.ensure((size_t)batch * HW * 2, &ctx->held))) return s;
+  if ((s = hv_af_crops(ctx, holo, batch, AN, AN, cb.ptr, 1, st))) return s;
+  return hv_af_train_step(md, cb.ptr, z_m, batch, lr, loss, hip_stream);
+}
+
 hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wavelength_m, double pitch_m, float tau_m,
                         int refine_candidates, float refine_k, float* z_out, float* sigma_out, int* used_fallback,
                         int* n_fallback, void* hip_stream) {

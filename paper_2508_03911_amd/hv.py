@@ -145,6 +145,7 @@ _sig = {
     "hv_af_infer": (_I, [_P, _P, _I, _P, _P]),
     "hv_af_loss_grad": (_I, [_P, _P, _P, _I, _P, _P, _P]),
     "hv_af_train_step": (_I, [_P, _P, _P, _I, C.c_float, _P, _P]),
+    "hv_af_train_step_holo": (_I, [_P, _P, _P, _I, C.c_float, _P, _P]),
     "hv_af_predict": (_I, [_P, _P, _I, C.c_double, C.c_double, C.c_float, _I, C.c_float, _P, _P, _P, C.POINTER(_I),
                            _P]),
     "hv_af_scan_ranges": (_I, [_P, _P, _I, _I, _I, C.c_double, C.c_double, _P, _P, _I, _P, _P, _P]),
@@ -655,6 +656,12 @@ class AfModel:
     def train_step(self, crops: torch.Tensor, z_m: torch.Tensor, lr: float, loss: torch.Tensor = None):
         _check(lib.hv_af_train_step(self.handle, _ptr(crops), _ptr(z_m), crops.shape[0], lr, _ptr(loss),
                                     _stream(crops.device)))
+        return loss
+
+    def train_step_holo(self, holo: torch.Tensor, z_m: torch.Tensor, lr: float, loss: torch.Tensor = None):
+        """One Adam step from u8 holograms [batch, 256, 256] (crops taken inside)."""
+        _check(lib.hv_af_train_step_holo(self.handle, _ptr(holo), _ptr(z_m), holo.shape[0], lr, _ptr(loss),
+                                         _stream(holo.device)))
         return loss
 
     def state(self):

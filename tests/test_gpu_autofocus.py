@@ -157,6 +157,33 @@ def test_adam_step_and_checkpoint(ctx, hv, init):
     m2.close()
 
 
+def test_train_step_from_holograms(ctx, hv, init, holos):
+    """hv_af_train_step_holo is the crops of hv_af_crops followed by
+    hv_af_train_step: the two give bitwise the same parameters and moments."""
+    say("Adam step from holograms")
+    h, zs = holos
+    hd = torch.from_numpy(h).cuda()
+    zd = torch.from_numpy(zs.astype(np.float32)).cuda()
+    b = len(h)
+    a = ctx.af_model(init, b, Z_MEAN, Z_SCALE)
+    c = ctx.af_model(init, b, Z_MEAN, Z_SCALE)
+    la = torch.zeros(1, dtype=torch.float32, device="cuda")
+    lc = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        a.train_step_holo(hd, zd, 1e-3, la)
+        c.train_step(ctx.hv_af_crops(hd), zd, 1e-3, lc)
+    sa, sc = a.state(), c.state()
+    assert sa["step"] == sc["step"] == 2
+    for k in ("params", "m", "v"):
+        assert np.array_equal(sa[k], sc[k]), k
+    assert torch.equal(la, lc)
+    with pytest.raises(hv.HvError) as e:
+        a.train_step_holo(torch.cat([hd, hd]), torch.cat([zd, zd]), 1e-3)
+    assert e.value.status == hv.HV_ERR_SHAPE
+    a.close()
+    c.close()
+
+
 def test_synthesis_deterministic(ctx):
     say("training-hologram synthesis")
     z = np.repeat([0.12, 0.3, 0.44], 4)
