@@ -256,6 +256,11 @@ def he_normal_init(seed):
     return np.concatenate(parts).astype(np.float32)
 
 
+# local scan seeded by the network: candidates (half over z +- AF_K sigma,
+# half over one coarse step around the best of those)
+AF_REFINE, AF_K = 16, 2.0
+
+
 def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
     """Learned autofocus: train the CNN on n_train holograms synthesised on
     the GPU by the project's forward model (z uniform in [0.05, 0.5] m,
@@ -307,20 +312,24 @@ def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
     eh = torch.cat(eh)
     ez = ez.cpu().numpy()
 
-    def timed(fn):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
+    def timed(fn, reps=3):
+        # one untimed call (tables, workspaces), then the median of `reps`
         r = fn()
-        torch.cuda.synchronize()
-        return r, time.perf_counter() - t
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return r, float(np.median(ts))
 
     (zs, _), t_scan = timed(lambda: ctx.hv_af_scan(eh, lam, pitch))
     (zn, sig, _, _), t_net = timed(lambda: model.predict(eh, lam, pitch, tau=1e9))
     tau = float(np.quantile(sig.cpu().numpy(), 0.9))
     (zf, _, used, nfb), t_fb = timed(lambda: model.predict(eh, lam, pitch, tau=tau))
-    model.predict(eh[:8], lam, pitch, tau=1e9, refine=16)  # the local scan's table, outside the timing
-    (zl, _, _, _), t_loc = timed(lambda: model.predict(eh, lam, pitch, tau=1e9, refine=16))
-    (zlf, _, _, nlf), t_lf = timed(lambda: model.predict(eh, lam, pitch, tau=tau, refine=16))
+    (zl, _, _, _), t_loc = timed(lambda: model.predict(eh, lam, pitch, tau=1e9, refine=AF_REFINE, refine_k=AF_K))
+    (zlf, _, _, nlf), t_lf = timed(lambda: model.predict(eh, lam, pitch, tau=tau, refine=AF_REFINE, refine_k=AF_K))
 
     def err(zhat):
         e = np.abs(zhat.cpu().numpy() - ez) * 1e3
@@ -334,7 +343,7 @@ def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
            "cnn": {**err(zn), "holograms_per_s": n_eval / t_net},
            "cnn_fallback": {**err(zf), "holograms_per_s": n_eval / t_fb, "fallback_fraction": nfb / n_eval,
                             "tau_m": tau},
-           "cnn_local_scan": {**err(zl), "holograms_per_s": n_eval / t_loc, "candidates": 16, "k_sigma": 2.5,
+           "cnn_local_scan": {**err(zl), "holograms_per_s": n_eval / t_loc, "candidates": AF_REFINE, "k_sigma": AF_K,
                               "speedup_vs_scan": t_scan / t_loc},
            "cnn_local_scan_fallback": {**err(zlf), "holograms_per_s": n_eval / t_lf,
                                        "fallback_fraction": nlf / n_eval, "speedup_vs_scan": t_scan / t_lf},
