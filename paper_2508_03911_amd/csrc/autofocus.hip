@@ -283,15 +283,14 @@ __global__ void k_af_ranges(const float* __restrict__ z, const float* __restrict
 }
 
 // ------------------------------------------------------------------ CNN: convolution
-// Direct 3x3 convolution, zero padding 1, on one 16 x 16 output tile of one
-// sample; wave w produces output channels 8w..8w+7 (weights are wave-uniform
-// and come through the scalar cache), each lane 4 pixels.
-//   MODE 0 (forward):   out = ReLU(b + W * in)
-//   MODE 1 (input grad): out = W^T(flipped) * (in masked by mask > 0)
-template <int CIN, typename TIN, int MODE>
-__global__ __launch_bounds__(256) void k_conv(const TIN* __restrict__ in, const float* __restrict__ mask,
-                                              const float* __restrict__ params, int woff, int boff,
-                                              float* __restrict__ out) {
+// First layer of training's forward pass (1 -> 32 channels: nine taps, too
+// few for the matrix cores): direct 3x3 convolution, zero padding 1, on one
+// 16 x 16 output tile of one sample; wave w produces output channels
+// 8w..8w+7 (weights are wave-uniform and come through the scalar cache),
+// each lane 4 pixels: out = ReLU(b + W * in).
+template <int CIN, typename TIN>
+__global__ __launch_bounds__(256) void k_conv(const TIN* __restrict__ in, const float* __restrict__ params, int woff,
+                                              int boff, float* __restrict__ out) {
   __shared__ float tile[CIN][18][19];
   const int tid = threadIdx.x;
   const int ty0 = (blockIdx.x >> 2) * 16, tx0 = (blockIdx.x & 3) * 16;
@@ -300,11 +299,7 @@ __global__ __launch_bounds__(256) void k_conv(const TIN* __restrict__ in, const 
     const int c = q / 324, r = (q % 324) / 18, col = q % 18;
     const int y = ty0 + r - 1, x = tx0 + col - 1;
     float v = 0.f;
-    if (y >= 0 && y < CROP && x >= 0 && x < CROP) {
-      const long idx = ((b * CIN + c) * CROP + y) * CROP + x;
-      v = to_f(in[idx]);
-      if (MODE == 1 && !(mask[idx] > 0.f)) v = 0.f;
-    }
+    if (y >= 0 && y < CROP && x >= 0 && x < CROP) v = to_f(in[((b * CIN + c) * CROP + y) * CROP + x]);
     tile[c][r][col] = v;
   }
   __syncthreads();
@@ -329,8 +324,7 @@ __global__ __launch_bounds__(256) void k_conv(const TIN* __restrict__ in, const 
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int o = 8 * wave + k;
-          const float w = MODE == 0 ? params[woff + ((o * CIN + c) * 3 + dy) * 3 + dx]
-                                    : params[woff + ((c * NCH + o) * 3 + (2 - dy)) * 3 + (2 - dx)];
+          const float w = params[woff + ((o * CIN + c) * 3 + dy) * 3 + dx];
 #pragma unroll
           for (int p = 0; p < 4; ++p) acc[k][p] += w * xv[p];
         }
@@ -339,14 +333,12 @@ __global__ __launch_bounds__(256) void k_conv(const TIN* __restrict__ in, const 
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int o = 8 * wave + k;
-    const float bias = MODE == 0 ? params[boff + o] : 0.f;
+    const float bias = params[boff + o];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int idx = lane + 64 * p;
       const int y = ty0 + (idx >> 4), x = tx0 + (idx & 15);
-      float v = acc[k][p] + bias;
-      if (MODE == 0) v = fmaxf(v, 0.f);
-      out[((b * NCH + o) * CROP + y) * CROP + x] = v;
+      out[((b * NCH + o) * CROP + y) * CROP + x] = fmaxf(acc[k][p] + bias, 0.f);
     }
   }
 }
@@ -534,73 +526,222 @@ __global__ __launch_bounds__(256) void k_head_pooled(const float* __restrict__ p
   }
 }
 
-// Weight and bias gradients of one conv layer, partial over a split of the
-// batch: dW[o][c][tap] = sum dZ[b][o][p] X[b][c][p + tap - 1], dZ = dA [A > 0].
-// Threads t < CIN*9 own (c, tap) for CG output channels; the next CG threads
-// accumulate the bias gradients.
-template <int CIN, typename TIN, int CG>
-__global__ void k_wgrad(const TIN* __restrict__ x, const float* __restrict__ dA, const float* __restrict__ aout,
-                        int bsize, int per_split, float* __restrict__ part_w, float* __restrict__ part_b) {
-  __shared__ float xt[CIN][18][19];
-  __shared__ float dz[256][CG];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int cg = blockIdx.x, split = blockIdx.y;
-  const bool isw = tid < CIN * 9;
-  const int c = tid / 9, tap = tid % 9, dy = tap / 3, dx = tap % 3;
-  const bool isb = tid >= CIN * 9 && tid < CIN * 9 + CG;
-  const int kb = tid - CIN * 9;
-  float acc[CG];
+// A 32-channel convolution of training as an implicit GEMM on the matrix
+// cores (FP32 operands, v_mfma_f32_32x32x2f32): per 16 x 16 output tile,
+// [256 pixels] x [288 = 9 c + tap] times [288] x [32 output channels], with
+// NCHW FP32 activations, in two modes:
+//   MODE 0 (forward):   out = ReLU(b + W * in)
+//   MODE 1 (input grad): out = W^T(flipped) * (in masked by mask > 0)
+// Persistent: the layer's weights sit in LDS as B[k][o] for all of the
+// block's units; wave w owns the 32-pixel M tiles 2w and 2w + 1; the
+// outputs are staged in LDS so that each channel's 16-pixel rows are stored
+// contiguously.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv_f32mfma(const float* __restrict__ in, const float* __restrict__ mask,
+                                                      const float* __restrict__ params, int woff, int boff,
+                                                      float* __restrict__ out, int nunits) {
+  constexpr int K = NCH * 9;
+  constexpr int OS = 257;  // staging row stride
+  static_assert(NCH * OS <= NCH * 18 * 19, "output staging fits in the input tile");
+  __shared__ float xt[NCH][18][19];
+  __shared__ float wl[K * NCH];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 31, kb = lane >> 5;
+  for (int q = tid; q < K * NCH; q += 256) {
+    const int k = q / NCH, o = q % NCH, c = k / 9, tap = k % 9;
+    wl[q] = MODE == 0 ? params[woff + (o * NCH + c) * 9 + tap] : params[woff + (c * NCH + o) * 9 + (8 - tap)];
+  }
+  const float bias = MODE == 0 ? params[boff + n] : 0.f;
+  float* ot = &xt[0][0][0];
+  const float* xflat = &xt[0][0][0];
+  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const long b = u >> 4;
+    const int ty0 = ((u & 15) >> 2) * 16, tx0 = (u & 3) * 16;
+    // every load of the tile is issued before the first LDS write
+    constexpr int PER = (NCH * 324 + 255) / 256;
+    float v[PER];
 #pragma unroll
-  for (int k = 0; k < CG; ++k) acc[k] = 0.f;
-  float accb = 0.f;
-  const int b0 = split * per_split, b1 = min(bsize, b0 + per_split);
-  for (int b = b0; b < b1; ++b)
-    for (int tile = 0; tile < 16; ++tile) {
-      const int ty0 = (tile >> 2) * 16, tx0 = (tile & 3) * 16;
-      for (int q = tid; q < CIN * 324; q += nt) {
-        const int cc = q / 324, r = (q % 324) / 18, col = q % 18;
-        const int y = ty0 + r - 1, xx = tx0 + col - 1;
-        float v = 0.f;
-        if (y >= 0 && y < CROP && xx >= 0 && xx < CROP) v = to_f(x[(((long)b * CIN + cc) * CROP + y) * CROP + xx]);
-        xt[cc][r][col] = v;
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + 256 * i;
+      const int c = q / 324, r = (q % 324) / 18, col = q % 18;
+      const int y = ty0 + r - 1, x = tx0 + col - 1;
+      v[i] = 0.f;
+      if (q < NCH * 324 && y >= 0 && y < CROP && x >= 0 && x < CROP) {
+        const long idx = ((b * NCH + c) * CROP + y) * CROP + x;
+        v[i] = in[idx];
+        if (MODE == 1 && !(mask[idx] > 0.f)) v[i] = 0.f;
       }
-      for (int q = tid; q < 256 * CG; q += nt) {
-        const int p = q / CG, k = q % CG;
-        const long idx = (((long)b * NCH + cg * CG + k) * CROP + ty0 + (p >> 4)) * CROP + tx0 + (p & 15);
-        dz[p][k] = aout[idx] > 0.f ? dA[idx] : 0.f;
-      }
-      __syncthreads();
-      if (isw) {
-        for (int p = 0; p < 256; ++p) {
-          const float xv = xt[c][(p >> 4) + dy][(p & 15) + dx];
-#pragma unroll
-          for (int k = 0; k < CG; ++k) acc[k] += dz[p][k] * xv;
-        }
-      } else if (isb) {
-        for (int p = 0; p < 256; ++p) accb += dz[p][kb];
-      }
-      __syncthreads();
     }
-  if (isw)
+    __syncthreads();  // the previous unit's staged outputs are stored
 #pragma unroll
-    for (int k = 0; k < CG; ++k) part_w[((long)(split * NCH + cg * CG + k) * CIN + c) * 9 + tap] = acc[k];
-  if (isb) part_b[split * NCH + cg * CG + kb] = accb;
+    for (int i = 0; i < PER; ++i) {
+      const int q = tid + 256 * i;
+      if (q < NCH * 324) xt[q / 324][(q % 324) / 18][q % 18] = v[i];
+    }
+    __syncthreads();
+    f32x16 acc[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mt][r] = 0.f;
+      const int p = (2 * w + mt) * 32 + n, pbase = (p >> 4) * 19 + (p & 15);
+#pragma unroll 16
+      for (int ks = 0; ks < K / 2; ++ks) {
+        const int k = 2 * ks + kb, c = k / 9, tap = k % 9;
+        const float a = xflat[c * (18 * 19) + (tap / 3) * 19 + tap % 3 + pbase];
+        const float bv = wl[k * NCH + n];
+        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[mt], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every read of the input tile is done
+    // result register r of lane l: pixel 8 (r / 4) + 4 (l / 32) + r % 4 of the M tile, output channel l % 32
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int p = (2 * w + mt) * 32 + 8 * (r >> 2) + 4 * kb + (r & 3);
+        float v = acc[mt][r] + bias;
+        if (MODE == 0) v = fmaxf(v, 0.f);
+        ot[n * OS + p] = v;
+      }
+    __syncthreads();
+    for (int q = tid; q < NCH * 256; q += 256) {
+      const int o = q >> 8, pp = q & 255;
+      out[((b * NCH + o) * CROP + ty0 + (pp >> 4)) * CROP + tx0 + (pp & 15)] = ot[o * OS + pp];
+    }
+  }
 }
 
-// Sum of the per-split partials in split order into the gradient vector.
+// Weight and bias gradients of one conv layer as a GEMM on the matrix cores
+// (FP32 operands, v_mfma_f32_32x32x2f32): dW[o][k] = sum_n dZ[n][o] X[n][k] over
+// n = (sample, pixel), k = 9 c + tap, X[n][k] the input at pixel n moved by
+// the tap (zero outside the image), dZ = dA [A > 0].  Block g accumulates the
+// units (sample, 16 x 16 tile) g, g + G, ... in registers and writes its
+// partial sums; k_wgrad_reduce adds the G partials in block order, so the
+// result does not depend on scheduling.  CIN = 32: wave w (of nine) owns the
+// 32 k columns [32 w, 32 w + 32); CIN = 1: the nine taps (padded to 32
+// columns) with the 128 pixel pairs of a tile split over four waves, whose
+// partials are added in wave order.  Threads 0..31 sum the bias gradient of
+// their output channel over the block's pixels in order.
+template <int CIN, typename TIN>
+__global__ __launch_bounds__(CIN == 1 ? 256 : 576) void k_wgrad_mfma(const TIN* __restrict__ x,
+                                                                   const float* __restrict__ dA,
+                                                                   const float* __restrict__ aout, int nunits,
+                                                                   float* __restrict__ part_w,
+                                                                   float* __restrict__ part_b) {
+  constexpr int NW = CIN == 1 ? 4 : 9;
+  constexpr int NT = NW * 64;
+  constexpr int NK = CIN * 9;
+  constexpr int DS = 257;  // dz row stride: the 32 rows of an A read fall on distinct banks
+  __shared__ float xt[CIN][18][19];
+  __shared__ float dzt[NCH * DS];  // dZ of the unit, [o][pixel]
+  __shared__ float red[CIN == 1 ? 3 * 16 * 64 : 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 31, kb = lane >> 5;
+  const int kcol = CIN == 1 ? n : 32 * w + n;
+  const bool kval = kcol < NK;
+  const int c = kval ? kcol / 9 : 0, tap = kval ? kcol % 9 : 0;
+  const float* xb = &xt[c][tap / 3][tap % 3];
+  constexpr int KS = CIN == 1 ? 32 : 128;  // pixel pairs per wave and unit
+  const int ks0 = CIN == 1 ? KS * w : 0;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  float accb = 0.f;
+  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const long b = u >> 4;
+    const int ty0 = ((u & 15) >> 2) * 16, tx0 = (u & 3) * 16;
+    // the loads of each array are all issued before its first LDS write
+    constexpr int PX = (CIN * 324 + NT - 1) / NT, PZ = (NCH * 256 + NT - 1) / NT;
+    {
+      float vx[PX];
+#pragma unroll
+      for (int i = 0; i < PX; ++i) {
+        const int q = tid + NT * i;
+        const int cc = q / 324, r = (q % 324) / 18, col = q % 18;
+        const int y = ty0 + r - 1, xx = tx0 + col - 1;
+        vx[i] = (q < CIN * 324 && y >= 0 && y < CROP && xx >= 0 && xx < CROP)
+                    ? to_f(x[((b * CIN + cc) * CROP + y) * CROP + xx])
+                    : 0.f;
+      }
+      __syncthreads();  // the previous unit's reads are done
+#pragma unroll
+      for (int i = 0; i < PX; ++i) {
+        const int q = tid + NT * i;
+        if (q < CIN * 324) xt[q / 324][(q % 324) / 18][q % 18] = vx[i];
+      }
+    }
+    {
+      float vz[PZ];
+#pragma unroll
+      for (int i = 0; i < PZ; ++i) {
+        const int q = tid + NT * i;
+        const int o = q >> 8, pp = q & 255;
+        vz[i] = 0.f;
+        if (q < NCH * 256) {
+          const long idx = ((b * NCH + o) * CROP + ty0 + (pp >> 4)) * CROP + tx0 + (pp & 15);
+          vz[i] = aout[idx] > 0.f ? dA[idx] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PZ; ++i) {
+        const int q = tid + NT * i;
+        if (q < NCH * 256) dzt[(q >> 8) * DS + (q & 255)] = vz[i];
+      }
+    }
+    __syncthreads();
+    if (tid < NCH)
+      for (int pp = 0; pp < 256; ++pp) accb += dzt[tid * DS + pp];
+#pragma unroll 8
+    for (int ks = ks0; ks < ks0 + KS; ++ks) {
+      const int pp = 2 * ks + kb, py = pp >> 4, px = pp & 15;
+      const float a = dzt[n * DS + pp];
+      const float bv = kval ? xb[(py * 19 + px)] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc, 0, 0, 0);
+    }
+  }
+  // result register r of lane l: output channel 8 (r / 4) + 4 (l / 32) + r % 4, k column n
+  if constexpr (CIN == 1) {
+    if (w > 0)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) red[((w - 1) * 16 + r) * 64 + lane] = acc[r];
+    __syncthreads();
+    if (w == 0 && kval)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float v = ((acc[r] + red[r * 64 + lane]) + red[(16 + r) * 64 + lane]) + red[(32 + r) * 64 + lane];
+        const int o = 8 * (r >> 2) + 4 * kb + (r & 3);
+        part_w[((long)blockIdx.x * NCH + o) * NK + kcol] = v;
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int o = 8 * (r >> 2) + 4 * kb + (r & 3);
+      part_w[((long)blockIdx.x * NCH + o) * NK + kcol] = acc[r];
+    }
+  }
+  if (tid < NCH) part_b[blockIdx.x * NCH + tid] = accb;
+}
+
+// Sum of the per-block partials into the gradient vector, in a fixed order
+// (eight interleaved running sums over the blocks, then those eight in
+// order), so the result does not depend on scheduling.
 __global__ void k_wgrad_reduce(const float* __restrict__ part_w, const float* __restrict__ part_b, int splits,
                                int cin, int woff, int boff, float* __restrict__ grad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nw = NCH * cin * 9;
-  if (i < nw) {
-    float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part_w[(long)k * nw + i];
-    grad[woff + i] = s;
-  } else if (i < nw + NCH) {
-    float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part_b[k * NCH + i - nw];
-    grad[boff + i - nw] = s;
-  }
+  if (i >= nw + NCH) return;
+  const float* src = i < nw ? part_w + i : part_b + (i - nw);
+  const long stride = i < nw ? nw : NCH;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int k = 0;
+  for (; k + 8 <= splits; k += 8)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += src[(long)(k + j) * stride];
+  for (int j = 0; k + j < splits; ++j) s[j] += src[(long)(k + j) * stride];
+  const float t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  if (i < nw)
+    grad[woff + i] = t;
+  else
+    grad[boff + i - nw] = t;
 }
 
 // ------------------------------------------------------------------ CNN: head
@@ -855,7 +996,7 @@ struct hv_af_model {
 
 namespace {
 
-constexpr int SPLITS = 64;
+constexpr int WG_BLOCKS = 512;  // workgroups (and partial sums) of the weight gradients
 
 hv_status dev_alloc(hv_af_model* md, void** p, size_t bytes) {
   if (hipMalloc(p, bytes) != hipSuccess) return fail(HV_ERR_NOMEM, "autofocus allocation of %zu bytes failed", bytes);
@@ -866,11 +1007,13 @@ hv_status dev_alloc(hv_af_model* md, void** p, size_t bytes) {
 // Forward through the four conv layers and the head.
 hv_status forward(hv_af_model* md, const _Float16* crops, int bsz, bool train, hipStream_t st) {
   const dim3 grid(16, bsz);
-  hipLaunchKernelGGL((k_conv<1, _Float16, 0>), grid, dim3(256), 0, st, crops, nullptr, md->params, OFF_W[0],
-                     OFF_B[0], md->act[0]);
+  hipLaunchKernelGGL((k_conv<1, _Float16>), grid, dim3(256), 0, st, crops, md->params, OFF_W[0], OFF_B[0],
+                     md->act[0]);
+  const int nu = 16 * bsz;
+  const int gf = hvi::persistent_grid(k_conv_f32mfma<0>, 256, nu);
   for (int l = 1; l < 4; ++l)
-    hipLaunchKernelGGL((k_conv<NCH, float, 0>), grid, dim3(256), 0, st, md->act[l - 1], nullptr, md->params,
-                       OFF_W[l], OFF_B[l], md->act[l]);
+    hipLaunchKernelGGL(k_conv_f32mfma<0>, dim3(gf), dim3(256), 0, st, md->act[l - 1], nullptr, md->params, OFF_W[l],
+                       OFF_B[l], md->act[l], nu);
   if (train)
     hipLaunchKernelGGL(k_head<true>, dim3(bsz), dim3(256), 0, st, md->act[3], md->params, md->zn, bsz, md->out,
                        md->loss_b, md->hpart, md->d1);
@@ -905,24 +1048,23 @@ hv_status infer(hv_af_model* md, const _Float16* crops, int bsz, hipStream_t st)
 hv_status backward(hv_af_model* md, const _Float16* crops, int bsz, float* grad, float* loss, hipStream_t st) {
   hipLaunchKernelGGL(k_head_reduce, dim3((HEAD_N + 1 + 255) / 256), dim3(256), 0, st, md->hpart, md->loss_b, bsz,
                      grad, loss);
-  const int per = (bsz + SPLITS - 1) / SPLITS;
-  const int splits = (bsz + per - 1) / per;
   float* dcur = md->d1;   // dA of the current layer's output
   float* dnext = md->d2;  // receives dA of its input
+  const int nu = 16 * bsz, gw = std::min(nu, WG_BLOCKS);
   for (int l = 3; l >= 0; --l) {
     if (l > 0) {
-      hipLaunchKernelGGL((k_wgrad<NCH, float, 8>), dim3(4, splits), dim3(320), 0, st, md->act[l - 1], dcur,
-                         md->act[l], bsz, per, md->part_w, md->part_b);
+      hipLaunchKernelGGL((k_wgrad_mfma<NCH, float>), dim3(gw), dim3(576), 0, st, md->act[l - 1], dcur, md->act[l], nu,
+                         md->part_w, md->part_b);
       hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
-                         md->part_b, splits, NCH, OFF_W[l], OFF_B[l], grad);
-      hipLaunchKernelGGL((k_conv<NCH, float, 1>), dim3(16, bsz), dim3(256), 0, st, dcur, md->act[l], md->params,
-                         OFF_W[l], 0, dnext);
+                         md->part_b, gw, NCH, OFF_W[l], OFF_B[l], grad);
+      hipLaunchKernelGGL(k_conv_f32mfma<1>, dim3(hvi::persistent_grid(k_conv_f32mfma<1>, 256, nu)), dim3(256), 0,
+                         st, dcur, md->act[l], md->params, OFF_W[l], 0, dnext, nu);
       std::swap(dcur, dnext);
     } else {
-      hipLaunchKernelGGL((k_wgrad<1, _Float16, NCH>), dim3(1, splits), dim3(64), 0, st, crops, dcur, md->act[0],
-                         bsz, per, md->part_w, md->part_b);
+      hipLaunchKernelGGL((k_wgrad_mfma<1, _Float16>), dim3(gw), dim3(256), 0, st, crops, dcur, md->act[0], nu,
+                         md->part_w, md->part_b);
       hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
-                         md->part_b, splits, 1, OFF_W[0], OFF_B[0], grad);
+                         md->part_b, gw, 1, OFF_W[0], OFF_B[0], grad);
     }
   }
   return launched("af backward");
@@ -1110,8 +1252,8 @@ hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batc
   const size_t ib = (size_t)md->infer_batch;
   hv_status s;
   const size_t act = (size_t)max_batch * NCH * HW * 4;
-  // any batch <= max_batch uses at most SPLITS splits (ceil(b / ceil(b / SPLITS)) <= SPLITS)
-  const int splits = SPLITS;
+  // the weight gradients of any batch use at most WG_BLOCKS partial sums
+  const int splits = WG_BLOCKS;
   auto fail_out = [&](hv_status e) {
     hv_af_model_destroy(md);
     return e;
