@@ -530,16 +530,16 @@ __global__ __launch_bounds__(256) void k_head_pooled(const float* __restrict__ p
 // cores (FP32 operands, v_mfma_f32_32x32x2f32): per 16 x 16 output tile,
 // [256 pixels] x [288 = 9 c + tap] times [288] x [32 output channels], with
 // NCHW FP32 activations, in two modes:
-//   MODE 0 (forward):   out = ReLU(b + W * in)
-//   MODE 1 (input grad): out = W^T(flipped) * (in masked by mask > 0)
+//   MODE 0 (forward):    out = ReLU(b + W * in)
+//   MODE 1 (input grad): out = W^T(flipped) * in, with in = dZ (the output
+//                        gradient already masked by the ReLU)
 // Persistent: the layer's weights sit in LDS as B[k][o] for all of the
 // block's units; wave w owns the 32-pixel M tiles 2w and 2w + 1; the
 // outputs are staged in LDS so that each channel's 16-pixel rows are stored
 // contiguously.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_conv_f32mfma(const float* __restrict__ in, const float* __restrict__ mask,
-                                                      const float* __restrict__ params, int woff, int boff,
-                                                      float* __restrict__ out, int nunits) {
+__global__ __launch_bounds__(256) void k_conv_f32mfma(const float* __restrict__ in, const float* __restrict__ params,
+                                                      int woff, int boff, float* __restrict__ out, int nunits) {
   constexpr int K = NCH * 9;
   constexpr int OS = 257;  // staging row stride
   static_assert(NCH * OS <= NCH * 18 * 19, "output staging fits in the input tile");
@@ -565,11 +565,7 @@ __global__ __launch_bounds__(256) void k_conv_f32mfma(const float* __restrict__ 
       const int c = q / 324, r = (q % 324) / 18, col = q % 18;
       const int y = ty0 + r - 1, x = tx0 + col - 1;
       v[i] = 0.f;
-      if (q < NCH * 324 && y >= 0 && y < CROP && x >= 0 && x < CROP) {
-        const long idx = ((b * NCH + c) * CROP + y) * CROP + x;
-        v[i] = in[idx];
-        if (MODE == 1 && !(mask[idx] > 0.f)) v[i] = 0.f;
-      }
+      if (q < NCH * 324 && y >= 0 && y < CROP && x >= 0 && x < CROP) v[i] = in[((b * NCH + c) * CROP + y) * CROP + x];
     }
     __syncthreads();  // the previous unit's staged outputs are stored
 #pragma unroll
@@ -611,10 +607,24 @@ __global__ __launch_bounds__(256) void k_conv_f32mfma(const float* __restrict__ 
   }
 }
 
+// dZ = dA [A > 0] in place: the gradient through the ReLU of a layer whose
+// output activation is A.
+__global__ void k_relu_mask(float4* __restrict__ d, const float4* __restrict__ a, long n4) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n4; i += (long)gridDim.x * blockDim.x) {
+    float4 v = d[i];
+    const float4 m = a[i];
+    v.x = m.x > 0.f ? v.x : 0.f;
+    v.y = m.y > 0.f ? v.y : 0.f;
+    v.z = m.z > 0.f ? v.z : 0.f;
+    v.w = m.w > 0.f ? v.w : 0.f;
+    d[i] = v;
+  }
+}
+
 // Weight and bias gradients of one conv layer as a GEMM on the matrix cores
 // (FP32 operands, v_mfma_f32_32x32x2f32): dW[o][k] = sum_n dZ[n][o] X[n][k] over
 // n = (sample, pixel), k = 9 c + tap, X[n][k] the input at pixel n moved by
-// the tap (zero outside the image), dZ = dA [A > 0].  Block g accumulates the
+// the tap (zero outside the image), dZ = dA [A > 0] (masked beforehand).  Block g accumulates the
 // units (sample, 16 x 16 tile) g, g + G, ... in registers and writes its
 // partial sums; k_wgrad_reduce adds the G partials in block order, so the
 // result does not depend on scheduling.  CIN = 32: wave w (of nine) owns the
@@ -624,8 +634,7 @@ __global__ __launch_bounds__(256) void k_conv_f32mfma(const float* __restrict__ 
 // their output channel over the block's pixels in order.
 template <int CIN, typename TIN>
 __global__ __launch_bounds__(CIN == 1 ? 256 : 576) void k_wgrad_mfma(const TIN* __restrict__ x,
-                                                                   const float* __restrict__ dA,
-                                                                   const float* __restrict__ aout, int nunits,
+                                                                   const float* __restrict__ dz, int nunits,
                                                                    float* __restrict__ part_w,
                                                                    float* __restrict__ part_b) {
   constexpr int NW = CIN == 1 ? 4 : 9;
@@ -676,10 +685,7 @@ __global__ __launch_bounds__(CIN == 1 ? 256 : 576) void k_wgrad_mfma(const TIN* 
         const int q = tid + NT * i;
         const int o = q >> 8, pp = q & 255;
         vz[i] = 0.f;
-        if (q < NCH * 256) {
-          const long idx = ((b * NCH + o) * CROP + ty0 + (pp >> 4)) * CROP + tx0 + (pp & 15);
-          vz[i] = aout[idx] > 0.f ? dA[idx] : 0.f;
-        }
+        if (q < NCH * 256) vz[i] = dz[((b * NCH + o) * CROP + ty0 + (pp >> 4)) * CROP + tx0 + (pp & 15)];
       }
 #pragma unroll
       for (int i = 0; i < PZ; ++i) {
@@ -1012,8 +1018,8 @@ hv_status forward(hv_af_model* md, const _Float16* crops, int bsz, bool train, h
   const int nu = 16 * bsz;
   const int gf = hvi::persistent_grid(k_conv_f32mfma<0>, 256, nu);
   for (int l = 1; l < 4; ++l)
-    hipLaunchKernelGGL(k_conv_f32mfma<0>, dim3(gf), dim3(256), 0, st, md->act[l - 1], nullptr, md->params, OFF_W[l],
-                       OFF_B[l], md->act[l], nu);
+    hipLaunchKernelGGL(k_conv_f32mfma<0>, dim3(gf), dim3(256), 0, st, md->act[l - 1], md->params, OFF_W[l], OFF_B[l],
+                       md->act[l], nu);
   if (train)
     hipLaunchKernelGGL(k_head<true>, dim3(bsz), dim3(256), 0, st, md->act[3], md->params, md->zn, bsz, md->out,
                        md->loss_b, md->hpart, md->d1);
@@ -1051,18 +1057,22 @@ hv_status backward(hv_af_model* md, const _Float16* crops, int bsz, float* grad,
   float* dcur = md->d1;   // dA of the current layer's output
   float* dnext = md->d2;  // receives dA of its input
   const int nu = 16 * bsz, gw = std::min(nu, WG_BLOCKS);
+  const long n4 = (long)bsz * NCH * HW / 4;
   for (int l = 3; l >= 0; --l) {
+    // dA of this layer's output -> dZ through its ReLU
+    hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<long>(4096, (n4 + 255) / 256)), dim3(256), 0, st,
+                       (float4*)dcur, (const float4*)md->act[l], n4);
     if (l > 0) {
-      hipLaunchKernelGGL((k_wgrad_mfma<NCH, float>), dim3(gw), dim3(576), 0, st, md->act[l - 1], dcur, md->act[l], nu,
-                         md->part_w, md->part_b);
+      hipLaunchKernelGGL((k_wgrad_mfma<NCH, float>), dim3(gw), dim3(576), 0, st, md->act[l - 1], dcur, nu, md->part_w,
+                         md->part_b);
       hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
                          md->part_b, gw, NCH, OFF_W[l], OFF_B[l], grad);
       hipLaunchKernelGGL(k_conv_f32mfma<1>, dim3(hvi::persistent_grid(k_conv_f32mfma<1>, 256, nu)), dim3(256), 0,
-                         st, dcur, md->act[l], md->params, OFF_W[l], 0, dnext, nu);
+                         st, dcur, md->params, OFF_W[l], 0, dnext, nu);
       std::swap(dcur, dnext);
     } else {
-      hipLaunchKernelGGL((k_wgrad_mfma<1, _Float16>), dim3(gw), dim3(256), 0, st, crops, dcur, md->act[0], nu,
-                         md->part_w, md->part_b);
+      hipLaunchKernelGGL((k_wgrad_mfma<1, _Float16>), dim3(gw), dim3(256), 0, st, crops, dcur, nu, md->part_w,
+                         md->part_b);
       hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
                          md->part_b, gw, 1, OFF_W[0], OFF_B[0], grad);
     }
