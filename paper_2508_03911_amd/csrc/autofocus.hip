@@ -67,83 +67,157 @@ __device__ inline double block_sum(double v, double* red) {
   return r;
 }
 
-// ------------------------------------------------------------------ spectrum crop
-// t1: row half-spectra [n][128][256] (column 0 packs the real DC and Nyquist columns).
-template <typename TOUT>
-__global__ __launch_bounds__(512) void k_af_crop(const float2* __restrict__ t1, TOUT* __restrict__ out) {
-  constexpr int NT = 512, NB = 33, S = lds_stride(AN);
-  __shared__ float2 buf[NB * S];
-  __shared__ float2 tw[tw_size(AN) > 0 ? tw_size(AN) : 1];
-  __shared__ float vals[HW];
-  __shared__ double red[NT];
+// ------------------------------------------------------------------ spectrum crop and sub-band
+// Straight from the camera bytes, one hologram per unit: CR, the network's
+// crop, from the 2-D spectrum X at columns kx = 0 .. 32 and rows
+// ky = -32 .. 32; SB, the +1-order sub-band, from columns and rows
+// 33 .. 96.  The 256 rows are taken in eight interleaved groups
+// (y = 8 m + g, m < 32), 32 rows = 16 complex FFTs of two real rows each
+// (the next group's bytes load into registers meanwhile); the two rows'
+// spectra are separated at the needed columns, a 32-point FFT along m
+// gives Y_g(ky mod 32, kx), and X(ky, kx) = sum_g W256^(g ky) Y_g(ky mod 32,
+// kx) is accumulated in registers, one output per (thread, slot) -- the
+// column transform split as 256 = 8 x 32, so that LDS holds one row group
+// rather than all 256 rows.  Then
+//   crop: log(1 + |X(fy, fx)|) for fy, fx in [-32, 32) (fx < 0 through
+//         X(fy, fx) = conj X(-fy, -fx), the DC bin zero as for h - mean),
+//         standardised over the crop (mean and variance in FP64);
+//   sub-band: bins ky = i - 96, kx = j - 96 (i, j < 64), read as
+//         conj X(96 - i, 96 - j), zero beyond 0.1 cycles/pixel of the
+//         carrier.
+template <bool CR, bool SB, typename TOUT>
+__global__ __launch_bounds__(256) void k_af_spec(const uint8_t* __restrict__ holo, int n, TOUT* __restrict__ crop,
+                                                 float2* __restrict__ sub) {
+  constexpr int NT = 256, S = lds_stride(AN), RG = 32, NBR = RG / 2, NG = AN / RG;
+  constexpr int S32 = lds_stride(RG);
+  constexpr int NCC = CR ? 33 : 0, NSC = SB ? 64 : 0, NSLOT = NCC + NSC;  // column slots
+  constexpr int NOC = CR ? 33 * 65 : 0, NOS = SB ? 64 * 64 : 0, NOUT = NOC + NOS;
+  constexpr int PERT = (NOUT + NT - 1) / NT;  // outputs per thread
+  static_assert(NBR * S * 8 >= NOC * 4 + NT * 8, "the crop's staging fits in the row buffer");
+  __shared__ float2 rb[NBR * S];  // a row group; the crop's staging after the last group
+  __shared__ float2 cb[NSLOT * S32];
+  __shared__ float2 tw[tw_size(AN)];
+  __shared__ float2 tw32[tw_size(RG)];
+  __shared__ float2 w256[AN];  // W256^k = exp(-2 pi i k / 256)
   const int tid = threadIdx.x;
-  const long n = blockIdx.x;
   fill_twiddles<AN>(tw, tid, NT);
-  const float2* src = t1 + n * (AN / 2) * AN;
-  for (int q = tid; q < NB * AN; q += NT) buf[(q / AN) * S + skew(q % AN)] = src[q];
-  __syncthreads();
-  fft_lds<AN, NB, NT, -1>(buf, tw, tid);
-  double s1 = 0.0, s2 = 0.0;
-  for (int q = tid; q < HW; q += NT) {
-    const int fy = q / CROP - CROP / 2, fx = q % CROP - CROP / 2;
-    int col, row;
-    if (fx >= 0) {
-      col = fx;
-      row = fy & (AN - 1);
-    } else {  // |X(fx, fy)| = |X(-fx, -fy)| for a real hologram
-      col = -fx;
-      row = (-fy) & (AN - 1);
-    }
-    float mag;
-    if (col == 0) {
-      const float2 a = buf[skew(row)], b = buf[skew((AN - row) & (AN - 1))];
-      const float re = 0.5f * (a.x + b.x), im = 0.5f * (a.y - b.y);
-      mag = row == 0 ? 0.f : sqrtf(re * re + im * im);  // DC removed with the mean
-    } else {
-      const float2 a = buf[col * S + skew(row)];
-      mag = sqrtf(a.x * a.x + a.y * a.y);
-    }
-    const float v = log1pf(mag);
-    vals[q] = v;
-    s1 += v;
-    s2 += (double)v * v;
+  fill_twiddles<RG>(tw32, tid, NT);
+  {
+    float sn, cs;
+    sincospif(-2.0f * (float)tid / AN, &sn, &cs);
+    w256[tid] = make_float2(cs, sn);
   }
-  s1 = block_sum<NT>(s1, red);
-  s2 = block_sum<NT>(s2, red);
-  const double mean = s1 / HW;
-  const double sd = sqrt(fmax(s2 / HW - mean * mean, 1e-30));
-  const float m = (float)mean, inv = (float)(1.0 / sd);
-  for (int q = tid; q < HW; q += NT) out[n * HW + q] = (TOUT)((vals[q] - m) * inv);
-}
-
-// ------------------------------------------------------------------ scan
-// Masked +1-order sub-band: bins ky = i - 96, kx = j - 96 (i, j < 64), read
-// through Hermitian symmetry from columns 96 - j and rows 96 - i.  Block
-// (n, half) transforms the 32 columns 33 + 32 half .. of hologram n and
-// writes the sub-band values that come from them.
-__global__ __launch_bounds__(512) void k_af_subband(const float2* __restrict__ t1, float2* __restrict__ sub) {
-  constexpr int NT = 512, NB = 32, S = lds_stride(AN);
-  __shared__ float2 buf[NB * S];
-  __shared__ float2 tw[tw_size(AN) > 0 ? tw_size(AN) : 1];
-  const int tid = threadIdx.x;
-  const long n = blockIdx.x;
-  const int c0 = 33 + 32 * blockIdx.y;
-  fill_twiddles<AN>(tw, tid, NT);
-  const float2* src = t1 + n * (AN / 2) * AN + (long)c0 * AN;
-  for (int q = tid; q < NB * AN; q += NT) buf[(q / AN) * S + skew(q % AN)] = src[q];
-  __syncthreads();
-  fft_lds<AN, NB, NT, -1>(buf, tw, tid);
-  for (int q = tid; q < SUB * SUB; q += NT) {
-    const int i = q / SUB, j = q % SUB;
-    const int col = 96 - j;
-    if (col < c0 || col >= c0 + NB) continue;
-    const int di = i - SUB / 2, dj = j - SUB / 2;
-    float2 v = make_float2(0.f, 0.f);
-    if (100 * (di * di + dj * dj) <= AN * AN) {  // radius 0.1 cycles/pixel
-      const float2 a = buf[(col - c0) * S + skew(96 - i)];
-      v = make_float2(a.x, -a.y);
+  // load slot: row pair lb (rows 16 lb + g and 16 lb + 8 + g: m = 2 lb and
+  // 2 lb + 1), bytes lx .. lx + 15
+  const int lb = tid >> 4, lx = (tid & 15) * 16;
+  uint4 w0, w1;
+  auto fetch = [&](long u, int g) {
+    const uint8_t* p = holo + u * (AN * AN) + (long)(16 * lb + g) * AN + lx;
+    w0 = *reinterpret_cast<const uint4*>(p);
+    w1 = *reinterpret_cast<const uint4*>(p + 8 * AN);
+  };
+  auto byte_of = [](const uint4& w, int e) {
+    const uint32_t v = e < 4 ? w.x : e < 8 ? w.y : e < 12 ? w.z : w.w;
+    return (float)((v >> (8 * (e & 3))) & 0xffu);
+  };
+  // output o of this thread: slot (column) and row ky
+  auto out_slot = [](int o) { return o < NOC ? o / 65 : NCC + (o - NOC) / 64; };
+  auto out_ky = [](int o) { return o < NOC ? o % 65 - 32 : 33 + (o - NOC) % 64; };
+  auto slot_kx = [](int sl) { return sl < NCC ? sl : 33 + (sl - NCC); };
+  if ((long)blockIdx.x < n) fetch(blockIdx.x, 0);
+  for (long u = blockIdx.x; u < n; u += gridDim.x) {
+    float2 acc[PERT];
+#pragma unroll
+    for (int j = 0; j < PERT; ++j) acc[j] = make_float2(0.f, 0.f);
+    for (int g = 0; g < NG; ++g) {
+      float2* dst = rb + lb * S;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) dst[skew(lx + e)] = make_float2(byte_of(w0, e), byte_of(w1, e));
+      __syncthreads();
+      if (g + 1 < NG)
+        fetch(u, g + 1);
+      else if (u + gridDim.x < n)
+        fetch(u + gridDim.x, 0);
+      fft_lds<AN, NBR, NT, -1>(rb, tw, tid);
+      // Z of rows x (real part) and y (imaginary part): X(f) = (Z(f) +
+      // conj Z(-f)) / 2, Y(f) = (Z(f) - conj Z(-f)) / 2i; column 0 is the
+      // real DC column alone
+      for (int q = tid; q < NBR * NSLOT; q += NT) {
+        const int b = q % NBR, sl = q / NBR, fx = slot_kx(sl);
+        const float2* prow = rb + b * S;
+        const float2 z1 = prow[skew(fx)];
+        float2 xe, xo;
+        if (fx == 0) {
+          xe = make_float2(z1.x, 0.f);
+          xo = make_float2(z1.y, 0.f);
+        } else {
+          const float2 z2 = c2::conj(prow[skew(AN - fx)]);
+          xe = c2::scale(c2::add(z1, z2), 0.5f);
+          const float2 d = c2::sub(z1, z2);
+          xo = make_float2(0.5f * d.y, -0.5f * d.x);
+        }
+        float2* col = cb + sl * S32;
+        col[skew(2 * b)] = xe;
+        col[skew(2 * b + 1)] = xo;
+      }
+      __syncthreads();
+      fft_lds<RG, NSLOT, NT, -1>(cb, tw32, tid);
+#pragma unroll
+      for (int j = 0; j < PERT; ++j) {
+        const int o = tid + NT * j;
+        if (NOUT % NT == 0 || o < NOUT) {
+          const int ky = out_ky(o);
+          const float2 y = cb[out_slot(o) * S32 + skew(ky & (RG - 1))];
+          const float2 w = w256[(g * ky) & (AN - 1)];
+          acc[j] = make_float2(acc[j].x + (y.x * w.x - y.y * w.y), acc[j].y + (y.x * w.y + y.y * w.x));
+        }
+      }
     }
-    sub[n * SUB * SUB + q] = v;
+    const long h = u;
+    if constexpr (SB) {
+#pragma unroll
+      for (int j = 0; j < PERT; ++j) {
+        const int o = tid + NT * j;
+        if (o >= NOC && o < NOUT) {
+          const int i = 96 - out_ky(o), jj = 96 - slot_kx(out_slot(o));
+          const int di = i - SUB / 2, dj = jj - SUB / 2;
+          const bool in_band = 100 * (di * di + dj * dj) <= AN * AN;  // radius 0.1 cycles/pixel
+          sub[h * SUB * SUB + i * SUB + jj] = in_band ? make_float2(acc[j].x, -acc[j].y) : make_float2(0.f, 0.f);
+        }
+      }
+    }
+    if constexpr (CR) {
+      // log-magnitudes of the 33 x 65 outputs, then the crop through the symmetry
+      float* lm = reinterpret_cast<float*>(rb);
+#pragma unroll
+      for (int j = 0; j < PERT; ++j) {
+        const int o = tid + NT * j;
+        if (o < NOC) {
+          const float mag = o == 32 ? 0.f : sqrtf(acc[j].x * acc[j].x + acc[j].y * acc[j].y);  // DC removed with the mean
+          lm[o] = log1pf(mag);
+        }
+      }
+      __syncthreads();
+      constexpr int PQ = HW / NT;
+      float v[PQ];
+      double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < PQ; ++j) {
+        const int q = tid + NT * j;
+        const int fy = q / CROP - CROP / 2, fx = q % CROP - CROP / 2;
+        v[j] = fx >= 0 ? lm[fx * 65 + fy + 32] : lm[-fx * 65 - fy + 32];
+        s1 += v[j];
+        s2 += (double)v[j] * v[j];
+      }
+      double* red = reinterpret_cast<double*>(lm + NOC + 1);  // 8-byte aligned past the staging
+      s1 = block_sum<NT>(s1, red);
+      s2 = block_sum<NT>(s2, red);
+      const double mean = s1 / HW;
+      const double sd = sqrt(fmax(s2 / HW - mean * mean, 1e-30));
+      const float m = (float)mean, inv = (float)(1.0 / sd);
+#pragma unroll
+      for (int j = 0; j < PQ; ++j) crop[h * HW + tid + NT * j] = (TOUT)((v[j] - m) * inv);
+    }
   }
 }
 
@@ -381,32 +455,64 @@ __global__ void k_pack_weights(const float* __restrict__ params, h8v* __restrict
   wf[q] = v;
 }
 
+// A 32-channel layer of the inference pass as an implicit GEMM on the
+// matrix cores: per 16 x 16 output tile, [256 pixels] x [288 = 9 taps x 32
+// channels] times [288] x [32 output channels], NHWC fp16 activations.
 // Persistent: workgroup g takes units g, g + gridDim.x, ... (unit = one
-// 16 x 16 output tile of one sample) with the layer's B fragments held in
+// output tile of one sample) with the layer's weight fragments held in
 // registers across units, and loads the next unit's input tile into
 // registers while the current unit's MFMAs run.  Wave w owns tile pixels
-// [64 w, 64 w + 64) as two 32-pixel M tiles.  LAST: no activation is
-// stored; the ReLU outputs of the tile are summed per channel into
-// pooled[sample][tile][32] (the global average pool, finished in the head
-// in a fixed order).
-template <int CIN, bool LAST>
+// [64 w, 64 w + 64) as two 32-pixel tiles.  The product is formed as
+// (channels x pixels) = W x X^T, so that a lane holds 16 output channels
+// of one pixel (channels 8 q + 4 h + j, q, j < 4) and stores them as four
+// 8-byte runs; LAST forms pixels x channels instead, a lane holding one
+// channel of 16 pixels, and stores no activation: the ReLU outputs of the
+// tile are summed per channel into pooled[sample][tile][32] (the global
+// average pool, finished in the head in a fixed order).  FIRST: `in` is
+// the crop, and the first layer (1 -> 32 channels, nine taps: one k-step
+// with the fragment wf0 and the biases at boff0) is evaluated on the
+// 18 x 18 input tile, one tile row per product (lanes 18 .. 31 idle), from
+// a 20 x 20 crop tile, rounded to fp16 after its ReLU and kept in LDS (zero
+// outside the image: the second layer's padding), so that the first
+// layer's activations never reach HBM.
+template <bool LAST, bool FIRST>
 __global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ in, const h8v* __restrict__ wf,
                                                    const float* __restrict__ params, int boff,
                                                    _Float16* __restrict__ out, float* __restrict__ pooled,
-                                                   int nunits) {
-  constexpr int PS = CIN == 1 ? 1 : CIN + 8;  // halves per LDS pixel (80 B: 16-B reads of 16 lanes hit distinct banks)
-  constexpr int KS = CIN == 1 ? 1 : 9 * CIN / 16;
-  // input items per unit: 18 x 18 pixels of one half (CIN = 1) or of CIN/8 chunks of 8 channels
-  constexpr int ITEMS = CIN == 1 ? 324 : 324 * (CIN / 8);
+                                                   int nunits, const h8v* __restrict__ wf0, int boff0) {
+  typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+  constexpr int PS = NCH + 8;  // halves per LDS pixel (80 B: 16-B reads of 16 lanes hit distinct banks)
+  constexpr int KS = 9 * NCH / 16;
+  constexpr int CT = 34;       // crop tile row stride (columns 20 .. 33 zero)
+  // input items per unit: 18 x 18 pixels of NCH/8 chunks of 8 channels, or
+  // (FIRST) 20 x 20 crop pixels
+  constexpr int ITEMS = FIRST ? 400 : 324 * (NCH / 8);
   constexpr int PER = (ITEMS + 255) / 256;
-  using Item = typename std::conditional<CIN == 1, _Float16, h8v>::type;
+  using Item = typename std::conditional<FIRST, _Float16, h8v>::type;
   __shared__ __attribute__((aligned(16))) _Float16 tile[18 * 18 * PS];
+  __shared__ _Float16 ctile[FIRST ? 20 * CT : 1];
   __shared__ float red[4][32];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31;
   h8v bw[KS];
 #pragma unroll
   for (int s = 0; s < KS; ++s) bw[s] = wf[s * 64 + lane];
-  const float bias = params[boff + c];
+  // biases of the channels this lane produces
+  float bias[LAST ? 1 : 16];
+  if constexpr (LAST) {
+    bias[0] = params[boff + c];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) bias[r] = params[boff + 8 * (r >> 2) + 4 * h + (r & 3)];
+  }
+  h8v bw0;
+  float bias0[FIRST ? 16 : 1];
+  if constexpr (FIRST) {
+    bw0 = wf0[lane];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) bias0[r] = params[boff0 + 8 * (r >> 2) + 4 * h + (r & 3)];
+    for (int q = tid; q < 20 * CT; q += 256)
+      if (q % CT >= 20) ctile[q] = (_Float16)0.f;
+  }
   Item nxt[PER];
   auto fetch = [&](int u) {
     const long b = u >> 4;
@@ -415,16 +521,18 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ 
     for (int i = 0; i < PER; ++i) {
       const int q = tid + 256 * i;
       if (ITEMS % 256 == 0 || q < ITEMS) {
-        const int pix = CIN == 1 ? q : q / (CIN / 8), ch = CIN == 1 ? 0 : q % (CIN / 8);
-        const int r = pix / 18, col = pix % 18, y = ty0 + r - 1, x = tx0 + col - 1;
-        const bool inside = y >= 0 && y < CROP && x >= 0 && x < CROP;
-        if constexpr (CIN == 1) {
+        if constexpr (FIRST) {
+          const int y = ty0 + q / 20 - 2, x = tx0 + q % 20 - 2;
+          const bool inside = y >= 0 && y < CROP && x >= 0 && x < CROP;
           nxt[i] = inside ? in[(b * CROP + y) * CROP + x] : (_Float16)0.f;
         } else {
+          const int pix = q / (NCH / 8), ch = q % (NCH / 8);
+          const int y = ty0 + pix / 18 - 1, x = tx0 + pix % 18 - 1;
           h8v v;
 #pragma unroll
           for (int e = 0; e < 8; ++e) v[e] = (_Float16)0.f;
-          if (inside) v = *reinterpret_cast<const h8v*>(in + ((b * CROP + y) * CROP + x) * CIN + 8 * ch);
+          if (y >= 0 && y < CROP && x >= 0 && x < CROP)
+            v = *reinterpret_cast<const h8v*>(in + ((b * CROP + y) * CROP + x) * NCH + 8 * ch);
           nxt[i] = v;
         }
       }
@@ -435,19 +543,56 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ 
   for (; u < nunits; u += gridDim.x) {
     const long b = u >> 4;
     const int t16 = u & 15, ty0 = (t16 >> 2) * 16, tx0 = (t16 & 3) * 16;
-    __syncthreads();  // the previous unit's reads of tile and red are done
+    __syncthreads();  // the previous unit's reads of tile, ctile and red are done
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int q = tid + 256 * i;
       if (ITEMS % 256 == 0 || q < ITEMS) {
-        if constexpr (CIN == 1)
-          tile[q] = nxt[i];
+        if constexpr (FIRST)
+          ctile[(q / 20) * CT + q % 20] = nxt[i];
         else
-          *reinterpret_cast<h8v*>(tile + (q / (CIN / 8)) * PS + 8 * (q % (CIN / 8))) = nxt[i];
+          *reinterpret_cast<h8v*>(tile + (q / (NCH / 8)) * PS + 8 * (q % (NCH / 8))) = nxt[i];
       }
     }
     __syncthreads();
-    if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+    if (!FIRST && u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+    if constexpr (FIRST) {
+      // tile row mt = wave + 4 i (< 18): pixel (mt, c), k = tap for k < 9
+      // (lanes h = 1 hold k = 8 .. 15: tap 8, then zeros)
+      const unsigned xin = tx0 + c - 1;
+#pragma unroll 1
+      for (int i = 0; i < 5; ++i) {
+        const int mt = wave + 4 * i;
+        if (mt < 18) {
+          const _Float16* cp = ctile + mt * CT + c;
+          h8v a;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const _Float16 v = cp[h ? 2 * CT + 2 : (e / 3) * CT + e % 3];
+            a[e] = h && e > 0 ? (_Float16)0.f : v;
+          }
+          f32x16 acc0;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc0[r] = 0.f;
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(bw0, a, acc0, 0, 0, 0);
+          if (c < 18) {
+            const bool inside = (unsigned)(ty0 + mt - 1) < (unsigned)CROP && xin < (unsigned)CROP;
+            _Float16* dst = tile + (mt * 18 + c) * PS + 4 * h;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              h4v v;
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                v[j] = inside ? (_Float16)fmaxf(acc0[4 * q + j] + bias0[4 * q + j], 0.f) : (_Float16)0.f;
+              *reinterpret_cast<h4v*>(dst + 8 * q) = v;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // the next crop tile loads under the second layer's MFMAs
+      if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+    }
     f32x16 acc[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
@@ -456,35 +601,33 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ 
       const int p = (2 * wave + mt) * 32 + c, py = p >> 4, px = p & 15;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        h8v a;
-        if constexpr (CIN == 1) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int k = 8 * h + e;
-            a[e] = k < 9 ? tile[(py + k / 3) * 18 + px + k % 3] : (_Float16)0.f;
-          }
-        } else {
-          const int tap = s >> 1, c0 = 16 * (s & 1) + 8 * h;
-          a = *reinterpret_cast<const h8v*>(tile + ((py + tap / 3) * 18 + px + tap % 3) * PS + c0);
-        }
-        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bw[s], acc[mt], 0, 0, 0);
+        const int tap = s >> 1, c0 = 16 * (s & 1) + 8 * h;
+        const h8v a = *reinterpret_cast<const h8v*>(tile + ((py + tap / 3) * 18 + px + tap % 3) * PS + c0);
+        if constexpr (LAST)
+          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bw[s], acc[mt], 0, 0, 0);
+        else
+          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bw[s], a, acc[mt], 0, 0, 0);
       }
     }
     if constexpr (!LAST) {
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
+      for (int mt = 0; mt < 2; ++mt) {
+        const int p = (2 * wave + mt) * 32 + c;
+        _Float16* dst = out + ((b * CROP + ty0 + (p >> 4)) * CROP + tx0 + (p & 15)) * NCH + 4 * h;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int p = (2 * wave + mt) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-          const int y = ty0 + (p >> 4), x = tx0 + (p & 15);
-          out[((b * CROP + y) * CROP + x) * NCH + c] = (_Float16)fmaxf(acc[mt][r] + bias, 0.f);
+        for (int q = 0; q < 4; ++q) {
+          h4v v;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = (_Float16)fmaxf(acc[mt][4 * q + j] + bias[4 * q + j], 0.f);
+          *reinterpret_cast<h4v*>(dst + 8 * q) = v;
         }
+      }
     } else {
       float sum = 0.f;
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) sum += fmaxf(acc[mt][r] + bias, 0.f);
+        for (int r = 0; r < 16; ++r) sum += fmaxf(acc[mt][r] + bias[0], 0.f);
       sum += __shfl_xor(sum, 32);
       if (h == 0) red[wave][c] = sum;
       __syncthreads();
@@ -1038,15 +1181,16 @@ hv_status infer(hv_af_model* md, const _Float16* crops, int bsz, hipStream_t st)
     md->packed = md->version;
   }
   const int nu = 16 * bsz;
-  hipLaunchKernelGGL((k_conv_mfma<1, false>), dim3(hvi::persistent_grid(k_conv_mfma<1, false>, 256, nu)), dim3(256),
-                     0, st, crops, wf, md->params, OFF_B[0], md->act16[0], nullptr, nu);
-  const int g32 = hvi::persistent_grid(k_conv_mfma<NCH, false>, 256, nu);
-  hipLaunchKernelGGL((k_conv_mfma<NCH, false>), dim3(g32), dim3(256), 0, st, md->act16[0], wf + 64, md->params,
-                     OFF_B[1], md->act16[1], nullptr, nu);
-  hipLaunchKernelGGL((k_conv_mfma<NCH, false>), dim3(g32), dim3(256), 0, st, md->act16[1], wf + 64 * 19, md->params,
-                     OFF_B[2], md->act16[0], nullptr, nu);
-  hipLaunchKernelGGL((k_conv_mfma<NCH, true>), dim3(hvi::persistent_grid(k_conv_mfma<NCH, true>, 256, nu)),
-                     dim3(256), 0, st, md->act16[0], wf + 64 * 37, md->params, OFF_B[3], nullptr, md->pooled, nu);
+  // layers 1 and 2 in one pass (the first layer's output stays in LDS)
+  hipLaunchKernelGGL((k_conv_mfma<false, true>),
+                     dim3(hvi::persistent_grid(k_conv_mfma<false, true>, 256, nu)), dim3(256), 0, st, crops,
+                     wf + 64, md->params, OFF_B[1], md->act16[1], nullptr, nu, wf, OFF_B[0]);
+  hipLaunchKernelGGL((k_conv_mfma<false, false>), dim3(hvi::persistent_grid(k_conv_mfma<false, false>, 256, nu)),
+                     dim3(256), 0, st, md->act16[1], wf + 64 * 19, md->params, OFF_B[2], md->act16[0], nullptr, nu,
+                     nullptr, 0);
+  hipLaunchKernelGGL((k_conv_mfma<true, false>), dim3(hvi::persistent_grid(k_conv_mfma<true, false>, 256, nu)),
+                     dim3(256), 0, st, md->act16[0], wf + 64 * 37, md->params, OFF_B[3], nullptr, md->pooled, nu,
+                     nullptr, 0);
   hipLaunchKernelGGL(k_head_pooled, dim3((bsz + 3) / 4), dim3(256), 0, st, md->pooled, md->params, bsz, md->iout);
   return launched("af inference");
 }
@@ -1090,13 +1234,27 @@ struct ScanPlan {
 
 using namespace hvi;
 
-static hv_status af_spectrum(hv_ctx* ctx, const uint8_t* holo, int n, hipStream_t st, float2** t1) {
-  DevBuf& tb = ctx->work(st, 20);
-  hv_status s;
-  if ((s = tb.ensure((size_t)n * (AN / 2) * AN * 8, &ctx->held))) return s;
-  if ((s = launch_row_r2c(holo, HV_U8, tb.ptr, false, n, AN, AN, 1.f, st))) return s;
-  *t1 = (float2*)tb.ptr;
-  return HV_OK;
+// The spectrum kernel reads the holograms in 16-byte words.
+static hv_status check_holo(const uint8_t* holo) {
+  return (reinterpret_cast<uintptr_t>(holo) & 15) ? fail(HV_ERR_ARG, "holograms must be 16-byte aligned") : HV_OK;
+}
+
+// Crops (fp16 or float) and/or +1-order sub-bands of n holograms in one
+// launch; a null output is not produced.
+template <bool CR, bool SB, typename TOUT>
+static void launch_spec(const uint8_t* holo, int n, void* crop, float2* sub, hipStream_t st) {
+  auto k = k_af_spec<CR, SB, TOUT>;
+  hipLaunchKernelGGL(k, dim3(hvi::persistent_grid(k, 256, n)), dim3(256), 0, st, holo, n, (TOUT*)crop, sub);
+}
+static hv_status af_spectrum(const uint8_t* holo, int n, void* crop, bool half, float2* sub, hipStream_t st) {
+  if (n <= 0 || (!crop && !sub)) return HV_OK;
+  if (!crop)
+    launch_spec<false, true, _Float16>(holo, n, nullptr, sub, st);
+  else if (half)
+    sub ? launch_spec<true, true, _Float16>(holo, n, crop, sub, st) : launch_spec<true, false, _Float16>(holo, n, crop, sub, st);
+  else
+    sub ? launch_spec<true, true, float>(holo, n, crop, sub, st) : launch_spec<true, false, float>(holo, n, crop, sub, st);
+  return launched("af spectrum");
 }
 
 extern "C" {
@@ -1108,17 +1266,10 @@ hv_status hv_af_crops(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, v
   if (!ctx || !holo || !out) return fail(HV_ERR_ARG, "NULL argument");
   if (ny != AN || nx != AN) return fail(HV_ERR_SHAPE, "autofocus works on 256x256 holograms");
   if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  if (hv_status e = check_holo(holo)) return e;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  hipStream_t st = (hipStream_t)hip_stream;
-  float2* t1;
-  hv_status s;
-  if ((s = af_spectrum(ctx, holo, n, st, &t1))) return s;
-  if (out_half)
-    hipLaunchKernelGGL(k_af_crop<_Float16>, dim3(n), dim3(512), 0, st, t1, (_Float16*)out);
-  else
-    hipLaunchKernelGGL(k_af_crop<float>, dim3(n), dim3(512), 0, st, t1, (float*)out);
-  return launched("af_crop");
+  return af_spectrum(holo, n, out, out_half != 0, nullptr, (hipStream_t)hip_stream);
 }
 
 hv_status hv_af_scan(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, double wavelength_m, double pitch_m,
@@ -1129,6 +1280,7 @@ hv_status hv_af_scan(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, do
   if (n_candidates < 2 || !(z_hi_m > z_lo_m) || !(wavelength_m > 0) || !(pitch_m > 0))
     return fail(HV_ERR_ARG, "need >= 2 candidates, z_hi > z_lo, positive wavelength and pitch");
   if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  if (hv_status e = check_holo(holo)) return e;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   hipStream_t st = (hipStream_t)hip_stream;
@@ -1158,13 +1310,11 @@ hv_status hv_af_scan(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int nx, do
     }
     if ((s = tab.upload(h.data(), h.size() * sizeof(float2), &ctx->held))) return s;
   }
-  float2* t1;
-  if ((s = af_spectrum(ctx, holo, n, st, &t1))) return s;
   DevBuf& sb = ctx->work(st, 21);
   DevBuf& sc = ctx->work(st, 22);
   if ((s = sb.ensure((size_t)n * SUB * SUB * 8, &ctx->held))) return s;
   if ((s = sc.ensure((size_t)n * n_candidates * 4, &ctx->held))) return s;
-  hipLaunchKernelGGL(k_af_subband, dim3(n, 2), dim3(512), 0, st, t1, (float2*)sb.ptr);
+  if ((s = af_spectrum(holo, n, nullptr, false, (float2*)sb.ptr, st))) return s;
   constexpr int CPB = 8;
   hipLaunchKernelGGL((k_af_scan<CPB, false>), dim3(n, (n_candidates + CPB - 1) / CPB), dim3(256), 0, st,
                      (const float2*)sb.ptr, (const float2*)tab.ptr, (const double*)nullptr, (const float*)nullptr,
@@ -1229,17 +1379,16 @@ hv_status hv_af_scan_ranges(hv_ctx* ctx, const uint8_t* holo, int n, int ny, int
   if (n_candidates < 2 || !(wavelength_m > 0) || !(pitch_m > 0))
     return fail(HV_ERR_ARG, "need >= 2 candidates, positive wavelength and pitch");
   if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  if (hv_status e = check_holo(holo)) return e;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(HV_ERR_DEVICE, "hipSetDevice failed");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   hipStream_t st = (hipStream_t)hip_stream;
   hv_status s;
   const double* kz;
   if ((s = af_kz_table(ctx, wavelength_m, pitch_m, &kz))) return s;
-  float2* t1;
-  if ((s = af_spectrum(ctx, holo, n, st, &t1))) return s;
   DevBuf& sb = ctx->work(st, 21);
   if ((s = sb.ensure((size_t)n * SUB * SUB * 8, &ctx->held))) return s;
-  hipLaunchKernelGGL(k_af_subband, dim3(n, 2), dim3(512), 0, st, t1, (float2*)sb.ptr);
+  if ((s = af_spectrum(holo, n, nullptr, false, (float2*)sb.ptr, st))) return s;
   // the ranges are read, never written, on this path
   return af_scan_ranges(ctx, (const float2*)sb.ptr, n, kz, const_cast<float*>(z_lo), const_cast<float*>(z_hi),
                         n_candidates, z_out, scores_out, false, st);
@@ -1398,6 +1547,7 @@ hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wave
                         int* n_fallback, void* hip_stream) {
   if (!md || !holo || !z_out) return fail(HV_ERR_ARG, "NULL argument");
   if (n <= 0) return n == 0 ? HV_OK : fail(HV_ERR_ARG, "negative count");
+  if (hv_status e = check_holo(holo)) return e;
   const bool refine = refine_candidates > 0;
   if (refine && (refine_candidates < 4 || !(refine_k > 0)))
     return fail(HV_ERR_ARG, "a local scan needs >= 4 candidates and a positive width in sigma");
@@ -1423,10 +1573,10 @@ hv_status hv_af_predict(hv_af_model* md, const uint8_t* holo, int n, double wave
     return fail(HV_ERR_DEVICE, "memset failed");
   for (int b0 = 0; b0 < n; b0 += md->infer_batch) {
     const int bs = std::min(md->infer_batch, n - b0);
-    if ((s = hv_af_crops(ctx, holo + (size_t)b0 * AN * AN, bs, AN, AN, cb.ptr, 1, st))) return s;
-    if (refine)  // the +1-order sub-band from the same spectrum the crops came from
-      hipLaunchKernelGGL(k_af_subband, dim3(bs, 2), dim3(512), 0, st, (const float2*)ctx->work(st, 20).ptr,
-                         subs + (size_t)b0 * SUB * SUB);
+    // the crops and, for the local scan, the +1-order sub-bands in one pass
+    if ((s = af_spectrum(holo + (size_t)b0 * AN * AN, bs, cb.ptr, true, refine ? subs + (size_t)b0 * SUB * SUB : nullptr,
+                         st)))
+      return s;
     if ((s = infer(md, (const _Float16*)cb.ptr, bs, st))) return s;
     hipLaunchKernelGGL(k_af_denorm, dim3((bs + 255) / 256), dim3(256), 0, st, md->iout, bs, (float)md->z_mean,
                        (float)md->z_scale, z_out + b0, sigma + b0);
