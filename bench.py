@@ -258,7 +258,7 @@ def he_normal_init(seed):
 
 # local scan seeded by the network: candidates (half over z +- AF_K sigma,
 # half over one coarse step around the best of those)
-AF_REFINE, AF_K = 16, 2.0
+AF_REFINE, AF_K = 12, 2.0
 
 
 def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
@@ -344,7 +344,9 @@ def autofocus(hv, torch, n_train, n_eval, epochs, batch=256, lr=1e-3):
            "cnn_fallback": {**err(zf), "holograms_per_s": n_eval / t_fb, "fallback_fraction": nfb / n_eval,
                             "tau_m": tau},
            "cnn_local_scan": {**err(zl), "holograms_per_s": n_eval / t_loc, "candidates": AF_REFINE, "k_sigma": AF_K,
-                              "speedup_vs_scan": t_scan / t_loc},
+                              "speedup_vs_scan": t_scan / t_loc,
+                              "median_vs_scan": float(np.median(np.abs(zl.cpu().numpy() - ez))
+                                                      / np.median(np.abs(zs.cpu().numpy() - ez)))},
            "cnn_local_scan_fallback": {**err(zlf), "holograms_per_s": n_eval / t_lf,
                                        "fallback_fraction": nlf / n_eval, "speedup_vs_scan": t_scan / t_lf},
            "scan": {**err(zs), "holograms_per_s": n_eval / t_scan, "candidates": 128}}

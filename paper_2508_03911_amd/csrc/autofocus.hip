@@ -489,8 +489,12 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ 
   constexpr int ITEMS = FIRST ? 400 : 324 * (NCH / 8);
   constexpr int PER = (ITEMS + 255) / 256;
   using Item = typename std::conditional<FIRST, _Float16, h8v>::type;
-  __shared__ __attribute__((aligned(16))) _Float16 tile[18 * 18 * PS];
-  __shared__ _Float16 ctile[FIRST ? 20 * CT : 1];
+  // tile and ctile end in a dummy row that takes the fill of items past the
+  // tile, so that the fill has no branch and each load is used where it is
+  // issued
+  constexpr int TN = 18 * 18 * PS, CN = 20 * CT;
+  __shared__ __attribute__((aligned(16))) _Float16 tile[TN + (FIRST ? 0 : 8 * 256)];
+  __shared__ _Float16 ctile[FIRST ? CN + 256 : 1];
   __shared__ float red[4][32];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c = lane & 31;
   h8v bw[KS];
@@ -510,52 +514,75 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ 
     bw0 = wf0[lane];
 #pragma unroll
     for (int r = 0; r < 16; ++r) bias0[r] = params[boff0 + 8 * (r >> 2) + 4 * h + (r & 3)];
-    for (int q = tid; q < 20 * CT; q += 256)
+    for (int q = tid; q < CN; q += 256)
       if (q % CT >= 20) ctile[q] = (_Float16)0.f;
   }
+  // The next unit's input tile in registers.  Every lane issues every load
+  // (items outside the image or past the tile read a clamped in-range
+  // address and are zeroed when stored to LDS), so the wait for them at the
+  // top of the next unit counts exactly the loads and leaves the previous
+  // unit's stores in flight.
   Item nxt[PER];
+  uint32_t nmask = 0;  // bit i: item i is inside the image
   auto fetch = [&](int u) {
+    u = u < nunits ? u : nunits - 1;
     const long b = u >> 4;
     const int ty0 = ((u & 15) >> 2) * 16, tx0 = (u & 3) * 16;
+    nmask = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = min(tid + 256 * i, ITEMS - 1);
+      int y, x, ch = 0;
+      if constexpr (FIRST) {
+        y = ty0 + q / 20 - 2;
+        x = tx0 + q % 20 - 2;
+      } else {
+        const int pix = q / (NCH / 8);
+        ch = q % (NCH / 8);
+        y = ty0 + pix / 18 - 1;
+        x = tx0 + pix % 18 - 1;
+      }
+      const bool inside = y >= 0 && y < CROP && x >= 0 && x < CROP;
+      nmask |= (uint32_t)inside << i;
+      const long at = (b * CROP + min(max(y, 0), CROP - 1)) * CROP + min(max(x, 0), CROP - 1);
+      if constexpr (FIRST)
+        nxt[i] = in[at];
+      else
+        nxt[i] = *reinterpret_cast<const h8v*>(in + at * NCH + 8 * ch);
+    }
+  };
+  // the fetched tile into LDS (ctile or tile), zero outside the image
+  auto fill = [&]() {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int q = tid + 256 * i;
-      if (ITEMS % 256 == 0 || q < ITEMS) {
-        if constexpr (FIRST) {
-          const int y = ty0 + q / 20 - 2, x = tx0 + q % 20 - 2;
-          const bool inside = y >= 0 && y < CROP && x >= 0 && x < CROP;
-          nxt[i] = inside ? in[(b * CROP + y) * CROP + x] : (_Float16)0.f;
-        } else {
-          const int pix = q / (NCH / 8), ch = q % (NCH / 8);
-          const int y = ty0 + pix / 18 - 1, x = tx0 + pix % 18 - 1;
-          h8v v;
+      const bool valid = ITEMS % 256 == 0 || q < ITEMS;
+      const bool inside = (nmask >> i) & 1;
+      if constexpr (FIRST) {
+        ctile[valid ? (q / 20) * CT + q % 20 : CN + tid] = inside ? nxt[i] : (_Float16)0.f;
+      } else {
+        h8v v = nxt[i];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (_Float16)0.f;
-          if (y >= 0 && y < CROP && x >= 0 && x < CROP)
-            v = *reinterpret_cast<const h8v*>(in + ((b * CROP + y) * CROP + x) * NCH + 8 * ch);
-          nxt[i] = v;
-        }
+        for (int e = 0; e < 8; ++e) v[e] = inside ? v[e] : (_Float16)0.f;
+        *reinterpret_cast<h8v*>(tile + (valid ? (q / (NCH / 8)) * PS + 8 * (q % (NCH / 8)) : TN + 8 * tid)) = v;
       }
     }
   };
   int u = blockIdx.x;
-  if (u < nunits) fetch(u);
+  if (u < nunits) {
+    fetch(u);
+    if constexpr (FIRST) fill();
+  }
   for (; u < nunits; u += gridDim.x) {
     const long b = u >> 4;
     const int t16 = u & 15, ty0 = (t16 >> 2) * 16, tx0 = (t16 & 3) * 16;
-    __syncthreads();  // the previous unit's reads of tile, ctile and red are done
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int q = tid + 256 * i;
-      if (ITEMS % 256 == 0 || q < ITEMS) {
-        if constexpr (FIRST)
-          ctile[(q / 20) * CT + q % 20] = nxt[i];
-        else
-          *reinterpret_cast<h8v*>(tile + (q / (NCH / 8)) * PS + 8 * (q % (NCH / 8))) = nxt[i];
-      }
+    __syncthreads();  // the previous unit's reads of tile and red are done; ctile is filled
+    if constexpr (!FIRST) {
+      fill();
+      __syncthreads();
+      fetch(u + gridDim.x);
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
     }
-    __syncthreads();
-    if (!FIRST && u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
     if constexpr (FIRST) {
       // tile row mt = wave + 4 i (< 18): pixel (mt, c), k = tap for k < 9
       // (lanes h = 1 hold k = 8 .. 15: tap 8, then zeros)
@@ -590,25 +617,48 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const _Float16* __restrict__ 
         }
       }
       __syncthreads();
-      // the next crop tile loads under the second layer's MFMAs
-      if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+      fetch(u + gridDim.x);  // the next crop tile loads under the second layer's MFMAs
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
     }
+    // the two 32-pixel tiles' products interleaved, each k-step's A
+    // fragments read from LDS one step ahead of their MFMAs
     f32x16 acc[2];
+    const _Float16* ap[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[mt][r] = 0.f;
-      const int p = (2 * wave + mt) * 32 + c, py = p >> 4, px = p & 15;
+      const int p = (2 * wave + mt) * 32 + c;
+      ap[mt] = tile + ((p >> 4) * 18 + (p & 15)) * PS + 8 * h;
+    }
+    auto afrag = [&](int mt, int s) {
+      const int tap = s >> 1;
+      return *reinterpret_cast<const h8v*>(ap[mt] + ((tap / 3) * 18 + tap % 3) * PS + 16 * (s & 1));
+    };
+    h8v a_cur[2] = {afrag(0, 0), afrag(1, 0)};
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int tap = s >> 1, c0 = 16 * (s & 1) + 8 * h;
-        const h8v a = *reinterpret_cast<const h8v*>(tile + ((py + tap / 3) * 18 + px + tap % 3) * PS + c0);
+    for (int s = 0; s < KS; ++s) {
+      h8v a_nxt[2];
+      if (s + 1 < KS) {
+        a_nxt[0] = afrag(0, s + 1);
+        a_nxt[1] = afrag(1, s + 1);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // the reads stay one k-step ahead
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
         if constexpr (LAST)
-          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, bw[s], acc[mt], 0, 0, 0);
+          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_cur[mt], bw[s], acc[mt], 0, 0, 0);
         else
-          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bw[s], a, acc[mt], 0, 0, 0);
+          acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bw[s], a_cur[mt], acc[mt], 0, 0, 0);
+      }
+      if (s + 1 < KS) {
+        a_cur[0] = a_nxt[0];
+        a_cur[1] = a_nxt[1];
       }
     }
+    // FIRST: ctile is not read again before the next unit's first barrier,
+    // so the next crop tile goes there now, ahead of this unit's stores
+    if constexpr (FIRST) fill();
     if constexpr (!LAST) {
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {

@@ -228,28 +228,26 @@ def test_training_gain_over_scan(ctx, hv, init):
     assert losses[-1] < losses[0] - 0.5
     eh, _, ez = _dataset(ctx, 1024, seed=999, base=10 ** 6)
     ez = ez.cpu().numpy()
-    ctx.hv_af_scan(eh[:8], LAM, PITCH)  # tables built outside the timing
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    zs, _ = ctx.hv_af_scan(eh, LAM, PITCH)
-    torch.cuda.synchronize()
-    t_scan = time.perf_counter() - t0
+    def timed(fn):
+        # one untimed call (tables, workspaces), then the median of three
+        r = fn()
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return r, float(np.median(ts))
+
+    (zs, _), t_scan = timed(lambda: ctx.hv_af_scan(eh, LAM, PITCH))
     e_scan = np.abs(zs.cpu().numpy() - ez)
     zp, sig, used, nfb = m.predict(eh, LAM, PITCH, tau=1e9)  # network only
     e_net = np.abs(zp.cpu().numpy() - ez)
     tau = float(np.quantile(sig.cpu().numpy(), 0.9))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    zf, _, used, nfb = m.predict(eh, LAM, PITCH, tau=tau)
-    torch.cuda.synchronize()
-    t_fb = time.perf_counter() - t0
+    (zf, _, used, nfb), t_fb = timed(lambda: m.predict(eh, LAM, PITCH, tau=tau))
     e_fb = np.abs(zf.cpu().numpy() - ez)
-    m.predict(eh[:8], LAM, PITCH, tau=tau, refine=16)  # tables outside the timing
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    zl, _, _, nfl = m.predict(eh, LAM, PITCH, tau=tau, refine=16)
-    torch.cuda.synchronize()
-    t_loc = time.perf_counter() - t0
+    (zl, _, _, nfl), t_loc = timed(lambda: m.predict(eh, LAM, PITCH, tau=1e9, refine=16))
     e_loc = np.abs(zl.cpu().numpy() - ez)
     base = np.median(np.abs(ez - Z_MEAN))
     say(f"  median |dz| mm: mean-predictor {1e3 * base:.1f}, net {1e3 * np.median(e_net):.1f}, "
@@ -261,7 +259,10 @@ def test_training_gain_over_scan(ctx, hv, init):
     assert nfb <= 0.15 * len(ez)
     assert t_fb < t_scan
     # the network's estimate and its sigma seed a 16-candidate local scan:
-    # the scan's accuracy, in less time than the 128-candidate scan
+    # within 1.5x the scan's median error at a fraction of its time (the
+    # network is briefly trained and 1,024 holograms make short calls, so
+    # the bound on the speed-up is loose; the benchmark measures it on
+    # 10,000 holograms and a fully trained network)
     assert np.median(e_loc) <= 1.5 * np.median(e_scan)
-    assert t_loc < t_scan
+    assert t_scan / t_loc >= 2.5
     m.close()
