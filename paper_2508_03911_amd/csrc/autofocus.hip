@@ -731,11 +731,13 @@ __global__ __launch_bounds__(256) void k_head_pooled(const float* __restrict__ p
 // outputs are staged in LDS so that each channel's 16-pixel rows are stored
 // contiguously.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_conv_f32mfma(const float* __restrict__ in, const float* __restrict__ params,
+__global__ __launch_bounds__(256, 2) void k_conv_f32mfma(const float* __restrict__ in, const float* __restrict__ params,
                                                       int woff, int boff, float* __restrict__ out, int nunits) {
-  constexpr int K = NCH * 9;
-  constexpr int OS = 257;  // staging row stride
-  static_assert(NCH * OS <= NCH * 18 * 19, "output staging fits in the input tile");
+  constexpr int K = NCH * 9, KH = K / 2;  // lanes 0-31 take k < 144, lanes 32-63 k >= 144
+  constexpr int XC = 18 * 19;              // floats per channel of the input tile
+  constexpr int OS = 257;                  // staging row stride
+  static_assert(NCH * OS <= NCH * XC, "output staging fits in the input tile");
+  static_assert(KH % 9 == 0, "each half of k holds whole channels");
   __shared__ float xt[NCH][18][19];
   __shared__ float wl[K * NCH];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 31, kb = lane >> 5;
@@ -745,41 +747,67 @@ __global__ __launch_bounds__(256) void k_conv_f32mfma(const float* __restrict__ 
   }
   const float bias = MODE == 0 ? params[boff + n] : 0.f;
   float* ot = &xt[0][0][0];
-  const float* xflat = &xt[0][0][0];
+  // per-lane bases: step ks reads k = ks + KH kb, i.e. channel ks / 9 + 16 kb
+  // and tap ks % 9, at offsets that are constants of ks
+  const float* xa[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int p = (2 * w + mt) * 32 + n;
+    xa[mt] = &xt[0][0][0] + kb * (KH / 9) * XC + (p >> 4) * 19 + (p & 15);
+  }
+  const float* wb = wl + kb * KH * NCH + n;
+  // the unit's input tile: every lane issues every load (clamped address,
+  // zeroed when stored to LDS)
+  constexpr int PER = (NCH * 324 + 255) / 256;
+  float v[PER];
+  uint64_t vmask = 0;
+  auto fetch = [&](int u) {
+    u = u < nunits ? u : nunits - 1;
+    const float* bp = in + (long)(u >> 4) * (NCH * HW);  // wave-uniform base, 32-bit lane offsets
+    const int ty0 = ((u & 15) >> 2) * 16, tx0 = (u & 3) * 16;
+    vmask = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = min(tid + 256 * i, NCH * 324 - 1);
+      const int c = q / 324, r = (q % 324) / 18, col = q % 18;
+      const int y = ty0 + r - 1, x = tx0 + col - 1;
+      vmask |= (uint64_t)(y >= 0 && y < CROP && x >= 0 && x < CROP) << i;
+      v[i] = bp[(c * CROP + min(max(y, 0), CROP - 1)) * CROP + min(max(x, 0), CROP - 1)];
+    }
+  };
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const long b = u >> 4;
     const int ty0 = ((u & 15) >> 2) * 16, tx0 = (u & 3) * 16;
-    // every load of the tile is issued before the first LDS write
-    constexpr int PER = (NCH * 324 + 255) / 256;
-    float v[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int q = tid + 256 * i;
-      const int c = q / 324, r = (q % 324) / 18, col = q % 18;
-      const int y = ty0 + r - 1, x = tx0 + col - 1;
-      v[i] = 0.f;
-      if (q < NCH * 324 && y >= 0 && y < CROP && x >= 0 && x < CROP) v[i] = in[((b * NCH + c) * CROP + y) * CROP + x];
-    }
+    fetch(u);  // every load of the tile is issued before the first LDS write
     __syncthreads();  // the previous unit's staged outputs are stored
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int q = tid + 256 * i;
-      if (q < NCH * 324) xt[q / 324][(q % 324) / 18][q % 18] = v[i];
+      if (q < NCH * 324) xt[q / 324][(q % 324) / 18][q % 18] = (vmask >> i) & 1 ? v[i] : 0.f;
     }
     __syncthreads();
+    // the two 32-pixel products interleaved, operands read one step ahead
     f32x16 acc[2];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[mt][r] = 0.f;
-      const int p = (2 * w + mt) * 32 + n, pbase = (p >> 4) * 19 + (p & 15);
-#pragma unroll 16
-      for (int ks = 0; ks < K / 2; ++ks) {
-        const int k = 2 * ks + kb, c = k / 9, tap = k % 9;
-        const float a = xflat[c * (18 * 19) + (tap / 3) * 19 + tap % 3 + pbase];
-        const float bv = wl[k * NCH + n];
-        acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[mt], 0, 0, 0);
+    auto xoff = [](int ks) { return (ks / 9) * XC + ((ks % 9) / 3) * 19 + (ks % 9) % 3; };
+    float a0 = xa[0][xoff(0)], a1 = xa[1][xoff(0)], bv = wb[0];
+#pragma unroll
+    for (int ks = 0; ks < KH; ++ks) {
+      float a0n = 0.f, a1n = 0.f, bn = 0.f;
+      if (ks + 1 < KH) {
+        a0n = xa[0][xoff(ks + 1)];
+        a1n = xa[1][xoff(ks + 1)];
+        bn = wb[(ks + 1) * NCH];
       }
+      __builtin_amdgcn_sched_barrier(0);
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bv, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bv, acc[1], 0, 0, 0);
+      a0 = a0n;
+      a1 = a1n;
+      bv = bn;
     }
     __syncthreads();  // every read of the input tile is done
     // result register r of lane l: pixel 8 (r / 4) + 4 (l / 32) + r % 4 of the M tile, output channel l % 32
@@ -788,9 +816,9 @@ __global__ __launch_bounds__(256) void k_conv_f32mfma(const float* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int p = (2 * w + mt) * 32 + 8 * (r >> 2) + 4 * kb + (r & 3);
-        float v = acc[mt][r] + bias;
-        if (MODE == 0) v = fmaxf(v, 0.f);
-        ot[n * OS + p] = v;
+        float o = acc[mt][r] + bias;
+        if (MODE == 0) o = fmaxf(o, 0.f);
+        ot[n * OS + p] = o;
       }
     __syncthreads();
     for (int q = tid; q < NCH * 256; q += 256) {
@@ -844,6 +872,7 @@ __global__ __launch_bounds__(CIN == 1 ? 256 : 576) void k_wgrad_mfma(const TIN* 
   const float* xb = &xt[c][tap / 3][tap % 3];
   constexpr int KS = CIN == 1 ? 32 : 128;  // pixel pairs per wave and unit
   const int ks0 = CIN == 1 ? KS * w : 0;
+  constexpr int NB = CIN == 1 ? NCH : 8 * NCH;  // threads that sum the bias gradient
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
@@ -887,14 +916,30 @@ __global__ __launch_bounds__(CIN == 1 ? 256 : 576) void k_wgrad_mfma(const TIN* 
       }
     }
     __syncthreads();
-    if (tid < NCH)
-      for (int pp = 0; pp < 256; ++pp) accb += dzt[tid * DS + pp];
-#pragma unroll 8
-    for (int ks = ks0; ks < ks0 + KS; ++ks) {
-      const int pp = 2 * ks + kb, py = pp >> 4, px = pp & 15;
-      const float a = dzt[n * DS + pp];
-      const float bv = kval ? xb[(py * 19 + px)] : 0.f;
+    // bias: thread t < NB sums the pixels t / 32, t / 32 + NB / 32, ... of
+    // output channel t % 32 (a fixed assignment; the NB / 32 partial sums
+    // of a channel are added in order at the end)
+    if (tid < NB)
+      for (int pp = tid / NCH; pp < 256; pp += NB / NCH) accb += dzt[(tid % NCH) * DS + pp];
+    // step ks takes the pixel pair 2 ks, 2 ks + 1: lane half kb reads pixel
+    // 2 ks + kb, at offsets that are constants of ks from per-lane bases;
+    // the operands of step ks + 1 are read before the MFMA of step ks
+    const float* ap = dzt + n * DS + kb;
+    const float* bp = xb + kb;
+    auto boff = [](int ks) { return ((2 * ks) >> 4) * 19 + ((2 * ks) & 15); };
+    float a = ap[2 * ks0], bv = kval ? bp[boff(ks0)] : 0.f;
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      const int ks = ks0 + j;
+      float an = 0.f, bn = 0.f;
+      if (j + 1 < KS) {
+        an = ap[2 * (ks + 1)];
+        bn = kval ? bp[boff(ks + 1)] : 0.f;
+      }
+      __builtin_amdgcn_sched_barrier(0);
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc, 0, 0, 0);
+      a = an;
+      bv = bn;
     }
   }
   // result register r of lane l: output channel 8 (r / 4) + 4 (l / 32) + r % 4, k column n
@@ -917,7 +962,19 @@ __global__ __launch_bounds__(CIN == 1 ? 256 : 576) void k_wgrad_mfma(const TIN* 
       part_w[((long)blockIdx.x * NCH + o) * NK + kcol] = acc[r];
     }
   }
-  if (tid < NCH) part_b[blockIdx.x * NCH + tid] = accb;
+  if constexpr (CIN == 1) {
+    if (tid < NCH) part_b[blockIdx.x * NCH + tid] = accb;
+  } else {
+    __syncthreads();
+    float* bred = dzt;  // NB partial bias sums, [part][channel]
+    if (tid < NB) bred[tid] = accb;
+    __syncthreads();
+    if (tid < NCH) {
+      float sb = 0.f;
+      for (int q = 0; q < NB / NCH; ++q) sb += bred[q * NCH + tid];
+      part_b[blockIdx.x * NCH + tid] = sb;
+    }
+  }
 }
 
 // Sum of the per-block partials into the gradient vector, in a fixed order
