@@ -726,13 +726,16 @@ __global__ __launch_bounds__(256) void k_head_pooled(const float* __restrict__ p
 //   MODE 0 (forward):    out = ReLU(b + W * in)
 //   MODE 1 (input grad): out = W^T(flipped) * in, with in = dZ (the output
 //                        gradient already masked by the ReLU)
+// MODE 1 with relu_of (the activation A of the layer below): the stored
+// gradient is already taken through that layer's ReLU, out [A > 0].
 // Persistent: the layer's weights sit in LDS as B[k][o] for all of the
 // block's units; wave w owns the 32-pixel M tiles 2w and 2w + 1; the
 // outputs are staged in LDS so that each channel's 16-pixel rows are stored
 // contiguously.
 template <int MODE>
 __global__ __launch_bounds__(256, 2) void k_conv_f32mfma(const float* __restrict__ in, const float* __restrict__ params,
-                                                      int woff, int boff, float* __restrict__ out, int nunits) {
+                                                         int woff, int boff, float* __restrict__ out, int nunits,
+                                                         const float* __restrict__ relu_of) {
   constexpr int K = NCH * 9, KH = K / 2;  // lanes 0-31 take k < 144, lanes 32-63 k >= 144
   constexpr int XC = 18 * 19;              // floats per channel of the input tile
   constexpr int OS = 257;                  // staging row stride
@@ -821,9 +824,24 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32mfma(const float* __restrict
         ot[n * OS + p] = o;
       }
     __syncthreads();
-    for (int q = tid; q < NCH * 256; q += 256) {
-      const int o = q >> 8, pp = q & 255;
-      out[((b * NCH + o) * CROP + ty0 + (pp >> 4)) * CROP + tx0 + (pp & 15)] = ot[o * OS + pp];
+    // thread tid stores pixel tid of every channel, eight channels at a time
+    // (with relu_of, the eight activations are loaded together first)
+    float* op = out + (b * NCH * CROP + ty0 + (tid >> 4)) * CROP + tx0 + (tid & 15);
+#pragma unroll
+    for (int o0 = 0; o0 < NCH; o0 += 8) {
+      float keep[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) keep[e] = 1.f;
+      if (MODE == 1 && relu_of) {
+        const float* ap = relu_of + (op - out);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) keep[e] = ap[(o0 + e) * HW];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float o_v = ot[(o0 + e) * OS + tid];
+        op[(o0 + e) * HW] = keep[e] > 0.f ? o_v : 0.f;
+      }
     }
   }
 }
@@ -842,37 +860,33 @@ __global__ void k_relu_mask(float4* __restrict__ d, const float4* __restrict__ a
   }
 }
 
-// Weight and bias gradients of one conv layer as a GEMM on the matrix cores
-// (FP32 operands, v_mfma_f32_32x32x2f32): dW[o][k] = sum_n dZ[n][o] X[n][k] over
-// n = (sample, pixel), k = 9 c + tap, X[n][k] the input at pixel n moved by
-// the tap (zero outside the image), dZ = dA [A > 0] (masked beforehand).  Block g accumulates the
-// units (sample, 16 x 16 tile) g, g + G, ... in registers and writes its
-// partial sums; k_wgrad_reduce adds the G partials in block order, so the
-// result does not depend on scheduling.  CIN = 32: wave w (of nine) owns the
-// 32 k columns [32 w, 32 w + 32); CIN = 1: the nine taps (padded to 32
-// columns) with the 128 pixel pairs of a tile split over four waves, whose
-// partials are added in wave order.  Threads 0..31 sum the bias gradient of
-// their output channel over the block's pixels in order.
-template <int CIN, typename TIN>
-__global__ __launch_bounds__(CIN == 1 ? 256 : 576) void k_wgrad_mfma(const TIN* __restrict__ x,
-                                                                   const float* __restrict__ dz, int nunits,
-                                                                   float* __restrict__ part_w,
-                                                                   float* __restrict__ part_b) {
-  constexpr int NW = CIN == 1 ? 4 : 9;
-  constexpr int NT = NW * 64;
-  constexpr int NK = CIN * 9;
-  constexpr int DS = 257;  // dz row stride: the 32 rows of an A read fall on distinct banks
-  __shared__ float xt[CIN][18][19];
+// Weight and bias gradients of a conv layer as a GEMM on the matrix cores:
+// dW[o][k] = sum_n dZ[n][o] X[n][k] over n = (sample, pixel), k = 9 c + tap,
+// X[n][k] the input at pixel n moved by the tap (zero outside the image),
+// dZ = dA [A > 0] (masked beforehand).  Workgroup g accumulates the units
+// (sample, 16 x 16 tile) g, g + G, ... in registers and writes its partial
+// sums; k_wgrad_reduce adds the G partials in workgroup order, so the
+// result does not depend on scheduling.
+//
+// k_wgrad1, the first layer (nine taps of the fp16 crop), on
+// v_mfma_f32_32x32x2f32: the nine k columns padded to 32, the 128 pixel
+// pairs of a tile split over four waves whose partials are added in wave
+// order; threads 0..31 sum the bias gradient of their output channel over
+// the workgroup's pixels in order.  Each step's operands are read from LDS
+// one step ahead of its MFMA.
+__global__ __launch_bounds__(256) void k_wgrad1(const _Float16* __restrict__ x, const float* __restrict__ dz,
+                                                int nunits, float* __restrict__ part_w,
+                                                float* __restrict__ part_b) {
+  constexpr int NK = 9, KS = 32;  // k columns; pixel pairs per wave and unit
+  constexpr int DS = 257;          // dz row stride: the 32 rows of an A read fall on distinct banks
+  __shared__ float xt[18][19];
   __shared__ float dzt[NCH * DS];  // dZ of the unit, [o][pixel]
-  __shared__ float red[CIN == 1 ? 3 * 16 * 64 : 1];
+  __shared__ float red[3 * 16 * 64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 31, kb = lane >> 5;
-  const int kcol = CIN == 1 ? n : 32 * w + n;
-  const bool kval = kcol < NK;
-  const int c = kval ? kcol / 9 : 0, tap = kval ? kcol % 9 : 0;
-  const float* xb = &xt[c][tap / 3][tap % 3];
-  constexpr int KS = CIN == 1 ? 32 : 128;  // pixel pairs per wave and unit
-  const int ks0 = CIN == 1 ? KS * w : 0;
-  constexpr int NB = CIN == 1 ? NCH : 8 * NCH;  // threads that sum the bias gradient
+  const bool kval = n < NK;
+  const int tap = kval ? n : 0;
+  const float* xb = &xt[tap / 3][tap % 3];
+  const int ks0 = KS * w;
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
@@ -881,49 +895,34 @@ __global__ __launch_bounds__(CIN == 1 ? 256 : 576) void k_wgrad_mfma(const TIN* 
     const long b = u >> 4;
     const int ty0 = ((u & 15) >> 2) * 16, tx0 = (u & 3) * 16;
     // the loads of each array are all issued before its first LDS write
-    constexpr int PX = (CIN * 324 + NT - 1) / NT, PZ = (NCH * 256 + NT - 1) / NT;
+    constexpr int PX = (324 + 255) / 256, PZ = NCH;
     {
       float vx[PX];
 #pragma unroll
       for (int i = 0; i < PX; ++i) {
-        const int q = tid + NT * i;
-        const int cc = q / 324, r = (q % 324) / 18, col = q % 18;
-        const int y = ty0 + r - 1, xx = tx0 + col - 1;
-        vx[i] = (q < CIN * 324 && y >= 0 && y < CROP && xx >= 0 && xx < CROP)
-                    ? to_f(x[((b * CIN + cc) * CROP + y) * CROP + xx])
-                    : 0.f;
+        const int q = tid + 256 * i, y = ty0 + q / 18 - 1, xx = tx0 + q % 18 - 1;
+        vx[i] = (q < 324 && y >= 0 && y < CROP && xx >= 0 && xx < CROP) ? (float)x[(b * CROP + y) * CROP + xx] : 0.f;
       }
       __syncthreads();  // the previous unit's reads are done
 #pragma unroll
       for (int i = 0; i < PX; ++i) {
-        const int q = tid + NT * i;
-        if (q < CIN * 324) xt[q / 324][(q % 324) / 18][q % 18] = vx[i];
+        const int q = tid + 256 * i;
+        if (q < 324) xt[q / 18][q % 18] = vx[i];
       }
     }
     {
+      const float* pz = dz + ((b * NCH) * CROP + ty0 + (tid >> 4)) * CROP + tx0 + (tid & 15);
       float vz[PZ];
 #pragma unroll
-      for (int i = 0; i < PZ; ++i) {
-        const int q = tid + NT * i;
-        const int o = q >> 8, pp = q & 255;
-        vz[i] = 0.f;
-        if (q < NCH * 256) vz[i] = dz[((b * NCH + o) * CROP + ty0 + (pp >> 4)) * CROP + tx0 + (pp & 15)];
-      }
+      for (int o = 0; o < PZ; ++o) vz[o] = pz[o * HW];
 #pragma unroll
-      for (int i = 0; i < PZ; ++i) {
-        const int q = tid + NT * i;
-        if (q < NCH * 256) dzt[(q >> 8) * DS + (q & 255)] = vz[i];
-      }
+      for (int o = 0; o < PZ; ++o) dzt[o * DS + tid] = vz[o];
     }
     __syncthreads();
-    // bias: thread t < NB sums the pixels t / 32, t / 32 + NB / 32, ... of
-    // output channel t % 32 (a fixed assignment; the NB / 32 partial sums
-    // of a channel are added in order at the end)
-    if (tid < NB)
-      for (int pp = tid / NCH; pp < 256; pp += NB / NCH) accb += dzt[(tid % NCH) * DS + pp];
+    if (tid < NCH)
+      for (int pp = 0; pp < 256; ++pp) accb += dzt[tid * DS + pp];
     // step ks takes the pixel pair 2 ks, 2 ks + 1: lane half kb reads pixel
-    // 2 ks + kb, at offsets that are constants of ks from per-lane bases;
-    // the operands of step ks + 1 are read before the MFMA of step ks
+    // 2 ks + kb, at offsets that are constants of ks from per-lane bases
     const float* ap = dzt + n * DS + kb;
     const float* bp = xb + kb;
     auto boff = [](int ks) { return ((2 * ks) >> 4) * 19 + ((2 * ks) & 15); };
@@ -943,37 +942,135 @@ __global__ __launch_bounds__(CIN == 1 ? 256 : 576) void k_wgrad_mfma(const TIN* 
     }
   }
   // result register r of lane l: output channel 8 (r / 4) + 4 (l / 32) + r % 4, k column n
-  if constexpr (CIN == 1) {
-    if (w > 0)
+  if (w > 0)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) red[((w - 1) * 16 + r) * 64 + lane] = acc[r];
-    __syncthreads();
-    if (w == 0 && kval)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float v = ((acc[r] + red[r * 64 + lane]) + red[(16 + r) * 64 + lane]) + red[(32 + r) * 64 + lane];
-        const int o = 8 * (r >> 2) + 4 * kb + (r & 3);
-        part_w[((long)blockIdx.x * NCH + o) * NK + kcol] = v;
-      }
-  } else {
+    for (int r = 0; r < 16; ++r) red[((w - 1) * 16 + r) * 64 + lane] = acc[r];
+  __syncthreads();
+  if (w == 0 && kval)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
+      const float v = ((acc[r] + red[r * 64 + lane]) + red[(16 + r) * 64 + lane]) + red[(32 + r) * 64 + lane];
       const int o = 8 * (r >> 2) + 4 * kb + (r & 3);
-      part_w[((long)blockIdx.x * NCH + o) * NK + kcol] = acc[r];
+      part_w[((long)blockIdx.x * NCH + o) * NK + n] = v;
+    }
+  if (tid < NCH) part_b[blockIdx.x * NCH + tid] = accb;
+}
+
+// k_wgrad32, a 32-channel layer, in 16 x 16 tiles
+// (v_mfma_f32_16x16x4f32): [32 outputs] x
+// [288 k columns] is 2 x 18 tiles, nine per wave, so the four waves of a
+// workgroup (one per SIMD) carry equal work and two workgroups share a CU.
+// Step s takes pixels 4 s .. 4 s + 3 of the unit; every operand read is a
+// constant offset from a per-lane base, and the operands of step s + 1 are
+// read before the MFMAs of step s.  The bias gradient as eight fixed
+// partial sums per channel (pixels t / 32, t / 32 + 8, ... of channel
+// t % 32 for thread t), added in order.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256, 2) void k_wgrad32(const float* __restrict__ x, const float* __restrict__ dz,
+                                                    int nunits, float* __restrict__ part_w,
+                                                    float* __restrict__ part_b) {
+  constexpr int NK = NCH * 9, DS = 257, XC = 18 * 19, NTW = 9, NS = 64;
+  __shared__ float xt[NCH * XC];
+  __shared__ float dzt[NCH * DS];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, i16 = lane & 15, kk = lane >> 4;
+  const int mt = w & 1, nt0 = NTW * (w >> 1);
+  // A (16 x 4): lane l holds dZ[pixel 4 s + l / 16][output 16 mt + l % 16];
+  // B (4 x 16): lane l holds X[pixel 4 s + l / 16][k column 16 nt + l % 16]
+  const float* ap = dzt + (16 * mt + i16) * DS + kk;
+  int xb[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) {
+    const int kcol = 16 * (nt0 + j) + i16, c = kcol / 9, tap = kcol % 9;
+    xb[j] = c * XC + (tap / 3) * 19 + tap % 3 + kk;
+  }
+  f32x4 acc[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[j][r] = 0.f;
+  float accb = 0.f;
+  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const int ty0 = ((u & 15) >> 2) * 16, tx0 = (u & 3) * 16;
+    const float* xp = x + (long)(u >> 4) * (NCH * HW);
+    const float* zp = dz + (long)(u >> 4) * (NCH * HW);
+    // The input tile (pixel tid of every channel; then the 68 x 32 items of
+    // pixels 256 .. 323) and dZ (pixel tid of every channel), each batch of
+    // loads issued (clamped address, zeroed when stored) before its LDS
+    // writes; offsets are a per-lane value plus a constant per channel.
+    __syncthreads();  // the previous unit's reads are done
+    {
+      const int r0 = tid / 18, c0 = tid % 18, y = ty0 + r0 - 1, xx = tx0 + c0 - 1;
+      const bool in0 = y >= 0 && y < CROP && xx >= 0 && xx < CROP;
+      const float* p0 = xp + min(max(y, 0), CROP - 1) * CROP + min(max(xx, 0), CROP - 1);
+      float v[NCH];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) v[c] = p0[c * HW];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) xt[c * XC + r0 * 19 + c0] = in0 ? v[c] : 0.f;
+    }
+    {
+      constexpr int N1 = NCH * 68, P1 = (N1 + 255) / 256;
+      float v[P1];
+      uint32_t m = 0;
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        const int j = min(tid + 256 * k, N1 - 1), c = j / 68, pp = 256 + j % 68;
+        const int y = ty0 + pp / 18 - 1, xx = tx0 + pp % 18 - 1;
+        m |= (uint32_t)(y >= 0 && y < CROP && xx >= 0 && xx < CROP) << k;
+        v[k] = xp[(c * CROP + min(max(y, 0), CROP - 1)) * CROP + min(max(xx, 0), CROP - 1)];
+      }
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        const int j = tid + 256 * k, c = j / 68, pp = 256 + j % 68;
+        if (j < N1) xt[c * XC + (pp / 18) * 19 + pp % 18] = (m >> k) & 1 ? v[k] : 0.f;
+      }
+    }
+    {
+      const float* pz = zp + (ty0 + (tid >> 4)) * CROP + tx0 + (tid & 15);
+      float v[NCH];
+#pragma unroll
+      for (int o = 0; o < NCH; ++o) v[o] = pz[o * HW];
+#pragma unroll
+      for (int o = 0; o < NCH; ++o) dzt[o * DS + tid] = v[o];
+    }
+    __syncthreads();
+    // bias: thread t sums pixels t / 32, t / 32 + 8, ... of channel t % 32
+    for (int pp = tid / NCH; pp < 256; pp += 256 / NCH) accb += dzt[(tid % NCH) * DS + pp];
+    auto boff = [](int st) { return ((4 * st) >> 4) * 19 + ((4 * st) & 15); };
+    float a = ap[0], bv[NTW];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) bv[j] = xt[xb[j] + boff(0)];
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      float an = 0.f, bn[NTW];
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) bn[j] = 0.f;
+      if (st + 1 < NS) {
+        an = ap[4 * (st + 1)];
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) bn[j] = xt[xb[j] + boff(st + 1)];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[j], acc[j], 0, 0, 0);
+      a = an;
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) bv[j] = bn[j];
     }
   }
-  if constexpr (CIN == 1) {
-    if (tid < NCH) part_b[blockIdx.x * NCH + tid] = accb;
-  } else {
-    __syncthreads();
-    float* bred = dzt;  // NB partial bias sums, [part][channel]
-    if (tid < NB) bred[tid] = accb;
-    __syncthreads();
-    if (tid < NCH) {
-      float sb = 0.f;
-      for (int q = 0; q < NB / NCH; ++q) sb += bred[q * NCH + tid];
-      part_b[blockIdx.x * NCH + tid] = sb;
-    }
+  // D of lane l: row 4 (l / 16) + r = output channel 16 mt + 4 kk + r, column l % 16 = k column 16 nt + i16
+#pragma unroll
+  for (int j = 0; j < NTW; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      part_w[((long)blockIdx.x * NCH + 16 * mt + 4 * kk + r) * NK + 16 * (nt0 + j) + i16] = acc[j][r];
+  __syncthreads();
+  dzt[tid] = accb;  // the 256 partial bias sums, [part][channel]
+  __syncthreads();
+  if (tid < NCH) {
+    float sb = 0.f;
+    for (int q = 0; q < 256 / NCH; ++q) sb += dzt[q * NCH + tid];
+    part_b[blockIdx.x * NCH + tid] = sb;
   }
 }
 
@@ -1269,7 +1366,7 @@ hv_status forward(hv_af_model* md, const _Float16* crops, int bsz, bool train, h
   const int gf = hvi::persistent_grid(k_conv_f32mfma<0>, 256, nu);
   for (int l = 1; l < 4; ++l)
     hipLaunchKernelGGL(k_conv_f32mfma<0>, dim3(gf), dim3(256), 0, st, md->act[l - 1], md->params, OFF_W[l], OFF_B[l],
-                       md->act[l], nu);
+                       md->act[l], nu, (const float*)nullptr);
   if (train)
     hipLaunchKernelGGL(k_head<true>, dim3(bsz), dim3(256), 0, st, md->act[3], md->params, md->zn, bsz, md->out,
                        md->loss_b, md->hpart, md->d1);
@@ -1309,20 +1406,21 @@ hv_status backward(hv_af_model* md, const _Float16* crops, int bsz, float* grad,
   float* dnext = md->d2;  // receives dA of its input
   const int nu = 16 * bsz, gw = std::min(nu, WG_BLOCKS);
   const long n4 = (long)bsz * NCH * HW / 4;
+  // dA of the last layer's output -> dZ through its ReLU; below it, the
+  // input-gradient kernel applies the ReLU of the layer it feeds
+  hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<long>(4096, (n4 + 255) / 256)), dim3(256), 0, st,
+                     (float4*)dcur, (const float4*)md->act[3], n4);
   for (int l = 3; l >= 0; --l) {
-    // dA of this layer's output -> dZ through its ReLU
-    hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<long>(4096, (n4 + 255) / 256)), dim3(256), 0, st,
-                       (float4*)dcur, (const float4*)md->act[l], n4);
     if (l > 0) {
-      hipLaunchKernelGGL((k_wgrad_mfma<NCH, float>), dim3(gw), dim3(576), 0, st, md->act[l - 1], dcur, nu, md->part_w,
-                         md->part_b);
+      hipLaunchKernelGGL(k_wgrad32, dim3(gw), dim3(256), 0, st, (const float*)md->act[l - 1], (const float*)dcur, nu,
+                         md->part_w, md->part_b);
       hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
                          md->part_b, gw, NCH, OFF_W[l], OFF_B[l], grad);
       hipLaunchKernelGGL(k_conv_f32mfma<1>, dim3(hvi::persistent_grid(k_conv_f32mfma<1>, 256, nu)), dim3(256), 0,
-                         st, dcur, md->params, OFF_W[l], 0, dnext, nu);
+                         st, dcur, md->params, OFF_W[l], 0, dnext, nu, (const float*)md->act[l - 1]);
       std::swap(dcur, dnext);
     } else {
-      hipLaunchKernelGGL((k_wgrad_mfma<1, _Float16>), dim3(gw), dim3(256), 0, st, crops, dcur, nu, md->part_w,
+      hipLaunchKernelGGL(k_wgrad1, dim3(gw), dim3(256), 0, st, crops, (const float*)dcur, nu, md->part_w,
                          md->part_b);
       hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
                          md->part_b, gw, 1, OFF_W[0], OFF_B[0], grad);
