@@ -846,20 +846,6 @@ __global__ __launch_bounds__(256, 2) void k_conv_f32mfma(const float* __restrict
   }
 }
 
-// dZ = dA [A > 0] in place: the gradient through the ReLU of a layer whose
-// output activation is A.
-__global__ void k_relu_mask(float4* __restrict__ d, const float4* __restrict__ a, long n4) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n4; i += (long)gridDim.x * blockDim.x) {
-    float4 v = d[i];
-    const float4 m = a[i];
-    v.x = m.x > 0.f ? v.x : 0.f;
-    v.y = m.y > 0.f ? v.y : 0.f;
-    v.z = m.z > 0.f ? v.z : 0.f;
-    v.w = m.w > 0.f ? v.w : 0.f;
-    d[i] = v;
-  }
-}
-
 // Weight and bias gradients of a conv layer as a GEMM on the matrix cores:
 // dW[o][k] = sum_n dZ[n][o] X[n][k] over n = (sample, pixel), k = 9 c + tap,
 // X[n][k] the input at pixel n moved by the tap (zero outside the image),
@@ -1074,39 +1060,53 @@ __global__ __launch_bounds__(256, 2) void k_wgrad32(const float* __restrict__ x,
   }
 }
 
-// Sum of the per-block partials into the gradient vector, in a fixed order
-// (eight interleaved running sums over the blocks, then those eight in
-// order), so the result does not depend on scheduling.
-__global__ void k_wgrad_reduce(const float* __restrict__ part_w, const float* __restrict__ part_b, int splits,
-                               int cin, int woff, int boff, float* __restrict__ grad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of the per-workgroup partials into the gradient vector, in a fixed
+// order (eight interleaved running sums over the workgroups, s_j over
+// workgroups j, j + 8, ..., then ((s0 + s1) + (s2 + s3)) + ((s4 + s5) +
+// (s6 + s7))), so the result does not depend on scheduling.  A workgroup
+// of 256 threads takes 32 outputs; thread t runs sum t / 32 of output t % 32.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part_w,
+                                                      const float* __restrict__ part_b, int splits, int cin,
+                                                      int woff, int boff, float* __restrict__ grad) {
+  __shared__ float red[8][32];
+  const int t = threadIdx.x, j = t >> 5, i = blockIdx.x * 32 + (t & 31);
   const int nw = NCH * cin * 9;
-  if (i >= nw + NCH) return;
+  const bool live = i < nw + NCH;
   const float* src = i < nw ? part_w + i : part_b + (i - nw);
   const long stride = i < nw ? nw : NCH;
-  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int k = 0;
-  for (; k + 8 <= splits; k += 8)
+  float sj = 0.f;
+  if (live)
+    for (int k0 = j; k0 < splits; k0 += 64) {
+      float v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s[j] += src[(long)(k + j) * stride];
-  for (int j = 0; k + j < splits; ++j) s[j] += src[(long)(k + j) * stride];
-  const float t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-  if (i < nw)
-    grad[woff + i] = t;
-  else
-    grad[boff + i - nw] = t;
+      for (int e = 0; e < 8; ++e) v[e] = k0 + 8 * e < splits ? src[(long)(k0 + 8 * e) * stride] : 0.f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (k0 + 8 * e < splits) sj += v[e];
+    }
+  red[j][t & 31] = sj;
+  __syncthreads();
+  if (j == 0 && live) {
+    const int c = t & 31;
+    const float r = ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) + ((red[4][c] + red[5][c]) + (red[6][c] + red[7][c]));
+    if (i < nw)
+      grad[woff + i] = r;
+    else
+      grad[boff + i - nw] = r;
+  }
 }
 
 // ------------------------------------------------------------------ CNN: head
 // Global average pooling, FC(32->64) ReLU, FC(64->2), and for training the
-// Gaussian NLL, the head gradients (per sample) and dA4 = dg / HW.
+// Gaussian NLL, the head gradients (per sample) and dg4[b][c] = dL/dg_c / HW,
+// the gradient of every pixel of channel c of the last activation.
 template <bool TRAIN>
 __global__ __launch_bounds__(256) void k_head(const float* __restrict__ a4, const float* __restrict__ params,
                                               const float* __restrict__ zn, int bsize, float* __restrict__ out,
                                               float* __restrict__ loss_b, float* __restrict__ hpart,
-                                              float* __restrict__ da4) {
+                                              float* __restrict__ dg4) {
   __shared__ float red[256][NCH + 1];
-  __shared__ float g[NCH], h1[64], dh1[64], outs[2], dout[2], dgs[NCH];
+  __shared__ float g[NCH], h1[64], dh1[64], outs[2], dout[2];
   const int tid = threadIdx.x;
   const long b = blockIdx.x;
   float acc[NCH];
@@ -1119,8 +1119,15 @@ __global__ __launch_bounds__(256) void k_head(const float* __restrict__ a4, cons
   for (int c = 0; c < NCH; ++c) red[tid][c] = acc[c];
   __syncthreads();
   if (tid < NCH) {
+    // in thread order, sixteen reads issued ahead of their additions
     float s = 0.f;
-    for (int t = 0; t < 256; ++t) s += red[t][tid];
+    for (int t0 = 0; t0 < 256; t0 += 16) {
+      float v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = red[t0 + j][tid];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) s += v[j];
+    }
     g[tid] = s / HW;
   }
   __syncthreads();
@@ -1160,18 +1167,35 @@ __global__ __launch_bounds__(256) void k_head(const float* __restrict__ a4, cons
   if (tid < NCH) {
     float d = 0.f;
     for (int o = 0; o < 64; ++o) d += dh1[o] * params[OFF_FC1W + o * NCH + tid];
-    dgs[tid] = d / HW;
+    dg4[b * NCH + tid] = d / HW;
   }
-  __syncthreads();
-  for (int q = tid; q < NCH * HW; q += 256) da4[b * NCH * HW + q] = dgs[q / HW];
+}
+
+// dZ of the last layer: dA = dg4[b][c] at every pixel of channel c, taken
+// through the layer's ReLU: dz = [A > 0] dg4.
+__global__ void k_dz_last(const float4* __restrict__ a, const float* __restrict__ dg4, float4* __restrict__ dz,
+                          long n4) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n4; i += (long)gridDim.x * blockDim.x) {
+    const float d = dg4[(i * 4) / HW];  // four consecutive pixels of one channel
+    const float4 m = a[i];
+    dz[i] = make_float4(m.x > 0.f ? d : 0.f, m.y > 0.f ? d : 0.f, m.z > 0.f ? d : 0.f, m.w > 0.f ? d : 0.f);
+  }
 }
 
 __global__ void k_head_reduce(const float* __restrict__ hpart, const float* __restrict__ loss_b, int bsize,
                               float* __restrict__ grad, float* __restrict__ loss) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < HEAD_N) {
+    // in sample order, sixteen loads issued ahead of their additions
     float s = 0.f;
-    for (int b = 0; b < bsize; ++b) s += hpart[(long)b * HEAD_N + i];
+    for (int b0 = 0; b0 < bsize; b0 += 16) {
+      float v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = b0 + j < bsize ? hpart[(long)(b0 + j) * HEAD_N + i] : 0.f;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (b0 + j < bsize) s += v[j];
+    }
     grad[OFF_FC1W + i] = s;  // fc1 w, fc1 b, fc2 w, fc2 b are contiguous
   } else if (i == HEAD_N && loss) {
     float s = 0.f;
@@ -1337,6 +1361,7 @@ struct hv_af_model {
   float* act[4] = {nullptr, nullptr, nullptr, nullptr};
   float *d1 = nullptr, *d2 = nullptr;
   float *part_w = nullptr, *part_b = nullptr, *hpart = nullptr, *loss_b = nullptr, *out = nullptr, *zn = nullptr;
+  float* dg4 = nullptr;  // [max_batch][32]: the last activation's gradient per channel
   float* loss_tmp = nullptr;
   int infer_batch = 0;                       // batch of the inference kernels (>= max_batch)
   _Float16* act16[2] = {nullptr, nullptr};  // inference activations, NHWC fp16 [infer_batch]
@@ -1369,7 +1394,7 @@ hv_status forward(hv_af_model* md, const _Float16* crops, int bsz, bool train, h
                        md->act[l], nu, (const float*)nullptr);
   if (train)
     hipLaunchKernelGGL(k_head<true>, dim3(bsz), dim3(256), 0, st, md->act[3], md->params, md->zn, bsz, md->out,
-                       md->loss_b, md->hpart, md->d1);
+                       md->loss_b, md->hpart, md->dg4);
   else
     hipLaunchKernelGGL(k_head<false>, dim3(bsz), dim3(256), 0, st, md->act[3], md->params, nullptr, bsz, md->out,
                        nullptr, nullptr, nullptr);
@@ -1406,15 +1431,15 @@ hv_status backward(hv_af_model* md, const _Float16* crops, int bsz, float* grad,
   float* dnext = md->d2;  // receives dA of its input
   const int nu = 16 * bsz, gw = std::min(nu, WG_BLOCKS);
   const long n4 = (long)bsz * NCH * HW / 4;
-  // dA of the last layer's output -> dZ through its ReLU; below it, the
-  // input-gradient kernel applies the ReLU of the layer it feeds
-  hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<long>(4096, (n4 + 255) / 256)), dim3(256), 0, st,
-                     (float4*)dcur, (const float4*)md->act[3], n4);
+  // dZ of the last layer from the head's per-channel gradient; below it,
+  // the input-gradient kernel applies the ReLU of the layer it feeds
+  hipLaunchKernelGGL(k_dz_last, dim3((unsigned)std::min<long>(4096, (n4 + 255) / 256)), dim3(256), 0, st,
+                     (const float4*)md->act[3], (const float*)md->dg4, (float4*)dcur, n4);
   for (int l = 3; l >= 0; --l) {
     if (l > 0) {
       hipLaunchKernelGGL(k_wgrad32, dim3(gw), dim3(256), 0, st, (const float*)md->act[l - 1], (const float*)dcur, nu,
                          md->part_w, md->part_b);
-      hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
+      hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * NCH * 9 + NCH + 31) / 32), dim3(256), 0, st, md->part_w,
                          md->part_b, gw, NCH, OFF_W[l], OFF_B[l], grad);
       hipLaunchKernelGGL(k_conv_f32mfma<1>, dim3(hvi::persistent_grid(k_conv_f32mfma<1>, 256, nu)), dim3(256), 0,
                          st, dcur, md->params, OFF_W[l], 0, dnext, nu, (const float*)md->act[l - 1]);
@@ -1422,7 +1447,7 @@ hv_status backward(hv_af_model* md, const _Float16* crops, int bsz, float* grad,
     } else {
       hipLaunchKernelGGL(k_wgrad1, dim3(gw), dim3(256), 0, st, crops, (const float*)dcur, nu, md->part_w,
                          md->part_b);
-      hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * 9 + NCH + 255) / 256), dim3(256), 0, st, md->part_w,
+      hipLaunchKernelGGL(k_wgrad_reduce, dim3((NCH * 9 + NCH + 31) / 32), dim3(256), 0, st, md->part_w,
                          md->part_b, gw, 1, OFF_W[0], OFF_B[0], grad);
     }
   }
@@ -1632,6 +1657,7 @@ hv_status hv_af_model_create(hv_ctx* ctx, const float* init_params, int max_batc
       (s = dev_alloc(md, (void**)&md->part_b, (size_t)splits * NCH * 4)) ||
       (s = dev_alloc(md, (void**)&md->hpart, (size_t)max_batch * HEAD_N * 4)) ||
       (s = dev_alloc(md, (void**)&md->loss_b, (size_t)max_batch * 4)) ||
+      (s = dev_alloc(md, (void**)&md->dg4, (size_t)max_batch * NCH * 4)) ||
       (s = dev_alloc(md, (void**)&md->out, (size_t)max_batch * 8)) ||
       (s = dev_alloc(md, (void**)&md->zn, (size_t)max_batch * 4)) || (s = dev_alloc(md, (void**)&md->loss_tmp, 4)) ||
       (s = dev_alloc(md, (void**)&md->act16[0], ib * NCH * HW * 2)) ||
