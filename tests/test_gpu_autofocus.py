@@ -184,6 +184,48 @@ def test_train_step_from_holograms(ctx, hv, init, holos):
     c.close()
 
 
+def test_spectrum_pass_many_units(ctx, hv, init, holos):
+    """The one-pass spectrum kernel over more holograms than it has
+    workgroups (each workgroup takes several, loading the next one's bytes
+    ahead): crops and scan scores sampled against the oracle across the
+    workgroup boundaries, equal copies of a hologram give equal outputs, the
+    crops of the crop-and-sub-band variant (the local scan's pass) are those
+    of the crop-only variant (the network's sigma is bit for bit the same
+    with and without the local scan), and misaligned holograms are
+    refused."""
+    say("spectrum pass over 1,500 holograms")
+    h, _ = holos
+    big = np.concatenate([h] * 250)
+    hd = torch.from_numpy(big).cuda()
+    c = ctx.hv_af_crops(hd, half=False).cpu().numpy()
+    for i in (0, 5, 511, 512, 767, 768, 1499):
+        assert rel_l2(c[i], oaf.spectrum_crop(big[i])) < 1e-5
+    assert np.array_equal(c[0], c[6]) and np.array_equal(c[5], c[1499])
+    zc = oaf.candidates(16)
+    _, sc = ctx.hv_af_scan(hd, LAM, PITCH, n_candidates=16, want_scores=True)
+    sc = sc.cpu().numpy()
+    for i in (0, 511, 512, 1499):
+        assert rel_l2(sc[i], oaf.scan_scores(big[i], LAM, PITCH, zc)) < 1e-4
+    assert np.array_equal(sc[1], sc[7])
+    m = ctx.af_model(init, 256, Z_MEAN, Z_SCALE)
+    try:
+        z0, s0, _, _ = m.predict(hd, LAM, PITCH, tau=1e9)
+        z1, s1, _, _ = m.predict(hd, LAM, PITCH, tau=1e9, refine=12, refine_k=2.0)
+        assert torch.equal(s0, s1)
+        z1 = z1.cpu().numpy()
+        assert np.all((z1 >= 0.05 - 1e-6) & (z1 <= 0.5 + 1e-6))
+        zs, _, _, _ = m.predict(hd[:1], LAM, PITCH, tau=1e9, refine=12, refine_k=2.0)  # a single hologram
+        assert zs.shape == (1,) and abs(float(zs[0]) - z1[0]) < 1e-6
+    finally:
+        m.close()
+    flat = torch.zeros(2 * 65536 + 64, dtype=torch.uint8, device="cuda")
+    mis = flat[1:1 + 65536].view(1, 256, 256)
+    for call in (lambda: ctx.hv_af_crops(mis), lambda: ctx.hv_af_scan(mis, LAM, PITCH)):
+        with pytest.raises(hv.HvError) as e:
+            call()
+        assert e.value.status == hv.HV_ERR_ARG
+
+
 def test_synthesis_deterministic(ctx):
     say("training-hologram synthesis")
     z = np.repeat([0.12, 0.3, 0.44], 4)
