@@ -518,8 +518,10 @@ hv_status hv_af_model_load(hv_af_model* model, const float* params, const float*
 hv_status hv_af_forward(hv_af_model* model, const void* crops, int batch, float* out, void* hip_stream);
 /* The same output from the inference kernels that hv_af_predict runs: each
  * convolution as an implicit GEMM on the matrix cores with fp16 weights and
- * activations and FP32 accumulation, the pooling fused into the last
- * convolution.  Agrees with hv_af_forward to fp16 rounding. */
+ * activations and FP32 accumulation, the first layer evaluated inside the
+ * second layer's kernel, the pooling fused into the last convolution.
+ * Agrees with hv_af_forward to fp16 rounding.  batch <= max(max_batch,
+ * 1024) (HV_ERR_SHAPE otherwise). */
 hv_status hv_af_infer(hv_af_model* model, const void* crops, int batch, float* out, void* hip_stream);
 /* Mean Gaussian NLL 0.5 (s + (z_n - zhat)^2 e^{-s}) over the batch (loss,
  * device float[1], nullable) and its gradient with respect to every parameter
