@@ -150,9 +150,12 @@ __global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT
       }
     }
   };
-  int u = blockIdx.x;
-  if (u < nunits) fetch(u);
-  for (; u < nunits; u += gridDim.x) {
+  // One unit.  The next unit's loads are issued on every pass (the last one
+  // re-reads a unit) and the stores are unrolled; with the first pass peeled
+  // off the loop, the loop is entered with the same operations in flight as
+  // on its back edge, so the wait for the loads at the top of a pass counts
+  // them exactly and leaves the previous pass's stores in flight.
+  auto pass = [&](int u) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       if (CH % NT == 0 || tid + i * NT < CH) {
@@ -163,12 +166,12 @@ __global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT
       }
     }
     __syncthreads();
-    if (u + (int)gridDim.x < nunits) fetch(u + gridDim.x);
+    fetch(u + (int)gridDim.x < nunits ? u + (int)gridDim.x : nunits - 1);
     fft_lds<NX, NB, NT, -1>(buf, tw, tid);
     // The complex FFT Z of rows x (real part) and y (imaginary part) gives
     // X(f) = (Z(f) + conj Z(-f)) / 2 and Y(f) = (Z(f) - conj Z(-f)) / 2i.
     TOUT* dst = out + (long)(u / tiles) * (NX / 2) * ny + (u % tiles) * ROWS;
-#pragma unroll 4
+#pragma unroll
     for (int k = 0; k < (NX / 2) / FPK; ++k) {
       const int fx = fs + k * FPK;
       const float2 z1 = prow[skew(fx)];
@@ -187,7 +190,12 @@ __global__ __launch_bounds__(NT) void k_row_r2c(const TIN* __restrict__ in, TOUT
                  c2::scale(ve, scale), c2::scale(vo, scale));
     }
     __syncthreads();
-  }
+  };
+  int u = blockIdx.x;
+  if (u >= nunits) return;
+  fetch(u);
+  pass(u);
+  for (u += gridDim.x; u < nunits; u += gridDim.x) pass(u);
 }
 
 // ------------------------------------------------------------------ K2
@@ -248,16 +256,16 @@ __global__ __launch_bounds__(NT) void k_col_as(const TIO* __restrict__ in, TIO* 
       for (int r = 0; r < RF; ++r) v0[u][r] = ld_off(src + r * SP, o);
     }
   }
-  // transfer-function values of this thread's outputs, fetched now so that
-  // their latency hides behind the column FFT
-  // The angular-spectrum H depends on fx^2 + fy^2 only, so H(-fx, fy) =
-  // H(fx, fy): the -fx table is read only for the packed column fx = 0,
-  // whose -fx partner is the Nyquist column.
+  // transfer-function values of this thread's outputs (+fx and -fx
+  // tables; for the packed column fx = 0 the -fx partner is the Nyquist
+  // column), fetched now so that their latency hides behind the column FFT.
+  // Both are loaded unconditionally: a copy of one into the other where
+  // they are equal would wait for every load issued before it.
   float2 ha[U], hb[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     ha[u] = ld_off(hpos + TS::row_i(u) * NY + TS::col_i(u), off_h);
-    hb[u] = f0 + st + TS::row_i(u) == 0 ? ld_off(hneg + TS::row_i(u) * NY + TS::col_i(u), off_h) : ha[u];
+    hb[u] = ld_off(hneg + TS::row_i(u) * NY + TS::col_i(u), off_h);
   }
   fft_lds_io<NY, BC, NT, -1>(buf, tw, tid, [&](int u, int r, int, int) { return load_c(&v0[u][r]); }, nullptr);
   // Sequences BC..2BC-1 are free until the inverse transform: the -fx
