@@ -484,26 +484,55 @@ __global__ __launch_bounds__(NT) void k_gram(const TIN* __restrict__ u, long npi
     }
     __syncthreads();
     if (p0 + GP < pend) fetch(p0 + GP);
+    if constexpr (MIXED) {
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-      const int tile = wave + NW * i;
-      if (tile < T * T) {
-        const int mt = tile / T, nt = tile % T;
-        const int ma = 32 * mt + (lane & 31), nb = 32 * nt + (lane & 31);
-        if constexpr (MIXED) {
+      for (int i = 0; i < TPW; ++i) {
+        const int tile = wave + NW * i;
+        if (tile < T * T) {
+          const int mt = tile / T, nt = tile % T;
+          const int ma = 32 * mt + (lane & 31), nb = 32 * nt + (lane & 31);
 #pragma unroll
           for (int kk = 0; kk < GP / 16; ++kk) {
             hv_h8 a = *reinterpret_cast<const hv_h8*>(&l16[ma * LS16 + 16 * kk + 8 * h]);
             hv_h8 b = *reinterpret_cast<const hv_h8*>(&l16[nb * LS16 + 16 * kk + 8 * h]);
             acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc[i], 0, 0, 0);
           }
-        } else {
-#pragma unroll 8
-          for (int kk = 0; kk < GP / 2; ++kk) {
-            float a = l32[ma * LS32 + 2 * kk + h];
-            float b = l32[nb * LS32 + 2 * kk + h];
-            acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[i], 0, 0, 0);
-          }
+        }
+      }
+    } else {
+      // the wave's tiles interleaved per k-step (independent accumulators),
+      // each step's operands read from LDS one step ahead of its MFMAs; each
+      // accumulator sees its k-steps in the same order as one tile at a time
+      const float* ap[TPW];
+      const float* bp[TPW];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int tile = min(wave + NW * i, T * T - 1), mt = tile / T, nt = tile % T;
+        ap[i] = l32 + (32 * mt + (lane & 31)) * LS32 + h;
+        bp[i] = l32 + (32 * nt + (lane & 31)) * LS32 + h;
+      }
+      float a[TPW], b[TPW];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        a[i] = ap[i][0];
+        b[i] = bp[i][0];
+      }
+#pragma unroll
+      for (int kk = 0; kk < GP / 2; ++kk) {
+        float an[TPW], bn[TPW];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          an[i] = kk + 1 < GP / 2 ? ap[i][2 * (kk + 1)] : 0.f;
+          bn[i] = kk + 1 < GP / 2 ? bp[i][2 * (kk + 1)] : 0.f;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+          if (wave + NW * i < T * T) acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[i], acc[i], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          a[i] = an[i];
+          b[i] = bn[i];
         }
       }
     }
