@@ -489,6 +489,22 @@ def precision_case(hv, torch, steps):
                                          "frac_of_hbm_peak": gemm_b / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                          "useful_TFLOPs": flops["field_coef"] * npix / (ms_g * 1e-3) / 1e12}
         del fld, mo
+        # PCA of one window: a single chunk, so its covariance, eigensolve and
+        # projection run on one stream with nothing beside them
+        ctx.hv_pca(x[:w], opt, w, w, 1, 63, prec)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        for _ in range(steps):
+            ctx.hv_pca(x[:w], opt, w, w, 1, 63, prec)
+        torch.cuda.synchronize()
+        for k in ("gram", "jacobi", "proj_energy"):
+            ms, cnt = ctx.kernel_time(k)
+            if cnt:
+                alone[k + "_one_window"] = {"avg_ms": ms / cnt}
+                if k in flops:
+                    tf = flops[k] * npix / (ms / cnt * 1e-3) / 1e12
+                    alone[k + "_one_window"].update({"useful_TFLOPs": tf, "frac": tf / MFMA_PEAK_TFLOPS[name]})
+        ctx.set_timing(False)
         out[name] = {"stft_moments_frames_per_s": n / (ms_s * 1e-3), "pca_frames_per_s": n / (ms_p * 1e-3),
                      "ssa_fft_moments_frames_per_s": n / (ms_a * 1e-3), "kernels": kern, "kernels_alone": alone}
         log(f"precision case {name}: {out[name]}")
